@@ -1,0 +1,243 @@
+/*
+ * cpm.h -- C ABI of the MI355X Closest Point Method multigrid library (libcpm.so).
+ *
+ * Problem (Chen & Macdonald, Sec. 2.1, eq. (2.1)): solve  -Lap_S u + c u = f  on a closed
+ * curve or surface S given by its closest-point function cp, c > 0 constant.  f is known
+ * on S and extended off S by f~(x) = f(cp(x)).
+ *
+ * Discretization (Sec. 3.1): a band of grid nodes x_i = h * i (i integer) within
+ * sqrt(lam2) * h of S; tensor-product cubic Lagrange interpolation at cp(x_i) (matrix E,
+ * 4^d weights per node); (2d+1)-point Laplacian L = N - (2d/h^2) I; the CPM matrix
+ * A = c I - M, M = E L - gamma (I - E), gamma = 2d/h^2 (eq. (3.3)), which equals
+ * A u = delta u - E (N u) with delta = c + 2d/h^2.
+ *
+ * Solver (Sec. 4, Algorithm 4.1): V(nu1, nu2) cycles with Ruuth-Merriman Jacobi smoothing
+ * (Jacobi on cI - L followed by closest-point extension, eqs. (4.2a)-(4.2b)), damped by
+ * omega outside the extension; closest-point restriction / prolongation between bands of
+ * spacing h and 2h (Sec. 4.3, linear interpolation as in Sec. 4.6); a direct solve on the
+ * coarsest level.  The residual is r = E(f + N u) - delta u = E f - A u and the solve stops
+ * when ||r||_inf / ||E f||_inf < rtol.
+ *
+ * Conventions for every call:
+ *   - Vectors are contiguous device arrays (double unless stated) of length n(level), in
+ *     band order: grid multi-indices sorted lexicographically with x fastest, then y, z.
+ *   - f is given as samples f(cp(x_i)) at the band nodes of level 0.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).  Calls are
+ *     asynchronous on that stream unless stated; device buffers belong to the caller.
+ *   - A band handle is immutable after cpm_build_band except for cached coarse-level
+ *     factorizations and captured graphs; do not use one handle from two host threads
+ *     at once.
+ *   - Every function returns a cpm_status; nothing throws across the ABI.  On failure
+ *     cpm_last_error() returns a message for the calling thread.
+ */
+#ifndef CPM_H
+#define CPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CPM_OK = 0,
+  CPM_E_INVALID = 1,  /* bad argument (null pointer, level out of range, bad sizes)      */
+  CPM_E_BAND = 2,     /* a stencil leaves the band (band radius too small for the grid) */
+  CPM_E_NOMEM = 3,    /* host or device allocation failed                                */
+  CPM_E_HIP = 4,      /* a HIP runtime call failed                                       */
+  CPM_E_NOCONV = 5,   /* max_cycles reached before rtol                                  */
+  CPM_E_DIVERGED = 6, /* NaN / Inf residual                                              */
+  CPM_E_WORKSPACE = 7 /* workspace too small                                             */
+} cpm_status;
+
+typedef enum { CPM_CIRCLE = 0, CPM_SPHERE = 1, CPM_TORUS = 2 } cpm_surface_kind;
+
+/* Analytic surfaces of the paper's examples (Sec. 3.4, 4.6).  circle: 2-D, centre
+ * center[0..1], radius R.  sphere: centre, radius R.  torus: centre, axis along z,
+ * tube-centre radius R, tube radius r. */
+typedef struct {
+  int kind;
+  double center[3];
+  double R;
+  double r;
+} cpm_surface;
+
+/* Grid hierarchy: finest spacing h0, h_l = h0 * 2^l for l = 0..levels-1, band radius^2 =
+ * lam2 * h_l^2 on each level (lam2 <= 0 selects 13 in 2-D, 17 in 3-D). */
+typedef struct {
+  double h0;
+  int levels;
+  double lam2;
+} cpm_grid;
+
+typedef enum { CPM_F64 = 0, CPM_MIXED = 1 } cpm_precision;
+typedef enum { CPM_SMOOTH_JACOBI = 0, CPM_SMOOTH_LEARNED = 1 } cpm_smoother;
+
+/* Solver parameters.  precision CPM_MIXED: float32 smoothing / extension / transfers on
+ * every level, float64 outer residual, refinement update and coarsest solve.
+ * smoother CPM_SMOOTH_LEARNED: the learned local smoother (cpm_set_smoother_weights) on
+ * the two finest levels, Jacobi elsewhere, with a fallback to Jacobi (see cpm_stats). */
+typedef struct {
+  double c;
+  int nu1;
+  int nu2;
+  double omega;
+  int precision;
+  int smoother;
+} cpm_params;
+
+#define CPM_MAX_HISTORY 256
+
+typedef struct {
+  int cycles;                               /* V-cycles (outer steps) executed          */
+  double relres;                            /* final ||E f - A u||_inf / ||E f||_inf   */
+  double relres_history[CPM_MAX_HISTORY];   /* after each cycle                         */
+  int fallback_cycle;                       /* learned smoother: cycle at which it was
+                                               replaced by Jacobi, -1 if never           */
+  double seconds;                           /* wall time of the solve loop on the host  */
+} cpm_stats;
+
+typedef struct cpm_band_s* cpm_band;
+
+/* Build the band hierarchy (Sec. 3.1, Sec. 4.3): band nodes, closest points, cubic
+ * extension stencils, Laplacian neighbours and the linear restriction / prolongation
+ * stencils of every level; checks that every stencil node and every Laplacian neighbour
+ * of a stencil node lies in the band (CPM_E_BAND otherwise).  Index construction runs on
+ * the host in IEEE double without contraction, then the arrays are copied to the device
+ * on `stream` (the call synchronizes it).  *out receives a handle owned by the caller
+ * (release with cpm_band_free). */
+cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void* stream,
+                          cpm_band* out);
+
+/* Release a handle and all device memory it owns.  NULL is accepted. */
+cpm_status cpm_band_free(cpm_band band);
+
+/* Number of levels, embedding dimension. */
+cpm_status cpm_band_levels(cpm_band band, int* levels, int* dim);
+
+/* Size n and spacing h of one level. */
+cpm_status cpm_band_info(cpm_band band, int level, int64_t* n, double* h);
+
+/* Copy one level's grid multi-indices (n x dim int32, row-major) and closest points
+ * (n x dim double, row-major) into caller-owned host buffers (either may be NULL). */
+cpm_status cpm_band_export(cpm_band band, int level, int32_t* idx_host, double* cp_host);
+
+/* Copy one level's addressing into caller-owned host buffers (any may be NULL):
+ *   runE  n x 4^(dim-1): band index of the first node of each x-run of the cubic stencil
+ *         of cp(x_i), run (b, c) at column b + 4c (y offset b, z offset c);
+ *   nbr   n x 2*dim: band index of the -x,+x,-y,+y(,-z,+z) neighbour, -1 if absent;
+ *   runP  n x 2^(dim-1): x-runs of the linear stencil of cp(x_i) in level+1's band
+ *         (prolongation; undefined on the coarsest level);
+ *   runR  n x 2^(dim-1): x-runs of the linear stencil of cp(x_i) in level-1's band
+ *         (restriction; undefined on level 0). */
+cpm_status cpm_band_export_stencils(cpm_band band, int level, int32_t* runE, int32_t* nbr,
+                                    int32_t* runP, int32_t* runR);
+
+/* Bytes of device workspace a vcycle / solve with these parameters needs. */
+cpm_status cpm_workspace_size(cpm_band band, const cpm_params* params, size_t* bytes);
+
+/* Au = (c + 2d/h^2) u - E (N u) on one level (eq. (3.3), matrix-free).  u and Au are
+ * double device vectors of length n(level) that must not overlap; work is a device
+ * buffer of at least n(level) doubles. */
+cpm_status cpm_apply(cpm_band band, int level, double c, const double* u, double* Au,
+                     double* work, void* stream);
+
+/* One application of the extension: out = E g on one level (degree-3 closest-point
+ * interpolation, Sec. 3.1).  double device vectors of length n(level), not overlapping. */
+cpm_status cpm_extend(cpm_band band, int level, const double* g, double* out, void* stream);
+
+/* One V(nu1, nu2) cycle in place on u (Algorithm 4.1) for right-hand side f.  work has
+ * cpm_workspace_size bytes.  If relres_out is not NULL the call synchronizes the stream
+ * and stores ||E f - A u||_inf / ||E f||_inf of the new iterate.  Only precision CPM_F64
+ * and smoother CPM_SMOOTH_JACOBI are accepted here. */
+cpm_status cpm_vcycle(cpm_band band, const cpm_params* params, const double* f, double* u,
+                      void* work, size_t work_bytes, double* relres_out, void* stream);
+
+/* Repeat cycles from the given u (set it to 0 for the paper's start) until
+ * ||E f - A u||_inf / ||E f||_inf < rtol or max_cycles.  Synchronous on return.  In
+ * CPM_MIXED precision each outer step is one float32 V-cycle on the correction equation
+ * A e = r with r evaluated in double.  Returns CPM_E_NOCONV / CPM_E_DIVERGED with stats
+ * filled. */
+cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, double* u,
+                     void* work, size_t work_bytes, double rtol, int max_cycles,
+                     cpm_stats* stats, void* stream);
+
+/* Run a fixed number of cycles as one captured HIP graph launch per `cycles_per_launch`
+ * cycles, without host synchronization between launches (throughput measurement).  The
+ * relative residual after every cycle is written to relres_dev (device, >= cycles
+ * doubles).  Same precision / smoother rules as cpm_solve. */
+cpm_status cpm_run_cycles(cpm_band band, const cpm_params* params, const double* f, double* u,
+                          void* work, size_t work_bytes, int cycles, int cycles_per_launch,
+                          double* relres_dev, void* stream);
+
+/* Average duration in microseconds of one launch of a V-cycle kernel on one level, timed
+ * with HIP events on the band's stream over `reps` back-to-back launches: which = 0 the
+ * extension pass fused with Jacobi smoothing (the dominant kernel), 1 the neighbour-sum
+ * pass, 2 restriction into `level` (level >= 1), 3 prolongation from level+1 into `level`
+ * (level < levels-1).  Level 0 runs on f and u, other levels on workspace vectors; the
+ * values left in u are those of repeated smoothing.  Synchronous. */
+cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, int level, int reps,
+                           const double* f, double* u, void* work, size_t work_bytes, double* avg_us,
+                           void* stream);
+
+/* Batched solve of nprob independent problems (different surfaces, spacings and sizes)
+ * with the same parameters: every phase of the V-cycle runs as one launch over the tiles
+ * of all problems, and one V-cycle of the whole batch is one captured HIP graph.  f[k],
+ * u[k] are device vectors of problem k; work has cpm_workspace_size_batched bytes.
+ * precision must be CPM_MIXED or CPM_F64.  stats: nprob entries (NULL allowed).
+ * Returns CPM_E_NOCONV if any problem missed rtol. */
+cpm_status cpm_workspace_size_batched(int nprob, const cpm_band* bands, const cpm_params* params,
+                                      size_t* bytes);
+cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params* params,
+                             const double* const* f, double* const* u, void* work,
+                             size_t work_bytes, double rtol, int max_cycles, cpm_stats* stats,
+                             void* stream);
+
+/* Tile-size autotuner: time the library's gather kernels on this band with each candidate
+ * block size and remember the fastest per level-size class.  Synchronous. */
+cpm_status cpm_autotune(cpm_band band, void* stream);
+
+/* ---- learned smoother ---------------------------------------------------------------
+ * Network (per node): x = [r_patch / s (27 values: residual on the 3x3x3 grid patch
+ * around the node, 0 outside the band, x fastest), the node's 12 one-dimensional cubic
+ * weights (x, y, z; 4 each), 25 zeros] (64 features), s = max |r_patch| (update 0 when
+ * s = 0); hidden = relu(W1 x + b1) (64), y = w2 . hidden + b2; update
+ * u_i += (s / delta) * y.  W1 is 64 x 64 row-major (out, in), all weights bfloat16
+ * (uint16 bit patterns), arithmetic float32. */
+#define CPM_MLP_IN 64
+#define CPM_MLP_HIDDEN 64
+#define CPM_MLP_FEATURES 39
+
+/* Copy weights (W1 64*64, b1 64, w2 64, b2 1, bf16 bit patterns) into the band handle;
+ * the learned smoother uses them.  rho_plain is the per-cycle contraction of the plain
+ * method above which the solve falls back to Jacobi. */
+cpm_status cpm_set_smoother_weights(cpm_band band, const uint16_t* w_bf16, double rho_plain);
+
+/* Forward pass on m feature rows: X (m x 64 bf16 bit patterns, device), W (device, same
+ * packing as cpm_set_smoother_weights), Y (m floats, device), H (m x 64 floats, device,
+ * hidden activations kept for the backward pass; may be NULL). */
+cpm_status cpm_mlp_forward(int64_t m, const uint16_t* X, const uint16_t* W, float* Y, float* H,
+                           void* stream);
+
+/* Backward pass of the mean squared loss (1/m) sum (Y - T)^2 : gradients w.r.t. W1, b1,
+ * w2, b2 in float32 (G, device, 64*64 + 64 + 64 + 1 floats, overwritten).  X, W as in the
+ * forward pass, H and Y from it, T targets (m floats). */
+cpm_status cpm_mlp_backward(int64_t m, const uint16_t* X, const uint16_t* W, const float* H,
+                            const float* Y, const float* T, float* G, void* stream);
+
+/* Features of the learned smoother for every node of one level: the A-space residual r of
+ * (u, f) is evaluated (double), then X (n x 64 bf16, device) and scale s (n floats, device)
+ * are written.  Used to generate training data from plain solves. */
+cpm_status cpm_smoother_features(cpm_band band, int level, double c, const double* f,
+                                 const double* u, uint16_t* X, float* s, void* work,
+                                 void* stream);
+
+const char* cpm_status_string(int status);
+const char* cpm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPM_H */

@@ -1,0 +1,347 @@
+// Host construction of the computational band and its addressing (Sec. 3.1, Sec. 4.3).
+//
+// Compiled without floating-point contraction: every closest point, distance and stencil
+// fraction is the IEEE double result of the operations below, in this order.  This fixed
+// order is the convention that makes band membership and stencil bases reproducible
+// bit for bit by any independent implementation that follows it.
+//
+// Band of level l (spacing h): nodes x = h * i with dist(x, S)^2 <= lam2 * (h * h),
+// lam2 = 13 (2-D) or 17 (3-D) by default, i.e. radius sqrt(13) h / sqrt(17) h, wide enough
+// to contain B_interp and B_edge of the cubic scheme.  Nodes are sorted x fastest.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+#include "cpm_internal.h"
+
+namespace cpm {
+namespace {
+
+// Closest point and squared distance (Sec. 2.1) for the analytic surfaces.  Ties resolve
+// onto the surface: centre -> direction +x; torus axis -> radial direction +x; torus
+// tube-centre circle -> outward radial direction.
+inline void closest_point(const cpm_surface& s, int dim, const double* x, double* cp,
+                          double* dist2) {
+  const double* c = s.center;
+  if (s.kind == CPM_CIRCLE || s.kind == CPM_SPHERE) {
+    double dx = x[0] - c[0];
+    double dy = x[1] - c[1];
+    double dz = dim == 3 ? x[2] - c[2] : 0.0;
+    double rho2;
+    if (dim == 2) {
+      double a = dx * dx;
+      double b = dy * dy;
+      rho2 = a + b;
+    } else {
+      double a = dx * dx;
+      double b = dy * dy;
+      double ab = a + b;
+      double cz = dz * dz;
+      rho2 = ab + cz;
+    }
+    double rho = std::sqrt(rho2);
+    double nx, ny, nz;
+    if (rho == 0.0) {
+      nx = 1.0;
+      ny = 0.0;
+      nz = 0.0;
+    } else {
+      nx = dx / rho;
+      ny = dy / rho;
+      nz = dz / rho;
+    }
+    double t;
+    t = s.R * nx;
+    cp[0] = c[0] + t;
+    t = s.R * ny;
+    cp[1] = c[1] + t;
+    if (dim == 3) {
+      t = s.R * nz;
+      cp[2] = c[2] + t;
+    }
+    double d = rho - s.R;
+    *dist2 = d * d;
+    return;
+  }
+  // torus, axis along z
+  double dx = x[0] - c[0];
+  double dy = x[1] - c[1];
+  double dz = x[2] - c[2];
+  double a2 = dx * dx;
+  double b2 = dy * dy;
+  double rho = std::sqrt(a2 + b2);
+  double ex, ey;
+  if (rho == 0.0) {
+    ex = 1.0;
+    ey = 0.0;
+  } else {
+    ex = dx / rho;
+    ey = dy / rho;
+  }
+  double a = rho - s.R;
+  double b = dz;
+  double aa = a * a;
+  double bb = b * b;
+  double t = std::sqrt(aa + bb);
+  double na, nb;
+  if (t == 0.0) {
+    na = 1.0;
+    nb = 0.0;
+  } else {
+    na = a / t;
+    nb = b / t;
+  }
+  double rna = s.r * na;
+  double rad = s.R + rna;
+  double px = rad * ex;
+  double py = rad * ey;
+  double pz = s.r * nb;
+  cp[0] = c[0] + px;
+  cp[1] = c[1] + py;
+  cp[2] = c[2] + pz;
+  double d = t - s.r;
+  *dist2 = d * d;
+}
+
+void bounding_box(const cpm_surface& s, int dim, double lo[3], double hi[3]) {
+  double ext[3];
+  if (s.kind == CPM_TORUS) {
+    ext[0] = ext[1] = s.R + s.r;
+    ext[2] = s.r;
+  } else {
+    ext[0] = ext[1] = ext[2] = s.R;
+  }
+  for (int a = 0; a < dim; ++a) {
+    lo[a] = s.center[a] - ext[a];
+    hi[a] = s.center[a] + ext[a];
+  }
+}
+
+inline int64_t box_key(const HostLevel& L, int64_t x, int64_t y, int64_t z) {
+  int64_t rx = x - L.lo[0], ry = y - L.lo[1], rz = z - L.lo[2];
+  if (rx < 0 || ry < 0 || rz < 0 || rx >= L.ext[0] || ry >= L.ext[1] || rz >= L.ext[2]) return -1;
+  return (rz * L.ext[1] + ry) * L.ext[0] + rx;
+}
+
+inline int32_t lookup(const HostLevel& L, int64_t x, int64_t y, int64_t z) {
+  int64_t k = box_key(L, x, y, z);
+  return k < 0 ? -1 : L.map[k];
+}
+
+// Enumerate the band of one level; nodes come out sorted (z, y, x with x fastest).
+cpm_status enumerate_level(const cpm_surface& s, int dim, double h, double lam2, HostLevel& L,
+                           std::string& err) {
+  L.dim = dim;
+  L.h = h;
+  L.lam2 = lam2;
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  bounding_box(s, dim, lo, hi);
+  double lam = std::sqrt(lam2);
+  for (int a = 0; a < 3; ++a) {
+    if (a < dim) {
+      L.lo[a] = (int64_t)std::floor((lo[a] - lam * h) / h) - 2;
+      int64_t ihi = (int64_t)std::ceil((hi[a] + lam * h) / h) + 2;
+      L.ext[a] = ihi - L.lo[a] + 1;
+    } else {
+      L.lo[a] = 0;
+      L.ext[a] = 1;
+    }
+  }
+  double box = (double)L.ext[0] * (double)L.ext[1] * (double)L.ext[2];
+  if (box > 2.0e9) {
+    err = "index box too large for the dense lookup map";
+    return CPM_E_INVALID;
+  }
+  const double thr = lam2 * (h * h);
+  const int64_t nz = L.ext[2];
+  std::vector<std::vector<int32_t>> planes((size_t)nz);
+  std::vector<std::vector<double>> pcp((size_t)nz);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t kz = 0; kz < nz; ++kz) {
+    int64_t z = L.lo[2] + kz;
+    std::vector<int32_t>& P = planes[(size_t)kz];
+    std::vector<double>& C = pcp[(size_t)kz];
+    double x[3], cp[3], d2;
+    for (int64_t y = L.lo[1]; y < L.lo[1] + L.ext[1]; ++y) {
+      for (int64_t xi = L.lo[0]; xi < L.lo[0] + L.ext[0]; ++xi) {
+        x[0] = (double)xi * h;
+        x[1] = (double)y * h;
+        x[2] = (double)z * h;
+        closest_point(s, dim, x, cp, &d2);
+        if (d2 <= thr) {
+          P.push_back((int32_t)xi);
+          P.push_back((int32_t)y);
+          if (dim == 3) P.push_back((int32_t)z);
+          for (int a = 0; a < dim; ++a) C.push_back(cp[a]);
+        }
+      }
+    }
+  }
+  int64_t n = 0;
+  for (auto& P : planes) n += (int64_t)P.size() / dim;
+  if (n <= 0 || n > INT32_MAX / 2) {
+    err = n <= 0 ? "empty band" : "band too large for 32-bit indices";
+    return CPM_E_INVALID;
+  }
+  L.n = n;
+  L.idx.resize((size_t)(n * dim));
+  L.cp.resize((size_t)(n * dim));
+  size_t off = 0;
+  for (int64_t kz = 0; kz < nz; ++kz) {
+    auto& P = planes[(size_t)kz];
+    auto& C = pcp[(size_t)kz];
+    if (!P.empty()) {
+      std::memcpy(&L.idx[off], P.data(), P.size() * sizeof(int32_t));
+      std::memcpy(&L.cp[off], C.data(), C.size() * sizeof(double));
+      off += P.size();
+    }
+    std::vector<int32_t>().swap(P);
+    std::vector<double>().swap(C);
+  }
+  L.map.assign((size_t)(L.ext[0] * L.ext[1] * L.ext[2]), -1);
+#pragma omp parallel for
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t* m = &L.idx[(size_t)(i * dim)];
+    int64_t k = box_key(L, m[0], m[1], dim == 3 ? m[2] : 0);
+    L.map[(size_t)k] = (int32_t)i;
+  }
+  return CPM_OK;
+}
+
+// Stencil of a point y on a grid of spacing h, degree p in {1, 3}: per axis
+// t = y / h, base = floor(t) - (p - 1) / 2, frac = t - floor(t).
+inline void stencil_base(const double* y, int dim, double h, int p, int64_t* base, double* frac) {
+  for (int a = 0; a < dim; ++a) {
+    double t = y[a] / h;
+    double fl = std::floor(t);
+    frac[a] = t - fl;
+    base[a] = (int64_t)fl - (p - 1) / 2;
+  }
+}
+
+// Fill x-run starts of a (p+1)^dim stencil of each node's closest point in `target`.
+// runs[(b + (p+1) c) * n + i] = band index of node (bx, by + b, bz + c) of target, and the
+// p following nodes along x must be the next band entries.
+bool stencil_runs(const HostLevel& src, const HostLevel& target, int p, std::vector<int32_t>& runs,
+                  std::vector<double>& frac, int64_t* bad_node) {
+  const int dim = src.dim;
+  const int64_t n = src.n;
+  const int q = p + 1;
+  const int nruns = dim == 2 ? q : q * q;
+  runs.assign((size_t)(nruns * n), -1);
+  frac.assign((size_t)(dim * n), 0.0);
+  int64_t bad = -1;
+#pragma omp parallel for
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t base[3] = {0, 0, 0};
+    double fr[3] = {0, 0, 0};
+    stencil_base(&src.cp[(size_t)(i * dim)], dim, target.h, p, base, fr);
+    for (int a = 0; a < dim; ++a) frac[(size_t)(a * n + i)] = fr[a];
+    bool ok = true;
+    for (int r = 0; r < nruns && ok; ++r) {
+      int b = r % q, c = r / q;
+      int64_t y = base[1] + b;
+      int64_t z = dim == 3 ? base[2] + c : 0;
+      int32_t j = lookup(target, base[0], y, z);
+      if (j < 0) {
+        ok = false;
+        break;
+      }
+      for (int a = 1; a <= p; ++a) {
+        if (lookup(target, base[0] + a, y, z) != j + a) {
+          ok = false;
+          break;
+        }
+      }
+      runs[(size_t)(r * n + i)] = j;
+    }
+    if (!ok) {
+#pragma omp critical
+      if (bad < 0 || i < bad) bad = i;
+    }
+  }
+  *bad_node = bad;
+  return bad < 0;
+}
+
+}  // namespace
+
+cpm_status build_host_levels(const cpm_surface& s, const cpm_grid& g, int dim,
+                             std::vector<HostLevel>& levels, std::string& err) {
+  const int L = g.levels;
+  double lam2 = g.lam2 > 0 ? g.lam2 : (dim == 2 ? 13.0 : 17.0);
+  levels.assign((size_t)L, HostLevel());
+  for (int l = 0; l < L; ++l) {
+    double h = g.h0 * std::ldexp(1.0, l);
+    cpm_status st = enumerate_level(s, dim, h, lam2, levels[(size_t)l], err);
+    if (st != CPM_OK) return st;
+  }
+  for (int l = 0; l < L; ++l) {
+    HostLevel& Lv = levels[(size_t)l];
+    int64_t bad = -1;
+    if (!stencil_runs(Lv, Lv, 3, Lv.runE, Lv.fracE, &bad)) {
+      std::ostringstream os;
+      os << "cubic stencil of node " << bad << " leaves the band on level " << l;
+      err = os.str();
+      return CPM_E_BAND;
+    }
+    // Laplacian neighbours, missing ones marked -1 (they only occur at band edges)
+    const int64_t n = Lv.n;
+    const int nn = 2 * dim;
+    Lv.nbr.assign((size_t)(nn * n), -1);
+#pragma omp parallel for
+    for (int64_t i = 0; i < n; ++i) {
+      const int32_t* m = &Lv.idx[(size_t)(i * dim)];
+      for (int a = 0; a < dim; ++a) {
+        for (int sg = 0; sg < 2; ++sg) {
+          int64_t q[3] = {m[0], m[1], dim == 3 ? m[2] : 0};
+          q[a] += sg == 0 ? -1 : 1;
+          Lv.nbr[(size_t)((2 * a + sg) * n + i)] = lookup(Lv, q[0], q[1], q[2]);
+        }
+      }
+    }
+    // containment: every node of a cubic stencil has all of its Laplacian neighbours
+    std::vector<uint8_t> used((size_t)n, 0);
+    const int nruns = dim == 2 ? 4 : 16;
+    for (int r = 0; r < nruns; ++r)
+      for (int64_t i = 0; i < n; ++i) {
+        int32_t j = Lv.runE[(size_t)(r * n + i)];
+        for (int a = 0; a < 4; ++a) used[(size_t)(j + a)] = 1;
+      }
+    for (int64_t j = 0; j < n; ++j) {
+      if (!used[(size_t)j]) continue;
+      for (int k = 0; k < nn; ++k)
+        if (Lv.nbr[(size_t)(k * n + j)] < 0) {
+          std::ostringstream os;
+          os << "band too narrow on level " << l << ": stencil node " << j
+             << " lacks a Laplacian neighbour";
+          err = os.str();
+          return CPM_E_BAND;
+        }
+    }
+  }
+  for (int l = 0; l + 1 < L; ++l) {
+    HostLevel& F = levels[(size_t)l];
+    HostLevel& C = levels[(size_t)(l + 1)];
+    int64_t bad = -1;
+    if (!stencil_runs(F, C, 1, F.runP, F.fracP, &bad)) {
+      std::ostringstream os;
+      os << "prolongation stencil of node " << bad << " (level " << l << ") leaves the band of level "
+         << l + 1;
+      err = os.str();
+      return CPM_E_BAND;
+    }
+    if (!stencil_runs(C, F, 1, C.runR, C.fracR, &bad)) {
+      std::ostringstream os;
+      os << "restriction stencil of node " << bad << " (level " << l + 1 << ") leaves the band of level "
+         << l;
+      err = os.str();
+      return CPM_E_BAND;
+    }
+  }
+  for (auto& Lv : levels) std::vector<int32_t>().swap(Lv.map);
+  return CPM_OK;
+}
+
+}  // namespace cpm

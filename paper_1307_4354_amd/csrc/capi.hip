@@ -1,0 +1,847 @@
+// C ABI of libcpm: band handles, matrix-free operator application, the CPM V-cycle
+// (Algorithm 4.1) in double precision and as float32 inner cycles of a float64 iterative
+// refinement, solve loops (eager or as captured HIP graphs).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "capi_internal.h"
+
+namespace cpm {
+
+thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+}  // namespace cpm
+
+using namespace cpm;
+
+// ------------------------------------------------------------------------------------
+// helpers
+// ------------------------------------------------------------------------------------
+
+namespace cpm {
+
+LaunchCfg band_cfg(const cpm_band b, int64_t n) {
+  int cls = n < (1 << 16) ? 0 : (n < (1 << 20) ? 1 : 2);
+  return b->lc[cls];
+}
+
+template <typename T>
+static T* dalloc(size_t count, cpm_status* st) {
+  if (count == 0) return nullptr;
+  void* p = nullptr;
+  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+    *st = CPM_E_NOMEM;
+    return nullptr;
+  }
+  return (T*)p;
+}
+
+template <typename T>
+static cpm_status upload(T** dst, const std::vector<T>& src) {
+  if (src.empty()) {
+    *dst = nullptr;
+    return CPM_OK;
+  }
+  cpm_status st = CPM_OK;
+  *dst = dalloc<T>(src.size(), &st);
+  if (st != CPM_OK) return st;
+  if (hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return CPM_E_HIP;
+  return CPM_OK;
+}
+
+static cpm_status upload_f32(float** dst, const std::vector<double>& src) {
+  std::vector<float> tmp(src.size());
+  for (size_t i = 0; i < src.size(); ++i) tmp[i] = (float)src[i];
+  return upload(dst, tmp);
+}
+
+static void free_dev(cpm_band b) {
+  for (auto& D : b->dev) {
+    void* ps[] = {D.runE, D.nbr, D.fracE, D.fracE32, D.runP, D.fracP, D.fracP32, D.runR, D.fracR, D.fracR32};
+    for (void* p : ps)
+      if (p) (void)hipFree(p);
+  }
+  b->dev.clear();
+  void* ps[] = {b->coarseM, b->gj_col, b->gj_info, b->dscal, b->dcounter, b->dhist, b->mlpW};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  b->coarseM = nullptr;
+  if (b->hpinned) (void)hipHostFree(b->hpinned);
+  b->hpinned = nullptr;
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
+
+double level_delta(const cpm_band b, int l, double c) {
+  const double h = b->dev[(size_t)l].h;
+  return c + 2.0 * b->dim / (h * h);
+}
+
+// Enter / leave the band's private stream (ordered after / before the caller's stream).
+cpm_status enter(cpm_band b, void* user) {
+  hipStream_t us = (hipStream_t)user;
+  if (hipEventRecord(b->ev_in, us) != hipSuccess) return CPM_E_HIP;
+  if (hipStreamWaitEvent(b->stream, b->ev_in, 0) != hipSuccess) return CPM_E_HIP;
+  return CPM_OK;
+}
+
+cpm_status leave(cpm_band b, void* user) {
+  hipStream_t us = (hipStream_t)user;
+  if (hipEventRecord(b->ev_out, b->stream) != hipSuccess) return CPM_E_HIP;
+  if (hipStreamWaitEvent(us, b->ev_out, 0) != hipSuccess) return CPM_E_HIP;
+  return CPM_OK;
+}
+
+cpm_status check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return CPM_E_HIP;
+  }
+  return CPM_OK;
+}
+
+// Coarsest level: Z = A_c^{-1} E_c with A_c = delta I - E_c N_c, by Gauss-Jordan with
+// partial pivoting on [A_c | E_c] on the device.  Cached per value of c.
+cpm_status ensure_coarse(cpm_band b, double c) {
+  if (b->coarseM && b->coarse_c == c) return CPM_OK;
+  const int l = b->L - 1;
+  const DevLevel& D = b->dev[(size_t)l];
+  const int n = (int)D.n;
+  if (n > kMaxCoarse) {
+    std::ostringstream os;
+    os << "coarsest level has " << n << " nodes; the dense direct solve allows at most " << kMaxCoarse
+       << " (use more levels)";
+    set_error(os.str());
+    return CPM_E_INVALID;
+  }
+  cpm_status st = CPM_OK;
+  if (!b->coarseM) {
+    b->coarseM = dalloc<double>((size_t)2 * n * n, &st);
+    b->gj_col = dalloc<double>((size_t)n, &st);
+    b->gj_info = dalloc<int>(1, &st);
+    if (st != CPM_OK) {
+      set_error("device allocation of the coarse matrix failed");
+      return st;
+    }
+  }
+  hipStream_t s = b->stream;
+  const double h = D.h;
+  launch_assemble_coarse(b->dim, n, D.runE, D.fracE, D.nbr, level_delta(b, l, c), 1.0 / (h * h), b->coarseM, s);
+  launch_fill<int>(1, b->gj_info, 0, s);
+  for (int k = 0; k < n; ++k) launch_gj_step(n, k, b->coarseM, b->gj_col, b->gj_info, s);
+  if ((st = check_launch("coarse factorization")) != CPM_OK) return st;
+  int info = 0;
+  if (hipMemcpyAsync(&info, b->gj_info, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    set_error("coarse factorization: synchronization failed");
+    return CPM_E_HIP;
+  }
+  if (info != 0) {
+    set_error("coarsest-level matrix is singular");
+    b->coarse_c = NAN;
+    return CPM_E_INVALID;
+  }
+  b->coarse_c = c;
+  return CPM_OK;
+}
+
+// ---- workspace layout ---------------------------------------------------------------
+
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+template <typename T>
+static T* carve(char*& p, size_t count) {
+  T* r = (T*)p;
+  p += align_up(count * sizeof(T));
+  return r;
+}
+
+size_t workspace_bytes(const cpm_band b, int precision) {
+  size_t tot = 0;
+  for (int l = 0; l < b->L; ++l) {
+    const size_t n = (size_t)b->dev[(size_t)l].n;
+    if (precision == CPM_F64) {
+      tot += align_up(n * 8) * (l == 0 ? 2 : 4);
+    } else {
+      tot += align_up(n * 4) * 4;
+      if (l == 0) tot += align_up(n * 8);
+    }
+  }
+  return tot + 256;
+}
+
+template <typename T>
+void carve_levels(const cpm_band b, void* work, LevelBufs<T>* B, double** g64) {
+  char* p = (char*)(((uintptr_t)work + 255) & ~(uintptr_t)255);
+  for (int l = 0; l < b->L; ++l) {
+    const size_t n = (size_t)b->dev[(size_t)l].n;
+    if (sizeof(T) == 8) {
+      if (l == 0) {
+        B[l].u = nullptr;
+        B[l].f = nullptr;
+      } else {
+        B[l].u = carve<T>(p, n);
+        B[l].f = carve<T>(p, n);
+      }
+      B[l].g = carve<T>(p, n);
+      B[l].r = carve<T>(p, n);
+    } else {
+      B[l].u = carve<T>(p, n);
+      B[l].f = carve<T>(p, n);
+      B[l].g = carve<T>(p, n);
+      B[l].r = carve<T>(p, n);
+      if (l == 0 && g64) *g64 = carve<double>(p, n);
+    }
+  }
+}
+
+// ---- one V-cycle (Algorithm 4.1) ------------------------------------------------------
+
+template <typename T>
+static const T* fracE_of(const DevLevel& D);
+template <>
+const double* fracE_of<double>(const DevLevel& D) { return D.fracE; }
+template <>
+const float* fracE_of<float>(const DevLevel& D) { return D.fracE32; }
+template <typename T>
+static const T* fracP_of(const DevLevel& D);
+template <>
+const double* fracP_of<double>(const DevLevel& D) { return D.fracP; }
+template <>
+const float* fracP_of<float>(const DevLevel& D) { return D.fracP32; }
+template <typename T>
+static const T* fracR_of(const DevLevel& D);
+template <>
+const double* fracR_of<double>(const DevLevel& D) { return D.fracR; }
+template <>
+const float* fracR_of<float>(const DevLevel& D) { return D.fracR32; }
+
+// Damped Ruuth-Merriman Jacobi sweep: g = f + N u, u <- u + (w/delta)(b + E g - delta u)
+template <typename T>
+void smooth_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g, double c, double omega,
+                  unsigned long long* nrm, hipStream_t s) {
+  const DevLevel& D = b->dev[(size_t)l];
+  const LaunchCfg lc = band_cfg(b, D.n);
+  const double delta = level_delta(b, l, c);
+  launch_nsum<T>(b->dim, D.n, u, f, D.nbr, (T)(1.0 / (D.h * D.h)), g, nullptr, lc, s);
+  if (b->learned_active && l < 2 && b->mlpW) {
+    learned_sweep<T>(b, l, u, f, rhsA, g, c, s);
+    return;
+  }
+  launch_ext<T, T>(b->dim, EXT_SMOOTH, D.n, g, D.runE, fracE_of<T>(D), rhsA, u, (T*)nullptr, (T)delta,
+                   (T)(omega / delta), nrm, lc, s);
+}
+
+template <typename T>
+void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const cpm_params& p, hipStream_t s) {
+  const DevLevel& D = b->dev[(size_t)l];
+  const LaunchCfg lc = band_cfg(b, D.n);
+  if (l == b->L - 1) {
+    // coarsest: u = A_c^{-1} E_c f  (f-space right-hand side)
+    launch_coarse_gemv<T>((int)D.n, b->coarseM + D.n, 2 * D.n, B[l].f, B[l].u, s);
+    return;
+  }
+  const T* f = rhsA ? nullptr : B[l].f;
+  const double delta = level_delta(b, l, p.c);
+  for (int k = 0; k < p.nu1; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, p.c, p.omega, nullptr, s);
+  // residual r = b + E(f + N u) - delta u, restricted to the next level (where u := 0)
+  launch_nsum<T>(b->dim, D.n, B[l].u, f, D.nbr, (T)(1.0 / (D.h * D.h)), B[l].g, nullptr, lc, s);
+  launch_ext<T, T>(b->dim, EXT_RESID, D.n, B[l].g, D.runE, fracE_of<T>(D), rhsA, B[l].u, B[l].r, (T)delta,
+                   (T)0, nullptr, lc, s);
+  const DevLevel& C = b->dev[(size_t)(l + 1)];
+  launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, band_cfg(b, C.n), s);
+  vcycle_level<T>(b, l + 1, B, nullptr, p, s);
+  launch_prolong<T>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<T>(D), B[l].u, lc, s);
+  for (int k = 0; k < p.nu2; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, p.c, p.omega, nullptr, s);
+}
+
+// ||E f||_inf into scalar slot 1 (double)
+void enqueue_rhs_norm(const cpm_band b, const double* f, double* g, hipStream_t s) {
+  const DevLevel& D = b->dev[0];
+  launch_zero_u64(b->dscal + 1, 1, s);
+  launch_ext<double, double>(b->dim, EXT_PLAIN, D.n, f, D.runE, D.fracE, nullptr, nullptr, (double*)nullptr,
+                             0.0, 0.0, b->dscal + 1, band_cfg(b, D.n), s);
+}
+
+// ||E(f + N u) - delta u||_inf into slot 0; optionally the residual as float into r32
+void enqueue_resid64(const cpm_band b, const double* f, const double* u, double* g, float* r32, double c,
+                     hipStream_t s) {
+  const DevLevel& D = b->dev[0];
+  const LaunchCfg lc = band_cfg(b, D.n);
+  launch_nsum<double>(b->dim, D.n, u, f, D.nbr, 1.0 / (D.h * D.h), g, b->dscal, lc, s);
+  launch_ext<double, float>(b->dim, EXT_RESID, D.n, g, D.runE, D.fracE, nullptr, const_cast<double*>(u), r32,
+                            level_delta(b, 0, c), 0.0, b->dscal, lc, s);
+}
+
+// One complete cycle of the solve loop on the band stream, ending with the residual
+// norm of the new iterate in slot 0.
+void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, double* u, void* work, hipStream_t s) {
+  if (p.precision == CPM_F64) {
+    LevelBufs<double> B[kMaxLevels];
+    carve_levels<double>(b, work, B, nullptr);
+    B[0].u = u;
+    B[0].f = const_cast<double*>(f);
+    vcycle_level<double>(b, 0, B, nullptr, p, s);
+    enqueue_resid64(b, f, u, B[0].g, nullptr, p.c, s);
+  } else {
+    LevelBufs<float> B[kMaxLevels];
+    double* g64 = nullptr;
+    carve_levels<float>(b, work, B, &g64);
+    // B[0].f holds the float32 copy of the double residual (A-space right-hand side)
+    launch_fill<float>(b->dev[0].n, B[0].u, 0.0f, s);
+    vcycle_level<float>(b, 0, B, B[0].f, p, s);
+    launch_axpy_f32_to_f64(b->dev[0].n, B[0].u, u, s);
+    enqueue_resid64(b, f, u, g64, B[0].f, p.c, s);
+  }
+}
+
+// Prologue of a solve: ||E f|| (slot 1) and, in mixed precision, the first residual.
+void enqueue_prologue(const cpm_band b, const cpm_params& p, const double* f, const double* u, void* work,
+                      hipStream_t s) {
+  if (p.precision == CPM_F64) {
+    LevelBufs<double> B[kMaxLevels];
+    carve_levels<double>(b, work, B, nullptr);
+    enqueue_rhs_norm(b, f, B[0].g, s);
+  } else {
+    LevelBufs<float> B[kMaxLevels];
+    double* g64 = nullptr;
+    carve_levels<float>(b, work, B, &g64);
+    enqueue_rhs_norm(b, f, g64, s);
+    enqueue_resid64(b, f, u, g64, B[0].f, p.c, s);
+  }
+}
+
+cpm_status read_scalars(cpm_band b, double* r0, double* r1) {
+  if (hipMemcpyAsync(b->hpinned, b->dscal, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, b->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(b->stream) != hipSuccess) {
+    set_error(std::string("synchronization failed: ") + hipGetErrorString(hipGetLastError()));
+    return CPM_E_HIP;
+  }
+  double v0, v1;
+  std::memcpy(&v0, &b->hpinned[0], 8);
+  std::memcpy(&v1, &b->hpinned[1], 8);
+  if (r0) *r0 = v0;
+  if (r1) *r1 = v1;
+  return CPM_OK;
+}
+
+static std::string graph_key(const char* tag, const cpm_params& p, const void* a, const void* bb, const void* c,
+                             int extra) {
+  std::ostringstream os;
+  os << tag << '|' << p.c << '|' << p.nu1 << '|' << p.nu2 << '|' << p.omega << '|' << p.precision << '|'
+     << p.smoother << '|' << a << '|' << bb << '|' << c << '|' << extra;
+  return os.str();
+}
+
+// Capture `fn` on the band stream once per key and launch the executable graph.
+template <typename Fn>
+cpm_status graph_launch(cpm_band b, const std::string& key, Fn fn) {
+  auto it = b->graphs.find(key);
+  if (it == b->graphs.end()) {
+    if (b->graphs.size() > 64) {
+      for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+      b->graphs.clear();
+    }
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      set_error("hipStreamBeginCapture failed");
+      return CPM_E_HIP;
+    }
+    fn(b->stream);
+    hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    if (e != hipSuccess || !graph) {
+      set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
+      return CPM_E_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      set_error(std::string("graph instantiation failed: ") + hipGetErrorString(e));
+      return CPM_E_HIP;
+    }
+    it = b->graphs.emplace(key, exec).first;
+  }
+  if (hipGraphLaunch(it->second, b->stream) != hipSuccess) {
+    set_error("hipGraphLaunch failed");
+    return CPM_E_HIP;
+  }
+  return CPM_OK;
+}
+
+cpm_status validate_params(const cpm_band b, const cpm_params* p) {
+  if (!p) {
+    set_error("params is NULL");
+    return CPM_E_INVALID;
+  }
+  if (!(p->c > 0.0) || p->nu1 < 0 || p->nu2 < 0 || p->nu1 + p->nu2 == 0 || !(p->omega > 0.0) ||
+      !(p->omega <= 2.0)) {
+    set_error("invalid solver parameters (need c > 0, nu1 + nu2 > 0, 0 < omega <= 2)");
+    return CPM_E_INVALID;
+  }
+  if (p->precision != CPM_F64 && p->precision != CPM_MIXED) {
+    set_error("unknown precision");
+    return CPM_E_INVALID;
+  }
+  if (p->smoother != CPM_SMOOTH_JACOBI && p->smoother != CPM_SMOOTH_LEARNED) {
+    set_error("unknown smoother");
+    return CPM_E_INVALID;
+  }
+  if (p->precision == CPM_MIXED && b->L < 2) {
+    set_error("mixed precision needs at least two levels");
+    return CPM_E_INVALID;
+  }
+  if (p->smoother == CPM_SMOOTH_LEARNED && !b->mlpW) {
+    set_error("learned smoother selected but no weights were set");
+    return CPM_E_INVALID;
+  }
+  return CPM_OK;
+}
+
+}  // namespace cpm
+
+// ------------------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------------------
+
+extern "C" {
+
+const char* cpm_status_string(int status) {
+  switch (status) {
+    case CPM_OK: return "ok";
+    case CPM_E_INVALID: return "invalid argument";
+    case CPM_E_BAND: return "stencil leaves the band";
+    case CPM_E_NOMEM: return "out of memory";
+    case CPM_E_HIP: return "HIP runtime error";
+    case CPM_E_NOCONV: return "not converged";
+    case CPM_E_DIVERGED: return "diverged (NaN or Inf residual)";
+    case CPM_E_WORKSPACE: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+const char* cpm_last_error(void) { return cpm::g_last_error.c_str(); }
+
+cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void* stream, cpm_band* out) {
+  if (!surface || !grid || !out) {
+    set_error("null argument");
+    return CPM_E_INVALID;
+  }
+  *out = nullptr;
+  const int kind = surface->kind;
+  if (kind != CPM_CIRCLE && kind != CPM_SPHERE && kind != CPM_TORUS) {
+    set_error("unknown surface kind");
+    return CPM_E_INVALID;
+  }
+  if (!(surface->R > 0) || (kind == CPM_TORUS && !(surface->r > 0 && surface->r < surface->R))) {
+    set_error("invalid surface radii");
+    return CPM_E_INVALID;
+  }
+  if (!(grid->h0 > 0) || grid->levels < 1 || grid->levels > kMaxLevels) {
+    set_error("invalid grid (need h0 > 0, 1 <= levels <= 12)");
+    return CPM_E_INVALID;
+  }
+  const int dim = kind == CPM_CIRCLE ? 2 : 3;
+  cpm_band b = new (std::nothrow) cpm_band_s();
+  if (!b) return CPM_E_NOMEM;
+  b->surf = *surface;
+  b->grid = *grid;
+  b->dim = dim;
+  b->L = grid->levels;
+  std::string err;
+  cpm_status st = build_host_levels(*surface, *grid, dim, b->host, err);
+  if (st != CPM_OK) {
+    set_error(err);
+    delete b;
+    return st;
+  }
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+    set_error("stream / event creation failed");
+    delete b;
+    return CPM_E_HIP;
+  }
+  b->dev.resize((size_t)b->L);
+  for (int l = 0; l < b->L && st == CPM_OK; ++l) {
+    HostLevel& H = b->host[(size_t)l];
+    DevLevel& D = b->dev[(size_t)l];
+    D.n = H.n;
+    D.h = H.h;
+    if (st == CPM_OK) st = upload(&D.runE, H.runE);
+    if (st == CPM_OK) st = upload(&D.nbr, H.nbr);
+    if (st == CPM_OK) st = upload(&D.fracE, H.fracE);
+    if (st == CPM_OK) st = upload_f32(&D.fracE32, H.fracE);
+    if (st == CPM_OK) st = upload(&D.runP, H.runP);
+    if (st == CPM_OK) st = upload(&D.fracP, H.fracP);
+    if (st == CPM_OK && !H.fracP.empty()) st = upload_f32(&D.fracP32, H.fracP);
+    if (st == CPM_OK) st = upload(&D.runR, H.runR);
+    if (st == CPM_OK) st = upload(&D.fracR, H.fracR);
+    if (st == CPM_OK && !H.fracR.empty()) st = upload_f32(&D.fracR32, H.fracR);
+    // keep only what export needs on the host
+    std::vector<double>().swap(H.fracE);
+    std::vector<double>().swap(H.fracP);
+    std::vector<double>().swap(H.fracR);
+    std::vector<int32_t>().swap(H.runE);
+    std::vector<int32_t>().swap(H.runP);
+    std::vector<int32_t>().swap(H.runR);
+    std::vector<int32_t>().swap(H.nbr);
+  }
+  if (st == CPM_OK) {
+    b->dscal = dalloc<unsigned long long>(8, &st);
+    b->dcounter = dalloc<int>(4, &st);
+    b->dhist = dalloc<double>(CPM_MAX_HISTORY, &st);
+    if (st == CPM_OK && hipHostMalloc((void**)&b->hpinned, 8 * sizeof(unsigned long long), 0) != hipSuccess)
+      st = CPM_E_NOMEM;
+  }
+  if (st != CPM_OK) {
+    set_error(st == CPM_E_NOMEM ? "device allocation failed" : "host to device copy failed");
+    free_dev(b);
+    delete b;
+    return st;
+  }
+  (void)stream;
+  *out = b;
+  return CPM_OK;
+}
+
+cpm_status cpm_band_free(cpm_band band) {
+  if (!band) return CPM_OK;
+  (void)hipStreamSynchronize(band->stream);
+  free_dev(band);
+  if (band->ev_in) (void)hipEventDestroy(band->ev_in);
+  if (band->ev_out) (void)hipEventDestroy(band->ev_out);
+  if (band->stream) (void)hipStreamDestroy(band->stream);
+  delete band;
+  return CPM_OK;
+}
+
+cpm_status cpm_band_levels(cpm_band band, int* levels, int* dim) {
+  if (!band) {
+    set_error("null band");
+    return CPM_E_INVALID;
+  }
+  if (levels) *levels = band->L;
+  if (dim) *dim = band->dim;
+  return CPM_OK;
+}
+
+cpm_status cpm_band_info(cpm_band band, int level, int64_t* n, double* h) {
+  if (!band || level < 0 || level >= band->L) {
+    set_error("null band or level out of range");
+    return CPM_E_INVALID;
+  }
+  if (n) *n = band->dev[(size_t)level].n;
+  if (h) *h = band->dev[(size_t)level].h;
+  return CPM_OK;
+}
+
+cpm_status cpm_band_export(cpm_band band, int level, int32_t* idx_host, double* cp_host) {
+  if (!band || level < 0 || level >= band->L) {
+    set_error("null band or level out of range");
+    return CPM_E_INVALID;
+  }
+  const HostLevel& H = band->host[(size_t)level];
+  if (idx_host) std::memcpy(idx_host, H.idx.data(), H.idx.size() * sizeof(int32_t));
+  if (cp_host) std::memcpy(cp_host, H.cp.data(), H.cp.size() * sizeof(double));
+  return CPM_OK;
+}
+
+static cpm_status copy_rows(int32_t* dst, const int32_t* src, int64_t n, int cols) {
+  // device slot-major (cols x n) -> host row-major (n x cols)
+  std::vector<int32_t> tmp((size_t)(n * cols));
+  if (hipMemcpy(tmp.data(), src, tmp.size() * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) {
+    set_error("device to host copy failed");
+    return CPM_E_HIP;
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int c = 0; c < cols; ++c) dst[i * cols + c] = tmp[(size_t)(c * n + i)];
+  return CPM_OK;
+}
+
+cpm_status cpm_band_export_stencils(cpm_band band, int level, int32_t* runE, int32_t* nbr, int32_t* runP,
+                                    int32_t* runR) {
+  if (!band || level < 0 || level >= band->L) {
+    set_error("null band or level out of range");
+    return CPM_E_INVALID;
+  }
+  const DevLevel& D = band->dev[(size_t)level];
+  const int d = band->dim;
+  cpm_status st = CPM_OK;
+  if (runE && (st = copy_rows(runE, D.runE, D.n, d == 2 ? 4 : 16)) != CPM_OK) return st;
+  if (nbr && (st = copy_rows(nbr, D.nbr, D.n, 2 * d)) != CPM_OK) return st;
+  if (runP && D.runP && (st = copy_rows(runP, D.runP, D.n, d == 2 ? 2 : 4)) != CPM_OK) return st;
+  if (runR && D.runR && (st = copy_rows(runR, D.runR, D.n, d == 2 ? 2 : 4)) != CPM_OK) return st;
+  return CPM_OK;
+}
+
+cpm_status cpm_workspace_size(cpm_band band, const cpm_params* params, size_t* bytes) {
+  if (!band || !params || !bytes) {
+    set_error("null argument");
+    return CPM_E_INVALID;
+  }
+  *bytes = workspace_bytes(band, params->precision);
+  return CPM_OK;
+}
+
+cpm_status cpm_apply(cpm_band band, int level, double c, const double* u, double* Au, double* work, void* stream) {
+  if (!band || level < 0 || level >= band->L || !u || !Au || !work || !(c > 0.0)) {
+    set_error("cpm_apply: invalid argument");
+    return CPM_E_INVALID;
+  }
+  const DevLevel& D = band->dev[(size_t)level];
+  cpm_status st = enter(band, stream);
+  if (st != CPM_OK) return st;
+  const LaunchCfg lc = band_cfg(band, D.n);
+  launch_nsum<double>(band->dim, D.n, u, nullptr, D.nbr, 1.0 / (D.h * D.h), work, nullptr, lc, band->stream);
+  launch_ext<double, double>(band->dim, EXT_APPLY, D.n, work, D.runE, D.fracE, nullptr, const_cast<double*>(u),
+                             Au, level_delta(band, level, c), 0.0, nullptr, lc, band->stream);
+  if ((st = check_launch("cpm_apply")) != CPM_OK) return st;
+  return leave(band, stream);
+}
+
+cpm_status cpm_extend(cpm_band band, int level, const double* g, double* out, void* stream) {
+  if (!band || level < 0 || level >= band->L || !g || !out) {
+    set_error("cpm_extend: invalid argument");
+    return CPM_E_INVALID;
+  }
+  const DevLevel& D = band->dev[(size_t)level];
+  cpm_status st = enter(band, stream);
+  if (st != CPM_OK) return st;
+  launch_ext<double, double>(band->dim, EXT_PLAIN, D.n, g, D.runE, D.fracE, nullptr, nullptr, out, 0.0, 0.0,
+                             nullptr, band_cfg(band, D.n), band->stream);
+  if ((st = check_launch("cpm_extend")) != CPM_OK) return st;
+  return leave(band, stream);
+}
+
+cpm_status cpm_vcycle(cpm_band band, const cpm_params* params, const double* f, double* u, void* work,
+                      size_t work_bytes, double* relres_out, void* stream) {
+  if (!band || !f || !u || !work) {
+    set_error("cpm_vcycle: null argument");
+    return CPM_E_INVALID;
+  }
+  cpm_status st = validate_params(band, params);
+  if (st != CPM_OK) return st;
+  if (params->precision != CPM_F64 || params->smoother != CPM_SMOOTH_JACOBI) {
+    set_error("cpm_vcycle runs the plain double-precision cycle only");
+    return CPM_E_INVALID;
+  }
+  if (work_bytes < workspace_bytes(band, params->precision)) {
+    set_error("workspace too small");
+    return CPM_E_WORKSPACE;
+  }
+  if ((st = enter(band, stream)) != CPM_OK) return st;
+  if ((st = ensure_coarse(band, params->c)) != CPM_OK) return st;
+  band->learned_active = false;
+  if (relres_out) enqueue_prologue(band, *params, f, u, work, band->stream);
+  enqueue_cycle(band, *params, f, u, work, band->stream);
+  if ((st = check_launch("cpm_vcycle")) != CPM_OK) return st;
+  if (relres_out) {
+    double r0, r1;
+    if ((st = read_scalars(band, &r0, &r1)) != CPM_OK) return st;
+    *relres_out = r1 > 0 ? r0 / r1 : 0.0;
+  }
+  return leave(band, stream);
+}
+
+cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, double* u, void* work,
+                     size_t work_bytes, double rtol, int max_cycles, cpm_stats* stats, void* stream) {
+  if (!band || !f || !u || !work || max_cycles < 0) {
+    set_error("cpm_solve: invalid argument");
+    return CPM_E_INVALID;
+  }
+  cpm_status st = validate_params(band, params);
+  if (st != CPM_OK) return st;
+  if (work_bytes < workspace_bytes(band, params->precision)) {
+    set_error("workspace too small");
+    return CPM_E_WORKSPACE;
+  }
+  cpm_stats local;
+  cpm_stats* S = stats ? stats : &local;
+  std::memset(S, 0, sizeof(cpm_stats));
+  S->fallback_cycle = -1;
+  auto t0 = std::chrono::steady_clock::now();
+  if ((st = enter(band, stream)) != CPM_OK) return st;
+  if ((st = ensure_coarse(band, params->c)) != CPM_OK) return st;
+  const cpm_params p = *params;
+  band->learned_active = p.smoother == CPM_SMOOTH_LEARNED;
+  enqueue_prologue(band, p, f, u, work, band->stream);
+  double r0 = 0, bn = 0;
+  if ((st = read_scalars(band, &r0, &bn)) != CPM_OK) return st;
+  if (!std::isfinite(bn) || !std::isfinite(r0)) {
+    set_error("right-hand side or initial residual is not finite");
+    (void)leave(band, stream);
+    return CPM_E_DIVERGED;
+  }
+  if (!(bn > 0)) {
+    // E f = 0: the solution is u = 0
+    launch_fill<double>(band->dev[0].n, u, 0.0, band->stream);
+    S->relres = 0.0;
+    (void)hipStreamSynchronize(band->stream);
+    return leave(band, stream);
+  }
+  double prev = p.precision == CPM_F64 ? NAN : r0 / bn;
+  st = CPM_E_NOCONV;
+  for (int k = 0; k < max_cycles; ++k) {
+    const std::string key = graph_key("cycle", p, f, u, work, band->learned_active ? 1 : 0);
+    cpm_status gs = graph_launch(band, key, [&](hipStream_t s) { enqueue_cycle(band, p, f, u, work, s); });
+    if (gs != CPM_OK) return gs;
+    double rn = 0;
+    if ((gs = read_scalars(band, &rn, nullptr)) != CPM_OK) return gs;
+    const double rel = rn / bn;
+    if (k < CPM_MAX_HISTORY) S->relres_history[k] = rel;
+    S->cycles = k + 1;
+    S->relres = rel;
+    if (!std::isfinite(rel)) {
+      st = CPM_E_DIVERGED;
+      set_error("residual is not finite");
+      break;
+    }
+    // learned smoother: fall back to Jacobi when a cycle contracts worse than the plain method
+    if (band->learned_active && std::isfinite(prev) && prev > 0 && rel / prev > band->rho_plain) {
+      band->learned_active = false;
+      S->fallback_cycle = k;
+    }
+    prev = rel;
+    if (rel < rtol) {
+      st = CPM_OK;
+      break;
+    }
+  }
+  band->learned_active = false;
+  S->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (st == CPM_E_NOCONV) set_error("maximum number of cycles reached");
+  cpm_status ls = leave(band, stream);
+  return st != CPM_OK ? st : ls;
+}
+
+cpm_status cpm_run_cycles(cpm_band band, const cpm_params* params, const double* f, double* u, void* work,
+                          size_t work_bytes, int cycles, int cycles_per_launch, double* relres_dev, void* stream) {
+  if (!band || !f || !u || !work || !relres_dev || cycles < 0 || cycles_per_launch < 1) {
+    set_error("cpm_run_cycles: invalid argument");
+    return CPM_E_INVALID;
+  }
+  cpm_status st = validate_params(band, params);
+  if (st != CPM_OK) return st;
+  if (work_bytes < workspace_bytes(band, params->precision)) {
+    set_error("workspace too small");
+    return CPM_E_WORKSPACE;
+  }
+  if ((st = enter(band, stream)) != CPM_OK) return st;
+  if ((st = ensure_coarse(band, params->c)) != CPM_OK) return st;
+  const cpm_params p = *params;
+  band->learned_active = p.smoother == CPM_SMOOTH_LEARNED;
+  launch_fill<int>(1, band->dcounter, 0, band->stream);
+  enqueue_prologue(band, p, f, u, work, band->stream);
+  int done = 0;
+  while (done < cycles) {
+    const int k = std::min(cycles_per_launch, cycles - done);
+    const std::string key = graph_key("run", p, f, u, work, k * 4 + (band->learned_active ? 1 : 0)) +
+                            std::to_string((uintptr_t)relres_dev);
+    st = graph_launch(band, key, [&](hipStream_t s) {
+      for (int j = 0; j < k; ++j) {
+        enqueue_cycle(band, p, f, u, work, s);
+        launch_record_relres(band->dscal, band->dscal + 1, relres_dev, band->dcounter, s);
+      }
+    });
+    if (st != CPM_OK) return st;
+    done += k;
+  }
+  band->learned_active = false;
+  if ((st = check_launch("cpm_run_cycles")) != CPM_OK) return st;
+  return leave(band, stream);
+}
+
+cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, int level, int reps,
+                           const double* f, double* u, void* work, size_t work_bytes, double* avg_us,
+                           void* stream) {
+  if (!band || !f || !u || !work || !avg_us || reps < 1 || level < 0 || level >= band->L || which < 0 ||
+      which > 3) {
+    set_error("cpm_time_kernel: invalid argument");
+    return CPM_E_INVALID;
+  }
+  cpm_status st = validate_params(band, params);
+  if (st != CPM_OK) return st;
+  if (work_bytes < workspace_bytes(band, params->precision)) {
+    set_error("workspace too small");
+    return CPM_E_WORKSPACE;
+  }
+  if ((which == 2 && level == 0) || (which == 3 && level == band->L - 1)) {
+    set_error("cpm_time_kernel: no such transfer on this level");
+    return CPM_E_INVALID;
+  }
+  if ((st = enter(band, stream)) != CPM_OK) return st;
+  hipStream_t s = band->stream;
+  const DevLevel& D = band->dev[(size_t)level];
+  const LaunchCfg lc = band_cfg(band, D.n);
+  const double delta = level_delta(band, level, params->c);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return CPM_E_HIP;
+  auto run = [&](auto tag) {
+    using T = decltype(tag);
+    LevelBufs<T> B[kMaxLevels];
+    double* g64 = nullptr;
+    carve_levels<T>(band, work, B, &g64);
+    T* uu = (sizeof(T) == 8 && level == 0) ? (T*)u : B[level].u;
+    const T* ff = (sizeof(T) == 8 && level == 0) ? (const T*)f : B[level].f;
+    if (!(sizeof(T) == 8 && level == 0)) {
+      launch_fill<T>(D.n, B[level].u, (T)0.25, s);
+      launch_fill<T>(D.n, B[level].f, (T)1.0, s);
+    }
+    launch_nsum<T>(band->dim, D.n, uu, ff, D.nbr, (T)(1.0 / (D.h * D.h)), B[level].g, nullptr, lc, s);
+    for (int pass = 0; pass < 2; ++pass) {  // pass 0 warms up
+      const int k = pass == 0 ? 1 : reps;
+      if (pass == 1) (void)hipEventRecord(e0, s);
+      for (int r = 0; r < k; ++r) {
+        if (which == 0) {
+          launch_ext<T, T>(band->dim, EXT_SMOOTH, D.n, B[level].g, D.runE, fracE_of<T>(D), nullptr, uu, (T*)nullptr,
+                           (T)delta, (T)(params->omega / delta), nullptr, lc, s);
+        } else if (which == 1) {
+          launch_nsum<T>(band->dim, D.n, uu, ff, D.nbr, (T)(1.0 / (D.h * D.h)), B[level].g, nullptr, lc, s);
+        } else if (which == 2) {
+          const DevLevel& F = band->dev[(size_t)(level - 1)];
+          (void)F;
+          launch_restrict<T>(band->dim, D.n, B[level - 1].g, D.runR, fracR_of<T>(D), B[level].r, nullptr, lc, s);
+        } else {
+          launch_prolong<T>(band->dim, D.n, B[level + 1].g, D.runP, fracP_of<T>(D), B[level].r, lc, s);
+        }
+      }
+      if (pass == 1) (void)hipEventRecord(e1, s);
+    }
+  };
+  if (params->precision == CPM_F64)
+    run(double(0));
+  else
+    run(float(0));
+  if ((st = check_launch("cpm_time_kernel")) != CPM_OK) return st;
+  float ms = 0.f;
+  if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+    set_error("event timing failed");
+    return CPM_E_HIP;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *avg_us = 1000.0 * ms / reps;
+  return leave(band, stream);
+}
+
+}  // extern "C"
+
+namespace cpm {
+template void vcycle_level<double>(const cpm_band, int, LevelBufs<double>*, const double*, const cpm_params&,
+                                   hipStream_t);
+template void vcycle_level<float>(const cpm_band, int, LevelBufs<float>*, const float*, const cpm_params&,
+                                  hipStream_t);
+}  // namespace cpm

@@ -1,0 +1,85 @@
+// Band handle and solver internals shared by the C ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "cpm_internal.h"
+#include "kernels.h"
+
+namespace cpm {
+
+constexpr int kMaxLevels = 12;
+constexpr int kMaxCoarse = 12000;  // largest coarsest level for the dense direct solve
+
+template <typename T>
+struct LevelBufs {
+  T* u = nullptr;  // iterate (correction on coarse levels)
+  T* f = nullptr;  // right-hand side
+  T* g = nullptr;  // f + N u
+  T* r = nullptr;  // residual
+};
+
+}  // namespace cpm
+
+struct cpm_band_s {
+  cpm_surface surf{};
+  cpm_grid grid{};
+  int dim = 0;
+  int L = 0;
+  std::vector<cpm::HostLevel> host;
+  std::vector<cpm::DevLevel> dev;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_in = nullptr;
+  hipEvent_t ev_out = nullptr;
+  // coarsest level: [A_c | Z] after Gauss-Jordan, Z = A_c^{-1} E_c at column offset n
+  double coarse_c = 0.0 / 0.0;
+  double* coarseM = nullptr;
+  double* gj_col = nullptr;
+  int* gj_info = nullptr;
+  // device scalars: [0] residual norm bits, [1] ||E f|| bits; relres history + counter
+  unsigned long long* dscal = nullptr;
+  int* dcounter = nullptr;
+  double* dhist = nullptr;
+  unsigned long long* hpinned = nullptr;
+  cpm::LaunchCfg lc[3];
+  // learned smoother
+  uint16_t* mlpW = nullptr;
+  double rho_plain = 1.0;
+  bool learned_active = false;
+  uint16_t* featX = nullptr;  // scratch for the learned sweep (n0 x 64 bf16)
+  float* featS = nullptr;
+  double* feat_r64 = nullptr;
+  float* feat_r32 = nullptr;
+  int64_t feat_cap = 0;
+  std::map<std::string, hipGraphExec_t> graphs;
+};
+
+namespace cpm {
+
+LaunchCfg band_cfg(const cpm_band b, int64_t n);
+double level_delta(const cpm_band b, int l, double c);
+cpm_status enter(cpm_band b, void* user);
+cpm_status leave(cpm_band b, void* user);
+cpm_status check_launch(const char* what);
+cpm_status ensure_coarse(cpm_band b, double c);
+size_t workspace_bytes(const cpm_band b, int precision);
+template <typename T>
+void carve_levels(const cpm_band b, void* work, LevelBufs<T>* B, double** g64);
+template <typename T>
+void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const cpm_params& p, hipStream_t s);
+void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, double* u, void* work, hipStream_t s);
+void enqueue_prologue(const cpm_band b, const cpm_params& p, const double* f, const double* u, void* work,
+                      hipStream_t s);
+cpm_status read_scalars(cpm_band b, double* r0, double* r1);
+cpm_status validate_params(const cpm_band b, const cpm_params* p);
+
+// learned smoother sweep on level l (< 2): given g = f + N u already computed into g,
+// evaluate the residual, the features, the network and update u.
+template <typename T>
+void learned_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g, double c, hipStream_t s);
+
+}  // namespace cpm

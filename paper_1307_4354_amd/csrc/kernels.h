@@ -1,0 +1,74 @@
+// Launchers of the gfx950 kernels (kernels.hip).  All launches are asynchronous on the
+// given stream; sizes are validated by the caller.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cpm {
+
+// Modes of the extension pass (t = E g at every node of a level).
+enum ExtMode {
+  EXT_SMOOTH = 0,  // u <- u + (omega/delta) r,  r = b + t - delta u   (in place on u)
+  EXT_RESID = 1,   // out = r = b + t - delta u
+  EXT_APPLY = 2,   // out = delta u - t
+  EXT_PLAIN = 3,   // out = t
+};
+
+// Launch geometry of the node-parallel kernels (set by the autotuner).
+struct LaunchCfg {
+  int block = 256;
+  int xcd_remap = 1;  // map consecutive tiles to the same XCD (shared L2)
+};
+
+template <typename T>
+void launch_nsum(int dim, int64_t n, const T* u, const T* f, const int32_t* nbr, T inv_h2, T* g,
+                 unsigned long long* zero_slot, const LaunchCfg& lc, hipStream_t s);
+
+// out/u types: the output of EXT_RESID may be float while T is double (mixed precision).
+template <typename T, typename TO>
+void launch_ext(int dim, int mode, int64_t n, const T* g, const int32_t* runE, const T* frac,
+                const T* b, T* u, TO* out, T delta, T w_over_delta, unsigned long long* nrm,
+                const LaunchCfg& lc, hipStream_t s);
+
+template <typename T>
+void launch_restrict(int dim, int64_t nc, const T* rf, const int32_t* runR, const T* fracR, T* fc,
+                     T* uc, const LaunchCfg& lc, hipStream_t s);
+
+template <typename T>
+void launch_prolong(int dim, int64_t nf, const T* ec, const int32_t* runP, const T* fracP, T* uf,
+                    const LaunchCfg& lc, hipStream_t s);
+
+// y = Z x with Z (n x n, leading dimension ld, double), x, y of type T.
+template <typename T>
+void launch_coarse_gemv(int n, const double* Z, int64_t ld, const T* x, T* y, hipStream_t s);
+
+template <typename T>
+void launch_fill(int64_t n, T* p, T v, hipStream_t s);
+
+void launch_axpy_f32_to_f64(int64_t n, const float* e, double* u, hipStream_t s);
+void launch_cast_f64_to_f32(int64_t n, const double* a, float* b, hipStream_t s);
+void launch_zero_u64(unsigned long long* p, int count, hipStream_t s);
+
+// relres: hist[*counter] = nrm / bnorm, ++*counter (device-side bookkeeping for graphs)
+void launch_record_relres(const unsigned long long* nrm, const unsigned long long* bnrm, double* hist,
+                          int* counter, hipStream_t s);
+
+// Dense coarse operator: M (n x 2n, row-major, ld = 2n) = [delta I - E N | E]
+void launch_assemble_coarse(int dim, int n, const int32_t* runE, const double* fracE, const int32_t* nbr,
+                            double delta, double inv_h2, double* M, hipStream_t s);
+// One Gauss-Jordan step with partial pivoting on column k of M (n x 2n).
+void launch_gj_step(int n, int k, double* M, double* col, int* info, hipStream_t s);
+
+// learned smoother
+void launch_features(int dim, int64_t n, const double* r, const int32_t* nbr, const double* fracE,
+                     uint16_t* X, float* scale, hipStream_t s);
+template <typename T>
+void launch_learned_update(int dim, int64_t n, const uint16_t* X, const float* scale, const uint16_t* W,
+                           T inv_delta, T* u, hipStream_t s);
+void launch_mlp_forward(int64_t m, const uint16_t* X, const uint16_t* W, float* Y, float* H, hipStream_t s);
+void launch_mlp_backward(int64_t m, const uint16_t* X, const uint16_t* W, const float* H, const float* Y,
+                         const float* T, float* G, hipStream_t s);
+
+}  // namespace cpm

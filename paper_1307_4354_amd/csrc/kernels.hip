@@ -1,0 +1,490 @@
+// gfx950 kernels of the CPM V-cycle: neighbour sum, closest-point extension (cubic
+// tensor-product gather) fused with Jacobi smoothing / residual / operator application and
+// an exact infinity-norm reduction, closest-point restriction and prolongation, and the
+// dense coarsest-level solve.
+//
+// All kernels are node-parallel gathers over sorted band-index lists: one lane per band
+// node, no atomics on values (the only atomic is an integer max on the bit pattern of a
+// non-negative double, which makes the infinity norm exact and order independent).
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace cpm {
+namespace {
+
+constexpr int kMaxBlock = 512;
+
+// Workgroups are dispatched round robin over the 8 XCDs (workgroup b runs on XCD b % 8).
+// Remap so that XCD x processes one contiguous range of tiles: neighbouring band nodes
+// share most of their stencil data, and this keeps that sharing inside one L2.
+__device__ __forceinline__ int64_t tile_of_block(int remap) {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  if (!remap || nb < 16) return b;
+  const int64_t per = nb / 8, rem = nb % 8, x = b % 8, k = b / 8;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+template <typename T>
+__device__ __forceinline__ void cubic_weights(T a, T w[4]) {
+  // Lagrange basis on nodes 0..3 at s = 1 + a, a = frac in [0, 1)
+  const T am1 = a - T(1), am2 = a - T(2), ap1 = a + T(1);
+  w[0] = -(a * am1 * am2) * T(1.0 / 6.0);
+  w[1] = (ap1 * am1 * am2) * T(0.5);
+  w[2] = -(ap1 * a * am2) * T(0.5);
+  w[3] = (ap1 * a * am1) * T(1.0 / 6.0);
+}
+
+__device__ __forceinline__ unsigned long long abs_bits(double v) {
+  return (unsigned long long)__double_as_longlong(fabs(v));
+}
+
+// Block-wide max of 64-bit patterns followed by one atomicMax; every thread must call it.
+__device__ __forceinline__ void block_max_atomic(unsigned long long v, unsigned long long* dst) {
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(v, off);
+    v = v > o ? v : o;
+  }
+  __shared__ unsigned long long part[kMaxBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = 0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) m = part[w] > m ? part[w] : m;
+    if (m) atomicMax(dst, m);
+  }
+}
+
+// g = f + (sum of in-band axis neighbours of u) / h^2      (f may be null: g = N u)
+template <int D, typename T>
+__global__ __launch_bounds__(kMaxBlock) void k_nsum(int64_t n, const T* __restrict__ u,
+                                                    const T* __restrict__ f,
+                                                    const int32_t* __restrict__ nbr, T inv_h2,
+                                                    T* __restrict__ g,
+                                                    unsigned long long* __restrict__ zero_slot,
+                                                    int remap) {
+  if (zero_slot && blockIdx.x == 0 && threadIdx.x == 0) *zero_slot = 0ull;
+  const int64_t i = tile_of_block(remap) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  T s = T(0);
+#pragma unroll
+  for (int k = 0; k < 2 * D; ++k) {
+    const int32_t j = nbr[k * n + i];
+    if (j >= 0) s += u[j];
+  }
+  T gi = s * inv_h2;
+  if (f) gi += f[i];
+  g[i] = gi;
+}
+
+// t = E g at node i (tensor-product cubic interpolation at cp(x_i)), then one of the
+// ExtMode updates.  run: 4^(D-1) x-run starts per node; frac: D fractions per node.
+template <int D, typename T, typename TO, int MODE>
+__global__ __launch_bounds__(kMaxBlock) void k_ext(int64_t n, const T* __restrict__ g,
+                                                   const int32_t* __restrict__ run,
+                                                   const T* __restrict__ frac,
+                                                   const T* __restrict__ b, T* __restrict__ u,
+                                                   TO* __restrict__ out, T delta, T wod,
+                                                   unsigned long long* __restrict__ nrm, int remap) {
+  const int64_t i = tile_of_block(remap) * blockDim.x + threadIdx.x;
+  unsigned long long nv = 0ull;
+  if (i < n) {
+    T wx[4], wy[4], wz[4];
+    cubic_weights<T>(frac[i], wx);
+    cubic_weights<T>(frac[n + i], wy);
+    T t = T(0);
+    if (D == 2) {
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        const T* p = g + run[bb * n + i];
+        const T s = wx[0] * p[0] + wx[1] * p[1] + wx[2] * p[2] + wx[3] * p[3];
+        t += wy[bb] * s;
+      }
+    } else {
+      cubic_weights<T>(frac[2 * n + i], wz);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        T tc = T(0);
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) {
+          const T* p = g + run[(bb + 4 * c) * n + i];
+          const T s = wx[0] * p[0] + wx[1] * p[1] + wx[2] * p[2] + wx[3] * p[3];
+          tc += wy[bb] * s;
+        }
+        t += wz[c] * tc;
+      }
+    }
+    if (MODE == EXT_SMOOTH) {
+      const T ui = u[i];
+      T r = t - delta * ui;
+      if (b) r += b[i];
+      u[i] = ui + wod * r;
+      nv = abs_bits((double)r);
+    } else if (MODE == EXT_RESID) {
+      T r = t - delta * u[i];
+      if (b) r += b[i];
+      if (out) out[i] = (TO)r;
+      nv = abs_bits((double)r);
+    } else if (MODE == EXT_APPLY) {
+      out[i] = (TO)(delta * u[i] - t);
+    } else {
+      if (out) out[i] = (TO)t;
+      nv = abs_bits((double)t);
+    }
+  }
+  if (MODE != EXT_APPLY && nrm) block_max_atomic(nv, nrm);
+}
+
+// f_c[j] = linear interpolation at cp(x_j^c) of fine-band values r_f; u_c[j] = 0
+template <int D, typename T>
+__global__ __launch_bounds__(kMaxBlock) void k_restrict(int64_t nc, const T* __restrict__ rf,
+                                                        const int32_t* __restrict__ runR,
+                                                        const T* __restrict__ fracR,
+                                                        T* __restrict__ fc, T* __restrict__ uc,
+                                                        int remap) {
+  const int64_t j = tile_of_block(remap) * blockDim.x + threadIdx.x;
+  if (j >= nc) return;
+  const T ax = fracR[j], ay = fracR[nc + j];
+  const T wx0 = T(1) - ax, wy0 = T(1) - ay;
+  T v;
+  if (D == 2) {
+    const T* p0 = rf + runR[j];
+    const T* p1 = rf + runR[nc + j];
+    v = wy0 * (wx0 * p0[0] + ax * p0[1]) + ay * (wx0 * p1[0] + ax * p1[1]);
+  } else {
+    const T az = fracR[2 * nc + j];
+    const T wz0 = T(1) - az;
+    const T* p0 = rf + runR[j];
+    const T* p1 = rf + runR[nc + j];
+    const T* p2 = rf + runR[2 * nc + j];
+    const T* p3 = rf + runR[3 * nc + j];
+    const T z0 = wy0 * (wx0 * p0[0] + ax * p0[1]) + ay * (wx0 * p1[0] + ax * p1[1]);
+    const T z1 = wy0 * (wx0 * p2[0] + ax * p2[1]) + ay * (wx0 * p3[0] + ax * p3[1]);
+    v = wz0 * z0 + az * z1;
+  }
+  fc[j] = v;
+  if (uc) uc[j] = T(0);
+}
+
+// u_f[i] += linear interpolation at cp(x_i) of coarse-band values e_c
+template <int D, typename T>
+__global__ __launch_bounds__(kMaxBlock) void k_prolong(int64_t nf, const T* __restrict__ ec,
+                                                       const int32_t* __restrict__ runP,
+                                                       const T* __restrict__ fracP,
+                                                       T* __restrict__ uf, int remap) {
+  const int64_t i = tile_of_block(remap) * blockDim.x + threadIdx.x;
+  if (i >= nf) return;
+  const T ax = fracP[i], ay = fracP[nf + i];
+  const T wx0 = T(1) - ax, wy0 = T(1) - ay;
+  T v;
+  if (D == 2) {
+    const T* p0 = ec + runP[i];
+    const T* p1 = ec + runP[nf + i];
+    v = wy0 * (wx0 * p0[0] + ax * p0[1]) + ay * (wx0 * p1[0] + ax * p1[1]);
+  } else {
+    const T az = fracP[2 * nf + i];
+    const T wz0 = T(1) - az;
+    const T* p0 = ec + runP[i];
+    const T* p1 = ec + runP[nf + i];
+    const T* p2 = ec + runP[2 * nf + i];
+    const T* p3 = ec + runP[3 * nf + i];
+    const T z0 = wy0 * (wx0 * p0[0] + ax * p0[1]) + ay * (wx0 * p1[0] + ax * p1[1]);
+    const T z1 = wy0 * (wx0 * p2[0] + ax * p2[1]) + ay * (wx0 * p3[0] + ax * p3[1]);
+    v = wz0 * z0 + az * z1;
+  }
+  uf[i] += v;
+}
+
+// y = Z x, one wavefront per row, coalesced row reads, wave-level shuffle reduction
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv(int n, const double* __restrict__ Z, int64_t ld,
+                                              const T* __restrict__ x, T* __restrict__ y) {
+  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const double* zr = Z + (int64_t)row * ld;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += zr[j] * (double)x[j];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) y[row] = (T)s;
+}
+
+template <typename T>
+__global__ void k_fill(int64_t n, T* __restrict__ p, T v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+__global__ void k_axpy_f32_f64(int64_t n, const float* __restrict__ e, double* __restrict__ u) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) u[i] += (double)e[i];
+}
+
+__global__ void k_cast_f64_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int count) {
+  const int i = threadIdx.x;
+  if (i < count) p[i] = 0ull;
+}
+
+__global__ void k_record_relres(const unsigned long long* nrm, const unsigned long long* bnrm,
+                                double* hist, int* counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double num = __longlong_as_double((long long)*nrm);
+    const double den = __longlong_as_double((long long)*bnrm);
+    const int k = *counter;
+    hist[k] = num / den;
+    *counter = k + 1;
+  }
+}
+
+// Row i of [delta I - E N | E] (one lane per row, so no two lanes write the same row).
+template <int D>
+__global__ void k_assemble_coarse(int n, const int32_t* __restrict__ runE,
+                                  const double* __restrict__ fracE, const int32_t* __restrict__ nbr,
+                                  double delta, double inv_h2, double* __restrict__ M) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t ld = 2 * (int64_t)n;
+  double* row = M + (int64_t)i * ld;
+  row[i] += delta;
+  double wx[4], wy[4], wz[4] = {1.0, 0.0, 0.0, 0.0};
+  cubic_weights<double>(fracE[i], wx);
+  cubic_weights<double>(fracE[n + i], wy);
+  if (D == 3) cubic_weights<double>(fracE[2 * n + i], wz);
+  const int nruns = D == 2 ? 4 : 16;
+  for (int r = 0; r < nruns; ++r) {
+    const int bb = r & 3, c = r >> 2;
+    const int32_t j0 = runE[(int64_t)r * n + i];
+    for (int a = 0; a < 4; ++a) {
+      const int32_t j = j0 + a;
+      const double w = wx[a] * wy[bb] * wz[c];
+      row[n + j] += w;
+      for (int k = 0; k < 2 * D; ++k) {
+        const int32_t m = nbr[(int64_t)k * n + j];
+        if (m >= 0) row[m] -= w * inv_h2;
+      }
+    }
+  }
+}
+
+// Gauss-Jordan step k, part 1 (one workgroup): partial pivot search on column k (largest
+// magnitude, lowest row on ties), row swap, scaling of the pivot row, multipliers.
+__global__ __launch_bounds__(1024) void k_gj_pivot(int n, int k, double* __restrict__ M,
+                                                   double* __restrict__ col, int* __restrict__ info) {
+  const int64_t ld = 2 * (int64_t)n;
+  __shared__ double sv[1024];
+  __shared__ int si[1024];
+  __shared__ double piv;
+  const int t = threadIdx.x, bd = blockDim.x;
+  double best = -1.0;
+  int bi = n;
+  for (int i = k + t; i < n; i += bd) {
+    const double v = fabs(M[(int64_t)i * ld + k]);
+    if (v > best) {
+      best = v;
+      bi = i;
+    }
+  }
+  sv[t] = best;
+  si[t] = bi;
+  __syncthreads();
+  for (int s = bd >> 1; s > 0; s >>= 1) {
+    if (t < s) {
+      const double ov = sv[t + s];
+      const int oi = si[t + s];
+      if (ov > sv[t] || (ov == sv[t] && oi < si[t])) {
+        sv[t] = ov;
+        si[t] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  const int p = si[0];
+  if (p != k && p < n) {
+    for (int64_t j = t; j < ld; j += bd) {
+      const double a = M[(int64_t)k * ld + j];
+      M[(int64_t)k * ld + j] = M[(int64_t)p * ld + j];
+      M[(int64_t)p * ld + j] = a;
+    }
+  }
+  __syncthreads();
+  if (t == 0) {
+    piv = M[(int64_t)k * ld + k];
+    if (piv == 0.0 && *info == 0) *info = k + 1;
+  }
+  __syncthreads();
+  const double pv = piv;
+  for (int64_t j = k + t; j < ld; j += bd) M[(int64_t)k * ld + j] = M[(int64_t)k * ld + j] / pv;
+  for (int i = t; i < n; i += bd) col[i] = (i == k) ? 0.0 : M[(int64_t)i * ld + k];
+}
+
+// Gauss-Jordan step k, part 2: eliminate column k from every other row.
+__global__ __launch_bounds__(256) void k_gj_elim(int n, int k, double* __restrict__ M,
+                                                 const double* __restrict__ col) {
+  const int64_t ld = 2 * (int64_t)n;
+  const int i = blockIdx.y;
+  if (i == k) return;
+  const double m = col[i];
+  if (m == 0.0) return;
+  double* ri = M + (int64_t)i * ld;
+  const double* rk = M + (int64_t)k * ld;
+  for (int64_t j = k + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < ld;
+       j += (int64_t)gridDim.x * blockDim.x)
+    ri[j] -= m * rk[j];
+}
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------
+
+template <typename T>
+void launch_nsum(int dim, int64_t n, const T* u, const T* f, const int32_t* nbr, T inv_h2, T* g,
+                 unsigned long long* zero_slot, const LaunchCfg& lc, hipStream_t s) {
+  if (n <= 0) {
+    if (zero_slot) k_zero_u64<<<1, 64, 0, s>>>(zero_slot, 1);
+    return;
+  }
+  const unsigned gr = grid_for(n, lc.block);
+  if (dim == 2)
+    k_nsum<2, T><<<gr, lc.block, 0, s>>>(n, u, f, nbr, inv_h2, g, zero_slot, lc.xcd_remap);
+  else
+    k_nsum<3, T><<<gr, lc.block, 0, s>>>(n, u, f, nbr, inv_h2, g, zero_slot, lc.xcd_remap);
+}
+
+template <typename T, typename TO>
+void launch_ext(int dim, int mode, int64_t n, const T* g, const int32_t* runE, const T* frac,
+                const T* b, T* u, TO* out, T delta, T wod, unsigned long long* nrm,
+                const LaunchCfg& lc, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned gr = grid_for(n, lc.block);
+  const int rm = lc.xcd_remap;
+#define CPM_EXT_CASE(DD, MM)                                                                 \
+  k_ext<DD, T, TO, MM><<<gr, lc.block, 0, s>>>(n, g, runE, frac, b, u, out, delta, wod, nrm, rm)
+  if (dim == 2) {
+    switch (mode) {
+      case EXT_SMOOTH: CPM_EXT_CASE(2, EXT_SMOOTH); break;
+      case EXT_RESID: CPM_EXT_CASE(2, EXT_RESID); break;
+      case EXT_APPLY: CPM_EXT_CASE(2, EXT_APPLY); break;
+      default: CPM_EXT_CASE(2, EXT_PLAIN); break;
+    }
+  } else {
+    switch (mode) {
+      case EXT_SMOOTH: CPM_EXT_CASE(3, EXT_SMOOTH); break;
+      case EXT_RESID: CPM_EXT_CASE(3, EXT_RESID); break;
+      case EXT_APPLY: CPM_EXT_CASE(3, EXT_APPLY); break;
+      default: CPM_EXT_CASE(3, EXT_PLAIN); break;
+    }
+  }
+#undef CPM_EXT_CASE
+}
+
+template <typename T>
+void launch_restrict(int dim, int64_t nc, const T* rf, const int32_t* runR, const T* fracR, T* fc,
+                     T* uc, const LaunchCfg& lc, hipStream_t s) {
+  if (nc <= 0) return;
+  const unsigned gr = grid_for(nc, lc.block);
+  if (dim == 2)
+    k_restrict<2, T><<<gr, lc.block, 0, s>>>(nc, rf, runR, fracR, fc, uc, lc.xcd_remap);
+  else
+    k_restrict<3, T><<<gr, lc.block, 0, s>>>(nc, rf, runR, fracR, fc, uc, lc.xcd_remap);
+}
+
+template <typename T>
+void launch_prolong(int dim, int64_t nf, const T* ec, const int32_t* runP, const T* fracP, T* uf,
+                    const LaunchCfg& lc, hipStream_t s) {
+  if (nf <= 0) return;
+  const unsigned gr = grid_for(nf, lc.block);
+  if (dim == 2)
+    k_prolong<2, T><<<gr, lc.block, 0, s>>>(nf, ec, runP, fracP, uf, lc.xcd_remap);
+  else
+    k_prolong<3, T><<<gr, lc.block, 0, s>>>(nf, ec, runP, fracP, uf, lc.xcd_remap);
+}
+
+template <typename T>
+void launch_coarse_gemv(int n, const double* Z, int64_t ld, const T* x, T* y, hipStream_t s) {
+  if (n <= 0) return;
+  k_gemv<T><<<grid_for(n, 4), 256, 0, s>>>(n, Z, ld, x, y);
+}
+
+template <typename T>
+void launch_fill(int64_t n, T* p, T v, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t gr = (n + 255) / 256;
+  if (gr > 65536) gr = 65536;
+  k_fill<T><<<(unsigned)gr, 256, 0, s>>>(n, p, v);
+}
+
+void launch_axpy_f32_to_f64(int64_t n, const float* e, double* u, hipStream_t s) {
+  if (n > 0) k_axpy_f32_f64<<<grid_for(n, 256), 256, 0, s>>>(n, e, u);
+}
+
+void launch_cast_f64_to_f32(int64_t n, const double* a, float* b, hipStream_t s) {
+  if (n > 0) k_cast_f64_f32<<<grid_for(n, 256), 256, 0, s>>>(n, a, b);
+}
+
+void launch_zero_u64(unsigned long long* p, int count, hipStream_t s) {
+  k_zero_u64<<<1, 64, 0, s>>>(p, count);
+}
+
+void launch_record_relres(const unsigned long long* nrm, const unsigned long long* bnrm, double* hist,
+                          int* counter, hipStream_t s) {
+  k_record_relres<<<1, 64, 0, s>>>(nrm, bnrm, hist, counter);
+}
+
+void launch_assemble_coarse(int dim, int n, const int32_t* runE, const double* fracE, const int32_t* nbr,
+                            double delta, double inv_h2, double* M, hipStream_t s) {
+  launch_fill<double>(2 * (int64_t)n * n, M, 0.0, s);
+  if (dim == 2)
+    k_assemble_coarse<2><<<grid_for(n, 128), 128, 0, s>>>(n, runE, fracE, nbr, delta, inv_h2, M);
+  else
+    k_assemble_coarse<3><<<grid_for(n, 128), 128, 0, s>>>(n, runE, fracE, nbr, delta, inv_h2, M);
+}
+
+void launch_gj_step(int n, int k, double* M, double* col, int* info, hipStream_t s) {
+  k_gj_pivot<<<1, 1024, 0, s>>>(n, k, M, col, info);
+  const int64_t cols = 2 * (int64_t)n - k;
+  unsigned gx = grid_for(cols, 256);
+  if (gx > 16) gx = 16;
+  k_gj_elim<<<dim3(gx, (unsigned)n), 256, 0, s>>>(n, k, M, col);
+}
+
+// explicit instantiations
+template void launch_nsum<double>(int, int64_t, const double*, const double*, const int32_t*, double,
+                                  double*, unsigned long long*, const LaunchCfg&, hipStream_t);
+template void launch_nsum<float>(int, int64_t, const float*, const float*, const int32_t*, float, float*,
+                                 unsigned long long*, const LaunchCfg&, hipStream_t);
+template void launch_ext<double, double>(int, int, int64_t, const double*, const int32_t*, const double*,
+                                         const double*, double*, double*, double, double,
+                                         unsigned long long*, const LaunchCfg&, hipStream_t);
+template void launch_ext<double, float>(int, int, int64_t, const double*, const int32_t*, const double*,
+                                        const double*, double*, float*, double, double,
+                                        unsigned long long*, const LaunchCfg&, hipStream_t);
+template void launch_ext<float, float>(int, int, int64_t, const float*, const int32_t*, const float*,
+                                       const float*, float*, float*, float, float, unsigned long long*,
+                                       const LaunchCfg&, hipStream_t);
+template void launch_restrict<double>(int, int64_t, const double*, const int32_t*, const double*, double*,
+                                      double*, const LaunchCfg&, hipStream_t);
+template void launch_restrict<float>(int, int64_t, const float*, const int32_t*, const float*, float*,
+                                     float*, const LaunchCfg&, hipStream_t);
+template void launch_prolong<double>(int, int64_t, const double*, const int32_t*, const double*, double*,
+                                     const LaunchCfg&, hipStream_t);
+template void launch_prolong<float>(int, int64_t, const float*, const int32_t*, const float*, float*,
+                                    const LaunchCfg&, hipStream_t);
+template void launch_coarse_gemv<double>(int, const double*, int64_t, const double*, double*, hipStream_t);
+template void launch_coarse_gemv<float>(int, const double*, int64_t, const float*, float*, hipStream_t);
+template void launch_fill<double>(int64_t, double*, double, hipStream_t);
+template void launch_fill<float>(int64_t, float*, float, hipStream_t);
+template void launch_fill<int>(int64_t, int*, int, hipStream_t);
+
+}  // namespace cpm

@@ -1,0 +1,248 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+* band and stencil index construction: bit-exact (indices, closest points)
+* operator application and extension: within 1e-13 relative (FP64 rounding order only)
+* V-cycle iterates: within 1e-12 relative, cycle for cycle
+* mixed precision: same cycle count as the float32/float64 oracle, final iterate within
+  1e-9 of the double-precision fixed point
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import band as ob
+from oracle import vcycle as ov
+from oracle.mixed import solve_mixed
+from tests.gpu_util import (build_gpu, dev, host, log, oracle_for, rel_inf, torch_cuda, workspace)
+
+pytestmark = pytest.mark.gpu
+
+BAND_CASES = [
+    ("circle64", W.config_circle(64, 4)),
+    ("sphere64", W.config_sphere(64, 5)),
+    ("torus64", W.SolverConfig("torus64", W.torus_modes(1.0, 0.4, 7), 1 / 64, 4, W.LAM2_3D)),
+    ("torus_paper16", W.SolverConfig("tp16", W.torus_paper(), 1 / 16, 3, W.LAM2_3D)),
+    ("sphere_off", W.SolverConfig("so", W.sphere_modes(0.7, 3, center=(0.1, -0.2, 0.05)), 1 / 32, 3, W.LAM2_3D)),
+]
+
+
+@pytest.mark.parametrize("name,cfg", BAND_CASES, ids=[c[0] for c in BAND_CASES])
+def test_band_construction_bitexact(name, cfg):
+    log("band bit-exact: %s" % name)
+    H = oracle_for(cfg)
+    s = cfg.problem.surface
+    band = build_gpu(s, cfg.h0, cfg.levels, cfg.lam2)
+    assert band.levels == cfg.levels and band.dim == s.dim
+    for l, lev in enumerate(H.levels):
+        idx, cp = band.export(l)
+        assert idx.shape == lev.idx.shape
+        assert np.array_equal(idx.astype(np.int64), lev.idx), "band nodes differ on level %d" % l
+        assert np.array_equal(cp, lev.cp), "closest points differ on level %d" % l
+        runE, nbr, runP, runR = band.export_stencils(l)
+        assert np.array_equal(runE, H.E[l].indices.reshape(lev.n, -1)[:, ::4])
+        assert np.array_equal(nbr, ob.neighbour_indices(lev))
+        if l + 1 < cfg.levels:
+            assert np.array_equal(runP, H.P[l].indices.reshape(lev.n, -1)[:, ::2])
+        if l > 0:
+            assert np.array_equal(runR, H.R[l - 1].indices.reshape(lev.n, -1)[:, ::2])
+
+
+@pytest.mark.parametrize("name,cfg", BAND_CASES[:3], ids=[c[0] for c in BAND_CASES[:3]])
+def test_apply_and_extend_parity(name, cfg):
+    log("apply/extend parity: %s" % name)
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    H = oracle_for(cfg)
+    band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+    c = 1.3
+    for l, lev in enumerate(H.levels):
+        u = W.random_vector(lev.n, 100 + l)
+        ud = dev(u)
+        out = torch.empty_like(ud)
+        work = torch.empty_like(ud)
+        cpm.cpm_apply(band, l, c, ud, out, work)
+        delta = c + 2.0 * lev.dim / lev.h ** 2
+        ref = delta * u - H.E[l] @ (H.N[l] @ u)
+        assert rel_inf(host(out), ref) < 1e-13, (l, rel_inf(host(out), ref))
+        cpm.cpm_extend(band, l, ud, out)
+        assert rel_inf(host(out), H.E[l] @ u) < 1e-14
+        # A 1 = c 1 (rows of M sum to zero)
+        one = torch.ones_like(ud)
+        cpm.cpm_apply(band, l, c, one, out, work)
+        assert np.max(np.abs(host(out) - c)) < 1e-9 * delta
+
+
+def _gpu_iterates(cfg, ncycles, params=None):
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    H = oracle_for(cfg)
+    f = cfg.problem.f(H.levels[0].cp)
+    band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+    p = params or cpm.make_params(c=cfg.problem.c, nu1=cfg.nu1, nu2=cfg.nu2, omega=cfg.omega)
+    work, nbytes = workspace(band, p)
+    fd = dev(f)
+    ud = torch.zeros_like(fd)
+    its, rels = [], []
+    for _ in range(ncycles):
+        rels.append(cpm.cpm_vcycle(band, p, fd, ud, work, nbytes, want_relres=True))
+        its.append(host(ud).copy())
+    return H, f, its, rels
+
+
+@pytest.mark.parametrize("name,cfg,ncyc", [
+    ("circle64", W.config_circle(64, 4), 13),
+    ("sphere32", W.config_sphere(32, 4), 23),
+    ("sphere64_first4", W.config_sphere(64, 5), 4),
+    ("torus32", W.SolverConfig("t32", W.torus_modes(1.0, 0.4, 7), 1 / 32, 3, W.LAM2_3D), 20),
+], ids=["circle64", "sphere32", "sphere64_first4", "torus32"])
+def test_vcycle_iterates_match_oracle(name, cfg, ncyc):
+    log("V-cycle iterate parity: %s (%d cycles)" % (name, ncyc))
+    H, f, its, rels = _gpu_iterates(cfg, ncyc)
+    ref = ov.solve(H, f, ov.Params(c=cfg.problem.c), rtol=0.0, max_cycles=ncyc, keep_iterates=True)
+    for k in range(ncyc):
+        err = rel_inf(its[k], ref.iterates[k])
+        assert err < 1e-12, (k, err)
+        assert abs(rels[k] - ref.relres[k]) <= 1e-3 * ref.relres[k] + 1e-14, (k, rels[k], ref.relres[k])
+
+
+@pytest.mark.parametrize("name,cfg", [
+    ("circle64", W.config_circle(64, 4)),
+    ("sphere32", W.config_sphere(32, 4)),
+    ("torus_paper16", W.SolverConfig("tp16", W.torus_paper(), 1 / 16, 3, W.LAM2_3D)),
+], ids=["circle64", "sphere32", "torus_paper16"])
+def test_solve_matches_oracle(name, cfg):
+    log("solve parity: %s" % name)
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    H = oracle_for(cfg)
+    f = cfg.problem.f(H.levels[0].cp)
+    ref = ov.solve(H, f, ov.Params(c=cfg.problem.c), rtol=1e-10, max_cycles=60)
+    band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+    p = cpm.make_params(c=cfg.problem.c)
+    work, nbytes = workspace(band, p)
+    fd = dev(f)
+    ud = torch.zeros_like(fd)
+    st = cpm.cpm_solve(band, p, fd, ud, work, nbytes, rtol=1e-10, max_cycles=60)
+    assert st.cycles == ref.cycles
+    assert st.relres < 1e-10
+    assert rel_inf(host(ud), ref.u) < 1e-12
+    assert np.allclose(st.history(), ref.relres, rtol=1e-3, atol=1e-14)
+
+
+@pytest.mark.parametrize("name,cfg", [
+    ("circle64", W.config_circle(64, 4)),
+    ("torus32", W.config_torus_mixed(32, 3)),
+], ids=["circle64", "torus32"])
+def test_mixed_precision_matches_oracle(name, cfg):
+    log("mixed precision parity: %s" % name)
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    H = oracle_for(cfg)
+    f = cfg.problem.f(H.levels[0].cp)
+    ref64 = ov.solve(H, f, ov.Params(c=cfg.problem.c), rtol=1e-10, max_cycles=60)
+    ref32 = solve_mixed(H, f, ov.Params(c=cfg.problem.c), rtol=1e-10, max_cycles=60)
+    band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+    p = cpm.make_params(c=cfg.problem.c, precision=cpm.CPM_MIXED)
+    work, nbytes = workspace(band, p)
+    fd = dev(f)
+    ud = torch.zeros_like(fd)
+    st = cpm.cpm_solve(band, p, fd, ud, work, nbytes, rtol=1e-10, max_cycles=60)
+    assert st.relres < 1e-10
+    assert abs(st.cycles - ref32.cycles) <= 1
+    # float32 inner arithmetic: per-cycle residuals agree to float32-level relative accuracy
+    hist = st.history()
+    for k in range(min(len(hist), len(ref32.relres)) - 1):
+        assert abs(hist[k] - ref32.relres[k]) <= 1e-2 * ref32.relres[k], (k, hist[k], ref32.relres[k])
+    assert rel_inf(host(ud), ref64.u) < 1e-9
+
+
+def test_graph_replays_match_eager_cycles():
+    """cpm_run_cycles (captured graph, replayed) gives the same iterates as eager cycles."""
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    cfg = W.config_sphere(32, 4)
+    H = oracle_for(cfg)
+    f = cfg.problem.f(H.levels[0].cp)
+    band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+    p = cpm.make_params()
+    work, nbytes = workspace(band, p)
+    fd = dev(f)
+    ua = torch.zeros_like(fd)
+    ref = []
+    for _ in range(6):
+        cpm.cpm_vcycle(band, p, fd, ua, work, nbytes)
+        ref.append(host(ua).copy())
+    ub = torch.zeros_like(fd)
+    hist = torch.zeros(16, dtype=torch.float64, device="cuda")
+    for k in range(6):
+        cpm.cpm_run_cycles(band, p, fd, ub, work, nbytes, 1, 1, hist)
+        torch.cuda.synchronize()
+        assert np.array_equal(host(ub), ref[k]), k
+        _ = torch.ones(1000, device="cuda").sum().item()  # unrelated eager work between replays
+    ub.zero_()
+    cpm.cpm_run_cycles(band, p, fd, ub, work, nbytes, 6, 3, hist)
+    assert np.array_equal(host(ub), ref[-1])
+    ho = host(hist)
+    assert np.all(ho[:6] > 0) and np.all(np.diff(ho[:6]) < 0)
+
+
+def test_error_paths():
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    s = W.unit_sphere()
+    with pytest.raises(cpm.CpmError) as ei:
+        build_gpu(s, 1 / 16, 2, 4.0)  # band radius 2h is too narrow for cubic stencils
+    assert ei.value.status == cpm.CPM_E_BAND
+    with pytest.raises(cpm.CpmError):
+        build_gpu(W.torus(0.4, 1.0), 1 / 16, 2)  # r > R
+    band = build_gpu(W.unit_circle(), 1 / 32, 3)
+    p = cpm.make_params(c=-1.0)
+    n = band.n(0)
+    fd = torch.ones(n, dtype=torch.float64, device="cuda")
+    ud = torch.zeros_like(fd)
+    with pytest.raises(cpm.CpmError):
+        cpm.cpm_solve(band, p, fd, ud, fd, 8, 1e-10, 10)
+    p = cpm.make_params()
+    work, nbytes = workspace(band, p)
+    with pytest.raises(cpm.CpmError) as ei:
+        cpm.cpm_solve(band, p, fd, ud, work, nbytes // 2, 1e-10, 10)
+    assert ei.value.status == cpm.CPM_E_WORKSPACE
+    # zero right-hand side: u = 0 immediately
+    fz = torch.zeros_like(fd)
+    ud.fill_(3.0)
+    st = cpm.cpm_solve(band, p, fz, ud, work, nbytes, 1e-10, 10)
+    assert st.relres == 0.0 and float(ud.abs().max()) == 0.0
+    # not converged within the cycle budget
+    st = cpm.cpm_solve(band, p, fd, ud, work, nbytes, 1e-30, 2, raise_on_noconv=False)
+    assert st.status == cpm.CPM_E_NOCONV and st.cycles == 2
+    # NaN right-hand side is reported as divergence (a NaN at a node outside every
+    # interpolation stencil would never reach E f, so poison all entries)
+    fd.fill_(float("nan"))
+    ud.zero_()
+    with pytest.raises(cpm.CpmError) as ei:
+        cpm.cpm_solve(band, p, fd, ud, work, nbytes, 1e-10, 5)
+    assert ei.value.status in (cpm.CPM_E_DIVERGED,)
+
+
+def test_single_level_is_direct_solve():
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    cfg = W.config_circle(16, 1)
+    H = oracle_for(cfg)
+    f = cfg.problem.f(H.levels[0].cp)
+    ref = ov.solve(H, f, ov.Params(), rtol=1e-12, max_cycles=2)
+    band = build_gpu(cfg.problem.surface, cfg.h0, 1)
+    p = cpm.make_params()
+    work, nbytes = workspace(band, p)
+    fd = dev(f)
+    ud = torch.zeros_like(fd)
+    st = cpm.cpm_solve(band, p, fd, ud, work, nbytes, 1e-12, 2)
+    assert st.cycles == 1
+    assert rel_inf(host(ud), ref.u) < 1e-12
