@@ -30,8 +30,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=4)
+    ap.add_argument("--cpu-cycles", type=int, default=100)
     ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--no-solve", action="store_true", help="skip the time-to-tolerance solves")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -115,7 +118,7 @@ def main():
 
     # time to 1e-10 from u = 0 (graph per cycle, one host check per cycle); first call warms up
     tt = {}
-    for name, p, nb in (("f64", p64, nb64), ("mixed", pmx, nbmx)):
+    for name, p, nb in (() if args.no_solve else (("f64", p64, nb64), ("mixed", pmx, nbmx))):
         ud.zero_()
         cpm.cpm_solve(band, p, fd, ud, work, nb, rtol=1e-10, max_cycles=80)
         ud.zero_()
@@ -136,6 +139,15 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "kernel": "k_ext<3,double,EXT_SMOOTH> level 0", "avg_launch_us": round(avg_us, 3),
                 "alg_bytes_per_launch": int(alg_bytes)}
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)  # reads and writes exactly 1 GiB
+        torch.cuda.synchronize()
+        del a, b
 
     line = {
         "metric": "band DOF*V-cycles/s and time to 1e-10 rel residual: FP64 vs mixed/learned",

@@ -96,6 +96,9 @@ typedef struct {
   int fallback_cycle;                       /* learned smoother: cycle at which it was
                                                replaced by Jacobi, -1 if never           */
   double seconds;                           /* wall time of the solve loop on the host  */
+  int tile_block;                           /* batched: workgroup size chosen by the
+                                               autotuner (0 for single solves)           */
+  int tile_blocks_per_cu;                   /* batched: resident workgroups per CU       */
 } cpm_stats;
 
 typedef struct cpm_band_s* cpm_band;
@@ -226,9 +229,18 @@ cpm_status cpm_mlp_forward(int64_t m, const uint16_t* X, const uint16_t* W, floa
 cpm_status cpm_mlp_backward(int64_t m, const uint16_t* X, const uint16_t* W, const float* H,
                             const float* Y, const float* T, float* G, void* stream);
 
-/* Features of the learned smoother for every node of one level: the A-space residual r of
- * (u, f) is evaluated (double), then X (n x 64 bf16, device) and scale s (n floats, device)
- * are written.  Used to generate training data from plain solves. */
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with step >= 1) on the
+ * float32 master weights w_master using gradient G; m1, m2 are the moment buffers (zero
+ * before step 1); w_bf16 receives the rounded weights.  All device arrays of
+ * 64*64 + 64 + 64 + 1 elements. */
+cpm_status cpm_mlp_adam(int step, float lr, float* w_master, float* m1, float* m2, const float* G,
+                        uint16_t* w_bf16, void* stream);
+
+/* Features of the learned smoother for every node of level 0 or 1: the residual
+ * r = E(f + N u) - delta u of (u, f) is evaluated in double, then X (n x 64 bf16, device,
+ * rows in band order) and the patch scale s (n floats, device) are written.  work is a
+ * device buffer of at least 2 n(level) doubles.  Used to generate training data from
+ * plain solves. */
 cpm_status cpm_smoother_features(cpm_band band, int level, double c, const double* f,
                                  const double* u, uint16_t* X, float* s, void* work,
                                  void* stream);

@@ -36,6 +36,7 @@ class Params:
     nu2: int = 3
     omega: float = 2.0 / 3.0
     residual_mode: str = "consistent"  # or "verbatim"
+    learned: Optional[np.ndarray] = None  # bf16 weights of the learned smoother (levels 0, 1)
 
 
 def delta(H: Hierarchy, l: int, c: float) -> float:
@@ -44,8 +45,14 @@ def delta(H: Hierarchy, l: int, c: float) -> float:
 
 
 def smooth(H: Hierarchy, l: int, u: np.ndarray, f: np.ndarray, p: Params) -> np.ndarray:
-    """Damped Ruuth-Merriman Jacobi step: u <- (1-w) u + w E(f + N u)/delta."""
+    """Damped Ruuth-Merriman Jacobi step: u <- (1-w) u + w E(f + N u)/delta; on the two
+    finest levels the learned local step replaces it when weights are given."""
     dl = delta(H, l, p.c)
+    if p.learned is not None and l < 2:
+        from .mlp import learned_update, patch_has_gap
+
+        if not patch_has_gap(H.levels[l]):
+            return u + learned_update(H.levels[l], residual(H, l, u, f, p), dl, p.learned)
     g = f + H.N[l] @ u
     return (1.0 - p.omega) * u + p.omega * (H.E[l] @ g) / dl
 

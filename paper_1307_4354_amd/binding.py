@@ -44,7 +44,8 @@ class cpm_params(Structure):
 
 class cpm_stats(Structure):
     _fields_ = [("cycles", c_int), ("relres", c_double), ("relres_history", c_double * CPM_MAX_HISTORY),
-                ("fallback_cycle", c_int), ("seconds", c_double)]
+                ("fallback_cycle", c_int), ("seconds", c_double), ("tile_block", c_int),
+                ("tile_blocks_per_cu", c_int)]
 
     def history(self):
         return [self.relres_history[k] for k in range(min(self.cycles, CPM_MAX_HISTORY))]
@@ -92,6 +93,7 @@ def _load():
         "cpm_set_smoother_weights": (c_int, [vp, vp, c_double]),
         "cpm_mlp_forward": (c_int, [c_int64, vp, vp, vp, vp, vp]),
         "cpm_mlp_backward": (c_int, [c_int64, vp, vp, vp, vp, vp, vp, vp]),
+        "cpm_mlp_adam": (c_int, [c_int, ctypes.c_float, vp, vp, vp, vp, vp, vp]),
         "cpm_smoother_features": (c_int, [vp, c_int, c_double, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sigs.items():
@@ -304,3 +306,8 @@ def cpm_time_kernel(band: Band, params: cpm_params, which: int, level: int, reps
     _check(_lib.cpm_time_kernel(band.handle, byref(params), int(which), int(level), int(reps), _ptr(f), _ptr(u),
                                 _ptr(work), work_bytes, byref(us), _stream(stream)))
     return us.value
+
+
+def cpm_mlp_adam(step: int, lr: float, w_master, m1, m2, G, w_bf16, stream=None) -> None:
+    _check(_lib.cpm_mlp_adam(int(step), float(lr), _ptr(w_master), _ptr(m1), _ptr(m2), _ptr(G), _ptr(w_bf16),
+                             _stream(stream)))

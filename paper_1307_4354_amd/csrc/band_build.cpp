@@ -265,6 +265,134 @@ bool stencil_runs(const HostLevel& src, const HostLevel& target, int p, std::vec
   return bad < 0;
 }
 
+// Stencil-ordered extension addressing and the B_interp neighbour lists of one level.
+cpm_status build_stencil_order(HostLevel& Lv, int level, std::string& err) {
+  const int dim = Lv.dim;
+  const int64_t n = Lv.n;
+  const int S = dim == 2 ? 4 : 16;
+  // stencil base of every node (x of the base = x of the first run node)
+  std::vector<int32_t> bx((size_t)n), by((size_t)n), bz((size_t)n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t j = Lv.runE[(size_t)i];  // run (0, 0): node (bx, by, bz)
+    bx[(size_t)i] = Lv.idx[(size_t)(j * dim)];
+    by[(size_t)i] = Lv.idx[(size_t)(j * dim + 1)];
+    if (dim == 3) bz[(size_t)i] = Lv.idx[(size_t)(j * dim + 2)];
+  }
+  std::vector<int32_t> order((size_t)n);
+  for (int64_t i = 0; i < n; ++i) order[(size_t)i] = (int32_t)i;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (bz[(size_t)a] != bz[(size_t)b]) return bz[(size_t)a] < bz[(size_t)b];
+    if (by[(size_t)a] != by[(size_t)b]) return by[(size_t)a] < by[(size_t)b];
+    return bx[(size_t)a] < bx[(size_t)b];
+  });
+  Lv.perm = order;
+  Lv.packed.assign((size_t)n, 0);
+  Lv.fracK.assign((size_t)(dim * n), 0.0);
+  Lv.origin.clear();
+  int64_t g = -1;
+  int32_t gx0 = 0, gy = 0, gz = 0;
+  std::vector<int32_t> org(S);
+  for (int64_t k = 0; k < n; ++k) {
+    const int32_t i = order[(size_t)k];
+    bool fresh = g < 0 || by[(size_t)i] != gy || bz[(size_t)i] != gz ||
+                 bx[(size_t)i] - gx0 >= (1 << kXoffBits);
+    if (!fresh) {
+      for (int s = 0; s < S; ++s)
+        if (Lv.runE[(size_t)(s * n + i)] - (bx[(size_t)i] - gx0) != org[(size_t)s]) {
+          fresh = true;
+          break;
+        }
+    }
+    if (fresh) {
+      ++g;
+      gx0 = bx[(size_t)i];
+      gy = by[(size_t)i];
+      gz = bz[(size_t)i];
+      for (int s = 0; s < S; ++s) {
+        org[(size_t)s] = Lv.runE[(size_t)(s * n + i)];
+        Lv.origin.push_back(org[(size_t)s]);
+      }
+    }
+    if (g >= kMaxGroups) {
+      std::ostringstream os;
+      os << "too many stencil groups on level " << level;
+      err = os.str();
+      return CPM_E_INVALID;
+    }
+    Lv.packed[(size_t)k] = (int32_t)((g << kXoffBits) | (bx[(size_t)i] - gx0));
+    for (int a = 0; a < dim; ++a) Lv.fracK[(size_t)(a * n + k)] = Lv.fracE[(size_t)(a * n + i)];
+  }
+  Lv.ngroups = g + 1;
+  // B_interp (every node of some cubic stencil) with its +-y, +-z neighbours
+  std::vector<uint8_t> used((size_t)n, 0);
+  for (int s = 0; s < S; ++s)
+    for (int64_t i = 0; i < n; ++i) {
+      const int32_t j = Lv.runE[(size_t)(s * n + i)];
+      for (int a = 0; a < 4; ++a) used[(size_t)(j + a)] = 1;
+    }
+  Lv.ilist.clear();
+  for (int64_t j = 0; j < n; ++j)
+    if (used[(size_t)j]) Lv.ilist.push_back((int32_t)j);
+  const int64_t m = (int64_t)Lv.ilist.size();
+  const int nq = 2 * dim - 2;
+  Lv.nbrI.assign((size_t)(nq * m), -1);
+  for (int64_t k = 0; k < m; ++k) {
+    const int32_t j = Lv.ilist[(size_t)k];
+    for (int q = 0; q < nq; ++q) Lv.nbrI[(size_t)(q * m + k)] = Lv.nbr[(size_t)((q + 2) * n + j)];
+    // the +-x neighbours are the adjacent band entries
+    if (Lv.nbr[(size_t)j] != j - 1 || Lv.nbr[(size_t)(n + j)] != j + 1) {
+      err = "internal: x neighbours of a stencil node are not adjacent";
+      return CPM_E_BAND;
+    }
+  }
+  return CPM_OK;
+}
+
+// 3^dim patch addressing (stencil order) for the learned smoother.
+cpm_status build_patches(HostLevel& Lv, int level, std::string& err) {
+  const int dim = Lv.dim;
+  const int64_t n = Lv.n;
+  const int rows = dim == 2 ? 3 : 9;
+  Lv.patchRow.assign((size_t)(rows * n), 0);
+  Lv.patchMask.assign((size_t)n, 0u);
+  bool gap = false;
+#pragma omp parallel for reduction(|| : gap)
+  for (int64_t k = 0; k < n; ++k) {
+    const int32_t i = Lv.perm[(size_t)k];
+    const int32_t* m = &Lv.idx[(size_t)(i * dim)];
+    uint32_t mask = 0;
+    for (int r = 0; r < rows; ++r) {
+      const int dy = r % 3 - 1, dz = dim == 3 ? r / 3 - 1 : 0;
+      int32_t ref = 0;
+      bool have = false;
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int32_t j = lookup(Lv, (int64_t)m[0] + dx, (int64_t)m[1] + dy, dim == 3 ? (int64_t)m[2] + dz : 0);
+        if (j < 0) continue;
+        const int32_t cand = j - (dx + 1);
+        if (!have) {
+          ref = cand;
+          have = true;
+        } else if (cand != ref) {
+          gap = true;  // present nodes of the row are not consecutive band entries
+        }
+        mask |= 1u << ((dx + 1) + 3 * r);
+      }
+      Lv.patchRow[(size_t)(r * n + k)] = ref;
+    }
+    Lv.patchMask[(size_t)k] = mask;
+  }
+  // A row whose present nodes are not consecutive band entries cannot be addressed by one
+  // reference index; the learned smoother is then not used on this level (Jacobi instead).
+  (void)level;
+  (void)err;
+  Lv.patchOK = !gap;
+  if (gap) {
+    std::vector<int32_t>().swap(Lv.patchRow);
+    std::vector<uint32_t>().swap(Lv.patchMask);
+  }
+  return CPM_OK;
+}
+
 }  // namespace
 
 cpm_status build_host_levels(const cpm_surface& s, const cpm_grid& g, int dim,
@@ -320,6 +448,11 @@ cpm_status build_host_levels(const cpm_surface& s, const cpm_grid& g, int dim,
           return CPM_E_BAND;
         }
     }
+  }
+  for (int l = 0; l < L; ++l) {
+    cpm_status st = build_stencil_order(levels[(size_t)l], l, err);
+    if (st != CPM_OK) return st;
+    if (l < 2 && (st = build_patches(levels[(size_t)l], l, err)) != CPM_OK) return st;
   }
   for (int l = 0; l + 1 < L; ++l) {
     HostLevel& F = levels[(size_t)l];

@@ -67,12 +67,15 @@ static cpm_status upload_f32(float** dst, const std::vector<double>& src) {
 
 static void free_dev(cpm_band b) {
   for (auto& D : b->dev) {
-    void* ps[] = {D.runE, D.nbr, D.fracE, D.fracE32, D.runP, D.fracP, D.fracP32, D.runR, D.fracR, D.fracR32};
+    void* ps[] = {D.runE,  D.nbr,   D.fracE,  D.fracE32, D.runP,    D.fracP,  D.fracP32, D.runR,
+                  D.fracR, D.fracR32, D.perm, D.packed, D.origin, D.fracK, D.fracK32, D.ilist, D.nbrI,
+                  D.patchRow, D.patchMask};
     for (void* p : ps)
       if (p) (void)hipFree(p);
   }
   b->dev.clear();
   void* ps[] = {b->coarseM, b->gj_col, b->gj_info, b->dscal, b->dcounter, b->dhist, b->mlpW};
+  b->mlpW = nullptr;
   for (void* p : ps)
     if (p) (void)hipFree(p);
   b->coarseM = nullptr;
@@ -214,6 +217,13 @@ template <>
 const double* fracE_of<double>(const DevLevel& D) { return D.fracE; }
 template <>
 const float* fracE_of<float>(const DevLevel& D) { return D.fracE32; }
+static ExtAddr ext_addr(const DevLevel& D) { return ExtAddr{D.perm, D.packed, D.origin}; }
+template <typename T>
+static const T* fracK_of(const DevLevel& D);
+template <>
+const double* fracK_of<double>(const DevLevel& D) { return D.fracK; }
+template <>
+const float* fracK_of<float>(const DevLevel& D) { return D.fracK32; }
 template <typename T>
 static const T* fracP_of(const DevLevel& D);
 template <>
@@ -229,17 +239,17 @@ const float* fracR_of<float>(const DevLevel& D) { return D.fracR32; }
 
 // Damped Ruuth-Merriman Jacobi sweep: g = f + N u, u <- u + (w/delta)(b + E g - delta u)
 template <typename T>
-void smooth_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g, double c, double omega,
+void smooth_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g, T* r, double c, double omega,
                   unsigned long long* nrm, hipStream_t s) {
   const DevLevel& D = b->dev[(size_t)l];
   const LaunchCfg lc = band_cfg(b, D.n);
   const double delta = level_delta(b, l, c);
-  launch_nsum<T>(b->dim, D.n, u, f, D.nbr, (T)(1.0 / (D.h * D.h)), g, nullptr, lc, s);
-  if (b->learned_active && l < 2 && b->mlpW) {
-    learned_sweep<T>(b, l, u, f, rhsA, g, c, s);
+  launch_nsum<T>(b->dim, D.m, D.ilist, D.nbrI, u, f, (T)(1.0 / (D.h * D.h)), g, nullptr, lc, s);
+  if (b->learned_active && l < 2 && b->mlpW && D.patchRow) {
+    learned_sweep<T>(b, l, u, f, rhsA, g, r, c, s);
     return;
   }
-  launch_ext<T, T>(b->dim, EXT_SMOOTH, D.n, g, D.runE, fracE_of<T>(D), rhsA, u, (T*)nullptr, (T)delta,
+  launch_ext<T, T>(b->dim, EXT_SMOOTH, D.n, g, ext_addr(D), fracK_of<T>(D), rhsA, u, (T*)nullptr, (T)delta,
                    (T)(omega / delta), nrm, lc, s);
 }
 
@@ -254,23 +264,23 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
   }
   const T* f = rhsA ? nullptr : B[l].f;
   const double delta = level_delta(b, l, p.c);
-  for (int k = 0; k < p.nu1; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, p.c, p.omega, nullptr, s);
+  for (int k = 0; k < p.nu1; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s);
   // residual r = b + E(f + N u) - delta u, restricted to the next level (where u := 0)
-  launch_nsum<T>(b->dim, D.n, B[l].u, f, D.nbr, (T)(1.0 / (D.h * D.h)), B[l].g, nullptr, lc, s);
-  launch_ext<T, T>(b->dim, EXT_RESID, D.n, B[l].g, D.runE, fracE_of<T>(D), rhsA, B[l].u, B[l].r, (T)delta,
+  launch_nsum<T>(b->dim, D.m, D.ilist, D.nbrI, B[l].u, f, (T)(1.0 / (D.h * D.h)), B[l].g, nullptr, lc, s);
+  launch_ext<T, T>(b->dim, EXT_RESID, D.n, B[l].g, ext_addr(D), fracK_of<T>(D), rhsA, B[l].u, B[l].r, (T)delta,
                    (T)0, nullptr, lc, s);
   const DevLevel& C = b->dev[(size_t)(l + 1)];
   launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, band_cfg(b, C.n), s);
   vcycle_level<T>(b, l + 1, B, nullptr, p, s);
   launch_prolong<T>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<T>(D), B[l].u, lc, s);
-  for (int k = 0; k < p.nu2; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, p.c, p.omega, nullptr, s);
+  for (int k = 0; k < p.nu2; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s);
 }
 
 // ||E f||_inf into scalar slot 1 (double)
 void enqueue_rhs_norm(const cpm_band b, const double* f, double* g, hipStream_t s) {
   const DevLevel& D = b->dev[0];
   launch_zero_u64(b->dscal + 1, 1, s);
-  launch_ext<double, double>(b->dim, EXT_PLAIN, D.n, f, D.runE, D.fracE, nullptr, nullptr, (double*)nullptr,
+  launch_ext<double, double>(b->dim, EXT_PLAIN, D.n, f, ext_addr(D), D.fracK, nullptr, nullptr, (double*)nullptr,
                              0.0, 0.0, b->dscal + 1, band_cfg(b, D.n), s);
 }
 
@@ -279,8 +289,8 @@ void enqueue_resid64(const cpm_band b, const double* f, const double* u, double*
                      hipStream_t s) {
   const DevLevel& D = b->dev[0];
   const LaunchCfg lc = band_cfg(b, D.n);
-  launch_nsum<double>(b->dim, D.n, u, f, D.nbr, 1.0 / (D.h * D.h), g, b->dscal, lc, s);
-  launch_ext<double, float>(b->dim, EXT_RESID, D.n, g, D.runE, D.fracE, nullptr, const_cast<double*>(u), r32,
+  launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, u, f, 1.0 / (D.h * D.h), g, b->dscal, lc, s);
+  launch_ext<double, float>(b->dim, EXT_RESID, D.n, g, ext_addr(D), D.fracK, nullptr, const_cast<double*>(u), r32,
                             level_delta(b, 0, c), 0.0, b->dscal, lc, s);
 }
 
@@ -480,10 +490,25 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     DevLevel& D = b->dev[(size_t)l];
     D.n = H.n;
     D.h = H.h;
-    if (st == CPM_OK) st = upload(&D.runE, H.runE);
-    if (st == CPM_OK) st = upload(&D.nbr, H.nbr);
-    if (st == CPM_OK) st = upload(&D.fracE, H.fracE);
-    if (st == CPM_OK) st = upload_f32(&D.fracE32, H.fracE);
+    D.m = (int64_t)H.ilist.size();
+    D.ngroups = H.ngroups;
+    if (st == CPM_OK) st = upload(&D.perm, H.perm);
+    if (st == CPM_OK) st = upload(&D.packed, H.packed);
+    if (st == CPM_OK) st = upload(&D.origin, H.origin);
+    if (st == CPM_OK) st = upload(&D.fracK, H.fracK);
+    if (st == CPM_OK) st = upload_f32(&D.fracK32, H.fracK);
+    if (st == CPM_OK) st = upload(&D.ilist, H.ilist);
+    if (st == CPM_OK) st = upload(&D.nbrI, H.nbrI);
+    if (st == CPM_OK) st = upload(&D.patchRow, H.patchRow);
+    if (st == CPM_OK) st = upload(&D.patchMask, H.patchMask);
+    std::vector<int32_t>().swap(H.patchRow);
+    std::vector<uint32_t>().swap(H.patchMask);
+    if (l == b->L - 1) {
+      // band-order addressing of the coarsest level, used to assemble its dense matrix
+      if (st == CPM_OK) st = upload(&D.runE, H.runE);
+      if (st == CPM_OK) st = upload(&D.nbr, H.nbr);
+      if (st == CPM_OK) st = upload(&D.fracE, H.fracE);
+    }
     if (st == CPM_OK) st = upload(&D.runP, H.runP);
     if (st == CPM_OK) st = upload(&D.fracP, H.fracP);
     if (st == CPM_OK && !H.fracP.empty()) st = upload_f32(&D.fracP32, H.fracP);
@@ -498,6 +523,12 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     std::vector<int32_t>().swap(H.runP);
     std::vector<int32_t>().swap(H.runR);
     std::vector<int32_t>().swap(H.nbr);
+    std::vector<int32_t>().swap(H.perm);
+    std::vector<int32_t>().swap(H.packed);
+    std::vector<int32_t>().swap(H.origin);
+    std::vector<double>().swap(H.fracK);
+    std::vector<int32_t>().swap(H.ilist);
+    std::vector<int32_t>().swap(H.nbrI);
   }
   if (st == CPM_OK) {
     b->dscal = dalloc<unsigned long long>(8, &st);
@@ -579,9 +610,42 @@ cpm_status cpm_band_export_stencils(cpm_band band, int level, int32_t* runE, int
   }
   const DevLevel& D = band->dev[(size_t)level];
   const int d = band->dim;
+  const int S = d == 2 ? 4 : 16;
+  const int64_t n = D.n;
   cpm_status st = CPM_OK;
-  if (runE && (st = copy_rows(runE, D.runE, D.n, d == 2 ? 4 : 16)) != CPM_OK) return st;
-  if (nbr && (st = copy_rows(nbr, D.nbr, D.n, 2 * d)) != CPM_OK) return st;
+  auto fetch = [&](std::vector<int32_t>& v, const int32_t* src, size_t count) -> cpm_status {
+    v.resize(count);
+    if (count && hipMemcpy(v.data(), src, count * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) {
+      set_error("device to host copy failed");
+      return CPM_E_HIP;
+    }
+    return CPM_OK;
+  };
+  if (runE) {
+    // reconstruct per-node x-run starts from the stencil-ordered groups
+    std::vector<int32_t> perm, packed, origin;
+    if ((st = fetch(perm, D.perm, (size_t)n)) != CPM_OK) return st;
+    if ((st = fetch(packed, D.packed, (size_t)n)) != CPM_OK) return st;
+    if ((st = fetch(origin, D.origin, (size_t)(D.ngroups * S))) != CPM_OK) return st;
+    for (int64_t k = 0; k < n; ++k) {
+      const int32_t i = perm[(size_t)k];
+      const int32_t gid = packed[(size_t)k] >> kXoffBits, xo = packed[(size_t)k] & ((1 << kXoffBits) - 1);
+      for (int s2 = 0; s2 < S; ++s2) runE[(int64_t)i * S + s2] = origin[(size_t)gid * S + s2] + xo;
+    }
+  }
+  if (nbr) {
+    // neighbours are stored for B_interp nodes only; other rows read -2
+    std::vector<int32_t> il, nb;
+    if ((st = fetch(il, D.ilist, (size_t)D.m)) != CPM_OK) return st;
+    if ((st = fetch(nb, D.nbrI, (size_t)(D.m * (2 * d - 2)))) != CPM_OK) return st;
+    for (int64_t i = 0; i < n * 2 * d; ++i) nbr[i] = -2;
+    for (int64_t k = 0; k < D.m; ++k) {
+      const int32_t j = il[(size_t)k];
+      nbr[(int64_t)j * 2 * d + 0] = j - 1;
+      nbr[(int64_t)j * 2 * d + 1] = j + 1;
+      for (int q = 0; q < 2 * d - 2; ++q) nbr[(int64_t)j * 2 * d + 2 + q] = nb[(size_t)(q * D.m + k)];
+    }
+  }
   if (runP && D.runP && (st = copy_rows(runP, D.runP, D.n, d == 2 ? 2 : 4)) != CPM_OK) return st;
   if (runR && D.runR && (st = copy_rows(runR, D.runR, D.n, d == 2 ? 2 : 4)) != CPM_OK) return st;
   return CPM_OK;
@@ -605,8 +669,8 @@ cpm_status cpm_apply(cpm_band band, int level, double c, const double* u, double
   cpm_status st = enter(band, stream);
   if (st != CPM_OK) return st;
   const LaunchCfg lc = band_cfg(band, D.n);
-  launch_nsum<double>(band->dim, D.n, u, nullptr, D.nbr, 1.0 / (D.h * D.h), work, nullptr, lc, band->stream);
-  launch_ext<double, double>(band->dim, EXT_APPLY, D.n, work, D.runE, D.fracE, nullptr, const_cast<double*>(u),
+  launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, u, nullptr, 1.0 / (D.h * D.h), work, nullptr, lc, band->stream);
+  launch_ext<double, double>(band->dim, EXT_APPLY, D.n, work, ext_addr(D), D.fracK, nullptr, const_cast<double*>(u),
                              Au, level_delta(band, level, c), 0.0, nullptr, lc, band->stream);
   if ((st = check_launch("cpm_apply")) != CPM_OK) return st;
   return leave(band, stream);
@@ -620,7 +684,7 @@ cpm_status cpm_extend(cpm_band band, int level, const double* g, double* out, vo
   const DevLevel& D = band->dev[(size_t)level];
   cpm_status st = enter(band, stream);
   if (st != CPM_OK) return st;
-  launch_ext<double, double>(band->dim, EXT_PLAIN, D.n, g, D.runE, D.fracE, nullptr, nullptr, out, 0.0, 0.0,
+  launch_ext<double, double>(band->dim, EXT_PLAIN, D.n, g, ext_addr(D), D.fracK, nullptr, nullptr, out, 0.0, 0.0,
                              nullptr, band_cfg(band, D.n), band->stream);
   if ((st = check_launch("cpm_extend")) != CPM_OK) return st;
   return leave(band, stream);
@@ -800,16 +864,16 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
       launch_fill<T>(D.n, B[level].u, (T)0.25, s);
       launch_fill<T>(D.n, B[level].f, (T)1.0, s);
     }
-    launch_nsum<T>(band->dim, D.n, uu, ff, D.nbr, (T)(1.0 / (D.h * D.h)), B[level].g, nullptr, lc, s);
+    launch_nsum<T>(band->dim, D.m, D.ilist, D.nbrI, uu, ff, (T)(1.0 / (D.h * D.h)), B[level].g, nullptr, lc, s);
     for (int pass = 0; pass < 2; ++pass) {  // pass 0 warms up
       const int k = pass == 0 ? 1 : reps;
       if (pass == 1) (void)hipEventRecord(e0, s);
       for (int r = 0; r < k; ++r) {
         if (which == 0) {
-          launch_ext<T, T>(band->dim, EXT_SMOOTH, D.n, B[level].g, D.runE, fracE_of<T>(D), nullptr, uu, (T*)nullptr,
+          launch_ext<T, T>(band->dim, EXT_SMOOTH, D.n, B[level].g, ext_addr(D), fracK_of<T>(D), nullptr, uu, (T*)nullptr,
                            (T)delta, (T)(params->omega / delta), nullptr, lc, s);
         } else if (which == 1) {
-          launch_nsum<T>(band->dim, D.n, uu, ff, D.nbr, (T)(1.0 / (D.h * D.h)), B[level].g, nullptr, lc, s);
+          launch_nsum<T>(band->dim, D.m, D.ilist, D.nbrI, uu, ff, (T)(1.0 / (D.h * D.h)), B[level].g, nullptr, lc, s);
         } else if (which == 2) {
           const DevLevel& F = band->dev[(size_t)(level - 1)];
           (void)F;

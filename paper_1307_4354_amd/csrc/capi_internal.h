@@ -80,6 +80,6 @@ cpm_status validate_params(const cpm_band b, const cpm_params* p);
 // learned smoother sweep on level l (< 2): given g = f + N u already computed into g,
 // evaluate the residual, the features, the network and update u.
 template <typename T>
-void learned_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g, double c, hipStream_t s);
+void learned_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g, T* r, double c, hipStream_t s);
 
 }  // namespace cpm

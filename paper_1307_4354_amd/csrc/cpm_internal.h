@@ -25,16 +25,46 @@ struct HostLevel {
   std::vector<double> fracE;   // dim * n: frac(cp / h) for the cubic stencil
   std::vector<int32_t> runE;   // 4^(dim-1) * n: first node of each x-run of the cubic stencil
   std::vector<int32_t> nbr;    // 2*dim * n: -x,+x,-y,+y,-z,+z neighbours, -1 if absent
+  // extension in stencil order: nodes sorted by the base of their cubic stencil (z, y, x);
+  // consecutive nodes with the same (y, z) base and the same row segments form a group
+  // whose 4^(dim-1) x-run starts are stored once: run(s) = origin[gid][s] + xoff.
+  std::vector<int32_t> perm;    // n: processing slot k -> band index
+  std::vector<int32_t> packed;  // n: (gid << kXoffBits) | xoff
+  std::vector<int32_t> origin;  // ngroups * 4^(dim-1)
+  std::vector<double> fracK;    // dim * n: fractions in processing order
+  int64_t ngroups = 0;
+  // Laplacian neighbours of interpolation-stencil nodes only (B_interp, ascending): the
+  // +-x neighbours are j -+ 1, the others stored as -y,+y(,-z,+z) slot-major
+  std::vector<int32_t> ilist;   // m
+  std::vector<int32_t> nbrI;    // (2*dim-2) * m
+  // learned smoother (two finest levels): 3^dim grid patch of every node, in stencil
+  // order; row (dy, dz) holds the band index of (x - 1, y + dy, z + dz) (virtual when that
+  // node is absent), mask bit (dx+1) + 3 (dy+1) + 9 (dz+1) marks nodes that are present
+  std::vector<int32_t> patchRow;  // 3^(dim-1) * n
+  std::vector<uint32_t> patchMask;  // n
+  bool patchOK = false;
   std::vector<double> fracP;   // dim * n: frac(cp / (2h)) (prolongation from level+1)
   std::vector<int32_t> runP;   // 2^(dim-1) * n: x-runs in level+1's band
   std::vector<double> fracR;   // dim * n: frac(cp / (h/2)) (restriction from level-1)
   std::vector<int32_t> runR;   // 2^(dim-1) * n: x-runs in level-1's band
 };
 
+constexpr int kXoffBits = 10;
+constexpr int kMaxGroups = 1 << (31 - kXoffBits);
+
 // Device copies of one level's addressing.
 struct DevLevel {
   int64_t n = 0;
+  int64_t m = 0;        // |B_interp|
+  int64_t ngroups = 0;
   double h = 0.0;
+  int32_t* perm = nullptr;
+  int32_t* packed = nullptr;
+  int32_t* origin = nullptr;
+  double* fracK = nullptr;
+  float* fracK32 = nullptr;
+  int32_t* ilist = nullptr;
+  int32_t* nbrI = nullptr;
   int32_t* runE = nullptr;
   int32_t* nbr = nullptr;
   double* fracE = nullptr;
@@ -45,6 +75,8 @@ struct DevLevel {
   int32_t* runR = nullptr;
   double* fracR = nullptr;
   float* fracR32 = nullptr;
+  int32_t* patchRow = nullptr;
+  uint32_t* patchMask = nullptr;
 };
 
 // Build every level of the band hierarchy on the host.  Returns CPM_OK or an error with

@@ -22,15 +22,23 @@ struct LaunchCfg {
   int xcd_remap = 1;  // map consecutive tiles to the same XCD (shared L2)
 };
 
+// Stencil-ordered extension addressing of one level (see HostLevel).
+struct ExtAddr {
+  const int32_t* perm;
+  const int32_t* packed;
+  const int32_t* origin;
+};
+
+// g = f + N u on the m nodes of B_interp (ilist), f may be null.
 template <typename T>
-void launch_nsum(int dim, int64_t n, const T* u, const T* f, const int32_t* nbr, T inv_h2, T* g,
-                 unsigned long long* zero_slot, const LaunchCfg& lc, hipStream_t s);
+void launch_nsum(int dim, int64_t m, const int32_t* ilist, const int32_t* nbrI, const T* u, const T* f, T inv_h2,
+                 T* g, unsigned long long* zero_slot, const LaunchCfg& lc, hipStream_t s);
 
 // out/u types: the output of EXT_RESID may be float while T is double (mixed precision).
+// frac: fractions in stencil order.
 template <typename T, typename TO>
-void launch_ext(int dim, int mode, int64_t n, const T* g, const int32_t* runE, const T* frac,
-                const T* b, T* u, TO* out, T delta, T w_over_delta, unsigned long long* nrm,
-                const LaunchCfg& lc, hipStream_t s);
+void launch_ext(int dim, int mode, int64_t n, const T* g, const ExtAddr& a, const T* frac, const T* b, T* u,
+                TO* out, T delta, T w_over_delta, unsigned long long* nrm, const LaunchCfg& lc, hipStream_t s);
 
 template <typename T>
 void launch_restrict(int dim, int64_t nc, const T* rf, const int32_t* runR, const T* fracR, T* fc,

@@ -8,132 +8,35 @@
 // non-negative double, which makes the infinity norm exact and order independent).
 #include <hip/hip_runtime.h>
 
-#include "kernels.h"
+#include "kernels_dev.h"
 
 namespace cpm {
 namespace {
 
-constexpr int kMaxBlock = 512;
-
-// Workgroups are dispatched round robin over the 8 XCDs (workgroup b runs on XCD b % 8).
-// Remap so that XCD x processes one contiguous range of tiles: neighbouring band nodes
-// share most of their stencil data, and this keeps that sharing inside one L2.
-__device__ __forceinline__ int64_t tile_of_block(int remap) {
-  const int64_t nb = gridDim.x, b = blockIdx.x;
-  if (!remap || nb < 16) return b;
-  const int64_t per = nb / 8, rem = nb % 8, x = b % 8, k = b / 8;
-  return x * per + (x < rem ? x : rem) + k;
-}
-
-template <typename T>
-__device__ __forceinline__ void cubic_weights(T a, T w[4]) {
-  // Lagrange basis on nodes 0..3 at s = 1 + a, a = frac in [0, 1)
-  const T am1 = a - T(1), am2 = a - T(2), ap1 = a + T(1);
-  w[0] = -(a * am1 * am2) * T(1.0 / 6.0);
-  w[1] = (ap1 * am1 * am2) * T(0.5);
-  w[2] = -(ap1 * a * am2) * T(0.5);
-  w[3] = (ap1 * a * am1) * T(1.0 / 6.0);
-}
-
-__device__ __forceinline__ unsigned long long abs_bits(double v) {
-  return (unsigned long long)__double_as_longlong(fabs(v));
-}
-
-// Block-wide max of 64-bit patterns followed by one atomicMax; every thread must call it.
-__device__ __forceinline__ void block_max_atomic(unsigned long long v, unsigned long long* dst) {
-  for (int off = 32; off > 0; off >>= 1) {
-    unsigned long long o = __shfl_xor(v, off);
-    v = v > o ? v : o;
-  }
-  __shared__ unsigned long long part[kMaxBlock / 64];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) part[wid] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long m = 0;
-    const int nw = (blockDim.x + 63) >> 6;
-    for (int w = 0; w < nw; ++w) m = part[w] > m ? part[w] : m;
-    if (m) atomicMax(dst, m);
-  }
-}
-
-// g = f + (sum of in-band axis neighbours of u) / h^2      (f may be null: g = N u)
 template <int D, typename T>
-__global__ __launch_bounds__(kMaxBlock) void k_nsum(int64_t n, const T* __restrict__ u,
-                                                    const T* __restrict__ f,
-                                                    const int32_t* __restrict__ nbr, T inv_h2,
-                                                    T* __restrict__ g,
+__global__ __launch_bounds__(kMaxBlock) void k_nsum(int64_t m, const int32_t* __restrict__ ilist,
+                                                    const int32_t* __restrict__ nbrI,
+                                                    const T* __restrict__ u, const T* __restrict__ f,
+                                                    T inv_h2, T* __restrict__ g,
                                                     unsigned long long* __restrict__ zero_slot,
                                                     int remap) {
   if (zero_slot && blockIdx.x == 0 && threadIdx.x == 0) *zero_slot = 0ull;
-  const int64_t i = tile_of_block(remap) * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  T s = T(0);
-#pragma unroll
-  for (int k = 0; k < 2 * D; ++k) {
-    const int32_t j = nbr[k * n + i];
-    if (j >= 0) s += u[j];
-  }
-  T gi = s * inv_h2;
-  if (f) gi += f[i];
-  g[i] = gi;
+  const int64_t k = tile_of_block(remap) * blockDim.x + threadIdx.x;
+  if (k < m) nsum_node<D, T>(k, m, ilist, nbrI, u, f, inv_h2, g);
 }
 
-// t = E g at node i (tensor-product cubic interpolation at cp(x_i)), then one of the
-// ExtMode updates.  run: 4^(D-1) x-run starts per node; frac: D fractions per node.
 template <int D, typename T, typename TO, int MODE>
 __global__ __launch_bounds__(kMaxBlock) void k_ext(int64_t n, const T* __restrict__ g,
-                                                   const int32_t* __restrict__ run,
+                                                   const int32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ packed,
+                                                   const int32_t* __restrict__ origin,
                                                    const T* __restrict__ frac,
                                                    const T* __restrict__ b, T* __restrict__ u,
                                                    TO* __restrict__ out, T delta, T wod,
                                                    unsigned long long* __restrict__ nrm, int remap) {
-  const int64_t i = tile_of_block(remap) * blockDim.x + threadIdx.x;
+  const int64_t k = tile_of_block(remap) * blockDim.x + threadIdx.x;
   unsigned long long nv = 0ull;
-  if (i < n) {
-    T wx[4], wy[4], wz[4];
-    cubic_weights<T>(frac[i], wx);
-    cubic_weights<T>(frac[n + i], wy);
-    T t = T(0);
-    if (D == 2) {
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        const T* p = g + run[bb * n + i];
-        const T s = wx[0] * p[0] + wx[1] * p[1] + wx[2] * p[2] + wx[3] * p[3];
-        t += wy[bb] * s;
-      }
-    } else {
-      cubic_weights<T>(frac[2 * n + i], wz);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        T tc = T(0);
-#pragma unroll
-        for (int bb = 0; bb < 4; ++bb) {
-          const T* p = g + run[(bb + 4 * c) * n + i];
-          const T s = wx[0] * p[0] + wx[1] * p[1] + wx[2] * p[2] + wx[3] * p[3];
-          tc += wy[bb] * s;
-        }
-        t += wz[c] * tc;
-      }
-    }
-    if (MODE == EXT_SMOOTH) {
-      const T ui = u[i];
-      T r = t - delta * ui;
-      if (b) r += b[i];
-      u[i] = ui + wod * r;
-      nv = abs_bits((double)r);
-    } else if (MODE == EXT_RESID) {
-      T r = t - delta * u[i];
-      if (b) r += b[i];
-      if (out) out[i] = (TO)r;
-      nv = abs_bits((double)r);
-    } else if (MODE == EXT_APPLY) {
-      out[i] = (TO)(delta * u[i] - t);
-    } else {
-      if (out) out[i] = (TO)t;
-      nv = abs_bits((double)t);
-    }
-  }
+  if (k < n) nv = ext_node<D, T, TO, MODE>(k, n, g, perm, packed, origin, frac, b, u, out, delta, wod);
   if (MODE != EXT_APPLY && nrm) block_max_atomic(nv, nrm);
 }
 
@@ -146,25 +49,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_restrict(int64_t nc, const T* __r
                                                         int remap) {
   const int64_t j = tile_of_block(remap) * blockDim.x + threadIdx.x;
   if (j >= nc) return;
-  const T ax = fracR[j], ay = fracR[nc + j];
-  const T wx0 = T(1) - ax, wy0 = T(1) - ay;
-  T v;
-  if (D == 2) {
-    const T* p0 = rf + runR[j];
-    const T* p1 = rf + runR[nc + j];
-    v = wy0 * (wx0 * p0[0] + ax * p0[1]) + ay * (wx0 * p1[0] + ax * p1[1]);
-  } else {
-    const T az = fracR[2 * nc + j];
-    const T wz0 = T(1) - az;
-    const T* p0 = rf + runR[j];
-    const T* p1 = rf + runR[nc + j];
-    const T* p2 = rf + runR[2 * nc + j];
-    const T* p3 = rf + runR[3 * nc + j];
-    const T z0 = wy0 * (wx0 * p0[0] + ax * p0[1]) + ay * (wx0 * p1[0] + ax * p1[1]);
-    const T z1 = wy0 * (wx0 * p2[0] + ax * p2[1]) + ay * (wx0 * p3[0] + ax * p3[1]);
-    v = wz0 * z0 + az * z1;
-  }
-  fc[j] = v;
+  fc[j] = linear_node<D, T>(j, nc, rf, runR, fracR);
   if (uc) uc[j] = T(0);
 }
 
@@ -176,39 +61,23 @@ __global__ __launch_bounds__(kMaxBlock) void k_prolong(int64_t nf, const T* __re
                                                        T* __restrict__ uf, int remap) {
   const int64_t i = tile_of_block(remap) * blockDim.x + threadIdx.x;
   if (i >= nf) return;
-  const T ax = fracP[i], ay = fracP[nf + i];
-  const T wx0 = T(1) - ax, wy0 = T(1) - ay;
-  T v;
-  if (D == 2) {
-    const T* p0 = ec + runP[i];
-    const T* p1 = ec + runP[nf + i];
-    v = wy0 * (wx0 * p0[0] + ax * p0[1]) + ay * (wx0 * p1[0] + ax * p1[1]);
-  } else {
-    const T az = fracP[2 * nf + i];
-    const T wz0 = T(1) - az;
-    const T* p0 = ec + runP[i];
-    const T* p1 = ec + runP[nf + i];
-    const T* p2 = ec + runP[2 * nf + i];
-    const T* p3 = ec + runP[3 * nf + i];
-    const T z0 = wy0 * (wx0 * p0[0] + ax * p0[1]) + ay * (wx0 * p1[0] + ax * p1[1]);
-    const T z1 = wy0 * (wx0 * p2[0] + ax * p2[1]) + ay * (wx0 * p3[0] + ax * p3[1]);
-    v = wz0 * z0 + az * z1;
-  }
-  uf[i] += v;
+  uf[i] += linear_node<D, T>(i, nf, ec, runP, fracP);
 }
 
-// y = Z x, one wavefront per row, coalesced row reads, wave-level shuffle reduction
+// y = Z x, one workgroup per row (coalesced row reads spread over 256 lanes, so that many
+// loads are in flight), wavefront shuffle + LDS reduction.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemv(int n, const double* __restrict__ Z, int64_t ld,
                                               const T* __restrict__ x, T* __restrict__ y) {
-  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (row >= n) return;
+  const int row = blockIdx.x;
   const double* zr = Z + (int64_t)row * ld;
   double s = 0.0;
-  for (int j = lane; j < n; j += 64) s += zr[j] * (double)x[j];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) s += zr[j] * (double)x[j];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if (lane == 0) y[row] = (T)s;
+  __shared__ double part[4];
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) y[row] = (T)(((part[0] + part[1]) + part[2]) + part[3]);
 }
 
 template <typename T>
@@ -349,28 +218,28 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 // ------------------------------------------------------------------------------------
 
 template <typename T>
-void launch_nsum(int dim, int64_t n, const T* u, const T* f, const int32_t* nbr, T inv_h2, T* g,
-                 unsigned long long* zero_slot, const LaunchCfg& lc, hipStream_t s) {
-  if (n <= 0) {
+void launch_nsum(int dim, int64_t m, const int32_t* ilist, const int32_t* nbrI, const T* u, const T* f, T inv_h2,
+                 T* g, unsigned long long* zero_slot, const LaunchCfg& lc, hipStream_t s) {
+  if (m <= 0) {
     if (zero_slot) k_zero_u64<<<1, 64, 0, s>>>(zero_slot, 1);
     return;
   }
-  const unsigned gr = grid_for(n, lc.block);
+  const unsigned gr = grid_for(m, lc.block);
   if (dim == 2)
-    k_nsum<2, T><<<gr, lc.block, 0, s>>>(n, u, f, nbr, inv_h2, g, zero_slot, lc.xcd_remap);
+    k_nsum<2, T><<<gr, lc.block, 0, s>>>(m, ilist, nbrI, u, f, inv_h2, g, zero_slot, lc.xcd_remap);
   else
-    k_nsum<3, T><<<gr, lc.block, 0, s>>>(n, u, f, nbr, inv_h2, g, zero_slot, lc.xcd_remap);
+    k_nsum<3, T><<<gr, lc.block, 0, s>>>(m, ilist, nbrI, u, f, inv_h2, g, zero_slot, lc.xcd_remap);
 }
 
 template <typename T, typename TO>
-void launch_ext(int dim, int mode, int64_t n, const T* g, const int32_t* runE, const T* frac,
-                const T* b, T* u, TO* out, T delta, T wod, unsigned long long* nrm,
-                const LaunchCfg& lc, hipStream_t s) {
+void launch_ext(int dim, int mode, int64_t n, const T* g, const ExtAddr& a, const T* frac, const T* b, T* u,
+                TO* out, T delta, T wod, unsigned long long* nrm, const LaunchCfg& lc, hipStream_t s) {
   if (n <= 0) return;
   const unsigned gr = grid_for(n, lc.block);
   const int rm = lc.xcd_remap;
-#define CPM_EXT_CASE(DD, MM)                                                                 \
-  k_ext<DD, T, TO, MM><<<gr, lc.block, 0, s>>>(n, g, runE, frac, b, u, out, delta, wod, nrm, rm)
+#define CPM_EXT_CASE(DD, MM)                                                                        \
+  k_ext<DD, T, TO, MM><<<gr, lc.block, 0, s>>>(n, g, a.perm, a.packed, a.origin, frac, b, u, out, delta, wod, \
+                                               nrm, rm)
   if (dim == 2) {
     switch (mode) {
       case EXT_SMOOTH: CPM_EXT_CASE(2, EXT_SMOOTH); break;
@@ -414,7 +283,7 @@ void launch_prolong(int dim, int64_t nf, const T* ec, const int32_t* runP, const
 template <typename T>
 void launch_coarse_gemv(int n, const double* Z, int64_t ld, const T* x, T* y, hipStream_t s) {
   if (n <= 0) return;
-  k_gemv<T><<<grid_for(n, 4), 256, 0, s>>>(n, Z, ld, x, y);
+  k_gemv<T><<<(unsigned)n, 256, 0, s>>>(n, Z, ld, x, y);
 }
 
 template <typename T>
@@ -460,17 +329,17 @@ void launch_gj_step(int n, int k, double* M, double* col, int* info, hipStream_t
 }
 
 // explicit instantiations
-template void launch_nsum<double>(int, int64_t, const double*, const double*, const int32_t*, double,
+template void launch_nsum<double>(int, int64_t, const int32_t*, const int32_t*, const double*, const double*, double,
                                   double*, unsigned long long*, const LaunchCfg&, hipStream_t);
-template void launch_nsum<float>(int, int64_t, const float*, const float*, const int32_t*, float, float*,
-                                 unsigned long long*, const LaunchCfg&, hipStream_t);
-template void launch_ext<double, double>(int, int, int64_t, const double*, const int32_t*, const double*,
+template void launch_nsum<float>(int, int64_t, const int32_t*, const int32_t*, const float*, const float*, float,
+                                 float*, unsigned long long*, const LaunchCfg&, hipStream_t);
+template void launch_ext<double, double>(int, int, int64_t, const double*, const ExtAddr&, const double*,
                                          const double*, double*, double*, double, double,
                                          unsigned long long*, const LaunchCfg&, hipStream_t);
-template void launch_ext<double, float>(int, int, int64_t, const double*, const int32_t*, const double*,
+template void launch_ext<double, float>(int, int, int64_t, const double*, const ExtAddr&, const double*,
                                         const double*, double*, float*, double, double,
                                         unsigned long long*, const LaunchCfg&, hipStream_t);
-template void launch_ext<float, float>(int, int, int64_t, const float*, const int32_t*, const float*,
+template void launch_ext<float, float>(int, int, int64_t, const float*, const ExtAddr&, const float*,
                                        const float*, float*, float*, float, float, unsigned long long*,
                                        const LaunchCfg&, hipStream_t);
 template void launch_restrict<double>(int, int64_t, const double*, const int32_t*, const double*, double*,

@@ -1,0 +1,154 @@
+// Device-side building blocks shared by the single-problem and the batched kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "cpm_internal.h"
+#include "kernels.h"
+
+namespace cpm {
+
+constexpr int kMaxBlock = 512;
+
+// Workgroups are dispatched round robin over the 8 XCDs (workgroup b runs on XCD b % 8).
+// Remap so that XCD x processes one contiguous range of tiles: neighbouring band nodes
+// share most of their stencil data, and this keeps that sharing inside one L2.
+__device__ __forceinline__ int64_t tile_of_block(int remap) {
+  const int64_t nb = gridDim.x, b = blockIdx.x;
+  if (!remap || nb < 16) return b;
+  const int64_t per = nb / 8, rem = nb % 8, x = b % 8, k = b / 8;
+  return x * per + (x < rem ? x : rem) + k;
+}
+
+template <typename T>
+__device__ __forceinline__ void cubic_weights(T a, T w[4]) {
+  // Lagrange basis on nodes 0..3 at s = 1 + a, a = frac in [0, 1)
+  const T am1 = a - T(1), am2 = a - T(2), ap1 = a + T(1);
+  w[0] = -(a * am1 * am2) * T(1.0 / 6.0);
+  w[1] = (ap1 * am1 * am2) * T(0.5);
+  w[2] = -(ap1 * a * am2) * T(0.5);
+  w[3] = (ap1 * a * am1) * T(1.0 / 6.0);
+}
+
+__device__ __forceinline__ unsigned long long abs_bits(double v) {
+  return (unsigned long long)__double_as_longlong(fabs(v));
+}
+
+// Block-wide max of 64-bit patterns followed by one atomicMax; every thread must call it.
+__device__ __forceinline__ void block_max_atomic(unsigned long long v, unsigned long long* dst) {
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(v, off);
+    v = v > o ? v : o;
+  }
+  __shared__ unsigned long long part[kMaxBlock / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) part[wid] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = 0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int w = 0; w < nw; ++w) m = part[w] > m ? part[w] : m;
+    if (m) atomicMax(dst, m);
+  }
+  __syncthreads();  // part[] may be reused by a following call (grid-stride loops)
+}
+
+// g_j = f_j + (sum of the 2d axis neighbours of u) / h^2 at node k of B_interp (j = ilist[k]);
+// f may be null (g = N u).  Only these nodes are ever read by the extension, all of their
+// neighbours are in the band, and the +-x neighbours are the adjacent band entries.
+template <int D, typename T>
+__device__ __forceinline__ void nsum_node(int64_t k, int64_t m, const int32_t* __restrict__ ilist,
+                                          const int32_t* __restrict__ nbrI, const T* __restrict__ u,
+                                          const T* __restrict__ f, T inv_h2, T* __restrict__ g) {
+  const int32_t j = ilist[k];
+  T s = u[j - 1] + u[j + 1];
+#pragma unroll
+  for (int q = 0; q < 2 * D - 2; ++q) s += u[nbrI[q * m + k]];
+  T gj = s * inv_h2;
+  if (f) gj += f[j];
+  g[j] = gj;
+}
+
+// t = E g at the node in stencil slot k (tensor-product cubic interpolation at its closest
+// point), then one of the ExtMode updates; returns the bit pattern of |r| (or |t|) for the
+// infinity norm.  Nodes are visited in stencil order (sorted by the base of their cubic
+// stencil) so that the lanes of a wavefront gather from the same few rows: node
+// i = perm[k]; its x-run (b, c) starts at origin[gid * 4^(D-1) + b + 4c] + xoff with
+// (gid, xoff) packed in packed[k]; frac holds the fractions in stencil order.
+template <int D, typename T, typename TO, int MODE>
+__device__ __forceinline__ unsigned long long ext_node(int64_t k, int64_t n, const T* __restrict__ g,
+                                                       const int32_t* __restrict__ perm,
+                                                       const int32_t* __restrict__ packed,
+                                                       const int32_t* __restrict__ origin,
+                                                       const T* __restrict__ frac, const T* __restrict__ b,
+                                                       T* __restrict__ u, TO* __restrict__ out, T delta,
+                                                       T wod) {
+  constexpr int S = D == 2 ? 4 : 16;
+  const int32_t i = perm[k];
+  const int32_t pk = packed[k];
+  const int32_t* org = origin + (int64_t)(pk >> kXoffBits) * S;
+  const T* gx = g + (pk & ((1 << kXoffBits) - 1));
+  T wx[4], wy[4], wz[4];
+  cubic_weights<T>(frac[k], wx);
+  cubic_weights<T>(frac[n + k], wy);
+  T t = T(0);
+  if (D == 2) {
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+      const T* p = gx + org[bb];
+      const T s = wx[0] * p[0] + wx[1] * p[1] + wx[2] * p[2] + wx[3] * p[3];
+      t += wy[bb] * s;
+    }
+  } else {
+    cubic_weights<T>(frac[2 * n + k], wz);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      T tc = T(0);
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        const T* p = gx + org[bb + 4 * c];
+        const T s = wx[0] * p[0] + wx[1] * p[1] + wx[2] * p[2] + wx[3] * p[3];
+        tc += wy[bb] * s;
+      }
+      t += wz[c] * tc;
+    }
+  }
+  if (MODE == EXT_SMOOTH) {
+    const T ui = u[i];
+    T r = t - delta * ui;
+    if (b) r += b[i];
+    u[i] = ui + wod * r;
+    return abs_bits((double)r);
+  } else if (MODE == EXT_RESID) {
+    T r = t - delta * u[i];
+    if (b) r += b[i];
+    if (out) out[i] = (TO)r;
+    return abs_bits((double)r);
+  } else if (MODE == EXT_APPLY) {
+    out[i] = (TO)(delta * u[i] - t);
+    return 0ull;
+  } else {
+    if (out) out[i] = (TO)t;
+    return abs_bits((double)t);
+  }
+}
+
+// Linear interpolation at a closest point of values v through 2^(D-1) x-runs of length 2:
+// runs[r * cnt + j], fractions frac[a * cnt + j].
+template <int D, typename T>
+__device__ __forceinline__ T linear_node(int64_t j, int64_t cnt, const T* __restrict__ v,
+                                         const int32_t* __restrict__ runs, const T* __restrict__ frac) {
+  const T ax = frac[j], ay = frac[cnt + j];
+  const T wx0 = T(1) - ax, wy0 = T(1) - ay;
+  const T* p0 = v + runs[j];
+  const T* p1 = v + runs[cnt + j];
+  const T z0 = wy0 * (wx0 * p0[0] + ax * p0[1]) + ay * (wx0 * p1[0] + ax * p1[1]);
+  if (D == 2) return z0;
+  const T az = frac[2 * cnt + j];
+  const T* p2 = v + runs[2 * cnt + j];
+  const T* p3 = v + runs[3 * cnt + j];
+  const T z1 = wy0 * (wx0 * p2[0] + ax * p2[1]) + ay * (wx0 * p3[0] + ax * p3[1]);
+  return (T(1) - az) * z0 + az * z1;
+}
+
+}  // namespace cpm

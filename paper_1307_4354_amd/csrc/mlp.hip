@@ -1,0 +1,426 @@
+// Learned local smoother: a two-layer network (64 inputs, 64 hidden units, 1 output) that
+// maps a node's normalised 3^d residual patch and its own 1-D cubic interpolation weights
+// to an update of u, replacing the damped Jacobi step on the two finest levels.
+//
+// Layer 1 (the only dense contraction) runs on the matrix cores: for 64 nodes at a time a
+// wavefront computes H (64 x 64) = X (64 x 64, bf16) * W1^T (64 x 64, bf16) with
+// v_mfma_f32_32x32x8_bf16 in float32 accumulators (2 x 2 output tiles, 8 k-steps).
+// Operand layout of that instruction (per lane l, half = l / 32, col = l % 32):
+//   A (32 x 8): row col, k = 4 half .. 4 half + 3        (4 bf16 in one 64-bit register pair)
+//   B (8 x 32): col col, k = 4 half .. 4 half + 3
+//   D (32 x 32): register v holds row 8 (v / 4) + 4 half + v % 4, column col.
+// Layer 2 (64 -> 1) and the update are float32 VALU work.  The weight gradient of layer 1,
+// dW1 = dH^T X summed over nodes, uses the same instruction with the node index as k.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "capi_internal.h"
+#include "kernels_dev.h"
+
+namespace cpm {
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kIn = CPM_MLP_IN;
+constexpr int kHid = CPM_MLP_HIDDEN;
+constexpr int kB1 = kHid * kIn;      // offset of b1 in the packed weights
+constexpr int kW2 = kB1 + kHid;      // offset of w2
+constexpr int kB2 = kW2 + kHid;      // offset of b2
+constexpr int kWCount = kB2 + 1;
+constexpr int kPartStride = 33;      // padded row of the layer-2 partial sums in LDS
+
+__device__ __forceinline__ uint16_t f2bf(float x) {
+  uint32_t b = __float_as_uint(x);
+  b += 0x7FFFu + ((b >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(b >> 16);
+}
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// One wavefront evaluates the network on 64 feature rows X[row * 64 + k] (bf16, generic
+// pointer: global or LDS), rows >= valid read as zero.  Returns y for row = lane.  If H is
+// not null the hidden activations of valid rows are stored (float, row stride 64).  part is
+// this wavefront's LDS scratch (64 x kPartStride floats).  Every thread of the block must
+// call it (it synchronizes the block).
+__device__ float mlp_wave(const uint16_t* X, int valid, const uint16_t* __restrict__ W, float* part,
+                          float* __restrict__ H) {
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5, col = lane & 31;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
+#pragma unroll
+  for (int ks = 0; ks < 8; ++ks) {
+    bf16x4 av[2], bv[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      const int row = mb * 32 + col;
+      if (row < valid) {
+        av[mb] = *(const bf16x4*)(X + row * kIn + ks * 8 + half * 4);
+      } else {
+        av[mb] = bf16x4{0, 0, 0, 0};
+      }
+    }
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) bv[nb] = *(const bf16x4*)(W + (nb * 32 + col) * kIn + ks * 8 + half * 4);
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+  }
+  float b1v[2], w2v[2];
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    b1v[nb] = bf2f(W[kB1 + nb * 32 + col]);
+    w2v[nb] = bf2f(W[kW2 + nb * 32 + col]);
+  }
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int row = mb * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+      float p = 0.0f;
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const float hv = fmaxf(acc[mb][nb][v] + b1v[nb], 0.0f);
+        p += hv * w2v[nb];
+        if (H && row < valid) H[row * kHid + nb * 32 + col] = hv;
+      }
+      part[row * kPartStride + col] = p;
+    }
+  __syncthreads();
+  float y = bf2f(W[kB2]);
+  for (int c = 0; c < 32; ++c) y += part[lane * kPartStride + c];
+  __syncthreads();
+  return y;
+}
+
+// Features of one node (see oracle/mlp.py): residual patch / s, then the 1-D weights.
+// Writes 64 bf16 into xrow; returns s.
+template <int D, typename T>
+__device__ __forceinline__ float node_features(int64_t k, int64_t n, const T* __restrict__ r,
+                                               const int32_t* __restrict__ prow, const uint32_t* __restrict__ pmask,
+                                               const T* __restrict__ frac, uint16_t* xrow) {
+  constexpr int R = D == 2 ? 3 : 9;
+  constexpr int P = 3 * R;
+  const uint32_t mask = pmask[k];
+  T patch[P];
+  T s = T(0);
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const int32_t base = prow[q * n + k];
+#pragma unroll
+    for (int dx = 0; dx < 3; ++dx) {
+      const int bit = dx + 3 * q;
+      const T v = (mask >> bit) & 1u ? r[base + dx] : T(0);
+      patch[bit] = v;
+      s = fmax(s, (T)fabs((double)v));
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < P; ++q) xrow[q] = s > T(0) ? f2bf((float)(patch[q] / s)) : (uint16_t)0;
+  T w[4];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    cubic_weights<T>(frac[a * n + k], w);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xrow[P + 4 * a + j] = f2bf((float)w[j]);
+  }
+#pragma unroll
+  for (int q = P + 4 * D; q < kIn; ++q) xrow[q] = 0;
+  return (float)s;
+}
+
+// Features of every node of a level, rows in band order (row perm[k] for stencil slot k).
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_features(int64_t n, const T* __restrict__ r, const int32_t* __restrict__ perm,
+                                                  const int32_t* __restrict__ prow, const uint32_t* __restrict__ pmask,
+                                                  const T* __restrict__ frac, uint16_t* __restrict__ X,
+                                                  float* __restrict__ scale) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  uint16_t xr[kIn];
+  const float s = node_features<D, T>(k, n, r, prow, pmask, frac, xr);
+  const int32_t i = perm[k];
+  uint64_t* dst = (uint64_t*)(X + (int64_t)i * kIn);
+#pragma unroll
+  for (int q = 0; q < kIn / 4; ++q)
+    dst[q] = (uint64_t)xr[4 * q] | ((uint64_t)xr[4 * q + 1] << 16) | ((uint64_t)xr[4 * q + 2] << 32) |
+             ((uint64_t)xr[4 * q + 3] << 48);
+  scale[i] = s;
+}
+
+// Fused learned sweep: features of 64 nodes per wavefront into LDS, network on the matrix
+// cores, u_i += (s / delta) y.  r is the residual of the current iterate (read only).
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_learned(int64_t n, const T* __restrict__ r, const int32_t* __restrict__ perm,
+                                                 const int32_t* __restrict__ prow, const uint32_t* __restrict__ pmask,
+                                                 const T* __restrict__ frac, const uint16_t* __restrict__ W, T inv_delta,
+                                                 T* __restrict__ u) {
+  __shared__ uint16_t xs[4][64 * kIn];
+  __shared__ float part[4][64 * kPartStride];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t k0 = (blockIdx.x * 4 + wave) * (int64_t)64;
+  const int64_t k = k0 + lane;
+  float s = 0.0f;
+  if (k < n) {
+    s = node_features<D, T>(k, n, r, prow, pmask, frac, &xs[wave][lane * kIn]);
+  } else {
+    for (int q = 0; q < kIn; ++q) xs[wave][lane * kIn + q] = 0;
+  }
+  __syncthreads();
+  int64_t rem = n - k0;
+  const int valid = rem <= 0 ? 0 : (rem >= 64 ? 64 : (int)rem);
+  const float y = mlp_wave(xs[wave], valid, W, part[wave], nullptr);
+  if (k < n) {
+    const int32_t i = perm[k];
+    u[i] += (T)s * inv_delta * (T)y;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mlp_fwd(int64_t m, const uint16_t* __restrict__ X,
+                                                 const uint16_t* __restrict__ W, float* __restrict__ Y,
+                                                 float* __restrict__ H) {
+  __shared__ float part[4][64 * kPartStride];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t r0 = (blockIdx.x * 4 + wave) * (int64_t)64;
+  const int64_t rem = m - r0;
+  const int valid = rem <= 0 ? 0 : (rem >= 64 ? 64 : (int)rem);
+  const uint16_t* Xw = X + (valid > 0 ? r0 * kIn : 0);
+  float* Hw = (H && valid > 0) ? H + r0 * kHid : nullptr;
+  const float y = mlp_wave(Xw, valid, W, part[wave], Hw);
+  if (lane < valid) Y[r0 + lane] = y;
+}
+
+// Gradient of (1/m) sum (y - t)^2.  Each wavefront takes chunks of 64 nodes; per chunk the
+// lanes own hidden unit j = lane for the small gradients, dH^T (bf16) and the X chunk are
+// staged in LDS, and dW1 += dH^T X on the matrix cores.  Partial sums end in G by atomics.
+__global__ __launch_bounds__(256) void k_mlp_bwd(int64_t m, const uint16_t* __restrict__ X,
+                                                 const uint16_t* __restrict__ W, const float* __restrict__ H,
+                                                 const float* __restrict__ Y, const float* __restrict__ T,
+                                                 float* __restrict__ G) {
+  constexpr int LS = 68;  // padded LDS row (bf16 elements)
+  __shared__ uint16_t dht[4][64 * LS];
+  __shared__ uint16_t xs[4][64 * LS];
+  __shared__ float dys[4][64];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int half = lane >> 5, col = lane & 31;
+  const float w2j = bf2f(W[kW2 + lane]);
+  const float two_over_m = 2.0f / (float)m;
+  float gw2 = 0.0f, gb1 = 0.0f, gb2 = 0.0f;
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][b][v] = 0.0f;
+  const int64_t nchunks = (m + 63) / 64;
+  for (int64_t cb = blockIdx.x; cb * 4 < nchunks; cb += gridDim.x) {  // same trip count for all waves
+    const int64_t c = cb * 4 + wave;
+    const int64_t i0 = c * 64;
+    const int64_t rem = m - i0;
+    const int valid = rem <= 0 ? 0 : (rem >= 64 ? 64 : (int)rem);
+    // stage X rows and dy
+    for (int q = 0; q < kIn; ++q) xs[wave][lane * LS + q] = lane < valid ? X[(i0 + lane) * kIn + q] : (uint16_t)0;
+    const float dy = lane < valid ? two_over_m * (Y[i0 + lane] - T[i0 + lane]) : 0.0f;
+    dys[wave][lane] = dy;
+    gb2 += dy;
+    __syncthreads();
+    // lane = hidden unit j: small gradients and dH^T
+    for (int i = 0; i < 64; ++i) {
+      const float hv = i < valid ? H[(i0 + i) * kHid + lane] : 0.0f;
+      const float d = dys[wave][i];
+      gw2 += d * hv;
+      const float dh = hv > 0.0f ? d * w2j : 0.0f;
+      gb1 += dh;
+      dht[wave][lane * LS + i] = f2bf(dh);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      bf16x4 av[2], bv[2];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) av[mb] = *(const bf16x4*)&dht[wave][(mb * 32 + col) * LS + ks * 8 + half * 4];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        const int kk = ks * 8 + half * 4;
+        bf16x4 t;
+        t[0] = (short)xs[wave][(kk + 0) * LS + nb * 32 + col];
+        t[1] = (short)xs[wave][(kk + 1) * LS + nb * 32 + col];
+        t[2] = (short)xs[wave][(kk + 2) * LS + nb * 32 + col];
+        t[3] = (short)xs[wave][(kk + 3) * LS + nb * 32 + col];
+        bv[nb] = t;
+      }
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+          acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av[mb], bv[nb], acc[mb][nb], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int j = mb * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+        atomicAdd(&G[j * kIn + nb * 32 + col], acc[mb][nb][v]);
+      }
+  atomicAdd(&G[kB1 + lane], gb1);
+  atomicAdd(&G[kW2 + lane], gw2);
+  for (int off = 32; off > 0; off >>= 1) gb2 += __shfl_xor(gb2, off);
+  if (lane == 0) atomicAdd(&G[kB2], gb2);
+}
+
+// Adam step on float32 master weights; the bf16 copy used by the kernels is refreshed.
+__global__ void k_adam(int count, float* __restrict__ w, float* __restrict__ m1, float* __restrict__ m2,
+                       const float* __restrict__ g, float lr, float b1, float b2, float eps, float c1, float c2,
+                       uint16_t* __restrict__ wb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const float gi = g[i];
+  const float a = b1 * m1[i] + (1.0f - b1) * gi;
+  const float b = b2 * m2[i] + (1.0f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = b;
+  const float wn = w[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
+  w[i] = wn;
+  wb[i] = f2bf(wn);
+}
+
+template <typename T>
+const T* frac_k(const DevLevel& D);
+template <>
+const double* frac_k<double>(const DevLevel& D) { return D.fracK; }
+template <>
+const float* frac_k<float>(const DevLevel& D) { return D.fracK32; }
+
+}  // namespace
+
+// r = b + E g - delta u into B.r, then the fused network update of u.
+template <typename T>
+void learned_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g, T* r, double c, hipStream_t s) {
+  (void)f;
+  const DevLevel& D = b->dev[(size_t)l];
+  const LaunchCfg lc = band_cfg(b, D.n);
+  const double delta = level_delta(b, l, c);
+  launch_ext<T, T>(b->dim, EXT_RESID, D.n, g, ExtAddr{D.perm, D.packed, D.origin}, frac_k<T>(D), rhsA, u, r,
+                   (T)delta, (T)0, nullptr, lc, s);
+  const unsigned gr = (unsigned)((D.n + 255) / 256);
+  if (b->dim == 2)
+    k_learned<2, T><<<gr, 256, 0, s>>>(D.n, r, D.perm, D.patchRow, D.patchMask, frac_k<T>(D), b->mlpW, (T)(1.0 / delta), u);
+  else
+    k_learned<3, T><<<gr, 256, 0, s>>>(D.n, r, D.perm, D.patchRow, D.patchMask, frac_k<T>(D), b->mlpW, (T)(1.0 / delta), u);
+}
+
+template void learned_sweep<double>(const cpm_band, int, double*, const double*, const double*, double*, double*,
+                                    double, hipStream_t);
+template void learned_sweep<float>(const cpm_band, int, float*, const float*, const float*, float*, float*, double,
+                                   hipStream_t);
+
+}  // namespace cpm
+
+using namespace cpm;
+
+extern "C" {
+
+cpm_status cpm_set_smoother_weights(cpm_band band, const uint16_t* w_bf16, double rho_plain) {
+  if (!band || !w_bf16 || !(rho_plain > 0.0)) {
+    set_error("cpm_set_smoother_weights: invalid argument");
+    return CPM_E_INVALID;
+  }
+  if (!band->mlpW && hipMalloc((void**)&band->mlpW, kWCount * sizeof(uint16_t)) != hipSuccess) {
+    band->mlpW = nullptr;
+    set_error("device allocation failed");
+    return CPM_E_NOMEM;
+  }
+  if (hipMemcpy(band->mlpW, w_bf16, kWCount * sizeof(uint16_t), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("weight upload failed");
+    return CPM_E_HIP;
+  }
+  band->rho_plain = rho_plain;
+  for (auto& kv : band->graphs) (void)hipGraphExecDestroy(kv.second);
+  band->graphs.clear();
+  return CPM_OK;
+}
+
+cpm_status cpm_mlp_forward(int64_t m, const uint16_t* X, const uint16_t* W, float* Y, float* H, void* stream) {
+  if (m < 0 || (m > 0 && (!X || !W || !Y))) {
+    set_error("cpm_mlp_forward: invalid argument");
+    return CPM_E_INVALID;
+  }
+  if (m == 0) return CPM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  k_mlp_fwd<<<(unsigned)((m + 255) / 256), 256, 0, s>>>(m, X, W, Y, H);
+  return check_launch("cpm_mlp_forward");
+}
+
+cpm_status cpm_mlp_backward(int64_t m, const uint16_t* X, const uint16_t* W, const float* H, const float* Y,
+                            const float* T, float* G, void* stream) {
+  if (m <= 0 || !X || !W || !H || !Y || !T || !G) {
+    set_error("cpm_mlp_backward: invalid argument");
+    return CPM_E_INVALID;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  launch_fill<float>(kWCount, G, 0.0f, s);
+  const int64_t chunks = (m + 63) / 64;
+  int64_t blocks = (chunks + 3) / 4;
+  if (blocks > 2048) blocks = 2048;
+  k_mlp_bwd<<<(unsigned)blocks, 256, 0, s>>>(m, X, W, H, Y, T, G);
+  return check_launch("cpm_mlp_backward");
+}
+
+cpm_status cpm_mlp_adam(int step, float lr, float* w_master, float* m1, float* m2, const float* G,
+                        uint16_t* w_bf16, void* stream) {
+  if (step < 1 || !(lr > 0.0f) || !w_master || !m1 || !m2 || !G || !w_bf16) {
+    set_error("cpm_mlp_adam: invalid argument");
+    return CPM_E_INVALID;
+  }
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  k_adam<<<(kWCount + 255) / 256, 256, 0, (hipStream_t)stream>>>(kWCount, w_master, m1, m2, G, lr, b1, b2, 1e-8f, c1,
+                                                                 c2, w_bf16);
+  return check_launch("cpm_mlp_adam");
+}
+
+cpm_status cpm_smoother_features(cpm_band band, int level, double c, const double* f, const double* u, uint16_t* X,
+                                 float* scale, void* work, void* stream) {
+  if (!band || level < 0 || level >= band->L || level > 1 || !f || !u || !X || !scale || !work || !(c > 0.0)) {
+    set_error("cpm_smoother_features: invalid argument (levels 0 and 1 only)");
+    return CPM_E_INVALID;
+  }
+  const DevLevel& D = band->dev[(size_t)level];
+  if (!D.patchRow) {
+    set_error("cpm_smoother_features: no patch addressing on this level");
+    return CPM_E_INVALID;
+  }
+  cpm_status st = enter(band, stream);
+  if (st != CPM_OK) return st;
+  hipStream_t s = band->stream;
+  const LaunchCfg lc = band_cfg(band, D.n);
+  double* g = (double*)work;
+  double* r = g + D.n;
+  launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, u, f, 1.0 / (D.h * D.h), g, nullptr, lc, s);
+  launch_ext<double, double>(band->dim, EXT_RESID, D.n, g, ExtAddr{D.perm, D.packed, D.origin}, D.fracK, nullptr,
+                             const_cast<double*>(u), r, level_delta(band, level, c), 0.0, nullptr, lc, s);
+  const unsigned gr = (unsigned)((D.n + 255) / 256);
+  if (band->dim == 2)
+    k_features<2, double><<<gr, 256, 0, s>>>(D.n, r, D.perm, D.patchRow, D.patchMask, D.fracK, X, scale);
+  else
+    k_features<3, double><<<gr, 256, 0, s>>>(D.n, r, D.perm, D.patchRow, D.patchMask, D.fracK, X, scale);
+  if ((st = check_launch("cpm_smoother_features")) != CPM_OK) return st;
+  return leave(band, stream);
+}
+
+}  // extern "C"

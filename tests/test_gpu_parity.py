@@ -40,7 +40,11 @@ def test_band_construction_bitexact(name, cfg):
         assert np.array_equal(cp, lev.cp), "closest points differ on level %d" % l
         runE, nbr, runP, runR = band.export_stencils(l)
         assert np.array_equal(runE, H.E[l].indices.reshape(lev.n, -1)[:, ::4])
-        assert np.array_equal(nbr, ob.neighbour_indices(lev))
+        # Laplacian neighbours are kept for B_interp (the nodes E reads); other rows read -2
+        interp = np.zeros(lev.n, bool)
+        interp[np.unique(H.E[l].indices)] = True
+        assert np.array_equal(nbr[interp], ob.neighbour_indices(lev)[interp])
+        assert np.all(nbr[~interp] == -2)
         if l + 1 < cfg.levels:
             assert np.array_equal(runP, H.P[l].indices.reshape(lev.n, -1)[:, ::2])
         if l > 0:

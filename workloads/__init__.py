@@ -292,10 +292,11 @@ class BatchItem:
 
 
 def batch_problems(nprob: int = 256, seed: int = SEED_BASE + 4,
-                   h_choices: Sequence[int] = (32, 64, 128), coarse_h_inv: int = 8) -> List[BatchItem]:
+                   h_choices: Sequence[int] = (32, 64, 128), coarse_h_inv: int = 4) -> List[BatchItem]:
     """Uneven batch: half spheres R ~ U[0.5, 1.5], half tori R ~ U[0.8, 1.2], r ~ U[0.2, 0.5],
     h drawn uniformly from 1/32, 1/64, 1/128, random mode right-hand sides, each problem
-    coarsened down to h = 1/coarse_h_inv."""
+    coarsened down to h = 1/coarse_h_inv (1/4 keeps every coarsest level below ~4.4k
+    nodes, so the dense coarsest inverses of all problems fit together)."""
     rng = np.random.default_rng(seed)
     items = []
     for k in range(nprob):
