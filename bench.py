@@ -91,6 +91,10 @@ def main():
     nb64 = cpm.cpm_workspace_size(band, p64)
     nbmx = cpm.cpm_workspace_size(band, pmx)
     work = torch.empty(max(nb64, nbmx), dtype=torch.uint8, device="cuda")
+    t0 = time.perf_counter()
+    cpm.cpm_autotune(band)  # per-level launch configurations (setup, like the band build)
+    t_tune = time.perf_counter() - t0
+    tuning = [cpm.cpm_band_tuning(band, l) for l in range(band.levels)]
     ud = torch.zeros_like(fd)
     hist = torch.zeros(max(args.steps, args.warmup) + 8, dtype=torch.float64, device="cuda")
     per_launch = 10
@@ -137,7 +141,7 @@ def main():
     achieved = alg_bytes / (avg_us * 1e-6) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_ext<3,double,EXT_SMOOTH> level 0", "avg_launch_us": round(avg_us, 3),
+                "kernel": ("k_ext_lds" if tuning[0][0] else "k_ext") + "<3,double,EXT_SMOOTH> level 0", "avg_launch_us": round(avg_us, 3),
                 "alg_bytes_per_launch": int(alg_bytes)}
 
     if args.copy_calibration:
@@ -167,6 +171,8 @@ def main():
         "mixed": {"value": n0 * args.steps / dt_mx, "ms_per_step": 1000.0 * dt_mx / args.steps, "dtype": "f32+f64"},
         "time_to_1e-10": tt,
         "band_build_s": t_build,
+        "autotune_s": t_tune,
+        "tuning": [{"level": l, "lds": t[0], "ext_block": t[1], "nsum_block": t[2]} for l, t in enumerate(tuning)],
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

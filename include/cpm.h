@@ -197,9 +197,14 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
                              size_t work_bytes, double rtol, int max_cycles, cpm_stats* stats,
                              void* stream);
 
-/* Tile-size autotuner: time the library's gather kernels on this band with each candidate
- * block size and remember the fastest per level-size class.  Synchronous. */
+/* Autotuner: for every level, time the two passes of a smoothing sweep with each candidate
+ * launch configuration on this band's addressing (extension: gathers with workgroups of
+ * 128 / 256 / 512 lanes or LDS-staged; neighbour sum: 128 / 256 / 512 lanes) and keep the
+ * fastest in the handle.  Allocates two temporary vectors; synchronous. */
 cpm_status cpm_autotune(cpm_band band, void* stream);
+
+/* Launch configuration chosen for one level (after cpm_autotune, or the defaults). */
+cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_block, int* nsum_block);
 
 /* ---- learned smoother ---------------------------------------------------------------
  * Network (per node): x = [r_patch / s (27 values: residual on the 3x3x3 grid patch

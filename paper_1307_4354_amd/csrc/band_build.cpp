@@ -10,6 +10,8 @@
 // to contain B_interp and B_edge of the cubic scheme.  Nodes are sorted x fastest.
 #include <algorithm>
 #include <cmath>
+#include <climits>
+#include <cstdlib>
 #include <cstring>
 #include <sstream>
 
@@ -265,6 +267,80 @@ bool stencil_runs(const HostLevel& src, const HostLevel& target, int p, std::vec
   return bad < 0;
 }
 
+// LDS staging tables of the extension (see HostLevel): for every workgroup of kExtBlock
+// consecutive stencil slots, merge the x-runs its nodes read into segments of consecutive
+// band indices, lay the segments out one after another in LDS and record, per local group
+// (a group cut at the workgroup boundary), where each x-run starts in LDS.
+void build_lds_tables(HostLevel& Lv, int S) {
+  const int64_t n = Lv.n;
+  const int64_t nb = (n + kExtBlock - 1) / kExtBlock;
+  const int32_t xmask = (1 << kXoffBits) - 1;
+  Lv.blkE.assign((size_t)nb + 1, 0);
+  Lv.blkG.assign((size_t)nb + 1, 0);
+  Lv.gidx.clear();
+  Lv.lorg.clear();
+  Lv.packedL.assign((size_t)n, 0);
+  Lv.maxE = 0;
+  Lv.maxG = 0;
+  std::vector<std::pair<int32_t, int32_t>> iv;  // [start, end) intervals of band indices
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t k0 = b * kExtBlock, k1 = std::min<int64_t>(n, k0 + kExtBlock);
+    // local groups: runs of equal global group id
+    std::vector<int64_t> lg_first;
+    std::vector<int32_t> lg_gid, lg_xmin, lg_xmax;
+    for (int64_t k = k0; k < k1; ++k) {
+      const int32_t gid = Lv.packed[(size_t)k] >> kXoffBits, xo = Lv.packed[(size_t)k] & xmask;
+      if (lg_gid.empty() || lg_gid.back() != gid) {
+        lg_first.push_back(k);
+        lg_gid.push_back(gid);
+        lg_xmin.push_back(xo);
+        lg_xmax.push_back(xo);
+      } else {
+        lg_xmin.back() = std::min(lg_xmin.back(), xo);
+        lg_xmax.back() = std::max(lg_xmax.back(), xo);
+      }
+      Lv.packedL[(size_t)k] = (int32_t)(((lg_gid.size() - 1) << kXoffBits) | (size_t)xo);
+    }
+    iv.clear();
+    for (size_t q = 0; q < lg_gid.size(); ++q)
+      for (int s = 0; s < S; ++s) {
+        const int32_t o = Lv.origin[(size_t)lg_gid[q] * S + s];
+        iv.emplace_back(o + lg_xmin[q], o + lg_xmax[q] + 4);
+      }
+    std::sort(iv.begin(), iv.end());
+    // merge into segments; seg_g[j], seg_l[j] = band start and LDS offset of segment j
+    std::vector<int32_t> seg_g, seg_e, seg_l;
+    int32_t off = 0;
+    for (auto& v : iv) {
+      if (!seg_g.empty() && v.first <= seg_e.back()) {
+        if (v.second > seg_e.back()) {
+          off += v.second - seg_e.back();
+          seg_e.back() = v.second;
+        }
+      } else {
+        seg_g.push_back(v.first);
+        seg_e.push_back(v.second);
+        seg_l.push_back(off);
+        off += v.second - v.first;
+      }
+    }
+    for (size_t j = 0; j < seg_g.size(); ++j)
+      for (int32_t x = seg_g[j]; x < seg_e[j]; ++x) Lv.gidx.push_back(x);
+    for (size_t q = 0; q < lg_gid.size(); ++q)
+      for (int s = 0; s < S; ++s) {
+        const int32_t o = Lv.origin[(size_t)lg_gid[q] * S + s];
+        const int32_t start = o + lg_xmin[q];
+        // segment containing start (segments are sorted and disjoint)
+        size_t j = (size_t)(std::upper_bound(seg_g.begin(), seg_g.end(), start) - seg_g.begin()) - 1;
+        Lv.lorg.push_back(seg_l[j] + (o - seg_g[j]));
+      }
+    Lv.blkE[(size_t)b + 1] = Lv.blkE[(size_t)b] + off;
+    Lv.blkG[(size_t)b + 1] = Lv.blkG[(size_t)b] + (int32_t)lg_gid.size();
+    Lv.maxE = std::max(Lv.maxE, off);
+    Lv.maxG = std::max(Lv.maxG, (int32_t)lg_gid.size());
+  }
+}
+
 // Stencil-ordered extension addressing and the B_interp neighbour lists of one level.
 cpm_status build_stencil_order(HostLevel& Lv, int level, std::string& err) {
   const int dim = Lv.dim;
@@ -278,9 +354,33 @@ cpm_status build_stencil_order(HostLevel& Lv, int level, std::string& err) {
     by[(size_t)i] = Lv.idx[(size_t)(j * dim + 1)];
     if (dim == 3) bz[(size_t)i] = Lv.idx[(size_t)(j * dim + 2)];
   }
+  // Visit order: stencil bases grouped into blocks of B^dim cells ordered along a Morton
+  // curve, (z, y, x) inside a block.  Consecutive workgroups then touch a compact region
+  // of the band, whose rows stay in L2 while their neighbours are processed.
+  int block_bits = -1;  // no blocking (plain (z, y, x) order) unless CPM_MORTON_BITS is set
+  if (const char* e = std::getenv("CPM_MORTON_BITS")) block_bits = std::atoi(e);
+  int32_t mn[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
+  for (int64_t i = 0; i < n; ++i) {
+    mn[0] = std::min(mn[0], bx[(size_t)i]);
+    mn[1] = std::min(mn[1], by[(size_t)i]);
+    mn[2] = std::min(mn[2], bz[(size_t)i]);
+  }
+  std::vector<uint64_t> key((size_t)n, 0);
+  if (block_bits >= 0) {
+    for (int64_t i = 0; i < n; ++i) {
+      const uint32_t c[3] = {(uint32_t)(bx[(size_t)i] - mn[0]) >> block_bits,
+                             (uint32_t)(by[(size_t)i] - mn[1]) >> block_bits,
+                             (uint32_t)(bz[(size_t)i] - mn[2]) >> block_bits};
+      uint64_t m = 0;
+      for (int bit = 0; bit < 20; ++bit)
+        for (int a = 0; a < 3; ++a) m |= (uint64_t)((c[a] >> bit) & 1u) << (3 * bit + a);
+      key[(size_t)i] = m;
+    }
+  }
   std::vector<int32_t> order((size_t)n);
   for (int64_t i = 0; i < n; ++i) order[(size_t)i] = (int32_t)i;
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    if (key[(size_t)a] != key[(size_t)b]) return key[(size_t)a] < key[(size_t)b];
     if (bz[(size_t)a] != bz[(size_t)b]) return bz[(size_t)a] < bz[(size_t)b];
     if (by[(size_t)a] != by[(size_t)b]) return by[(size_t)a] < by[(size_t)b];
     return bx[(size_t)a] < bx[(size_t)b];
@@ -323,6 +423,9 @@ cpm_status build_stencil_order(HostLevel& Lv, int level, std::string& err) {
     for (int a = 0; a < dim; ++a) Lv.fracK[(size_t)(a * n + k)] = Lv.fracE[(size_t)(a * n + i)];
   }
   Lv.ngroups = g + 1;
+  build_lds_tables(Lv, S);
+  Lv.packedB.assign((size_t)n, 0);
+  for (int64_t k = 0; k < n; ++k) Lv.packedB[(size_t)order[(size_t)k]] = Lv.packed[(size_t)k];
   // B_interp (every node of some cubic stencil) with its +-y, +-z neighbours
   std::vector<uint8_t> used((size_t)n, 0);
   for (int s = 0; s < S; ++s)

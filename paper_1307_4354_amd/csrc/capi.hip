@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -32,6 +33,18 @@ namespace cpm {
 LaunchCfg band_cfg(const cpm_band b, int64_t n) {
   int cls = n < (1 << 16) ? 0 : (n < (1 << 20) ? 1 : 2);
   return b->lc[cls];
+}
+
+LaunchCfg level_cfg(const DevLevel& D) {
+  LaunchCfg c;
+  c.block = D.nsum_block;
+  return c;
+}
+
+LaunchCfg ext_cfg(const DevLevel& D) {
+  LaunchCfg c;
+  c.block = D.ext_block;
+  return c;
 }
 
 template <typename T>
@@ -69,7 +82,7 @@ static void free_dev(cpm_band b) {
   for (auto& D : b->dev) {
     void* ps[] = {D.runE,  D.nbr,   D.fracE,  D.fracE32, D.runP,    D.fracP,  D.fracP32, D.runR,
                   D.fracR, D.fracR32, D.perm, D.packed, D.origin, D.fracK, D.fracK32, D.ilist, D.nbrI,
-                  D.patchRow, D.patchMask};
+                  D.patchRow, D.patchMask, D.packedB, D.packedL, D.blkE, D.gidx, D.blkG, D.lorg};
     for (void* p : ps)
       if (p) (void)hipFree(p);
   }
@@ -217,13 +230,26 @@ template <>
 const double* fracE_of<double>(const DevLevel& D) { return D.fracE; }
 template <>
 const float* fracE_of<float>(const DevLevel& D) { return D.fracE32; }
-static ExtAddr ext_addr(const DevLevel& D) { return ExtAddr{D.perm, D.packed, D.origin}; }
+ExtAddr ext_addr(const DevLevel& D) {
+  if (D.band_order) return ExtAddr{nullptr, D.packedB, D.origin};
+  ExtAddr a{D.perm, D.packed, D.origin};
+  if (D.lds && D.use_lds) {
+    a.packedL = D.packedL;
+    a.blkE = D.blkE;
+    a.gidx = D.gidx;
+    a.blkG = D.blkG;
+    a.lorg = D.lorg;
+    a.maxE = D.maxE;
+    a.maxG = D.maxG;
+  }
+  return a;
+}
 template <typename T>
 static const T* fracK_of(const DevLevel& D);
 template <>
-const double* fracK_of<double>(const DevLevel& D) { return D.fracK; }
+const double* fracK_of<double>(const DevLevel& D) { return D.band_order ? D.fracE : D.fracK; }
 template <>
-const float* fracK_of<float>(const DevLevel& D) { return D.fracK32; }
+const float* fracK_of<float>(const DevLevel& D) { return D.band_order ? D.fracE32 : D.fracK32; }
 template <typename T>
 static const T* fracP_of(const DevLevel& D);
 template <>
@@ -242,7 +268,7 @@ template <typename T>
 void smooth_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g, T* r, double c, double omega,
                   unsigned long long* nrm, hipStream_t s) {
   const DevLevel& D = b->dev[(size_t)l];
-  const LaunchCfg lc = band_cfg(b, D.n);
+  const LaunchCfg lc = level_cfg(D);
   const double delta = level_delta(b, l, c);
   launch_nsum<T>(b->dim, D.m, D.ilist, D.nbrI, u, f, (T)(1.0 / (D.h * D.h)), g, nullptr, lc, s);
   if (b->learned_active && l < 2 && b->mlpW && D.patchRow) {
@@ -250,13 +276,13 @@ void smooth_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g
     return;
   }
   launch_ext<T, T>(b->dim, EXT_SMOOTH, D.n, g, ext_addr(D), fracK_of<T>(D), rhsA, u, (T*)nullptr, (T)delta,
-                   (T)(omega / delta), nrm, lc, s);
+                   (T)(omega / delta), nrm, ext_cfg(D), s);
 }
 
 template <typename T>
 void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const cpm_params& p, hipStream_t s) {
   const DevLevel& D = b->dev[(size_t)l];
-  const LaunchCfg lc = band_cfg(b, D.n);
+  const LaunchCfg lc = level_cfg(D);
   if (l == b->L - 1) {
     // coarsest: u = A_c^{-1} E_c f  (f-space right-hand side)
     launch_coarse_gemv<T>((int)D.n, b->coarseM + D.n, 2 * D.n, B[l].f, B[l].u, s);
@@ -268,9 +294,9 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
   // residual r = b + E(f + N u) - delta u, restricted to the next level (where u := 0)
   launch_nsum<T>(b->dim, D.m, D.ilist, D.nbrI, B[l].u, f, (T)(1.0 / (D.h * D.h)), B[l].g, nullptr, lc, s);
   launch_ext<T, T>(b->dim, EXT_RESID, D.n, B[l].g, ext_addr(D), fracK_of<T>(D), rhsA, B[l].u, B[l].r, (T)delta,
-                   (T)0, nullptr, lc, s);
+                   (T)0, nullptr, ext_cfg(D), s);
   const DevLevel& C = b->dev[(size_t)(l + 1)];
-  launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, band_cfg(b, C.n), s);
+  launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
   vcycle_level<T>(b, l + 1, B, nullptr, p, s);
   launch_prolong<T>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<T>(D), B[l].u, lc, s);
   for (int k = 0; k < p.nu2; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s);
@@ -280,18 +306,18 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
 void enqueue_rhs_norm(const cpm_band b, const double* f, double* g, hipStream_t s) {
   const DevLevel& D = b->dev[0];
   launch_zero_u64(b->dscal + 1, 1, s);
-  launch_ext<double, double>(b->dim, EXT_PLAIN, D.n, f, ext_addr(D), D.fracK, nullptr, nullptr, (double*)nullptr,
-                             0.0, 0.0, b->dscal + 1, band_cfg(b, D.n), s);
+  launch_ext<double, double>(b->dim, EXT_PLAIN, D.n, f, ext_addr(D), fracK_of<double>(D), nullptr, nullptr, (double*)nullptr,
+                             0.0, 0.0, b->dscal + 1, ext_cfg(D), s);
 }
 
 // ||E(f + N u) - delta u||_inf into slot 0; optionally the residual as float into r32
 void enqueue_resid64(const cpm_band b, const double* f, const double* u, double* g, float* r32, double c,
                      hipStream_t s) {
   const DevLevel& D = b->dev[0];
-  const LaunchCfg lc = band_cfg(b, D.n);
+  const LaunchCfg lc = level_cfg(D);
   launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, u, f, 1.0 / (D.h * D.h), g, b->dscal, lc, s);
-  launch_ext<double, float>(b->dim, EXT_RESID, D.n, g, ext_addr(D), D.fracK, nullptr, const_cast<double*>(u), r32,
-                            level_delta(b, 0, c), 0.0, b->dscal, lc, s);
+  launch_ext<double, float>(b->dim, EXT_RESID, D.n, g, ext_addr(D), fracK_of<double>(D), nullptr, const_cast<double*>(u), r32,
+                            level_delta(b, 0, c), 0.0, b->dscal, ext_cfg(D), s);
 }
 
 // One complete cycle of the solve loop on the band stream, ending with the residual
@@ -485,6 +511,9 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     return CPM_E_HIP;
   }
   b->dev.resize((size_t)b->L);
+  // order in which the extension visits nodes: stencil order (default) or band order
+  const char* ord = std::getenv("CPM_EXT_ORDER");
+  const bool band_order = ord && std::strcmp(ord, "band") == 0;
   for (int l = 0; l < b->L && st == CPM_OK; ++l) {
     HostLevel& H = b->host[(size_t)l];
     DevLevel& D = b->dev[(size_t)l];
@@ -503,11 +532,37 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     if (st == CPM_OK) st = upload(&D.patchMask, H.patchMask);
     std::vector<int32_t>().swap(H.patchRow);
     std::vector<uint32_t>().swap(H.patchMask);
+    D.band_order = band_order;
+    // LDS-staged extension unless disabled or a workgroup would stage too many values
+    const char* lds_env = std::getenv("CPM_EXT_LDS");
+    D.lds = !band_order && H.maxE <= kMaxStaged && !(lds_env && std::strcmp(lds_env, "0") == 0);
+    // default before autotuning: LDS staging pays on levels up to ~2M nodes
+    D.use_lds = D.lds && H.n < (int64_t)(2 << 20);
+    D.maxE = H.maxE;
+    D.maxG = H.maxG;
+    if (D.lds) {
+      if (st == CPM_OK) st = upload(&D.packedL, H.packedL);
+      if (st == CPM_OK) st = upload(&D.blkE, H.blkE);
+      if (st == CPM_OK) st = upload(&D.gidx, H.gidx);
+      if (st == CPM_OK) st = upload(&D.blkG, H.blkG);
+      if (st == CPM_OK) st = upload(&D.lorg, H.lorg);
+    }
+    std::vector<int32_t>().swap(H.packedL);
+    std::vector<int32_t>().swap(H.blkE);
+    std::vector<int32_t>().swap(H.gidx);
+    std::vector<int32_t>().swap(H.blkG);
+    std::vector<int32_t>().swap(H.lorg);
+    if (band_order) {
+      if (st == CPM_OK) st = upload(&D.packedB, H.packedB);
+      if (st == CPM_OK) st = upload_f32(&D.fracE32, H.fracE);
+    }
+    if (band_order || l == b->L - 1) {
+      if (st == CPM_OK) st = upload(&D.fracE, H.fracE);
+    }
     if (l == b->L - 1) {
       // band-order addressing of the coarsest level, used to assemble its dense matrix
       if (st == CPM_OK) st = upload(&D.runE, H.runE);
       if (st == CPM_OK) st = upload(&D.nbr, H.nbr);
-      if (st == CPM_OK) st = upload(&D.fracE, H.fracE);
     }
     if (st == CPM_OK) st = upload(&D.runP, H.runP);
     if (st == CPM_OK) st = upload(&D.fracP, H.fracP);
@@ -525,6 +580,7 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     std::vector<int32_t>().swap(H.nbr);
     std::vector<int32_t>().swap(H.perm);
     std::vector<int32_t>().swap(H.packed);
+    std::vector<int32_t>().swap(H.packedB);
     std::vector<int32_t>().swap(H.origin);
     std::vector<double>().swap(H.fracK);
     std::vector<int32_t>().swap(H.ilist);
@@ -668,10 +724,10 @@ cpm_status cpm_apply(cpm_band band, int level, double c, const double* u, double
   const DevLevel& D = band->dev[(size_t)level];
   cpm_status st = enter(band, stream);
   if (st != CPM_OK) return st;
-  const LaunchCfg lc = band_cfg(band, D.n);
+  const LaunchCfg lc = level_cfg(D);
   launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, u, nullptr, 1.0 / (D.h * D.h), work, nullptr, lc, band->stream);
-  launch_ext<double, double>(band->dim, EXT_APPLY, D.n, work, ext_addr(D), D.fracK, nullptr, const_cast<double*>(u),
-                             Au, level_delta(band, level, c), 0.0, nullptr, lc, band->stream);
+  launch_ext<double, double>(band->dim, EXT_APPLY, D.n, work, ext_addr(D), fracK_of<double>(D), nullptr, const_cast<double*>(u),
+                             Au, level_delta(band, level, c), 0.0, nullptr, ext_cfg(D), band->stream);
   if ((st = check_launch("cpm_apply")) != CPM_OK) return st;
   return leave(band, stream);
 }
@@ -684,8 +740,8 @@ cpm_status cpm_extend(cpm_band band, int level, const double* g, double* out, vo
   const DevLevel& D = band->dev[(size_t)level];
   cpm_status st = enter(band, stream);
   if (st != CPM_OK) return st;
-  launch_ext<double, double>(band->dim, EXT_PLAIN, D.n, g, ext_addr(D), D.fracK, nullptr, nullptr, out, 0.0, 0.0,
-                             nullptr, band_cfg(band, D.n), band->stream);
+  launch_ext<double, double>(band->dim, EXT_PLAIN, D.n, g, ext_addr(D), fracK_of<double>(D), nullptr, nullptr, out, 0.0, 0.0,
+                             nullptr, ext_cfg(D), band->stream);
   if ((st = check_launch("cpm_extend")) != CPM_OK) return st;
   return leave(band, stream);
 }
@@ -849,7 +905,7 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
   if ((st = enter(band, stream)) != CPM_OK) return st;
   hipStream_t s = band->stream;
   const DevLevel& D = band->dev[(size_t)level];
-  const LaunchCfg lc = band_cfg(band, D.n);
+  const LaunchCfg lc = level_cfg(D);
   const double delta = level_delta(band, level, params->c);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return CPM_E_HIP;
@@ -871,7 +927,7 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
       for (int r = 0; r < k; ++r) {
         if (which == 0) {
           launch_ext<T, T>(band->dim, EXT_SMOOTH, D.n, B[level].g, ext_addr(D), fracK_of<T>(D), nullptr, uu, (T*)nullptr,
-                           (T)delta, (T)(params->omega / delta), nullptr, lc, s);
+                           (T)delta, (T)(params->omega / delta), nullptr, ext_cfg(D), s);
         } else if (which == 1) {
           launch_nsum<T>(band->dim, D.m, D.ilist, D.nbrI, uu, ff, (T)(1.0 / (D.h * D.h)), B[level].g, nullptr, lc, s);
         } else if (which == 2) {

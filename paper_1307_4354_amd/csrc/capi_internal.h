@@ -61,6 +61,9 @@ struct cpm_band_s {
 namespace cpm {
 
 LaunchCfg band_cfg(const cpm_band b, int64_t n);
+LaunchCfg level_cfg(const DevLevel& D);
+LaunchCfg ext_cfg(const DevLevel& D);
+ExtAddr ext_addr(const DevLevel& D);
 double level_delta(const cpm_band b, int l, double c);
 cpm_status enter(cpm_band b, void* user);
 cpm_status leave(cpm_band b, void* user);

@@ -30,9 +30,19 @@ struct HostLevel {
   // whose 4^(dim-1) x-run starts are stored once: run(s) = origin[gid][s] + xoff.
   std::vector<int32_t> perm;    // n: processing slot k -> band index
   std::vector<int32_t> packed;  // n: (gid << kXoffBits) | xoff
+  std::vector<int32_t> packedB; // n: the same, indexed by band position
   std::vector<int32_t> origin;  // ngroups * 4^(dim-1)
   std::vector<double> fracK;    // dim * n: fractions in processing order
   int64_t ngroups = 0;
+  // LDS staging of the extension: per workgroup of kExtBlock consecutive stencil slots, the
+  // g values its stencils read (gidx, in LDS order) and, per local group, the LDS offset of
+  // each x-run for xoff = 0 (lorg); packedL[k] = (local group << kXoffBits) | xoff
+  std::vector<int32_t> blkE;    // nblocks + 1: prefix of staged values
+  std::vector<int32_t> gidx;    // staged g indices
+  std::vector<int32_t> blkG;    // nblocks + 1: prefix of local groups
+  std::vector<int32_t> lorg;    // local groups * 4^(dim-1)
+  std::vector<int32_t> packedL; // n
+  int32_t maxE = 0, maxG = 0;   // largest staged set / local-group count of one workgroup
   // Laplacian neighbours of interpolation-stencil nodes only (B_interp, ascending): the
   // +-x neighbours are j -+ 1, the others stored as -y,+y(,-z,+z) slot-major
   std::vector<int32_t> ilist;   // m
@@ -50,6 +60,8 @@ struct HostLevel {
 };
 
 constexpr int kXoffBits = 10;
+constexpr int kExtBlock = 256;      // workgroup size of the LDS-staged extension
+constexpr int kMaxStaged = 8192;    // staged values per workgroup above which a level keeps the gather path
 constexpr int kMaxGroups = 1 << (31 - kXoffBits);
 
 // Device copies of one level's addressing.
@@ -58,8 +70,20 @@ struct DevLevel {
   int64_t m = 0;        // |B_interp|
   int64_t ngroups = 0;
   double h = 0.0;
+  bool band_order = false;  // extension visits nodes in band order (packedB, fracE)
+  bool lds = false;         // LDS-staged extension tables present
+  bool use_lds = false;     // extension runs LDS-staged (else gathers through L1)
+  int ext_block = 256;      // workgroup size of the gather extension
+  int nsum_block = 256;     // workgroup size of the neighbour sum and transfers
+  int32_t maxE = 0, maxG = 0;
+  int32_t* blkE = nullptr;
+  int32_t* gidx = nullptr;
+  int32_t* blkG = nullptr;
+  int32_t* lorg = nullptr;
+  int32_t* packedL = nullptr;
   int32_t* perm = nullptr;
   int32_t* packed = nullptr;
+  int32_t* packedB = nullptr;
   int32_t* origin = nullptr;
   double* fracK = nullptr;
   float* fracK32 = nullptr;

@@ -1,17 +1,118 @@
-// Tile-size autotuner of the single-problem kernels.
+// Autotuner of the single-problem kernels: for every level it times the candidate launch
+// configurations of the two passes of a smoothing sweep on the band's own addressing and
+// keeps the fastest (the extension: gathers through the vector caches with workgroups of
+// 128 / 256 / 512 lanes, or LDS-staged; the neighbour sum: 128 / 256 / 512 lanes).
 #include <hip/hip_runtime.h>
+
+#include <vector>
 
 #include "capi_internal.h"
 
 using namespace cpm;
 
+namespace {
+
+template <typename Fn>
+float time_us(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, Fn fn) {
+  fn();  // warm-up
+  (void)hipEventRecord(e0, s);
+  for (int r = 0; r < reps; ++r) fn();
+  (void)hipEventRecord(e1, s);
+  (void)hipEventSynchronize(e1);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  return 1000.f * ms / reps;
+}
+
+}  // namespace
+
 extern "C" {
 
 cpm_status cpm_autotune(cpm_band band, void* stream) {
-  (void)band;
-  (void)stream;
-  set_error("not available");
-  return CPM_E_INVALID;
+  if (!band) {
+    set_error("cpm_autotune: null band");
+    return CPM_E_INVALID;
+  }
+  cpm_status st = enter(band, stream);
+  if (st != CPM_OK) return st;
+  hipStream_t s = band->stream;
+  const int64_t n0 = band->dev[0].n;
+  double *g = nullptr, *u = nullptr;
+  if (hipMalloc((void**)&g, n0 * sizeof(double)) != hipSuccess || hipMalloc((void**)&u, n0 * sizeof(double)) != hipSuccess) {
+    if (g) (void)hipFree(g);
+    set_error("cpm_autotune: allocation failed");
+    return CPM_E_NOMEM;
+  }
+  launch_fill<double>(n0, g, 1.0, s);
+  launch_fill<double>(n0, u, 0.5, s);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  const int blocks[3] = {128, 256, 512};
+  for (int l = 0; l < band->L; ++l) {
+    DevLevel& D = band->dev[(size_t)l];
+    const int reps = D.n > (1 << 20) ? 5 : 20;
+    const double delta = level_delta(band, l, 1.0);
+    const double inv_h2 = 1.0 / (D.h * D.h);
+    float best = 1e30f;
+    bool best_lds = D.use_lds;
+    int best_blk = D.ext_block;
+    for (int cand = 0; cand < 4; ++cand) {
+      const bool lds = cand == 3;
+      if (lds && !D.lds) continue;
+      D.use_lds = lds;
+      D.ext_block = lds ? 256 : blocks[cand];
+      const ExtAddr a = ext_addr(D);
+      const LaunchCfg lc = ext_cfg(D);
+      const float t = time_us(s, e0, e1, reps, [&] {
+        launch_ext<double, double>(band->dim, EXT_SMOOTH, D.n, g, a, D.band_order ? D.fracE : D.fracK, nullptr, u,
+                                   (double*)nullptr, delta, 0.5 / delta, nullptr, lc, s);
+      });
+      if (t < best) {
+        best = t;
+        best_lds = lds;
+        best_blk = D.ext_block;
+      }
+    }
+    D.use_lds = best_lds;
+    D.ext_block = best_blk;
+    best = 1e30f;
+    int best_n = D.nsum_block;
+    for (int bi = 0; bi < 3; ++bi) {
+      LaunchCfg lc;
+      lc.block = blocks[bi];
+      const float t = time_us(s, e0, e1, reps, [&] {
+        launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, u, u, inv_h2, g, nullptr, lc, s);
+      });
+      if (t < best) {
+        best = t;
+        best_n = blocks[bi];
+      }
+    }
+    D.nsum_block = best_n;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(g);
+  (void)hipFree(u);
+  // captured graphs hold the old launch configurations
+  for (auto& kv : band->graphs) (void)hipGraphExecDestroy(kv.second);
+  band->graphs.clear();
+  if ((st = check_launch("cpm_autotune")) != CPM_OK) return st;
+  return leave(band, stream);
+}
+
+cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_block, int* nsum_block) {
+  if (!band || level < 0 || level >= band->L) {
+    set_error("cpm_band_tuning: invalid argument");
+    return CPM_E_INVALID;
+  }
+  const DevLevel& D = band->dev[(size_t)level];
+  if (use_lds) *use_lds = D.lds && D.use_lds ? 1 : 0;
+  if (ext_block) *ext_block = D.use_lds ? kExtBlock : D.ext_block;
+  if (nsum_block) *nsum_block = D.nsum_block;
+  return CPM_OK;
 }
 
 }  // extern "C"

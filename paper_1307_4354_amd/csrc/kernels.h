@@ -18,8 +18,8 @@ enum ExtMode {
 
 // Launch geometry of the node-parallel kernels (set by the autotuner).
 struct LaunchCfg {
-  int block = 256;
-  int xcd_remap = 1;  // map consecutive tiles to the same XCD (shared L2)
+  int block = 256;      // neighbour sum, transfers, gather extension
+  int xcd_remap = 1;    // map consecutive tiles to the same XCD (shared L2)
 };
 
 // Stencil-ordered extension addressing of one level (see HostLevel).
@@ -27,6 +27,14 @@ struct ExtAddr {
   const int32_t* perm;
   const int32_t* packed;
   const int32_t* origin;
+  // LDS staging (used when packedL is not null; stencil order only)
+  const int32_t* packedL = nullptr;
+  const int32_t* blkE = nullptr;
+  const int32_t* gidx = nullptr;
+  const int32_t* blkG = nullptr;
+  const int32_t* lorg = nullptr;
+  int32_t maxE = 0;
+  int32_t maxG = 0;
 };
 
 // g = f + N u on the m nodes of B_interp (ilist), f may be null.

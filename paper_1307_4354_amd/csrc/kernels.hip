@@ -26,7 +26,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_nsum(int64_t m, const int32_t* __
 }
 
 template <int D, typename T, typename TO, int MODE>
-__global__ __launch_bounds__(kMaxBlock) void k_ext(int64_t n, const T* __restrict__ g,
+__global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_ext(
+    int64_t n, const T* __restrict__ g,
                                                    const int32_t* __restrict__ perm,
                                                    const int32_t* __restrict__ packed,
                                                    const int32_t* __restrict__ origin,
@@ -37,6 +38,30 @@ __global__ __launch_bounds__(kMaxBlock) void k_ext(int64_t n, const T* __restric
   const int64_t k = tile_of_block(remap) * blockDim.x + threadIdx.x;
   unsigned long long nv = 0ull;
   if (k < n) nv = ext_node<D, T, TO, MODE>(k, n, g, perm, packed, origin, frac, b, u, out, delta, wod);
+  if (MODE != EXT_APPLY && nrm) block_max_atomic(nv, nrm);
+}
+
+template <int D, typename T, typename TO, int MODE>
+__global__ __launch_bounds__(kExtBlock) void k_ext_lds(int64_t n, const T* __restrict__ g,
+                                                       const int32_t* __restrict__ perm,
+                                                       const int32_t* __restrict__ packedL,
+                                                       const int32_t* __restrict__ blkE,
+                                                       const int32_t* __restrict__ gidx,
+                                                       const int32_t* __restrict__ blkG,
+                                                       const int32_t* __restrict__ lorg,
+                                                       const T* __restrict__ frac, const T* __restrict__ b,
+                                                       T* __restrict__ u, TO* __restrict__ out, T delta, T wod,
+                                                       unsigned long long* __restrict__ nrm, int remap,
+                                                       int lo_offset) {
+  constexpr int S = D == 2 ? 4 : 16;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  T* gl = (T*)smem;
+  int32_t* lo = (int32_t*)(smem + lo_offset);
+  const int64_t blk = tile_of_block(remap);
+  ext_stage<T>(blk, g, blkE, gidx, blkG, lorg, S, gl, lo);
+  const int64_t k = blk * kExtBlock + threadIdx.x;
+  unsigned long long nv = 0ull;
+  if (k < n) nv = ext_node_lds<D, T, TO, MODE>(k, n, gl, lo, perm, packedL, frac, b, u, out, delta, wod);
   if (MODE != EXT_APPLY && nrm) block_max_atomic(nv, nrm);
 }
 
@@ -235,6 +260,35 @@ template <typename T, typename TO>
 void launch_ext(int dim, int mode, int64_t n, const T* g, const ExtAddr& a, const T* frac, const T* b, T* u,
                 TO* out, T delta, T wod, unsigned long long* nrm, const LaunchCfg& lc, hipStream_t s) {
   if (n <= 0) return;
+  if (a.packedL) {
+    // LDS-staged path: fixed workgroup of kExtBlock stencil slots (the staging tables are
+    // built for it); dynamic LDS = staged values + local-group run offsets
+    const int S = dim == 2 ? 4 : 16;
+    const int lo_off = (int)(((size_t)a.maxE * sizeof(T) + 15) & ~(size_t)15);
+    const size_t shm = (size_t)lo_off + (size_t)a.maxG * S * sizeof(int32_t);
+    const unsigned gl = (unsigned)((n + kExtBlock - 1) / kExtBlock);
+    const int rm = lc.xcd_remap;
+#define CPM_EXTL_CASE(DD, MM)                                                                         \
+  k_ext_lds<DD, T, TO, MM><<<gl, kExtBlock, shm, s>>>(n, g, a.perm, a.packedL, a.blkE, a.gidx, a.blkG, a.lorg, \
+                                                       frac, b, u, out, delta, wod, nrm, rm, lo_off)
+    if (dim == 2) {
+      switch (mode) {
+        case EXT_SMOOTH: CPM_EXTL_CASE(2, EXT_SMOOTH); break;
+        case EXT_RESID: CPM_EXTL_CASE(2, EXT_RESID); break;
+        case EXT_APPLY: CPM_EXTL_CASE(2, EXT_APPLY); break;
+        default: CPM_EXTL_CASE(2, EXT_PLAIN); break;
+      }
+    } else {
+      switch (mode) {
+        case EXT_SMOOTH: CPM_EXTL_CASE(3, EXT_SMOOTH); break;
+        case EXT_RESID: CPM_EXTL_CASE(3, EXT_RESID); break;
+        case EXT_APPLY: CPM_EXTL_CASE(3, EXT_APPLY); break;
+        default: CPM_EXTL_CASE(3, EXT_PLAIN); break;
+      }
+    }
+#undef CPM_EXTL_CASE
+    return;
+  }
   const unsigned gr = grid_for(n, lc.block);
   const int rm = lc.xcd_remap;
 #define CPM_EXT_CASE(DD, MM)                                                                        \

@@ -48,7 +48,9 @@ __device__ __forceinline__ void block_max_atomic(unsigned long long v, unsigned 
     unsigned long long m = 0;
     const int nw = (blockDim.x + 63) >> 6;
     for (int w = 0; w < nw; ++w) m = part[w] > m ? part[w] : m;
-    if (m) atomicMax(dst, m);
+    // the stored maximum only grows: skip the atomic when it cannot change it, so that
+    // thousands of workgroups do not serialize on one address
+    if (m && m > __atomic_load_n(dst, __ATOMIC_RELAXED)) atomicMax(dst, m);
   }
   __syncthreads();  // part[] may be reused by a following call (grid-stride loops)
 }
@@ -69,6 +71,23 @@ __device__ __forceinline__ void nsum_node(int64_t k, int64_t m, const int32_t* _
   g[j] = gj;
 }
 
+// Weighted sum of one x-run of 4 consecutive values, loaded with 16-byte vector loads
+// (the run start is only element aligned; global loads of several dwords need dword
+// alignment, which every double and float address has).
+typedef double run_d2 __attribute__((ext_vector_type(2), aligned(8)));
+typedef float run_f4 __attribute__((ext_vector_type(4), aligned(4)));
+
+__device__ __forceinline__ double run_dot(const double* __restrict__ p, const double w[4]) {
+  const run_d2 a = *(const run_d2*)p;
+  const run_d2 b = *(const run_d2*)(p + 2);
+  return w[0] * a.x + w[1] * a.y + w[2] * b.x + w[3] * b.y;
+}
+
+__device__ __forceinline__ float run_dot(const float* __restrict__ p, const float w[4]) {
+  const run_f4 a = *(const run_f4*)p;
+  return w[0] * a.x + w[1] * a.y + w[2] * a.z + w[3] * a.w;
+}
+
 // t = E g at the node in stencil slot k (tensor-product cubic interpolation at its closest
 // point), then one of the ExtMode updates; returns the bit pattern of |r| (or |t|) for the
 // infinity norm.  Nodes are visited in stencil order (sorted by the base of their cubic
@@ -84,7 +103,7 @@ __device__ __forceinline__ unsigned long long ext_node(int64_t k, int64_t n, con
                                                        T* __restrict__ u, TO* __restrict__ out, T delta,
                                                        T wod) {
   constexpr int S = D == 2 ? 4 : 16;
-  const int32_t i = perm[k];
+  const int32_t i = perm ? perm[k] : (int32_t)k;  // null perm: band order
   const int32_t pk = packed[k];
   const int32_t* org = origin + (int64_t)(pk >> kXoffBits) * S;
   const T* gx = g + (pk & ((1 << kXoffBits) - 1));
@@ -94,22 +113,84 @@ __device__ __forceinline__ unsigned long long ext_node(int64_t k, int64_t n, con
   T t = T(0);
   if (D == 2) {
 #pragma unroll
-    for (int bb = 0; bb < 4; ++bb) {
-      const T* p = gx + org[bb];
-      const T s = wx[0] * p[0] + wx[1] * p[1] + wx[2] * p[2] + wx[3] * p[3];
-      t += wy[bb] * s;
-    }
+    for (int bb = 0; bb < 4; ++bb) t += wy[bb] * run_dot(gx + org[bb], wx);
   } else {
     cubic_weights<T>(frac[2 * n + k], wz);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       T tc = T(0);
 #pragma unroll
-      for (int bb = 0; bb < 4; ++bb) {
-        const T* p = gx + org[bb + 4 * c];
-        const T s = wx[0] * p[0] + wx[1] * p[1] + wx[2] * p[2] + wx[3] * p[3];
-        tc += wy[bb] * s;
-      }
+      for (int bb = 0; bb < 4; ++bb) tc += wy[bb] * run_dot(gx + org[bb + 4 * c], wx);
+      t += wz[c] * tc;
+    }
+  }
+  if (MODE == EXT_SMOOTH) {
+    const T ui = u[i];
+    T r = t - delta * ui;
+    if (b) r += b[i];
+    u[i] = ui + wod * r;
+    return abs_bits((double)r);
+  } else if (MODE == EXT_RESID) {
+    T r = t - delta * u[i];
+    if (b) r += b[i];
+    if (out) out[i] = (TO)r;
+    return abs_bits((double)r);
+  } else if (MODE == EXT_APPLY) {
+    out[i] = (TO)(delta * u[i] - t);
+    return 0ull;
+  } else {
+    if (out) out[i] = (TO)t;
+    return abs_bits((double)t);
+  }
+}
+
+// ---- LDS-staged extension ---------------------------------------------------------
+// A workgroup of kExtBlock consecutive stencil slots first copies the g values its
+// stencils read into LDS (a few hundred values instead of 64 gathers per node through the
+// vector caches), then every lane interpolates from LDS.
+
+template <typename T>
+__device__ __forceinline__ T run_dot_lds(const T* p, const T w[4]) {
+  return w[0] * p[0] + w[1] * p[1] + w[2] * p[2] + w[3] * p[3];
+}
+
+// Every thread of the workgroup must call it (it synchronizes the block).
+template <typename T>
+__device__ __forceinline__ void ext_stage(int64_t blk, const T* __restrict__ g, const int32_t* __restrict__ blkE,
+                                          const int32_t* __restrict__ gidx, const int32_t* __restrict__ blkG,
+                                          const int32_t* __restrict__ lorg, int S, T* gl, int32_t* lo) {
+  const int32_t e0 = blkE[blk], e1 = blkE[blk + 1];
+  for (int32_t e = e0 + (int32_t)threadIdx.x; e < e1; e += (int32_t)blockDim.x) gl[e - e0] = g[gidx[e]];
+  const int32_t q0 = blkG[blk] * S, q1 = blkG[blk + 1] * S;
+  for (int32_t q = q0 + (int32_t)threadIdx.x; q < q1; q += (int32_t)blockDim.x) lo[q - q0] = lorg[q];
+  __syncthreads();
+}
+
+template <int D, typename T, typename TO, int MODE>
+__device__ __forceinline__ unsigned long long ext_node_lds(int64_t k, int64_t n, const T* gl, const int32_t* lo,
+                                                           const int32_t* __restrict__ perm,
+                                                           const int32_t* __restrict__ packedL,
+                                                           const T* __restrict__ frac, const T* __restrict__ b,
+                                                           T* __restrict__ u, TO* __restrict__ out, T delta, T wod) {
+  constexpr int S = D == 2 ? 4 : 16;
+  const int32_t i = perm[k];
+  const int32_t pk = packedL[k];
+  const int32_t* org = lo + (pk >> kXoffBits) * S;
+  const T* gx = gl + (pk & ((1 << kXoffBits) - 1));
+  T wx[4], wy[4], wz[4];
+  cubic_weights<T>(frac[k], wx);
+  cubic_weights<T>(frac[n + k], wy);
+  T t = T(0);
+  if (D == 2) {
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) t += wy[bb] * run_dot_lds(gx + org[bb], wx);
+  } else {
+    cubic_weights<T>(frac[2 * n + k], wz);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      T tc = T(0);
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) tc += wy[bb] * run_dot_lds(gx + org[bb + 4 * c], wx);
       t += wz[c] * tc;
     }
   }

@@ -250,3 +250,26 @@ def test_single_level_is_direct_solve():
     st = cpm.cpm_solve(band, p, fd, ud, work, nbytes, 1e-12, 2)
     assert st.cycles == 1
     assert rel_inf(host(ud), ref.u) < 1e-12
+
+
+def test_autotuned_solve_matches_oracle():
+    """The autotuner changes launch configurations only: iterates still match the oracle."""
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    cfg = W.config_sphere(32, 4)
+    H = oracle_for(cfg)
+    f = cfg.problem.f(H.levels[0].cp)
+    ref = ov.solve(H, f, ov.Params(), rtol=1e-10, max_cycles=60)
+    band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+    cpm.cpm_autotune(band)
+    for l in range(band.levels):
+        lds, eb, nb = cpm.cpm_band_tuning(band, l)
+        assert eb in (128, 256, 512) and nb in (128, 256, 512)
+    p = cpm.make_params()
+    work, nbytes = workspace(band, p)
+    fd = dev(f)
+    ud = torch.zeros_like(fd)
+    st = cpm.cpm_solve(band, p, fd, ud, work, nbytes, rtol=1e-10, max_cycles=60)
+    assert st.cycles == ref.cycles
+    assert rel_inf(host(ud), ref.u) < 1e-12
