@@ -35,7 +35,182 @@ def parse():
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-tolerance solves")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--workload", default="sphere64",
+                    choices=["sphere64", "torus256", "batched256", "learned"],
+                    help="sphere64 (default, the headline line); the others are secondary measurements")
+    ap.add_argument("--nprob", type=int, default=256, help="batched256: number of problems")
+    ap.add_argument("--train-steps", type=int, default=3000, help="learned: Adam steps")
     return ap.parse_args()
+
+
+def _build(cpm, prob, h0, levels, lam2=0.0):
+    s = prob.surface
+    return cpm.cpm_build_band(cpm.make_surface(s.kind, s.R, s.r, s.center), h0, levels, lam2)
+
+
+def _solve(cpm, torch, band, p, fd, rtol=1e-10, max_cycles=120, repeat=True):
+    """Time to rtol from u = 0 (the first call warms graphs and the coarse factorization)."""
+    nb = cpm.cpm_workspace_size(band, p)
+    work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    ud = torch.zeros_like(fd)
+    if repeat:
+        cpm.cpm_solve(band, p, fd, ud, work, nb, rtol=rtol, max_cycles=max_cycles, raise_on_noconv=False)
+        ud.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = cpm.cpm_solve(band, p, fd, ud, work, nb, rtol=rtol, max_cycles=max_cycles, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    h = st.history()
+    rho = (h[-1] / h[1]) ** (1.0 / (len(h) - 2)) if len(h) > 3 else float("nan")
+    worst = max((h[k + 1] / h[k] for k in range(1, len(h) - 1)), default=float("nan"))
+    return ud, {"seconds": dt, "cycles": st.cycles, "relres": st.relres, "contraction": rho,
+                "worst_cycle_contraction": worst, "fallback_cycle": st.fallback_cycle, "status": st.status}
+
+
+def run_torus256(args):
+    """Mixed precision (float32 inner, float64 outer) vs FP64 on the torus R = 1, r = 0.4 at
+    h = 1/256 (6 levels), and the error of the mixed solution against the FP64 oracle at 1/64."""
+    import numpy as np
+    import torch
+
+    import paper_1307_4354_amd as cpm
+    import workloads as W
+    from oracle import band as ob
+    from oracle import vcycle as ov
+
+    cfg = W.config_torus_mixed(256)
+    t0 = time.perf_counter()
+    band = _build(cpm, cfg.problem, cfg.h0, cfg.levels)
+    t_build = time.perf_counter() - t0
+    cpm.cpm_autotune(band)
+    _, cp = band.export(0)
+    fd = torch.as_tensor(cfg.problem.f(cp)).to("cuda")
+    n0 = band.n(0)
+    out = {"workload": "torus_R1_r0.4_h1/256_6levels", "n_per_level": band.sizes(), "band_build_s": t_build}
+    u64, out["f64"] = _solve(cpm, torch, band, cpm.make_params(), fd)
+    umx, out["mixed"] = _solve(cpm, torch, band, cpm.make_params(precision=cpm.CPM_MIXED), fd)
+    out["mixed_vs_f64_max_rel_diff"] = float((umx - u64).abs().max() / u64.abs().max())
+    out["speedup_mixed_over_f64"] = out["f64"]["seconds"] / out["mixed"]["seconds"]
+    for k in ("f64", "mixed"):
+        out[k]["dof_cycles_per_s"] = n0 * out[k]["cycles"] / out[k]["seconds"]
+    band.free()
+    # error against the FP64 oracle at h = 1/64 (same torus, same right-hand side)
+    c64 = W.config_torus_mixed(64)
+    H = ob.build_hierarchy(c64.problem.surface, c64.h0, c64.levels, c64.lam2)
+    f = c64.problem.f(H.levels[0].cp)
+    ref = ov.solve(H, f, ov.Params(), rtol=1e-10, max_cycles=80)
+    b64 = _build(cpm, c64.problem, c64.h0, c64.levels)
+    ug, st = _solve(cpm, torch, b64, cpm.make_params(precision=cpm.CPM_MIXED), torch.as_tensor(f).to("cuda"),
+                    repeat=False)
+    ugh = ug.cpu().numpy()
+    out["h1/64_mixed_vs_fp64_oracle"] = {"n": H.levels[0].n, "max_rel_diff": float(np.max(np.abs(ugh - ref.u)) /
+                                                                                  np.max(np.abs(ref.u))),
+                                         "oracle_cycles": ref.cycles, "gpu_cycles": st["cycles"]}
+    print(json.dumps({"metric": "time to 1e-10 rel residual, FP64 vs mixed", **out}), flush=True)
+
+
+def run_batched256(args):
+    """256 uneven problems in one batched solve (float32 inner, float64 outer), against
+    unbatched solves of a sample of them."""
+    import torch
+
+    import paper_1307_4354_amd as cpm
+    import workloads as W
+
+    items = W.batch_problems(args.nprob)
+    t0 = time.perf_counter()
+    bands, fs = [], []
+    for it in items:
+        b = _build(cpm, it.problem, it.h0, it.levels, it.lam2)
+        _, cp = b.export(0)
+        bands.append(b)
+        fs.append(torch.as_tensor(it.problem.f(cp)).to("cuda"))
+    t_build = time.perf_counter() - t0
+    sizes = [b.n(0) for b in bands]
+    p = cpm.make_params(precision=cpm.CPM_MIXED)
+    nbytes = cpm.cpm_workspace_size_batched(bands, p)
+    work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    us = [torch.zeros_like(f) for f in fs]
+    cpm.cpm_solve_batched(bands, p, fs, us, work, nbytes, rtol=1e-10, max_cycles=120, raise_on_noconv=False)
+    for u in us:
+        u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, stats = cpm.cpm_solve_batched(bands, p, fs, us, work, nbytes, rtol=1e-10, max_cycles=120,
+                                          raise_on_noconv=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    dof_cycles = sum(n * st.cycles for n, st in zip(sizes, stats))
+    # unbatched reference on a sample: same cycles, same iterate, time
+    sample = list(range(0, len(bands), max(1, len(bands) // 8)))[:8]
+    seq_t, same = 0.0, True
+    for k in sample:
+        u1, r = _solve(cpm, torch, bands[k], p, fs[k])
+        seq_t += r["seconds"]
+        same &= r["cycles"] == stats[k].cycles and bool((u1 - us[k]).abs().max() <= 1e-14 * us[k].abs().max())
+    sample_n = sum(sizes[k] * stats[k].cycles for k in sample)
+    print(json.dumps({"metric": "batched band DOF*V-cycles/s (mixed precision, 1e-10)", "nprob": len(bands),
+                      "status": status, "total_finest_dofs": sum(sizes), "min_n": min(sizes), "max_n": max(sizes),
+                      "seconds": dt, "dof_cycles_per_s": dof_cycles / dt,
+                      "cycles_min": min(s.cycles for s in stats), "cycles_max": max(s.cycles for s in stats),
+                      "max_relres": max(s.relres for s in stats), "tile_block": stats[0].tile_block,
+                      "tile_blocks_per_cu": stats[0].tile_blocks_per_cu, "band_build_s": t_build,
+                      "unbatched_sample": {"problems": sample, "seconds": seq_t,
+                                           "dof_cycles_per_s": sample_n / seq_t, "identical_to_batched": same}}),
+          flush=True)
+
+
+def run_learned(args):
+    """Train the learned smoother on pairs from plain V-cycles (random spheres and tori), then
+    compare learned vs plain FP64 solves on the unit sphere and the torus at h = 1/256."""
+    import numpy as np
+    import torch
+
+    import paper_1307_4354_amd as cpm
+    import workloads as W
+    from paper_1307_4354_amd import learned
+
+    rng = np.random.default_rng(W.SEED_BASE + 5)
+    probs = []
+    for k in range(4):
+        if k % 2 == 0:
+            probs.append((W.sphere_modes(float(rng.uniform(0.7, 1.3)), int(rng.integers(1 << 30))), 1 / 64, 5))
+        else:
+            probs.append((W.torus_modes(float(rng.uniform(0.8, 1.2)), float(rng.uniform(0.3, 0.45)),
+                                        int(rng.integers(1 << 30))), 1 / 64, 4))
+    t0 = time.perf_counter()
+    pairs = learned.generate_pairs(probs, cycles=4)
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res = learned.train(pairs, steps=args.train_steps, batch=65536, lr=1e-3, log_every=250)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    w_jac = learned._bf16_bits(learned.jacobi_init(2.0 / 3.0, 3, 0))
+    out = {"metric": "learned smoother vs plain FP64 V-cycle, time to 1e-10", "pairs": int(pairs.X.shape[0]),
+           "data_s": t_data, "train_s": t_train, "train_steps": args.train_steps, "loss_history": res.losses,
+           "loss_jacobi_init": learned.evaluate_loss(pairs, w_jac), "loss_trained": learned.evaluate_loss(pairs, res.w_bits)}
+    evals = {"sphere_h1/256_7levels": (W.sphere_l3(), 1 / 256, 7),
+             "torus_R1_r0.4_h1/256_6levels": (W.config_torus_mixed(256).problem, 1 / 256, 6)}
+    for name, (prob, h0, levels) in evals.items():
+        band = _build(cpm, prob, h0, levels)
+        cpm.cpm_autotune(band)
+        _, cp = band.export(0)
+        fd = torch.as_tensor(prob.f(cp)).to("cuda")
+        _, plain = _solve(cpm, torch, band, cpm.make_params(), fd)
+        res_e = {"n": band.n(0), "plain_f64_V33": plain}
+        for k in (1, 2):
+            # same sweep count on the fine levels with Jacobi, for the per-sweep comparison
+            _, pk = _solve(cpm, torch, band, cpm.make_params(nu1=k, nu2=k), fd)
+            # fall back to Jacobi when a cycle contracts worse than plain V(3,3) ever did
+            cpm.cpm_set_smoother_weights(band, res.w_bits, plain["worst_cycle_contraction"])
+            _, lk = _solve(cpm, torch, band, cpm.make_params(smoother=cpm.CPM_SMOOTH_LEARNED, learned_sweeps=k), fd)
+            res_e["learned_%d_sweeps" % k] = lk
+            res_e["speedup_learned_%d_over_plain_V33" % k] = plain["seconds"] / lk["seconds"]
+            res_e["plain_V%d%d_for_reference" % (k, k)] = pk
+        out[name] = res_e
+        band.free()
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(cfg, cycles: int):
@@ -77,6 +252,9 @@ def main():
     import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload != "sphere64":
+        {"torus256": run_torus256, "batched256": run_batched256, "learned": run_learned}[args.workload](args)
+        return
     cfg = W.config_sphere(64, 5)
     s = cfg.problem.surface
     t0 = time.perf_counter()

@@ -85,6 +85,8 @@ typedef struct {
   double omega;
   int precision;
   int smoother;
+  int learned_sweeps; /* learned smoother: sweeps before and after the coarse correction on
+                         the levels where it runs (0 = nu1 / nu2 as everywhere else) */
 } cpm_params;
 
 #define CPM_MAX_HISTORY 256

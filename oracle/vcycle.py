@@ -37,6 +37,7 @@ class Params:
     omega: float = 2.0 / 3.0
     residual_mode: str = "consistent"  # or "verbatim"
     learned: Optional[np.ndarray] = None  # bf16 weights of the learned smoother (levels 0, 1)
+    learned_sweeps: int = 0  # sweeps per side on the learned levels (0: nu1 / nu2)
 
 
 def delta(H: Hierarchy, l: int, c: float) -> float:
@@ -92,13 +93,19 @@ def vcycle(H: Hierarchy, l: int, u: np.ndarray, f: np.ndarray, p: Params,
     """u^h = V^h(u^h, f^h), Algorithm 4.1, recursing down to the coarsest level."""
     if l == len(H.levels) - 1:
         return coarse(f)
-    for _ in range(p.nu1):  # step 1: pre-smoothing
+    nu1, nu2 = p.nu1, p.nu2
+    if p.learned is not None and l < 2 and p.learned_sweeps > 0:
+        from .mlp import patch_has_gap
+
+        if not patch_has_gap(H.levels[l]):
+            nu1 = nu2 = p.learned_sweeps
+    for _ in range(nu1):  # step 1: pre-smoothing
         u = smooth(H, l, u, f, p)
     r = residual(H, l, u, f, p)  # step 2: residual, restriction, coarse solve
     fc = H.R[l] @ r
     ec = vcycle(H, l + 1, np.zeros(H.levels[l + 1].n), fc, p, coarse)
     u = u + H.P[l] @ ec  # step 3: coarse-grid correction
-    for _ in range(p.nu2):  # step 4: post-smoothing
+    for _ in range(nu2):  # step 4: post-smoothing
         u = smooth(H, l, u, f, p)
     return u
 

@@ -290,7 +290,10 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
   }
   const T* f = rhsA ? nullptr : B[l].f;
   const double delta = level_delta(b, l, p.c);
-  for (int k = 0; k < p.nu1; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s);
+  const bool learned = b->learned_active && l < 2 && b->mlpW && D.patchRow && p.learned_sweeps > 0;
+  const int nu1 = learned ? p.learned_sweeps : p.nu1;
+  const int nu2 = learned ? p.learned_sweeps : p.nu2;
+  for (int k = 0; k < nu1; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s);
   // residual r = b + E(f + N u) - delta u, restricted to the next level (where u := 0)
   launch_nsum<T>(b->dim, D.m, D.ilist, D.nbrI, B[l].u, f, (T)(1.0 / (D.h * D.h)), B[l].g, nullptr, lc, s);
   launch_ext<T, T>(b->dim, EXT_RESID, D.n, B[l].g, ext_addr(D), fracK_of<T>(D), rhsA, B[l].u, B[l].r, (T)delta,
@@ -299,7 +302,7 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
   launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
   vcycle_level<T>(b, l + 1, B, nullptr, p, s);
   launch_prolong<T>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<T>(D), B[l].u, lc, s);
-  for (int k = 0; k < p.nu2; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s);
+  for (int k = 0; k < nu2; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s);
 }
 
 // ||E f||_inf into scalar slot 1 (double)
@@ -377,7 +380,7 @@ static std::string graph_key(const char* tag, const cpm_params& p, const void* a
                              int extra) {
   std::ostringstream os;
   os << tag << '|' << p.c << '|' << p.nu1 << '|' << p.nu2 << '|' << p.omega << '|' << p.precision << '|'
-     << p.smoother << '|' << a << '|' << bb << '|' << c << '|' << extra;
+     << p.smoother << '|' << p.learned_sweeps << '|' << a << '|' << bb << '|' << c << '|' << extra;
   return os.str();
 }
 
@@ -425,6 +428,10 @@ cpm_status validate_params(const cpm_band b, const cpm_params* p) {
   if (!(p->c > 0.0) || p->nu1 < 0 || p->nu2 < 0 || p->nu1 + p->nu2 == 0 || !(p->omega > 0.0) ||
       !(p->omega <= 2.0)) {
     set_error("invalid solver parameters (need c > 0, nu1 + nu2 > 0, 0 < omega <= 2)");
+    return CPM_E_INVALID;
+  }
+  if (p->learned_sweeps < 0) {
+    set_error("learned_sweeps must be >= 0");
     return CPM_E_INVALID;
   }
   if (p->precision != CPM_F64 && p->precision != CPM_MIXED) {

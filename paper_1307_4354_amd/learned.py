@@ -1,14 +1,17 @@
 """Training driver of the learned smoother (argument marshalling around libcpm's kernels).
 
-Training pairs come from the plain solver itself: for each problem the converged solution
-u* is computed, then plain V-cycles are run from u = 0; before each cycle the iterate is
-taken through a V(nu1, 0) cycle (pre-smoothing and coarse-grid correction, no
-post-smoothing), which is exactly the state the post-smoother has to clean up.  For that
-state w the library writes the network features of every node (normalised residual patch
-and interpolation weights) and the scale s, and the target is the local error in the
-network's units, t_i = delta (u*_i - w_i) / s_i (clipped).  Forward, backward and the Adam
-update all run in the library's kernels; torch only holds device memory and draws the
-minibatch indices.
+Training pairs come from the plain solver itself: plain V-cycles are run from u = 0 on
+random problems; before each cycle the iterate is also taken through a V(nu1, 0) cycle
+(pre-smoothing and coarse-grid correction, no post-smoothing), the state w the
+post-smoother has to clean up.  For that state the library writes the network features of
+every node (normalised residual patch and interpolation weights) and the patch scale s.
+The target is the error removed by the plain method's nu2 post-smoothing sweeps from that
+state, in the network's units: t_i = delta (v_i - w_i) / s_i with v the full V(nu1, nu2)
+cycle's result.  (The total error u* - w is not a usable target: its smooth part is far
+larger than the local residual can explain, so the regression is dominated by it.)  One
+learned step therefore learns to do the work of several Jacobi sweeps.  Forward, backward
+and the Adam update all run in the library's kernels; torch only holds device memory and
+draws the minibatch indices.
 """
 from __future__ import annotations
 
@@ -60,7 +63,7 @@ class Pairs:
     T: object  # torch float32 (N)
 
 
-def generate_pairs(problems: Sequence[Tuple[object, float, int]], cycles: int = 4, clip: float = 4.0,
+def generate_pairs(problems: Sequence[Tuple[object, float, int]], cycles: int = 4, clip: float = 16.0,
                    nu1: int = 3, omega: float = 2.0 / 3.0) -> Pairs:
     """problems: (workloads.Problem, h0, levels).  Returns features / targets of the
     finest level for every node with a non-zero residual patch."""
@@ -76,8 +79,6 @@ def generate_pairs(problems: Sequence[Tuple[object, float, int]], cycles: int = 
         pre = cpm.make_params(c=prob.c, nu1=nu1, nu2=0, omega=omega)
         nbytes = cpm.cpm_workspace_size(band, p)
         work = torch.empty(max(nbytes, 16 * n), dtype=torch.uint8, device="cuda")
-        ustar = torch.zeros_like(f)
-        cpm.cpm_solve(band, p, f, ustar, work, nbytes, rtol=1e-12, max_cycles=80)
         delta = prob.c + 2.0 * band.dim / band.h(0) ** 2
         u = torch.zeros_like(f)
         X = torch.empty((n, N_IN), dtype=torch.int16, device="cuda")
@@ -86,11 +87,11 @@ def generate_pairs(problems: Sequence[Tuple[object, float, int]], cycles: int = 
             w = u.clone()
             cpm.cpm_vcycle(band, pre, f, w, work, nbytes)
             cpm.cpm_smoother_features(band, 0, prob.c, f, w, X, sc, work)
+            cpm.cpm_vcycle(band, p, f, u, work, nbytes)  # same pre-state, with post-smoothing
             keep = sc > 0
-            t = (delta * (ustar - w) / sc.double().clamp_min(1e-300)).clamp(-clip, clip).float()
+            t = (delta * (u - w) / sc.double().clamp_min(1e-300)).clamp(-clip, clip).float()
             Xs.append(X[keep].clone())
             Ts.append(t[keep].clone())
-            cpm.cpm_vcycle(band, p, f, u, work, nbytes)
         band.free()
     return Pairs(torch.cat(Xs), torch.cat(Ts))
 
