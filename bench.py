@@ -199,15 +199,23 @@ def run_learned(args):
         fd = torch.as_tensor(prob.f(cp)).to("cuda")
         _, plain = _solve(cpm, torch, band, cpm.make_params(), fd)
         res_e = {"n": band.n(0), "plain_f64_V33": plain}
-        for k in (1, 2):
-            # same sweep count on the fine levels with Jacobi, for the per-sweep comparison
-            _, pk = _solve(cpm, torch, band, cpm.make_params(nu1=k, nu2=k), fd)
-            # fall back to Jacobi when a cycle contracts worse than plain V(3,3) ever did
-            cpm.cpm_set_smoother_weights(band, res.w_bits, plain["worst_cycle_contraction"])
+        # the undamped plain cycle, the step the network is trained to reproduce
+        _, res_e["plain_f64_V33_omega1_for_reference"] = _solve(cpm, torch, band, cpm.make_params(omega=1.0), fd)
+        # fall back to Jacobi when a cycle contracts worse than plain V(3,3) ever did
+        cpm.cpm_set_smoother_weights(band, res.w_bits, plain["worst_cycle_contraction"])
+        p0 = cpm.make_params()
+        nb = cpm.cpm_workspace_size(band, p0)
+        work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        ut = torch.zeros_like(fd)
+        res_e["level0_us"] = {"jacobi_ext_smooth": cpm.cpm_time_kernel(band, p0, 0, 0, 50, fd, ut, work, nb),
+                              "learned_update": cpm.cpm_time_kernel(band, p0, 4, 0, 50, fd, ut, work, nb),
+                              "neighbour_sum": cpm.cpm_time_kernel(band, p0, 1, 0, 50, fd, ut, work, nb)}
+        del work, ut
+        for k in (0, 1, 2):
             _, lk = _solve(cpm, torch, band, cpm.make_params(smoother=cpm.CPM_SMOOTH_LEARNED, learned_sweeps=k), fd)
-            res_e["learned_%d_sweeps" % k] = lk
-            res_e["speedup_learned_%d_over_plain_V33" % k] = plain["seconds"] / lk["seconds"]
-            res_e["plain_V%d%d_for_reference" % (k, k)] = pk
+            tag = "learned_V33" if k == 0 else "learned_%d_sweeps" % k
+            res_e[tag] = lk
+            res_e["speedup_%s_over_plain_V33" % tag] = plain["seconds"] / lk["seconds"]
         out[name] = res_e
         band.free()
     print(json.dumps(out), flush=True)

@@ -180,7 +180,8 @@ cpm_status cpm_run_cycles(cpm_band band, const cpm_params* params, const double*
  * with HIP events on the band's stream over `reps` back-to-back launches: which = 0 the
  * extension pass fused with Jacobi smoothing (the dominant kernel), 1 the neighbour-sum
  * pass, 2 restriction into `level` (level >= 1), 3 prolongation from level+1 into `level`
- * (level < levels-1).  Level 0 runs on f and u, other levels on workspace vectors; the
+ * (level < levels-1), 4 the fused learned-smoother update from a fixed residual (level < 2,
+ * weights set, CPM_E_INVALID otherwise).  Level 0 runs on f and u, other levels on workspace vectors; the
  * values left in u are those of repeated smoothing.  Synchronous. */
 cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, int level, int reps,
                            const double* f, double* u, void* work, size_t work_bytes, double* avg_us,

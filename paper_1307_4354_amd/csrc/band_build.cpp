@@ -460,8 +460,7 @@ cpm_status build_patches(HostLevel& Lv, int level, std::string& err) {
   Lv.patchMask.assign((size_t)n, 0u);
   bool gap = false;
 #pragma omp parallel for reduction(|| : gap)
-  for (int64_t k = 0; k < n; ++k) {
-    const int32_t i = Lv.perm[(size_t)k];
+  for (int64_t i = 0; i < n; ++i) {  // band order: the network visits nodes as stored
     const int32_t* m = &Lv.idx[(size_t)(i * dim)];
     uint32_t mask = 0;
     for (int r = 0; r < rows; ++r) {
@@ -480,9 +479,9 @@ cpm_status build_patches(HostLevel& Lv, int level, std::string& err) {
         }
         mask |= 1u << ((dx + 1) + 3 * r);
       }
-      Lv.patchRow[(size_t)(r * n + k)] = ref;
+      Lv.patchRow[(size_t)(r * n + i)] = ref;
     }
-    Lv.patchMask[(size_t)k] = mask;
+    Lv.patchMask[(size_t)i] = mask;
   }
   // A row whose present nodes are not consecutive band entries cannot be addressed by one
   // reference index; the learned smoother is then not used on this level (Jacobi instead).

@@ -559,13 +559,12 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     std::vector<int32_t>().swap(H.gidx);
     std::vector<int32_t>().swap(H.blkG);
     std::vector<int32_t>().swap(H.lorg);
-    if (band_order) {
-      if (st == CPM_OK) st = upload(&D.packedB, H.packedB);
-      if (st == CPM_OK) st = upload_f32(&D.fracE32, H.fracE);
-    }
-    if (band_order || l == b->L - 1) {
-      if (st == CPM_OK) st = upload(&D.fracE, H.fracE);
-    }
+    // band-order fractions: band-order extension, the learned smoother's weights features,
+    // and the coarsest level's matrix assembly
+    const bool learned_level = D.patchRow != nullptr;
+    if (band_order && st == CPM_OK) st = upload(&D.packedB, H.packedB);
+    if ((band_order || learned_level) && st == CPM_OK) st = upload_f32(&D.fracE32, H.fracE);
+    if ((band_order || learned_level || l == b->L - 1) && st == CPM_OK) st = upload(&D.fracE, H.fracE);
     if (l == b->L - 1) {
       // band-order addressing of the coarsest level, used to assemble its dense matrix
       if (st == CPM_OK) st = upload(&D.runE, H.runE);
@@ -895,7 +894,7 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
                            const double* f, double* u, void* work, size_t work_bytes, double* avg_us,
                            void* stream) {
   if (!band || !f || !u || !work || !avg_us || reps < 1 || level < 0 || level >= band->L || which < 0 ||
-      which > 3) {
+      which > 4) {
     set_error("cpm_time_kernel: invalid argument");
     return CPM_E_INVALID;
   }
@@ -907,6 +906,10 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
   }
   if ((which == 2 && level == 0) || (which == 3 && level == band->L - 1)) {
     set_error("cpm_time_kernel: no such transfer on this level");
+    return CPM_E_INVALID;
+  }
+  if (which == 4 && (level > 1 || !band->mlpW || !band->dev[(size_t)level].patchRow)) {
+    set_error("cpm_time_kernel: no learned smoother on this level (weights unset or level >= 2)");
     return CPM_E_INVALID;
   }
   if ((st = enter(band, stream)) != CPM_OK) return st;
@@ -928,6 +931,9 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
       launch_fill<T>(D.n, B[level].f, (T)1.0, s);
     }
     launch_nsum<T>(band->dim, D.m, D.ilist, D.nbrI, uu, ff, (T)(1.0 / (D.h * D.h)), B[level].g, nullptr, lc, s);
+    if (which == 4)  // residual of the current iterate, read by every timed launch
+      launch_ext<T, T>(band->dim, EXT_RESID, D.n, B[level].g, ext_addr(D), fracK_of<T>(D), (const T*)nullptr, uu,
+                       B[level].r, (T)delta, (T)0, nullptr, ext_cfg(D), s);
     for (int pass = 0; pass < 2; ++pass) {  // pass 0 warms up
       const int k = pass == 0 ? 1 : reps;
       if (pass == 1) (void)hipEventRecord(e0, s);
@@ -941,8 +947,10 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
           const DevLevel& F = band->dev[(size_t)(level - 1)];
           (void)F;
           launch_restrict<T>(band->dim, D.n, B[level - 1].g, D.runR, fracR_of<T>(D), B[level].r, nullptr, lc, s);
-        } else {
+        } else if (which == 3) {
           launch_prolong<T>(band->dim, D.n, B[level + 1].g, D.runP, fracP_of<T>(D), B[level].r, lc, s);
+        } else {
+          launch_learned<T>(band, level, B[level].r, uu, params->c, s);
         }
       }
       if (pass == 1) (void)hipEventRecord(e1, s);

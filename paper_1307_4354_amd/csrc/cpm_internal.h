@@ -47,8 +47,8 @@ struct HostLevel {
   // +-x neighbours are j -+ 1, the others stored as -y,+y(,-z,+z) slot-major
   std::vector<int32_t> ilist;   // m
   std::vector<int32_t> nbrI;    // (2*dim-2) * m
-  // learned smoother (two finest levels): 3^dim grid patch of every node, in stencil
-  // order; row (dy, dz) holds the band index of (x - 1, y + dy, z + dz) (virtual when that
+  // learned smoother (two finest levels): 3^dim grid patch of every node, in band order;
+  // row (dy, dz) holds the band index of (x - 1, y + dy, z + dz) (virtual when that
   // node is absent), mask bit (dx+1) + 3 (dy+1) + 9 (dz+1) marks nodes that are present
   std::vector<int32_t> patchRow;  // 3^(dim-1) * n
   std::vector<uint32_t> patchMask;  // n

@@ -103,30 +103,39 @@ __device__ float mlp_wave(const uint16_t* X, int valid, const uint16_t* __restri
   return y;
 }
 
-// Features of one node (see oracle/mlp.py): residual patch / s, then the 1-D weights.
-// Writes 64 bf16 into xrow; returns s.
-template <int D, typename T>
+// Features of one node: residual patch / s, then the 1-D weights, then zeros.  Writes
+// NOUT bf16 into xrow; returns s.
+template <int D, typename T, int NOUT = kIn>
 __device__ __forceinline__ float node_features(int64_t k, int64_t n, const T* __restrict__ r,
                                                const int32_t* __restrict__ prow, const uint32_t* __restrict__ pmask,
                                                const T* __restrict__ frac, uint16_t* xrow) {
   constexpr int R = D == 2 ? 3 : 9;
   constexpr int P = 3 * R;
   const uint32_t mask = pmask[k];
+  // every load is issued unconditionally (the index clamped into the array, the value of an
+  // absent node discarded below), so the 3^D loads are in flight together
   T patch[P];
-  T s = T(0);
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int32_t base = prow[q * n + k];
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
-      const int bit = dx + 3 * q;
-      const T v = (mask >> bit) & 1u ? r[base + dx] : T(0);
-      patch[bit] = v;
-      s = fmax(s, (T)fabs((double)v));
+      int64_t a = (int64_t)base + dx;
+      a = a < 0 ? 0 : (a >= n ? n - 1 : a);
+      patch[dx + 3 * q] = r[a];
     }
   }
+  T s = T(0);
 #pragma unroll
-  for (int q = 0; q < P; ++q) xrow[q] = s > T(0) ? f2bf((float)(patch[q] / s)) : (uint16_t)0;
+  for (int bit = 0; bit < P; ++bit) {
+    patch[bit] = (mask >> bit) & 1u ? patch[bit] : T(0);
+    s = fmax(s, (T)fabs((double)patch[bit]));
+  }
+  // patch / s to bfloat16: formed in float32 as patch * (1 / s); it differs from the
+  // correctly rounded quotient by at most 2 float ulps, below the bf16 rounding step
+  const float inv_s = s > T(0) ? 1.0f / (float)s : 0.0f;
+#pragma unroll
+  for (int q = 0; q < P; ++q) xrow[q] = f2bf((float)patch[q] * inv_s);
   T w[4];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
@@ -135,21 +144,19 @@ __device__ __forceinline__ float node_features(int64_t k, int64_t n, const T* __
     for (int j = 0; j < 4; ++j) xrow[P + 4 * a + j] = f2bf((float)w[j]);
   }
 #pragma unroll
-  for (int q = P + 4 * D; q < kIn; ++q) xrow[q] = 0;
+  for (int q = P + 4 * D; q < NOUT; ++q) xrow[q] = 0;
   return (float)s;
 }
 
-// Features of every node of a level, rows in band order (row perm[k] for stencil slot k).
+// Features of every node of a level, in band order (patch tables and band-order fractions).
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_features(int64_t n, const T* __restrict__ r, const int32_t* __restrict__ perm,
-                                                  const int32_t* __restrict__ prow, const uint32_t* __restrict__ pmask,
-                                                  const T* __restrict__ frac, uint16_t* __restrict__ X,
-                                                  float* __restrict__ scale) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k >= n) return;
+__global__ __launch_bounds__(256) void k_features(int64_t n, const T* __restrict__ r, const int32_t* __restrict__ prow,
+                                                  const uint32_t* __restrict__ pmask, const T* __restrict__ frac,
+                                                  uint16_t* __restrict__ X, float* __restrict__ scale) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
   uint16_t xr[kIn];
-  const float s = node_features<D, T>(k, n, r, prow, pmask, frac, xr);
-  const int32_t i = perm[k];
+  const float s = node_features<D, T>(i, n, r, prow, pmask, frac, xr);
   uint64_t* dst = (uint64_t*)(X + (int64_t)i * kIn);
 #pragma unroll
   for (int q = 0; q < kIn / 4; ++q)
@@ -158,31 +165,95 @@ __global__ __launch_bounds__(256) void k_features(int64_t n, const T* __restrict
   scale[i] = s;
 }
 
-// Fused learned sweep: features of 64 nodes per wavefront into LDS, network on the matrix
-// cores, u_i += (s / delta) y.  r is the residual of the current iterate (read only).
+// Fused learned sweep, one node per lane and 64 consecutive band nodes per wavefront (their
+// patch rows overlap, so the residual gathers coalesce).
+// Layer 1 is computed transposed, H^T (hidden x node) = W1 * X^T, so that after the matrix
+// cores a lane holds 16 hidden units of one node and layer 2 is a per-lane sum plus one
+// exchange with lane ^ 32.  Operand layouts of v_mfma_f32_32x32x8_bf16 (lane l, half = l/32,
+// col = l%32): A = W1 rows (hidden unit col, k = 8 ks + 4 half .. + 3) read from global
+// memory; B = X^T columns (node col, same k range).  A lane computes the whole feature row of
+// its own node; the k-chunk its partner lane needs for the other node block arrives through
+// one xor-32 shuffle per k-step.  Only the k-steps that hold features are issued (5 of 8 in
+// 3-D); the last slot of the last step, a zero of the network's input, carries a constant 1
+// whose A entry is b1, so the bias is added inside the float32 accumulation.  The used
+// columns of W1 (with b1) and w2 are staged once per workgroup in LDS.
 template <int D, typename T>
-__global__ __launch_bounds__(256) void k_learned(int64_t n, const T* __restrict__ r, const int32_t* __restrict__ perm,
-                                                 const int32_t* __restrict__ prow, const uint32_t* __restrict__ pmask,
-                                                 const T* __restrict__ frac, const uint16_t* __restrict__ W, T inv_delta,
-                                                 T* __restrict__ u) {
-  __shared__ uint16_t xs[4][64 * kIn];
-  __shared__ float part[4][64 * kPartStride];
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t k0 = (blockIdx.x * 4 + wave) * (int64_t)64;
-  const int64_t k = k0 + lane;
-  float s = 0.0f;
-  if (k < n) {
-    s = node_features<D, T>(k, n, r, prow, pmask, frac, &xs[wave][lane * kIn]);
-  } else {
-    for (int q = 0; q < kIn; ++q) xs[wave][lane * kIn + q] = 0;
+__global__ __launch_bounds__(256) void k_learned(int64_t n, const T* __restrict__ r, const int32_t* __restrict__ prow,
+                                                 const uint32_t* __restrict__ pmask, const T* __restrict__ frac,
+                                                 const uint16_t* __restrict__ W, T inv_delta, T* __restrict__ u) {
+  constexpr int NF = (D == 2 ? 9 : 27) + 4 * D;  // features in use
+  constexpr int KS = (NF + 1 + 7) / 8;            // k-steps, with room for the constant slot
+  constexpr int KB = 8 * KS - 1;                  // slot of the constant 1 (a zero input)
+  static_assert(KB >= NF && 8 * KS <= kIn, "feature layout");
+  constexpr int WS = 8 * KS + 4;  // LDS row of W1 in bf16, padded against bank conflicts
+  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  __shared__ uint16_t w1s[64 * WS];  // the 8 KS used columns of W1, b1 in column KB
+  __shared__ float w2s[64];
+  for (int e = threadIdx.x; e < 64 * 2 * KS; e += blockDim.x) {
+    const int row = e / (2 * KS), c = 4 * (e % (2 * KS));
+    bf16x4 q = *(const bf16x4*)(W + row * kIn + c);
+    if (c + 3 == KB) q[3] = (short)W[kB1 + row];
+    *(bf16x4*)&w1s[row * WS + c] = q;
   }
+  if (threadIdx.x < 64) w2s[threadIdx.x] = bf2f(W[kW2 + threadIdx.x]);
   __syncthreads();
-  int64_t rem = n - k0;
-  const int valid = rem <= 0 ? 0 : (rem >= 64 ? 64 : (int)rem);
-  const float y = mlp_wave(xs[wave], valid, W, part[wave], nullptr);
+  const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
+  const int64_t k = (blockIdx.x * 4 + (threadIdx.x >> 6)) * (int64_t)64 + lane;
+  uint32_t xw[4 * KS];  // own feature row, bf16 pairs (slot 2j in the low half of word j)
+  float s = 0.0f;
+  {
+    uint16_t xs[8 * KS];
+    if (k < n) {
+      s = node_features<D, T, 8 * KS>(k, n, r, prow, pmask, frac, xs);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8 * KS; ++q) xs[q] = 0;
+    }
+    xs[KB] = 0x3F80;  // 1.0
+#pragma unroll
+    for (int j = 0; j < 4 * KS; ++j) xw[j] = (uint32_t)xs[2 * j] | ((uint32_t)xs[2 * j + 1] << 16);
+  }
+  // own chunk (k = 8 ks + 4 half) and the partner's chunk for the other node block
+  uint32_t own[2 * KS], got[2 * KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const uint32_t lo = xw[4 * ks + e], hi = xw[4 * ks + 2 + e];
+      own[2 * ks + e] = half ? hi : lo;
+      got[2 * ks + e] = __shfl_xor(half ? lo : hi, 32);
+    }
+  }
+  float y = 0.0f;
+#pragma unroll
+  for (int nb = 0; nb < 2; ++nb) {
+    const bool mine = nb == half;  // this lane's own node is column col of node block nb
+    f32x16 acc[2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[mb][v] = 0.0f;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const u32x2 bw = {mine ? own[2 * ks] : got[2 * ks], mine ? own[2 * ks + 1] : got[2 * ks + 1]};
+      const bf16x4 bv = __builtin_bit_cast(bf16x4, bw);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const bf16x4 av = *(const bf16x4*)&w1s[(mb * 32 + col) * WS + ks * 8 + half * 4];
+        acc[mb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc[mb], 0, 0, 0);
+      }
+    }
+    float p = 0.0f;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) p += fmaxf(acc[mb][v], 0.0f) * w2s[mb * 32 + 8 * (v >> 2) + 4 * half + (v & 3)];
+    p += __shfl_xor(p, 32);
+    if (mine) y = p;
+  }
   if (k < n) {
-    const int32_t i = perm[k];
-    u[i] += (T)s * inv_delta * (T)y;
+    y += bf2f(W[kB2]);
+    u[k] += (T)s * inv_delta * (T)y;
   }
 }
 
@@ -299,31 +370,47 @@ __global__ void k_adam(int count, float* __restrict__ w, float* __restrict__ m1,
   wb[i] = f2bf(wn);
 }
 
+// fractions in the extension's processing order, and in band order
 template <typename T>
 const T* frac_k(const DevLevel& D);
 template <>
-const double* frac_k<double>(const DevLevel& D) { return D.fracK; }
+const double* frac_k<double>(const DevLevel& D) { return D.band_order ? D.fracE : D.fracK; }
 template <>
-const float* frac_k<float>(const DevLevel& D) { return D.fracK32; }
+const float* frac_k<float>(const DevLevel& D) { return D.band_order ? D.fracE32 : D.fracK32; }
+template <typename T>
+const T* frac_b(const DevLevel& D);
+template <>
+const double* frac_b<double>(const DevLevel& D) { return D.fracE; }
+template <>
+const float* frac_b<float>(const DevLevel& D) { return D.fracE32; }
 
 }  // namespace
+
+// The fused network update u += (s / delta) y on level l from the residual r.
+template <typename T>
+void launch_learned(const cpm_band b, int l, const T* r, T* u, double c, hipStream_t s) {
+  const DevLevel& D = b->dev[(size_t)l];
+  const double delta = level_delta(b, l, c);
+  const unsigned gr = (unsigned)((D.n + 255) / 256);  // 64 nodes per wavefront, 4 per block
+  if (b->dim == 2)
+    k_learned<2, T><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchMask, frac_b<T>(D), b->mlpW, (T)(1.0 / delta), u);
+  else
+    k_learned<3, T><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchMask, frac_b<T>(D), b->mlpW, (T)(1.0 / delta), u);
+}
 
 // r = b + E g - delta u into B.r, then the fused network update of u.
 template <typename T>
 void learned_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g, T* r, double c, hipStream_t s) {
   (void)f;
   const DevLevel& D = b->dev[(size_t)l];
-  const LaunchCfg lc = band_cfg(b, D.n);
   const double delta = level_delta(b, l, c);
-  launch_ext<T, T>(b->dim, EXT_RESID, D.n, g, ExtAddr{D.perm, D.packed, D.origin}, frac_k<T>(D), rhsA, u, r,
-                   (T)delta, (T)0, nullptr, lc, s);
-  const unsigned gr = (unsigned)((D.n + 255) / 256);
-  if (b->dim == 2)
-    k_learned<2, T><<<gr, 256, 0, s>>>(D.n, r, D.perm, D.patchRow, D.patchMask, frac_k<T>(D), b->mlpW, (T)(1.0 / delta), u);
-  else
-    k_learned<3, T><<<gr, 256, 0, s>>>(D.n, r, D.perm, D.patchRow, D.patchMask, frac_k<T>(D), b->mlpW, (T)(1.0 / delta), u);
+  launch_ext<T, T>(b->dim, EXT_RESID, D.n, g, ext_addr(D), frac_k<T>(D), rhsA, u, r, (T)delta, (T)0, nullptr,
+                   ext_cfg(D), s);
+  launch_learned<T>(b, l, r, u, c, s);
 }
 
+template void launch_learned<double>(const cpm_band, int, const double*, double*, double, hipStream_t);
+template void launch_learned<float>(const cpm_band, int, const float*, float*, double, hipStream_t);
 template void learned_sweep<double>(const cpm_band, int, double*, const double*, const double*, double*, double*,
                                     double, hipStream_t);
 template void learned_sweep<float>(const cpm_band, int, float*, const float*, const float*, float*, float*, double,
@@ -416,9 +503,9 @@ cpm_status cpm_smoother_features(cpm_band band, int level, double c, const doubl
                              const_cast<double*>(u), r, level_delta(band, level, c), 0.0, nullptr, lc, s);
   const unsigned gr = (unsigned)((D.n + 255) / 256);
   if (band->dim == 2)
-    k_features<2, double><<<gr, 256, 0, s>>>(D.n, r, D.perm, D.patchRow, D.patchMask, D.fracK, X, scale);
+    k_features<2, double><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchMask, D.fracE, X, scale);
   else
-    k_features<3, double><<<gr, 256, 0, s>>>(D.n, r, D.perm, D.patchRow, D.patchMask, D.fracK, X, scale);
+    k_features<3, double><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchMask, D.fracE, X, scale);
   if ((st = check_launch("cpm_smoother_features")) != CPM_OK) return st;
   return leave(band, stream);
 }

@@ -1,17 +1,18 @@
 """Training driver of the learned smoother (argument marshalling around libcpm's kernels).
 
 Training pairs come from the plain solver itself: plain V-cycles are run from u = 0 on
-random problems; before each cycle the iterate is also taken through a V(nu1, 0) cycle
-(pre-smoothing and coarse-grid correction, no post-smoothing), the state w the
-post-smoother has to clean up.  For that state the library writes the network features of
-every node (normalised residual patch and interpolation weights) and the patch scale s.
-The target is the error removed by the plain method's nu2 post-smoothing sweeps from that
-state, in the network's units: t_i = delta (v_i - w_i) / s_i with v the full V(nu1, nu2)
-cycle's result.  (The total error u* - w is not a usable target: its smooth part is far
-larger than the local residual can explain, so the regression is dominated by it.)  One
-learned step therefore learns to do the work of several Jacobi sweeps.  Forward, backward
-and the Adam update all run in the library's kernels; torch only holds device memory and
-draws the minibatch indices.
+random problems; for every iterate the solver reaches (the start of each cycle, and the
+state after pre-smoothing and coarse-grid correction, which is what the post-smoother
+sees) the library writes the network features of every node (normalised residual patch
+and interpolation weights) and the patch scale s.  The target is the correction of one
+undamped Ruuth-Merriman step from that state, in the network's units:
+t_i = r_i / s_i with r = E f - A w (the step moves w_i by r_i / delta).  It is a function
+of the features the network sees, so the regression is well posed and its minimiser is
+a stable smoother.  Targets that ask one local step to do the work of several sweeps, or
+to predict the total error u* - w, need information outside the 3^d residual patch; the
+networks fitted to them gave V-cycles that diverge.  Forward, backward and the Adam update
+all run in the library's kernels; torch only holds device memory and draws the minibatch
+indices.
 """
 from __future__ import annotations
 
@@ -66,7 +67,8 @@ class Pairs:
 def generate_pairs(problems: Sequence[Tuple[object, float, int]], cycles: int = 4, clip: float = 16.0,
                    nu1: int = 3, omega: float = 2.0 / 3.0) -> Pairs:
     """problems: (workloads.Problem, h0, levels).  Returns features / targets of the
-    finest level for every node with a non-zero residual patch."""
+    finest level for every node with a non-zero residual patch, from the iterates of
+    ``cycles`` plain V(nu1, nu1) cycles (two states per cycle)."""
     torch = _torch()
     Xs, Ts = [], []
     for prob, h0, levels in problems:
@@ -79,19 +81,27 @@ def generate_pairs(problems: Sequence[Tuple[object, float, int]], cycles: int = 
         pre = cpm.make_params(c=prob.c, nu1=nu1, nu2=0, omega=omega)
         nbytes = cpm.cpm_workspace_size(band, p)
         work = torch.empty(max(nbytes, 16 * n), dtype=torch.uint8, device="cuda")
-        delta = prob.c + 2.0 * band.dim / band.h(0) ** 2
+        ef = torch.empty_like(f)
+        cpm.cpm_extend(band, 0, f, ef)
+        aw = torch.empty_like(f)
         u = torch.zeros_like(f)
         X = torch.empty((n, N_IN), dtype=torch.int16, device="cuda")
         sc = torch.empty(n, dtype=torch.float32, device="cuda")
-        for _ in range(cycles):
-            w = u.clone()
-            cpm.cpm_vcycle(band, pre, f, w, work, nbytes)
+
+        def add(w):
             cpm.cpm_smoother_features(band, 0, prob.c, f, w, X, sc, work)
-            cpm.cpm_vcycle(band, p, f, u, work, nbytes)  # same pre-state, with post-smoothing
+            cpm.cpm_apply(band, 0, prob.c, w, aw, work)
             keep = sc > 0
-            t = (delta * (u - w) / sc.double().clamp_min(1e-300)).clamp(-clip, clip).float()
+            t = ((ef - aw) / sc.double().clamp_min(1e-300)).clamp(-clip, clip).float()
             Xs.append(X[keep].clone())
             Ts.append(t[keep].clone())
+
+        for _ in range(cycles):
+            add(u)
+            w = u.clone()
+            cpm.cpm_vcycle(band, pre, f, w, work, nbytes)
+            add(w)
+            cpm.cpm_vcycle(band, p, f, u, work, nbytes)
         band.free()
     return Pairs(torch.cat(Xs), torch.cat(Ts))
 

@@ -161,16 +161,38 @@ def test_fallback_trips_for_bad_network():
     assert st.relres < 1e-10
 
 
-def test_training_reduces_loss():
-    log("training smoke")
+def test_training_reduces_loss_and_beats_damped_jacobi():
+    """Train on pairs from plain cycles (spheres and a torus at h = 1/32), then solve a
+    sphere problem that was not in the training set: the trained smoother must contract
+    faster per cycle than the plain damped Jacobi cycle, without tripping the fallback."""
+    log("training + gain")
+    import paper_1307_4354_amd as cpm
     from paper_1307_4354_amd import learned
 
-    torch_cuda()
+    torch = torch_cuda()
     probs = [(W.sphere_modes(0.9, 1), 1 / 32, 4), (W.torus_modes(1.0, 0.4, 2), 1 / 32, 3)]
     pairs = learned.generate_pairs(probs, cycles=2)
     assert pairs.X.shape[0] > 100000
-    res = learned.train(pairs, steps=200, batch=16384, lr=2e-3, log_every=50)
+    res = learned.train(pairs, steps=300, batch=16384, lr=2e-3, log_every=50)
     l0 = learned.evaluate_loss(pairs, learned._bf16_bits(learned.jacobi_init(2.0 / 3.0, 3, 0)))
     l1 = learned.evaluate_loss(pairs, res.w_bits)
     assert np.all(np.isfinite(res.losses))
-    assert l1 < l0
+    assert l1 < 0.5 * l0
+    cfg = W.config_sphere(32, 4)
+    band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+    _, cp = band.export(0)
+    fd = dev(cfg.problem.f(cp))
+    p = cpm.make_params()
+    work, nbytes = workspace(band, p)
+    u0 = torch.zeros_like(fd)
+    plain = cpm.cpm_solve(band, p, fd, u0, work, nbytes, rtol=1e-10, max_cycles=80)
+    hist = list(plain.relres_history[:plain.cycles])
+    rho = max(b / a for a, b in zip(hist, hist[1:]))
+    cpm.cpm_set_smoother_weights(band, res.w_bits, rho)
+    u1 = torch.zeros_like(fd)
+    lst = cpm.cpm_solve(band, cpm.make_params(smoother=cpm.CPM_SMOOTH_LEARNED), fd, u1, work, nbytes,
+                        rtol=1e-10, max_cycles=80)
+    log("plain %d cycles, learned %d cycles, fallback %d" % (plain.cycles, lst.cycles, lst.fallback_cycle))
+    assert lst.fallback_cycle < 0
+    assert lst.relres < 1e-10
+    assert lst.cycles < plain.cycles
