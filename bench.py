@@ -221,6 +221,27 @@ def run_learned(args):
     print(json.dumps(out), flush=True)
 
 
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic_ext_smooth_sphere64.json")
+
+
+def _measured_traffic(kernel: str, grid: int):
+    """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when there is none, it is for another kernel or launch shape, or the
+    kernel's sources have changed since the counters were taken."""
+    from paper_1307_4354_amd import prof_summary
+
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel or t.get("grid") != grid:
+        return None
+    if t.get("source_sha256") != prof_summary.sources_sha256(t.get("sources", [])):
+        return None
+    return int(round(t["traffic_bytes"]))
+
+
 def cpu_baseline(cfg, cycles: int):
     """The oracle as it stands (scipy CSR, one BLAS thread) on a bounded sample: `cycles`
     V-cycles of the same hierarchy (setup not timed)."""
@@ -325,10 +346,14 @@ def main():
     avg_us = cpm.cpm_time_kernel(band, p64, 0, 0, args.kernel_reps, fd, ud, work, nb64)
     alg_bytes = 48.0 * n0
     achieved = alg_bytes / (avg_us * 1e-6) / 1e9
+    lds0, blk0 = tuning[0][0], (256 if tuning[0][0] else tuning[0][1])
+    kname = ("k_ext_lds" if lds0 else "k_ext") + "<3, double, double, 0>"
+    grid0 = -(-n0 // blk0) * blk0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": ("k_ext_lds" if tuning[0][0] else "k_ext") + "<3,double,EXT_SMOOTH> level 0", "avg_launch_us": round(avg_us, 3),
-                "alg_bytes_per_launch": int(alg_bytes)}
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": _measured_traffic(kname, grid0),
+                "kernel": kname + " (extension + Jacobi smoothing, level 0)", "grid": grid0,
+                "avg_launch_us": round(avg_us, 3), "alg_bytes_per_launch": int(alg_bytes)}
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
@@ -358,7 +383,8 @@ def main():
         "time_to_1e-10": tt,
         "band_build_s": t_build,
         "autotune_s": t_tune,
-        "tuning": [{"level": l, "lds": t[0], "ext_block": t[1], "nsum_block": t[2]} for l, t in enumerate(tuning)],
+        "tuning": [{"level": l, "lds": t[0], "ext_block": t[1], "nsum_block": t[2], "fused_sweep": t[3],
+                    "sweep_block": t[4]} for l, t in enumerate(tuning)],
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -181,7 +181,8 @@ cpm_status cpm_run_cycles(cpm_band band, const cpm_params* params, const double*
  * extension pass fused with Jacobi smoothing (the dominant kernel), 1 the neighbour-sum
  * pass, 2 restriction into `level` (level >= 1), 3 prolongation from level+1 into `level`
  * (level < levels-1), 4 the fused learned-smoother update from a fixed residual (level < 2,
- * weights set, CPM_E_INVALID otherwise).  Level 0 runs on f and u, other levels on workspace vectors; the
+ * weights set, CPM_E_INVALID otherwise), 5 the fused one-pass sweep (levels that have its
+ * addressing, CPM_E_INVALID otherwise).  Level 0 runs on f and u, other levels on workspace vectors; the
  * values left in u are those of repeated smoothing.  Synchronous. */
 cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, int level, int reps,
                            const double* f, double* u, void* work, size_t work_bytes, double* avg_us,
@@ -202,12 +203,17 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
 
 /* Autotuner: for every level, time the two passes of a smoothing sweep with each candidate
  * launch configuration on this band's addressing (extension: gathers with workgroups of
- * 128 / 256 / 512 lanes or LDS-staged; neighbour sum: 128 / 256 / 512 lanes) and keep the
- * fastest in the handle.  Allocates two temporary vectors; synchronous. */
+ * 128 / 256 / 512 lanes or LDS-staged; neighbour sum: 128 / 256 / 512 lanes), then the fused
+ * one-pass sweep (E f + (E N) u, 128 / 256 / 512 lanes; levels up to 2^21 nodes) against that
+ * pair, and keep the fastest in the handle.  The environment variable CPM_SWEEP=fused|split,
+ * read when the band is built, pins the sweep form instead.  Allocates two temporary
+ * vectors; synchronous. */
 cpm_status cpm_autotune(cpm_band band, void* stream);
 
-/* Launch configuration chosen for one level (after cpm_autotune, or the defaults). */
-cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_block, int* nsum_block);
+/* Launch configuration chosen for one level (after cpm_autotune, or the defaults); any
+ * output pointer may be NULL.  fused = 1 when the level sweeps with the fused pass. */
+cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_block, int* nsum_block, int* fused,
+                           int* sweep_block);
 
 /* ---- learned smoother ---------------------------------------------------------------
  * Network (per node): x = [r_patch / s (27 values: residual on the 3x3x3 grid patch

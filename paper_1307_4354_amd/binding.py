@@ -90,7 +90,8 @@ def _load():
         "cpm_solve_batched": (c_int, [c_int, POINTER(vp), POINTER(cpm_params), POINTER(vp), POINTER(vp), vp,
                                       c_size_t, c_double, c_int, POINTER(cpm_stats), vp]),
         "cpm_autotune": (c_int, [vp, vp]),
-        "cpm_band_tuning": (c_int, [vp, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
+        "cpm_band_tuning": (c_int, [vp, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int),
+                                    POINTER(c_int)]),
         "cpm_set_smoother_weights": (c_int, [vp, vp, c_double]),
         "cpm_mlp_forward": (c_int, [c_int64, vp, vp, vp, vp, vp]),
         "cpm_mlp_backward": (c_int, [c_int64, vp, vp, vp, vp, vp, vp, vp]),
@@ -316,7 +317,7 @@ def cpm_mlp_adam(step: int, lr: float, w_master, m1, m2, G, w_bf16, stream=None)
 
 
 def cpm_band_tuning(band: Band, level: int):
-    """(use_lds, ext_block, nsum_block) chosen for one level."""
-    a, b, c = c_int(), c_int(), c_int()
-    _check(_lib.cpm_band_tuning(band.handle, int(level), byref(a), byref(b), byref(c)))
-    return bool(a.value), b.value, c.value
+    """(use_lds, ext_block, nsum_block, fused, sweep_block) chosen for one level."""
+    a, b, c, d, e = c_int(), c_int(), c_int(), c_int(), c_int()
+    _check(_lib.cpm_band_tuning(band.handle, int(level), byref(a), byref(b), byref(c), byref(d), byref(e)))
+    return bool(a.value), b.value, c.value, bool(d.value), e.value

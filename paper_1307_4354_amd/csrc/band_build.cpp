@@ -389,16 +389,55 @@ cpm_status build_stencil_order(HostLevel& Lv, int level, std::string& err) {
   Lv.packed.assign((size_t)n, 0);
   Lv.fracK.assign((size_t)(dim * n), 0.0);
   Lv.origin.clear();
+  // cross rows of the widened stencil (fused sweep): first node of each row, which must be
+  // followed by the 3 other nodes of the row in consecutive band entries.  Only levels up to
+  // kFusedMaxNodes get them: the fused pass reads 2.5x the values of the extension, which pays
+  // where launches and load latency dominate, not on large levels.
+  const int SX = dim == 2 ? 2 : 16;
+  bool xok = n <= kFusedMaxNodes;
+  const int64_t nx = xok ? n : 0;
+  std::vector<int32_t> runX((size_t)SX * (size_t)nx, -1);
+#pragma omp parallel for reduction(&& : xok)
+  for (int64_t i = 0; i < nx; ++i) {
+    for (int s = 0; s < SX; ++s) {
+      int64_t yy, zz;
+      if (dim == 2) {
+        yy = s == 0 ? -1 : 4;
+        zz = 0;
+      } else if (s < 8) {
+        yy = s < 4 ? -1 : 4;
+        zz = s & 3;
+      } else {
+        yy = s & 3;
+        zz = s < 12 ? -1 : 4;
+      }
+      const int64_t x = bx[(size_t)i], y = by[(size_t)i] + yy, z = dim == 3 ? bz[(size_t)i] + zz : 0;
+      const int32_t j = lookup(Lv, x, y, z);
+      bool ok = j >= 0;
+      for (int a = 1; ok && a < 4; ++a) ok = lookup(Lv, x + a, y, z) == j + a;
+      if (!ok) xok = false;
+      runX[(size_t)(s * n + i)] = j;
+    }
+  }
+  Lv.fusedOK = xok;
+  Lv.originX.clear();
   int64_t g = -1;
   int32_t gx0 = 0, gy = 0, gz = 0;
-  std::vector<int32_t> org(S);
+  std::vector<int32_t> org(S), orgX(SX);
   for (int64_t k = 0; k < n; ++k) {
     const int32_t i = order[(size_t)k];
-    bool fresh = g < 0 || by[(size_t)i] != gy || bz[(size_t)i] != gz ||
-                 bx[(size_t)i] - gx0 >= (1 << kXoffBits);
+    const int32_t dx = bx[(size_t)i] - gx0;
+    bool fresh = g < 0 || by[(size_t)i] != gy || bz[(size_t)i] != gz || dx >= (1 << kXoffBits);
     if (!fresh) {
       for (int s = 0; s < S; ++s)
-        if (Lv.runE[(size_t)(s * n + i)] - (bx[(size_t)i] - gx0) != org[(size_t)s]) {
+        if (Lv.runE[(size_t)(s * n + i)] - dx != org[(size_t)s]) {
+          fresh = true;
+          break;
+        }
+    }
+    if (!fresh && xok) {
+      for (int s = 0; s < SX; ++s)
+        if (runX[(size_t)(s * n + i)] - dx != orgX[(size_t)s]) {
           fresh = true;
           break;
         }
@@ -412,6 +451,11 @@ cpm_status build_stencil_order(HostLevel& Lv, int level, std::string& err) {
         org[(size_t)s] = Lv.runE[(size_t)(s * n + i)];
         Lv.origin.push_back(org[(size_t)s]);
       }
+      if (xok)
+        for (int s = 0; s < SX; ++s) {
+          orgX[(size_t)s] = runX[(size_t)(s * n + i)];
+          Lv.originX.push_back(orgX[(size_t)s]);
+        }
     }
     if (g >= kMaxGroups) {
       std::ostringstream os;

@@ -47,6 +47,12 @@ LaunchCfg ext_cfg(const DevLevel& D) {
   return c;
 }
 
+LaunchCfg sweep_cfg(const DevLevel& D) {
+  LaunchCfg c;
+  c.block = D.sweep_block;
+  return c;
+}
+
 template <typename T>
 static T* dalloc(size_t count, cpm_status* st) {
   if (count == 0) return nullptr;
@@ -82,7 +88,7 @@ static void free_dev(cpm_band b) {
   for (auto& D : b->dev) {
     void* ps[] = {D.runE,  D.nbr,   D.fracE,  D.fracE32, D.runP,    D.fracP,  D.fracP32, D.runR,
                   D.fracR, D.fracR32, D.perm, D.packed, D.origin, D.fracK, D.fracK32, D.ilist, D.nbrI,
-                  D.patchRow, D.patchMask, D.packedB, D.packedL, D.blkE, D.gidx, D.blkG, D.lorg};
+                  D.patchRow, D.patchMask, D.packedB, D.packedL, D.blkE, D.gidx, D.blkG, D.lorg, D.originX};
     for (void* p : ps)
       if (p) (void)hipFree(p);
   }
@@ -188,9 +194,9 @@ size_t workspace_bytes(const cpm_band b, int precision) {
   for (int l = 0; l < b->L; ++l) {
     const size_t n = (size_t)b->dev[(size_t)l].n;
     if (precision == CPM_F64) {
-      tot += align_up(n * 8) * (l == 0 ? 2 : 4);
+      tot += align_up(n * 8) * (l == 0 ? 3 : 5);
     } else {
-      tot += align_up(n * 4) * 4;
+      tot += align_up(n * 4) * 5;
       if (l == 0) tot += align_up(n * 8);
     }
   }
@@ -212,11 +218,13 @@ void carve_levels(const cpm_band b, void* work, LevelBufs<T>* B, double** g64) {
       }
       B[l].g = carve<T>(p, n);
       B[l].r = carve<T>(p, n);
+      B[l].t = carve<T>(p, n);
     } else {
       B[l].u = carve<T>(p, n);
       B[l].f = carve<T>(p, n);
       B[l].g = carve<T>(p, n);
       B[l].r = carve<T>(p, n);
+      B[l].t = carve<T>(p, n);
       if (l == 0 && g64) *g64 = carve<double>(p, n);
     }
   }
@@ -263,20 +271,86 @@ const double* fracR_of<double>(const DevLevel& D) { return D.fracR; }
 template <>
 const float* fracR_of<float>(const DevLevel& D) { return D.fracR32; }
 
-// Damped Ruuth-Merriman Jacobi sweep: g = f + N u, u <- u + (w/delta)(b + E g - delta u)
+// stencil-order fractions (the fused sweep always visits nodes in stencil order)
+template <typename T>
+static const T* fracS_of(const DevLevel& D);
+template <>
+const double* fracS_of<double>(const DevLevel& D) { return D.fracK; }
+template <>
+const float* fracS_of<float>(const DevLevel& D) { return D.fracK32; }
+
+// Damped Ruuth-Merriman Jacobi sweep: g = f + N u, u <- u + (w/delta)(b + E g - delta u).
+// u_zero: u is known to be 0 (first sweep after restriction), so g = f and the neighbour
+// sum is skipped.
 template <typename T>
 void smooth_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g, T* r, double c, double omega,
-                  unsigned long long* nrm, hipStream_t s) {
+                  unsigned long long* nrm, hipStream_t s, bool u_zero = false) {
   const DevLevel& D = b->dev[(size_t)l];
   const LaunchCfg lc = level_cfg(D);
   const double delta = level_delta(b, l, c);
-  launch_nsum<T>(b->dim, D.m, D.ilist, D.nbrI, u, f, (T)(1.0 / (D.h * D.h)), g, nullptr, lc, s);
+  const T* gg = g;
+  if (u_zero && f)
+    gg = f;
+  else
+    launch_nsum<T>(b->dim, D.m, D.ilist, D.nbrI, u, f, (T)(1.0 / (D.h * D.h)), g, nullptr, lc, s);
   if (b->learned_active && l < 2 && b->mlpW && D.patchRow) {
-    learned_sweep<T>(b, l, u, f, rhsA, g, r, c, s);
+    learned_sweep<T>(b, l, u, f, rhsA, const_cast<T*>(gg), r, c, s);
     return;
   }
-  launch_ext<T, T>(b->dim, EXT_SMOOTH, D.n, g, ext_addr(D), fracK_of<T>(D), rhsA, u, (T*)nullptr, (T)delta,
+  launch_ext<T, T>(b->dim, EXT_SMOOTH, D.n, gg, ext_addr(D), fracK_of<T>(D), rhsA, u, (T*)nullptr, (T)delta,
                    (T)(omega / delta), nrm, ext_cfg(D), s);
+}
+
+// The level's smoothing and residual as fused passes (E f once per visit, then one pass per
+// sweep, alternating between u and t).  Returns the vector holding the iterate.
+template <typename T>
+static T* fused_pre(const cpm_band b, int l, LevelBufs<T>* B, const T* f, const T* rhsA, const cpm_params& p,
+                    int nu, bool u_zero, hipStream_t s) {
+  const DevLevel& D = b->dev[(size_t)l];
+  const double delta = level_delta(b, l, p.c);
+  const T wod = (T)(p.omega / delta), inv_h2 = (T)(1.0 / (D.h * D.h));
+  const SweepAddr sa{D.perm, D.packed, D.origin, D.originX};
+  T* Ef = nullptr;
+  T* cur = B[l].u;
+  T* oth = B[l].t;
+  int k0 = 0;
+  if (f) {
+    Ef = B[l].g;
+    if (u_zero && nu > 0) {
+      // first sweep from u = 0: u = (omega/delta)(b + E f), keeping E f
+      launch_ext<T, T>(b->dim, EXT_SMOOTH, D.n, f, ext_addr(D), fracK_of<T>(D), rhsA, cur, Ef, (T)delta, wod,
+                       nullptr, ext_cfg(D), s);
+      k0 = 1;
+    } else {
+      launch_ext<T, T>(b->dim, EXT_PLAIN, D.n, f, ext_addr(D), fracK_of<T>(D), nullptr, nullptr, Ef, (T)0, (T)0,
+                       nullptr, ext_cfg(D), s);
+    }
+  }
+  for (int k = k0; k < nu; ++k) {
+    launch_sweep<T>(b->dim, EXT_SMOOTH, D.n, cur, oth, Ef, rhsA, sa, fracS_of<T>(D), inv_h2, (T)delta, wod,
+                    sweep_cfg(D), s);
+    std::swap(cur, oth);
+  }
+  launch_sweep<T>(b->dim, EXT_RESID, D.n, cur, B[l].r, Ef, rhsA, sa, fracS_of<T>(D), inv_h2, (T)delta, (T)0,
+                  sweep_cfg(D), s);
+  return cur;
+}
+
+template <typename T>
+static void fused_post(const cpm_band b, int l, LevelBufs<T>* B, T* cur, const T* rhsA, const cpm_params& p, int nu,
+                       hipStream_t s) {
+  const DevLevel& D = b->dev[(size_t)l];
+  const double delta = level_delta(b, l, p.c);
+  const T wod = (T)(p.omega / delta), inv_h2 = (T)(1.0 / (D.h * D.h));
+  const SweepAddr sa{D.perm, D.packed, D.origin, D.originX};
+  const T* Ef = rhsA ? nullptr : B[l].g;
+  T* oth = cur == B[l].u ? B[l].t : B[l].u;
+  for (int k = 0; k < nu; ++k) {
+    launch_sweep<T>(b->dim, EXT_SMOOTH, D.n, cur, oth, Ef, rhsA, sa, fracS_of<T>(D), inv_h2, (T)delta, wod,
+                    sweep_cfg(D), s);
+    std::swap(cur, oth);
+  }
+  if (cur != B[l].u) launch_copy<T>(D.n, cur, B[l].u, s);
 }
 
 template <typename T>
@@ -290,15 +364,31 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
   }
   const T* f = rhsA ? nullptr : B[l].f;
   const double delta = level_delta(b, l, p.c);
-  const bool learned = b->learned_active && l < 2 && b->mlpW && D.patchRow && p.learned_sweeps > 0;
+  const bool learned_here = b->learned_active && l < 2 && b->mlpW && D.patchRow;
+  const bool learned = learned_here && p.learned_sweeps > 0;
   const int nu1 = learned ? p.learned_sweeps : p.nu1;
   const int nu2 = learned ? p.learned_sweeps : p.nu2;
-  for (int k = 0; k < nu1; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s);
-  // residual r = b + E(f + N u) - delta u, restricted to the next level (where u := 0)
-  launch_nsum<T>(b->dim, D.m, D.ilist, D.nbrI, B[l].u, f, (T)(1.0 / (D.h * D.h)), B[l].g, nullptr, lc, s);
-  launch_ext<T, T>(b->dim, EXT_RESID, D.n, B[l].g, ext_addr(D), fracK_of<T>(D), rhsA, B[l].u, B[l].r, (T)delta,
-                   (T)0, nullptr, ext_cfg(D), s);
+  const bool u_zero = l > 0;  // the restriction into this level set u = 0
   const DevLevel& C = b->dev[(size_t)(l + 1)];
+  if (D.fused && D.fusedOK && !learned_here) {
+    T* cur = fused_pre<T>(b, l, B, f, rhsA, p, nu1, u_zero, s);
+    launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
+    vcycle_level<T>(b, l + 1, B, nullptr, p, s);
+    launch_prolong<T>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<T>(D), cur, lc, s);
+    fused_post<T>(b, l, B, cur, rhsA, p, nu2, s);
+    return;
+  }
+  for (int k = 0; k < nu1; ++k)
+    smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s, u_zero && k == 0);
+  // residual r = b + E(f + N u) - delta u, restricted to the next level (where u := 0)
+  if (u_zero && nu1 == 0 && f) {
+    launch_ext<T, T>(b->dim, EXT_RESID, D.n, f, ext_addr(D), fracK_of<T>(D), rhsA, B[l].u, B[l].r, (T)delta,
+                     (T)0, nullptr, ext_cfg(D), s);
+  } else {
+    launch_nsum<T>(b->dim, D.m, D.ilist, D.nbrI, B[l].u, f, (T)(1.0 / (D.h * D.h)), B[l].g, nullptr, lc, s);
+    launch_ext<T, T>(b->dim, EXT_RESID, D.n, B[l].g, ext_addr(D), fracK_of<T>(D), rhsA, B[l].u, B[l].r, (T)delta,
+                     (T)0, nullptr, ext_cfg(D), s);
+  }
   launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
   vcycle_level<T>(b, l + 1, B, nullptr, p, s);
   launch_prolong<T>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<T>(D), B[l].u, lc, s);
@@ -540,6 +630,21 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     std::vector<int32_t>().swap(H.patchRow);
     std::vector<uint32_t>().swap(H.patchMask);
     D.band_order = band_order;
+    if (st == CPM_OK) st = upload(&D.originX, H.originX);
+    std::vector<int32_t>().swap(H.originX);
+    D.fusedOK = H.fusedOK && D.originX != nullptr;
+    {
+      // sweep form before autotuning: CPM_SWEEP=fused|split forces one, otherwise the fused
+      // pass on levels small enough for launch latency to dominate
+      const char* e = std::getenv("CPM_SWEEP");
+      D.sweep_forced = e && (std::strcmp(e, "fused") == 0 || std::strcmp(e, "split") == 0);
+      if (e && std::strcmp(e, "fused") == 0)
+        D.fused = D.fusedOK;
+      else if (e && std::strcmp(e, "split") == 0)
+        D.fused = false;
+      else
+        D.fused = D.fusedOK && H.n <= kFusedDefaultNodes;
+    }
     // LDS-staged extension unless disabled or a workgroup would stage too many values
     const char* lds_env = std::getenv("CPM_EXT_LDS");
     D.lds = !band_order && H.maxE <= kMaxStaged && !(lds_env && std::strcmp(lds_env, "0") == 0);
@@ -894,7 +999,7 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
                            const double* f, double* u, void* work, size_t work_bytes, double* avg_us,
                            void* stream) {
   if (!band || !f || !u || !work || !avg_us || reps < 1 || level < 0 || level >= band->L || which < 0 ||
-      which > 4) {
+      which > 5) {
     set_error("cpm_time_kernel: invalid argument");
     return CPM_E_INVALID;
   }
@@ -910,6 +1015,10 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
   }
   if (which == 4 && (level > 1 || !band->mlpW || !band->dev[(size_t)level].patchRow)) {
     set_error("cpm_time_kernel: no learned smoother on this level (weights unset or level >= 2)");
+    return CPM_E_INVALID;
+  }
+  if (which == 5 && !band->dev[(size_t)level].fusedOK) {
+    set_error("cpm_time_kernel: no fused-sweep addressing on this level");
     return CPM_E_INVALID;
   }
   if ((st = enter(band, stream)) != CPM_OK) return st;
@@ -949,6 +1058,12 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
           launch_restrict<T>(band->dim, D.n, B[level - 1].g, D.runR, fracR_of<T>(D), B[level].r, nullptr, lc, s);
         } else if (which == 3) {
           launch_prolong<T>(band->dim, D.n, B[level + 1].g, D.runP, fracP_of<T>(D), B[level].r, lc, s);
+        } else if (which == 5) {
+          // u -> t and back, reading E f from g
+          const bool odd = r & 1;
+          launch_sweep<T>(band->dim, EXT_SMOOTH, D.n, odd ? B[level].t : uu, odd ? uu : B[level].t, B[level].g,
+                          (const T*)nullptr, SweepAddr{D.perm, D.packed, D.origin, D.originX}, fracS_of<T>(D),
+                          (T)(1.0 / (D.h * D.h)), (T)delta, (T)(params->omega / delta), sweep_cfg(D), s);
         } else {
           launch_learned<T>(band, level, B[level].r, uu, params->c, s);
         }

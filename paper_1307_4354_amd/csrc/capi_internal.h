@@ -21,6 +21,7 @@ struct LevelBufs {
   T* f = nullptr;  // right-hand side
   T* g = nullptr;  // f + N u
   T* r = nullptr;  // residual
+  T* t = nullptr;  // second iterate of the fused sweep (it reads u while writing)
 };
 
 }  // namespace cpm
@@ -63,6 +64,7 @@ namespace cpm {
 LaunchCfg band_cfg(const cpm_band b, int64_t n);
 LaunchCfg level_cfg(const DevLevel& D);
 LaunchCfg ext_cfg(const DevLevel& D);
+LaunchCfg sweep_cfg(const DevLevel& D);
 ExtAddr ext_addr(const DevLevel& D);
 double level_delta(const cpm_band b, int l, double c);
 cpm_status enter(cpm_band b, void* user);

@@ -47,6 +47,12 @@ struct HostLevel {
   // +-x neighbours are j -+ 1, the others stored as -y,+y(,-z,+z) slot-major
   std::vector<int32_t> ilist;   // m
   std::vector<int32_t> nbrI;    // (2*dim-2) * m
+  // fused sweep (E f + (E N) u in one pass): per stencil group, the band index of the first
+  // node of each cross row of the stencil widened by the axis neighbours, for the group's
+  // reference x (rows (y0-1, z0+c), (y0+4, z0+c), (y0+b, z0-1), (y0+b, z0+4) in 3-D; (y0-1),
+  // (y0+4) in 2-D).  fusedOK is false when some node's cross rows do not follow that pattern.
+  std::vector<int32_t> originX;
+  bool fusedOK = false;
   // learned smoother (two finest levels): 3^dim grid patch of every node, in band order;
   // row (dy, dz) holds the band index of (x - 1, y + dy, z + dz) (virtual when that
   // node is absent), mask bit (dx+1) + 3 (dy+1) + 9 (dz+1) marks nodes that are present
@@ -63,6 +69,10 @@ constexpr int kXoffBits = 10;
 constexpr int kExtBlock = 256;      // workgroup size of the LDS-staged extension
 constexpr int kMaxStaged = 8192;    // staged values per workgroup above which a level keeps the gather path
 constexpr int kMaxGroups = 1 << (31 - kXoffBits);
+// largest level that gets the fused-sweep addressing
+constexpr int64_t kFusedMaxNodes = 2 << 20;
+// levels up to this size sweep with the fused pass unless the autotuner decides otherwise
+constexpr int64_t kFusedDefaultNodes = 128 << 10;
 
 // Device copies of one level's addressing.
 struct DevLevel {
@@ -75,6 +85,8 @@ struct DevLevel {
   bool use_lds = false;     // extension runs LDS-staged (else gathers through L1)
   int ext_block = 256;      // workgroup size of the gather extension
   int nsum_block = 256;     // workgroup size of the neighbour sum and transfers
+  int sweep_block = 256;    // workgroup size of the fused sweep
+  bool sweep_forced = false;  // fused / split chosen by the CPM_SWEEP environment variable
   int32_t maxE = 0, maxG = 0;
   int32_t* blkE = nullptr;
   int32_t* gidx = nullptr;
@@ -99,6 +111,9 @@ struct DevLevel {
   int32_t* runR = nullptr;
   double* fracR = nullptr;
   float* fracR32 = nullptr;
+  int32_t* originX = nullptr;
+  bool fusedOK = false;
+  bool fused = false;  // sweeps as one fused pass instead of neighbour sum + extension
   int32_t* patchRow = nullptr;
   uint32_t* patchMask = nullptr;
 };

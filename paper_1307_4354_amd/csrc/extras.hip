@@ -1,7 +1,9 @@
 // Autotuner of the single-problem kernels: for every level it times the candidate launch
 // configurations of the two passes of a smoothing sweep on the band's own addressing and
 // keeps the fastest (the extension: gathers through the vector caches with workgroups of
-// 128 / 256 / 512 lanes, or LDS-staged; the neighbour sum: 128 / 256 / 512 lanes).
+// 128 / 256 / 512 lanes, or LDS-staged; the neighbour sum: 128 / 256 / 512 lanes), then
+// times the fused one-pass sweep (128 / 256 / 512 lanes) against that pair and keeps the
+// faster form for the level.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -90,6 +92,35 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
       }
     }
     D.nsum_block = best_n;
+    if (!D.fusedOK) continue;
+    // split sweep (both passes, tuned) against the fused pass
+    const float t_split = time_us(s, e0, e1, reps, [&] {
+      launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, u, u, inv_h2, g, nullptr, level_cfg(D), s);
+      launch_ext<double, double>(band->dim, EXT_SMOOTH, D.n, g, ext_addr(D), D.band_order ? D.fracE : D.fracK,
+                                 nullptr, u, (double*)nullptr, delta, 0.5 / delta, nullptr, ext_cfg(D), s);
+    });
+    const SweepAddr sa{D.perm, D.packed, D.origin, D.originX};
+    float t_fused = 1e30f;
+    int best_s = D.sweep_block;
+    for (int bi = 0; bi < 3; ++bi) {
+      LaunchCfg lc;
+      lc.block = blocks[bi];
+      // u -> g and g -> u alternately, like the solver's ping-pong
+      int flip = 0;
+      const float t = time_us(s, e0, e1, reps, [&] {
+        const double* src = flip ? g : u;
+        double* dst = flip ? u : g;
+        flip ^= 1;
+        launch_sweep<double>(band->dim, EXT_SMOOTH, D.n, src, dst, src, nullptr, sa, D.fracK, inv_h2, delta,
+                             0.5 / delta, lc, s);
+      });
+      if (t < t_fused) {
+        t_fused = t;
+        best_s = blocks[bi];
+      }
+    }
+    D.sweep_block = best_s;
+    if (!D.sweep_forced) D.fused = t_fused < t_split;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -103,7 +134,8 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
   return leave(band, stream);
 }
 
-cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_block, int* nsum_block) {
+cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_block, int* nsum_block, int* fused,
+                           int* sweep_block) {
   if (!band || level < 0 || level >= band->L) {
     set_error("cpm_band_tuning: invalid argument");
     return CPM_E_INVALID;
@@ -112,6 +144,8 @@ cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_bloc
   if (use_lds) *use_lds = D.lds && D.use_lds ? 1 : 0;
   if (ext_block) *ext_block = D.use_lds ? kExtBlock : D.ext_block;
   if (nsum_block) *nsum_block = D.nsum_block;
+  if (fused) *fused = D.fused && D.fusedOK ? 1 : 0;
+  if (sweep_block) *sweep_block = D.sweep_block;
   return CPM_OK;
 }
 

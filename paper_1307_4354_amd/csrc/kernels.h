@@ -10,7 +10,7 @@ namespace cpm {
 
 // Modes of the extension pass (t = E g at every node of a level).
 enum ExtMode {
-  EXT_SMOOTH = 0,  // u <- u + (omega/delta) r,  r = b + t - delta u   (in place on u)
+  EXT_SMOOTH = 0,  // u <- u + (omega/delta) r,  r = b + t - delta u   (in place on u; out = t if not null)
   EXT_RESID = 1,   // out = r = b + t - delta u
   EXT_APPLY = 2,   // out = delta u - t
   EXT_PLAIN = 3,   // out = t
@@ -37,6 +37,21 @@ struct ExtAddr {
   int32_t maxG = 0;
 };
 
+// Fused sweep addressing (stencil order): ExtAddr's perm, packed, origin plus the cross-row
+// origins of the widened stencil.
+struct SweepAddr {
+  const int32_t* perm;
+  const int32_t* packed;
+  const int32_t* origin;
+  const int32_t* originX;
+};
+
+// mode EXT_SMOOTH: uo = u + (omega/delta)(b + E f + (E N) u - delta u); EXT_RESID: uo = that
+// residual.  Ef and b may be null; uo must not overlap u.
+template <typename T>
+void launch_sweep(int dim, int mode, int64_t n, const T* u, T* uo, const T* Ef, const T* b, const SweepAddr& a,
+                  const T* frac, T inv_h2, T delta, T wod, const LaunchCfg& lc, hipStream_t s);
+
 // g = f + N u on the m nodes of B_interp (ilist), f may be null.
 template <typename T>
 void launch_nsum(int dim, int64_t m, const int32_t* ilist, const int32_t* nbrI, const T* u, const T* f, T inv_h2,
@@ -59,6 +74,10 @@ void launch_prolong(int dim, int64_t nf, const T* ec, const int32_t* runP, const
 // y = Z x with Z (n x n, leading dimension ld, double), x, y of type T.
 template <typename T>
 void launch_coarse_gemv(int n, const double* Z, int64_t ld, const T* x, T* y, hipStream_t s);
+
+// dst = src (n elements)
+template <typename T>
+void launch_copy(int64_t n, const T* src, T* dst, hipStream_t s);
 
 template <typename T>
 void launch_fill(int64_t n, T* p, T v, hipStream_t s);

@@ -41,6 +41,19 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(6, 8)
   if (MODE != EXT_APPLY && nrm) block_max_atomic(nv, nrm);
 }
 
+// Fused sweep: one pass per Jacobi sweep (E f + (E N) u), stencil order, u read only.
+template <int D, typename T, int MODE>
+__global__ __launch_bounds__(kMaxBlock) void k_sweep(int64_t n, const T* __restrict__ u, T* __restrict__ uo,
+                                                     const T* __restrict__ Ef, const T* __restrict__ b,
+                                                     const int32_t* __restrict__ perm,
+                                                     const int32_t* __restrict__ packed,
+                                                     const int32_t* __restrict__ origin,
+                                                     const int32_t* __restrict__ originX, const T* __restrict__ frac,
+                                                     T inv_h2, T delta, T wod, int remap) {
+  const int64_t k = tile_of_block(remap) * blockDim.x + threadIdx.x;
+  if (k < n) sweep_node<D, T, MODE>(k, n, u, uo, Ef, b, perm, packed, origin, originX, frac, inv_h2, delta, wod);
+}
+
 template <int D, typename T, typename TO, int MODE>
 __global__ __launch_bounds__(kExtBlock) void k_ext_lds(int64_t n, const T* __restrict__ g,
                                                        const int32_t* __restrict__ perm,
@@ -341,6 +354,17 @@ void launch_coarse_gemv(int n, const double* Z, int64_t ld, const T* x, T* y, hi
 }
 
 template <typename T>
+__global__ void k_copy(int64_t n, const T* __restrict__ a, T* __restrict__ b) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
+
+template <typename T>
+void launch_copy(int64_t n, const T* src, T* dst, hipStream_t s) {
+  if (n > 0) k_copy<T><<<grid_for(n, 256), 256, 0, s>>>(n, src, dst);
+}
+
+template <typename T>
 void launch_fill(int64_t n, T* p, T v, hipStream_t s) {
   if (n <= 0) return;
   int64_t gr = (n + 255) / 256;
@@ -382,6 +406,23 @@ void launch_gj_step(int n, int k, double* M, double* col, int* info, hipStream_t
   k_gj_elim<<<dim3(gx, (unsigned)n), 256, 0, s>>>(n, k, M, col);
 }
 
+template <typename T>
+void launch_sweep(int dim, int mode, int64_t n, const T* u, T* uo, const T* Ef, const T* b, const SweepAddr& a,
+                  const T* frac, T inv_h2, T delta, T wod, const LaunchCfg& lc, hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned gr = grid_for(n, lc.block);
+  const int rm = lc.xcd_remap;
+#define CPM_SWEEP_CASE(DD, MM)                                                                                  \
+  k_sweep<DD, T, MM><<<gr, lc.block, 0, s>>>(n, u, uo, Ef, b, a.perm, a.packed, a.origin, a.originX, frac, inv_h2, \
+                                             delta, wod, rm)
+  if (dim == 2) {
+    if (mode == EXT_SMOOTH) CPM_SWEEP_CASE(2, EXT_SMOOTH); else CPM_SWEEP_CASE(2, EXT_RESID);
+  } else {
+    if (mode == EXT_SMOOTH) CPM_SWEEP_CASE(3, EXT_SMOOTH); else CPM_SWEEP_CASE(3, EXT_RESID);
+  }
+#undef CPM_SWEEP_CASE
+}
+
 // explicit instantiations
 template void launch_nsum<double>(int, int64_t, const int32_t*, const int32_t*, const double*, const double*, double,
                                   double*, unsigned long long*, const LaunchCfg&, hipStream_t);
@@ -396,6 +437,11 @@ template void launch_ext<double, float>(int, int, int64_t, const double*, const 
 template void launch_ext<float, float>(int, int, int64_t, const float*, const ExtAddr&, const float*,
                                        const float*, float*, float*, float, float, unsigned long long*,
                                        const LaunchCfg&, hipStream_t);
+template void launch_sweep<double>(int, int, int64_t, const double*, double*, const double*, const double*,
+                                   const SweepAddr&, const double*, double, double, double, const LaunchCfg&,
+                                   hipStream_t);
+template void launch_sweep<float>(int, int, int64_t, const float*, float*, const float*, const float*,
+                                  const SweepAddr&, const float*, float, float, float, const LaunchCfg&, hipStream_t);
 template void launch_restrict<double>(int, int64_t, const double*, const int32_t*, const double*, double*,
                                       double*, const LaunchCfg&, hipStream_t);
 template void launch_restrict<float>(int, int64_t, const float*, const int32_t*, const float*, float*,
@@ -406,6 +452,8 @@ template void launch_prolong<float>(int, int64_t, const float*, const int32_t*, 
                                     const LaunchCfg&, hipStream_t);
 template void launch_coarse_gemv<double>(int, const double*, int64_t, const double*, double*, hipStream_t);
 template void launch_coarse_gemv<float>(int, const double*, int64_t, const float*, float*, hipStream_t);
+template void launch_copy<double>(int64_t, const double*, double*, hipStream_t);
+template void launch_copy<float>(int64_t, const float*, float*, hipStream_t);
 template void launch_fill<double>(int64_t, double*, double, hipStream_t);
 template void launch_fill<float>(int64_t, float*, float, hipStream_t);
 template void launch_fill<int>(int64_t, int*, int, hipStream_t);

@@ -129,6 +129,7 @@ __device__ __forceinline__ unsigned long long ext_node(int64_t k, int64_t n, con
     T r = t - delta * ui;
     if (b) r += b[i];
     u[i] = ui + wod * r;
+    if (out) out[i] = (TO)t;  // optionally keep E g
     return abs_bits((double)r);
   } else if (MODE == EXT_RESID) {
     T r = t - delta * u[i];
@@ -142,6 +143,108 @@ __device__ __forceinline__ unsigned long long ext_node(int64_t k, int64_t n, con
     if (out) out[i] = (TO)t;
     return abs_bits((double)t);
   }
+}
+
+// ---- fused sweep ---------------------------------------------------------------------
+// E is linear, so E (f + N u) = E f + (E N) u.  (E N) u at a node reads the node's cubic
+// stencil widened by the axis neighbours of its nodes: the 4^(D-1) x-runs extended to 6
+// nodes (x0-1 .. x0+4, consecutive band entries because every x neighbour of a stencil node
+// is in the band and adjacent to it) plus the cross rows of 4 nodes just outside the stencil
+// in y (and z).  Its weights are the 1-D cubic weights convolved with (1, 0, 1):
+//   x: (w0, w1, w0+w2, w1+w3, w2, w3) over x0-1 .. x0+4,  y and z alike.
+
+// the 6 values p[0..5]
+__device__ __forceinline__ void run6(const double* __restrict__ p, double v[6]) {
+  const run_d2 a = *(const run_d2*)p, b = *(const run_d2*)(p + 2), c = *(const run_d2*)(p + 4);
+  v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y; v[4] = c.x; v[5] = c.y;
+}
+typedef float run_f2 __attribute__((ext_vector_type(2), aligned(4)));
+__device__ __forceinline__ void run6(const float* __restrict__ p, float v[6]) {
+  const run_f4 a = *(const run_f4*)p;
+  const run_f2 b = *(const run_f2*)(p + 4);
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y;
+}
+
+// (E N) u times h^2 at one node: ux = u + xoff, org / orgX its group's run origins.
+template <int D, typename T>
+__device__ __forceinline__ T en_node(const T* __restrict__ ux, const int32_t* __restrict__ org,
+                                     const int32_t* __restrict__ orgX, const T wx[4], const T wy[4],
+                                     const T wz[4]) {
+  const T cx[6] = {wx[0], wx[1], wx[0] + wx[2], wx[1] + wx[3], wx[2], wx[3]};
+  const T cy[4] = {wy[1], wy[0] + wy[2], wy[1] + wy[3], wy[2]};  // y-shift weights of the stencil rows
+  T acc = T(0);
+  if (D == 2) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      T v[6];
+      run6(ux + org[b] - 1, v);
+      T A = T(0), B = T(0);
+#pragma unroll
+      for (int a = 0; a < 6; ++a) A += cx[a] * v[a];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) B += wx[a] * v[a + 1];
+      acc += wy[b] * A + cy[b] * B;
+    }
+    acc += wy[0] * run_dot(ux + orgX[0], wx) + wy[3] * run_dot(ux + orgX[1], wx);
+  } else {
+    const T cz[4] = {wz[1], wz[0] + wz[2], wz[1] + wz[3], wz[2]};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      T zc = T(0);  // rows of this z: x and y shifts
+      T yc = T(0);  // rows of this z weighted for the z shift
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        T v[6];
+        run6(ux + org[b + 4 * c] - 1, v);
+        T A = T(0), B = T(0);
+#pragma unroll
+        for (int a = 0; a < 6; ++a) A += cx[a] * v[a];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) B += wx[a] * v[a + 1];
+        zc += wy[b] * A + cy[b] * B;
+        yc += wy[b] * B;
+      }
+      // cross rows y0-1 and y0+4 at this z
+      zc += wy[0] * run_dot(ux + orgX[c], wx) + wy[3] * run_dot(ux + orgX[4 + c], wx);
+      acc += wz[c] * zc + cz[c] * yc;
+    }
+    // cross rows z0-1 and z0+4
+    T zm = T(0), zp = T(0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      zm += wy[b] * run_dot(ux + orgX[8 + b], wx);
+      zp += wy[b] * run_dot(ux + orgX[12 + b], wx);
+    }
+    acc += wz[0] * zm + wz[3] * zp;
+  }
+  return acc;
+}
+
+// One Jacobi sweep (MODE EXT_SMOOTH: uo = u + (omega/delta) r) or the residual (EXT_RESID:
+// uo = r) with r = b + E f + (E N) u - delta u, at the node in stencil slot k.  Ef (E f of
+// this level) and b may be null.  u is only read: uo is another vector.
+template <int D, typename T, int MODE>
+__device__ __forceinline__ void sweep_node(int64_t k, int64_t n, const T* __restrict__ u, T* __restrict__ uo,
+                                           const T* __restrict__ Ef, const T* __restrict__ b,
+                                           const int32_t* __restrict__ perm, const int32_t* __restrict__ packed,
+                                           const int32_t* __restrict__ origin, const int32_t* __restrict__ originX,
+                                           const T* __restrict__ frac, T inv_h2, T delta, T wod) {
+  constexpr int S = D == 2 ? 4 : 16;
+  constexpr int SX = D == 2 ? 2 : 16;
+  const int32_t i = perm[k];
+  const int32_t pk = packed[k];
+  const int32_t gid = pk >> kXoffBits;
+  const T* ux = u + (pk & ((1 << kXoffBits) - 1));
+  T wx[4], wy[4], wz[4] = {T(0), T(0), T(0), T(0)};
+  cubic_weights<T>(frac[k], wx);
+  cubic_weights<T>(frac[n + k], wy);
+  if (D == 3) cubic_weights<T>(frac[2 * n + k], wz);
+  T t = en_node<D, T>(ux, origin + (int64_t)gid * S, originX + (int64_t)gid * SX, wx, wy, wz) * inv_h2;
+  if (Ef) t += Ef[i];
+  const T ui = u[i];
+  T r = t - delta * ui;
+  if (b) r += b[i];
+  uo[i] = MODE == EXT_SMOOTH ? ui + wod * r : r;
 }
 
 // ---- LDS-staged extension ---------------------------------------------------------
@@ -199,6 +302,7 @@ __device__ __forceinline__ unsigned long long ext_node_lds(int64_t k, int64_t n,
     T r = t - delta * ui;
     if (b) r += b[i];
     u[i] = ui + wod * r;
+    if (out) out[i] = (TO)t;  // optionally keep E g
     return abs_bits((double)r);
   } else if (MODE == EXT_RESID) {
     T r = t - delta * u[i];

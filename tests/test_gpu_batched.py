@@ -1,6 +1,8 @@
 """Batched solves: each problem of an uneven batch, solved in one batched launch sequence,
 equals its own unbatched mixed-precision solve (same cycles, same iterate), and reaches the
-tolerance.  The unbatched solve is itself checked against the oracle in test_gpu_parity."""
+tolerance.  The unbatched solve is itself checked against the oracle in test_gpu_parity.
+The batched kernels sweep with the two passes (neighbour sum, then extension), so the
+unbatched reference solves are pinned to that form (CPM_SWEEP=split) for bitwise equality."""
 import numpy as np
 import pytest
 
@@ -23,9 +25,10 @@ def _setup(items):
     return bands, fs
 
 
-def test_batched_equals_unbatched_mixed():
+def test_batched_equals_unbatched_mixed(monkeypatch):
     import paper_1307_4354_amd as cpm
 
+    monkeypatch.setenv("CPM_SWEEP", "split")
     torch = torch_cuda()
     items = W.batch_problems(8, seed=W.SEED_BASE + 40, h_choices=(16, 32), coarse_h_inv=4)
     log("batched parity: %d problems, sizes %s" % (len(items), [round(1 / it.h0) for it in items]))

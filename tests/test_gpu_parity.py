@@ -77,13 +77,16 @@ def test_apply_and_extend_parity(name, cfg):
         assert np.max(np.abs(host(out) - c)) < 1e-9 * delta
 
 
-def _gpu_iterates(cfg, ncycles, params=None):
+def _gpu_iterates(cfg, ncycles, params=None, check_sweep=None):
     import paper_1307_4354_amd as cpm
 
     torch = torch_cuda()
     H = oracle_for(cfg)
     f = cfg.problem.f(H.levels[0].cp)
     band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+    if check_sweep is not None:
+        fused = [cpm.cpm_band_tuning(band, l)[3] for l in range(band.levels - 1)]
+        assert all(fused) if check_sweep == "fused" else not any(fused), fused
     p = params or cpm.make_params(c=cfg.problem.c, nu1=cfg.nu1, nu2=cfg.nu2, omega=cfg.omega)
     work, nbytes = workspace(band, p)
     fd = dev(f)
@@ -101,9 +104,13 @@ def _gpu_iterates(cfg, ncycles, params=None):
     ("sphere64_first4", W.config_sphere(64, 5), 4),
     ("torus32", W.SolverConfig("t32", W.torus_modes(1.0, 0.4, 7), 1 / 32, 3, W.LAM2_3D), 20),
 ], ids=["circle64", "sphere32", "sphere64_first4", "torus32"])
-def test_vcycle_iterates_match_oracle(name, cfg, ncyc):
-    log("V-cycle iterate parity: %s (%d cycles)" % (name, ncyc))
-    H, f, its, rels = _gpu_iterates(cfg, ncyc)
+@pytest.mark.parametrize("sweep", ["split", "fused"])
+def test_vcycle_iterates_match_oracle(name, cfg, ncyc, sweep, monkeypatch):
+    """Both sweep forms (neighbour sum + extension passes, or the fused E f + (E N) u pass,
+    pinned with CPM_SWEEP when the band is built) give the oracle's iterates."""
+    log("V-cycle iterate parity: %s (%d cycles, %s sweeps)" % (name, ncyc, sweep))
+    monkeypatch.setenv("CPM_SWEEP", sweep)
+    H, f, its, rels = _gpu_iterates(cfg, ncyc, check_sweep=sweep)
     ref = ov.solve(H, f, ov.Params(c=cfg.problem.c), rtol=0.0, max_cycles=ncyc, keep_iterates=True)
     for k in range(ncyc):
         err = rel_inf(its[k], ref.iterates[k])
@@ -140,10 +147,12 @@ def test_solve_matches_oracle(name, cfg):
     ("circle64", W.config_circle(64, 4)),
     ("torus32", W.config_torus_mixed(32, 3)),
 ], ids=["circle64", "torus32"])
-def test_mixed_precision_matches_oracle(name, cfg):
-    log("mixed precision parity: %s" % name)
+@pytest.mark.parametrize("sweep", ["split", "fused"])
+def test_mixed_precision_matches_oracle(name, cfg, sweep, monkeypatch):
+    log("mixed precision parity: %s (%s sweeps)" % (name, sweep))
     import paper_1307_4354_amd as cpm
 
+    monkeypatch.setenv("CPM_SWEEP", sweep)
     torch = torch_cuda()
     H = oracle_for(cfg)
     f = cfg.problem.f(H.levels[0].cp)
@@ -264,8 +273,8 @@ def test_autotuned_solve_matches_oracle():
     band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
     cpm.cpm_autotune(band)
     for l in range(band.levels):
-        lds, eb, nb = cpm.cpm_band_tuning(band, l)
-        assert eb in (128, 256, 512) and nb in (128, 256, 512)
+        lds, eb, nb, fused, sb = cpm.cpm_band_tuning(band, l)
+        assert eb in (128, 256, 512) and nb in (128, 256, 512) and sb in (128, 256, 512)
     p = cpm.make_params()
     work, nbytes = workspace(band, p)
     fd = dev(f)
