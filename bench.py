@@ -144,11 +144,14 @@ def run_batched256(args):
     dof_cycles = sum(n * st.cycles for n, st in zip(sizes, stats))
     # unbatched reference on a sample: same cycles, same iterate, time
     sample = list(range(0, len(bands), max(1, len(bands) // 8)))[:8]
-    seq_t, same = 0.0, True
+    # (the unbatched solves may sweep small levels with the fused pass, which rounds
+    # differently from the batched two-pass sweep: compare cycles and the iterate's difference)
+    seq_t, same_cycles, max_diff = 0.0, True, 0.0
     for k in sample:
         u1, r = _solve(cpm, torch, bands[k], p, fs[k])
         seq_t += r["seconds"]
-        same &= r["cycles"] == stats[k].cycles and bool((u1 - us[k]).abs().max() <= 1e-14 * us[k].abs().max())
+        same_cycles &= r["cycles"] == stats[k].cycles
+        max_diff = max(max_diff, float((u1 - us[k]).abs().max() / us[k].abs().max()))
     sample_n = sum(sizes[k] * stats[k].cycles for k in sample)
     print(json.dumps({"metric": "batched band DOF*V-cycles/s (mixed precision, 1e-10)", "nprob": len(bands),
                       "status": status, "total_finest_dofs": sum(sizes), "min_n": min(sizes), "max_n": max(sizes),
@@ -157,7 +160,8 @@ def run_batched256(args):
                       "max_relres": max(s.relres for s in stats), "tile_block": stats[0].tile_block,
                       "tile_blocks_per_cu": stats[0].tile_blocks_per_cu, "band_build_s": t_build,
                       "unbatched_sample": {"problems": sample, "seconds": seq_t,
-                                           "dof_cycles_per_s": sample_n / seq_t, "identical_to_batched": same}}),
+                                           "dof_cycles_per_s": sample_n / seq_t, "same_cycles_as_batched": same_cycles,
+                                           "max_rel_diff_to_batched": max_diff}}),
           flush=True)
 
 
