@@ -72,12 +72,20 @@ typedef struct {
 } cpm_grid;
 
 typedef enum { CPM_F64 = 0, CPM_MIXED = 1 } cpm_precision;
-typedef enum { CPM_SMOOTH_JACOBI = 0, CPM_SMOOTH_LEARNED = 1 } cpm_smoother;
+typedef enum { CPM_SMOOTH_JACOBI = 0, CPM_SMOOTH_LEARNED = 1, CPM_SMOOTH_STANDARD = 2 } cpm_smoother;
 
 /* Solver parameters.  precision CPM_MIXED: float32 smoothing / extension / transfers on
  * every level, float64 outer residual, refinement update and coarsest solve.
+ * smoother CPM_SMOOTH_JACOBI: the Ruuth-Merriman step (Sec. 4.2), damped by omega.
  * smoother CPM_SMOOTH_LEARNED: the learned local smoother (cpm_set_smoother_weights) on
- * the two finest levels, Jacobi elsewhere, with a fallback to Jacobi (see cpm_stats). */
+ * the two finest levels, Jacobi elsewhere, with a fallback to Jacobi (see cpm_stats).
+ * smoother CPM_SMOOTH_STANDARD: the standard relaxation of Sec. 4.5 (CPM_F64 only): the
+ * cycle solves A u = f itself (no extension of f), smooths with Jacobi on A,
+ * u <- u + omega diag(A)^{-1} (f - A u), passes the residual f - A (E u) to the coarse grid
+ * and solves the coarsest level with A_c^{-1}; its progress is measured by the relative
+ * increment ||u_k - u_{k-1}||_inf / ||u_k||_inf (the paper's stopping test), which is what
+ * relres / relres_history / relres_out and rtol then refer to (the cycle's fixed point does
+ * not make f - A u vanish). */
 typedef struct {
   double c;
   int nu1;
@@ -154,8 +162,9 @@ cpm_status cpm_extend(cpm_band band, int level, const double* g, double* out, vo
 
 /* One V(nu1, nu2) cycle in place on u (Algorithm 4.1) for right-hand side f.  work has
  * cpm_workspace_size bytes.  If relres_out is not NULL the call synchronizes the stream
- * and stores ||E f - A u||_inf / ||E f||_inf of the new iterate.  Only precision CPM_F64
- * and smoother CPM_SMOOTH_JACOBI are accepted here. */
+ * and stores ||E f - A u||_inf / ||E f||_inf of the new iterate (the relative increment
+ * for CPM_SMOOTH_STANDARD).  Only precision CPM_F64 with smoother CPM_SMOOTH_JACOBI or
+ * CPM_SMOOTH_STANDARD is accepted here. */
 cpm_status cpm_vcycle(cpm_band band, const cpm_params* params, const double* f, double* u,
                       void* work, size_t work_bytes, double* relres_out, void* stream);
 

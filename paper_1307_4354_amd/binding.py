@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcpm.so")
 CPM_OK, CPM_E_INVALID, CPM_E_BAND, CPM_E_NOMEM, CPM_E_HIP, CPM_E_NOCONV, CPM_E_DIVERGED, CPM_E_WORKSPACE = range(8)
 CPM_CIRCLE, CPM_SPHERE, CPM_TORUS = 0, 1, 2
 CPM_F64, CPM_MIXED = 0, 1
-CPM_SMOOTH_JACOBI, CPM_SMOOTH_LEARNED = 0, 1
+CPM_SMOOTH_JACOBI, CPM_SMOOTH_LEARNED, CPM_SMOOTH_STANDARD = 0, 1, 2
 CPM_MAX_HISTORY = 256
 CPM_MLP_IN = 64
 CPM_MLP_HIDDEN = 64

@@ -539,6 +539,51 @@ cpm_status build_patches(HostLevel& Lv, int level, std::string& err) {
   return CPM_OK;
 }
 
+// Lagrange basis of the cubic stencil (nodes 0..3) at s = 1 + a, a in [0, 1).
+inline void cubic_basis(double a, double w[4]) {
+  const double am1 = a - 1.0, am2 = a - 2.0, ap1 = a + 1.0;
+  w[0] = -(a * am1 * am2) * (1.0 / 6.0);
+  w[1] = (ap1 * am1 * am2) * 0.5;
+  w[2] = -(ap1 * a * am2) * 0.5;
+  w[3] = (ap1 * a * am1) * (1.0 / 6.0);
+}
+
+// (E N)_ii for every node: the weights of node i's own cubic stencil at the stencil nodes
+// that are axis neighbours of node i, summed and divided by h^2.  diag(A) = delta - (E N)_ii
+// is the divisor of the standard Jacobi relaxation (Sec. 4.1, Sec. 4.5).
+void build_en_diagonal(HostLevel& Lv) {
+  const int dim = Lv.dim;
+  const int64_t n = Lv.n;
+  const double ih2 = 1.0 / (Lv.h * Lv.h);
+  Lv.qdiag.assign((size_t)n, 0.0);
+#pragma omp parallel for
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t j0 = Lv.runE[(size_t)i];  // run (0, 0) starts at the stencil base
+    int32_t base[3] = {0, 0, 0}, me[3] = {0, 0, 0};
+    double w[3][4] = {{1.0, 0.0, 0.0, 0.0}, {1.0, 0.0, 0.0, 0.0}, {1.0, 0.0, 0.0, 0.0}};
+    for (int a = 0; a < dim; ++a) {
+      base[a] = Lv.idx[(size_t)(j0 * dim + a)];
+      me[a] = Lv.idx[(size_t)(i * dim + a)];
+      cubic_basis(Lv.fracE[(size_t)(a * n + i)], w[a]);
+    }
+    double q = 0.0;
+    for (int a = 0; a < dim; ++a)
+      for (int sg = -1; sg <= 1; sg += 2) {
+        double prod = 1.0;
+        bool inside = true;
+        for (int b = 0; b < dim && inside; ++b) {
+          const int rel = me[b] + (b == a ? sg : 0) - base[b];
+          if (rel < 0 || rel > 3)
+            inside = false;
+          else
+            prod *= w[b][rel];
+        }
+        if (inside) q += prod;
+      }
+    Lv.qdiag[(size_t)i] = q * ih2;
+  }
+}
+
 }  // namespace
 
 cpm_status build_host_levels(const cpm_surface& s, const cpm_grid& g, int dim,
@@ -560,6 +605,7 @@ cpm_status build_host_levels(const cpm_surface& s, const cpm_grid& g, int dim,
       err = os.str();
       return CPM_E_BAND;
     }
+    build_en_diagonal(Lv);
     // Laplacian neighbours, missing ones marked -1 (they only occur at band edges)
     const int64_t n = Lv.n;
     const int nn = 2 * dim;

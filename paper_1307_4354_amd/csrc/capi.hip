@@ -88,16 +88,18 @@ static void free_dev(cpm_band b) {
   for (auto& D : b->dev) {
     void* ps[] = {D.runE,  D.nbr,   D.fracE,  D.fracE32, D.runP,    D.fracP,  D.fracP32, D.runR,
                   D.fracR, D.fracR32, D.perm, D.packed, D.origin, D.fracK, D.fracK32, D.ilist, D.nbrI,
-                  D.patchRow, D.patchMask, D.packedB, D.packedL, D.blkE, D.gidx, D.blkG, D.lorg, D.originX};
+                  D.patchRow, D.patchMask, D.packedB, D.packedL, D.blkE, D.gidx, D.blkG, D.lorg, D.originX,
+                  D.qdiag, D.wd};
     for (void* p : ps)
       if (p) (void)hipFree(p);
   }
   b->dev.clear();
-  void* ps[] = {b->coarseM, b->gj_col, b->gj_info, b->dscal, b->dcounter, b->dhist, b->mlpW};
+  void* ps[] = {b->coarseM, b->coarseS, b->gj_col, b->gj_info, b->dscal, b->dcounter, b->dhist, b->mlpW};
   b->mlpW = nullptr;
   for (void* p : ps)
     if (p) (void)hipFree(p);
   b->coarseM = nullptr;
+  b->coarseS = nullptr;
   if (b->hpinned) (void)hipHostFree(b->hpinned);
   b->hpinned = nullptr;
   for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -135,8 +137,10 @@ cpm_status check_launch(const char* what) {
 
 // Coarsest level: Z = A_c^{-1} E_c with A_c = delta I - E_c N_c, by Gauss-Jordan with
 // partial pivoting on [A_c | E_c] on the device.  Cached per value of c.
-cpm_status ensure_coarse(cpm_band b, double c) {
-  if (b->coarseM && b->coarse_c == c) return CPM_OK;
+// Dense inverse on the coarsest level: Gauss-Jordan on [A_c | E_c] (-> A_c^{-1} E_c, the
+// Ruuth-Merriman cycles) or on [A_c | I] (-> A_c^{-1}, the standard relaxation).
+static cpm_status coarse_inverse(cpm_band b, double c, bool identity_rhs, double** M, double* cached_c) {
+  if (*M && *cached_c == c) return CPM_OK;
   const int l = b->L - 1;
   const DevLevel& D = b->dev[(size_t)l];
   const int n = (int)D.n;
@@ -148,20 +152,19 @@ cpm_status ensure_coarse(cpm_band b, double c) {
     return CPM_E_INVALID;
   }
   cpm_status st = CPM_OK;
-  if (!b->coarseM) {
-    b->coarseM = dalloc<double>((size_t)2 * n * n, &st);
-    b->gj_col = dalloc<double>((size_t)n, &st);
-    b->gj_info = dalloc<int>(1, &st);
-    if (st != CPM_OK) {
-      set_error("device allocation of the coarse matrix failed");
-      return st;
-    }
+  if (!*M) *M = dalloc<double>((size_t)2 * n * n, &st);
+  if (!b->gj_col) b->gj_col = dalloc<double>((size_t)n, &st);
+  if (!b->gj_info) b->gj_info = dalloc<int>(1, &st);
+  if (st != CPM_OK) {
+    set_error("device allocation of the coarse matrix failed");
+    return st;
   }
   hipStream_t s = b->stream;
   const double h = D.h;
-  launch_assemble_coarse(b->dim, n, D.runE, D.fracE, D.nbr, level_delta(b, l, c), 1.0 / (h * h), b->coarseM, s);
+  launch_assemble_coarse(b->dim, n, D.runE, D.fracE, D.nbr, level_delta(b, l, c), 1.0 / (h * h), *M, s,
+                         identity_rhs);
   launch_fill<int>(1, b->gj_info, 0, s);
-  for (int k = 0; k < n; ++k) launch_gj_step(n, k, b->coarseM, b->gj_col, b->gj_info, s);
+  for (int k = 0; k < n; ++k) launch_gj_step(n, k, *M, b->gj_col, b->gj_info, s);
   if ((st = check_launch("coarse factorization")) != CPM_OK) return st;
   int info = 0;
   if (hipMemcpyAsync(&info, b->gj_info, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -171,10 +174,31 @@ cpm_status ensure_coarse(cpm_band b, double c) {
   }
   if (info != 0) {
     set_error("coarsest-level matrix is singular");
-    b->coarse_c = NAN;
+    *cached_c = NAN;
     return CPM_E_INVALID;
   }
-  b->coarse_c = c;
+  *cached_c = c;
+  return CPM_OK;
+}
+
+cpm_status ensure_coarse(cpm_band b, double c) { return coarse_inverse(b, c, false, &b->coarseM, &b->coarse_c); }
+
+// Standard relaxation: A_c^{-1} and omega / diag(A) on every level for (c, omega).
+static cpm_status ensure_std(cpm_band b, double c, double omega) {
+  cpm_status st = coarse_inverse(b, c, true, &b->coarseS, &b->coarse_std_c);
+  if (st != CPM_OK) return st;
+  if (b->std_c == c && b->std_omega == omega) return CPM_OK;
+  for (int l = 0; l < b->L; ++l) {
+    DevLevel& D = b->dev[(size_t)l];
+    if (!D.wd && !(D.wd = dalloc<double>((size_t)D.n, &st))) {
+      set_error("device allocation of the relaxation weights failed");
+      return st != CPM_OK ? st : CPM_E_NOMEM;
+    }
+    launch_std_scale(D.n, D.qdiag, level_delta(b, l, c), omega, D.wd, b->stream);
+  }
+  if ((st = check_launch("relaxation weights")) != CPM_OK) return st;
+  b->std_c = c;
+  b->std_omega = omega;
   return CPM_OK;
 }
 
@@ -194,7 +218,7 @@ size_t workspace_bytes(const cpm_band b, int precision) {
   for (int l = 0; l < b->L; ++l) {
     const size_t n = (size_t)b->dev[(size_t)l].n;
     if (precision == CPM_F64) {
-      tot += align_up(n * 8) * (l == 0 ? 3 : 5);
+      tot += align_up(n * 8) * (l == 0 ? 4 : 5);
     } else {
       tot += align_up(n * 4) * 5;
       if (l == 0) tot += align_up(n * 8);
@@ -219,6 +243,7 @@ void carve_levels(const cpm_band b, void* work, LevelBufs<T>* B, double** g64) {
       B[l].g = carve<T>(p, n);
       B[l].r = carve<T>(p, n);
       B[l].t = carve<T>(p, n);
+      if (l == 0) B[l].p = carve<T>(p, n);
     } else {
       B[l].u = carve<T>(p, n);
       B[l].f = carve<T>(p, n);
@@ -395,6 +420,36 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
   for (int k = 0; k < nu2; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s);
 }
 
+// V-cycle with the standard relaxation (Sec. 4.5): Jacobi on A_l e = f_l in steps 1 and 4,
+// u <- u + (omega / diag(A)) (f - A u) with f - A u = f + E(N u) - delta u, and the residual
+// r = f - A (E u) passed to the coarse grid; the coarsest level is solved with A_c^{-1}.
+static void vcycle_std(const cpm_band b, int l, LevelBufs<double>* B, const cpm_params& p, hipStream_t s) {
+  const DevLevel& D = b->dev[(size_t)l];
+  if (l == b->L - 1) {
+    launch_coarse_gemv<double>((int)D.n, b->coarseS + D.n, 2 * D.n, B[l].f, B[l].u, s);
+    return;
+  }
+  const LaunchCfg lc = level_cfg(D);
+  const double delta = level_delta(b, l, p.c), inv_h2 = 1.0 / (D.h * D.h);
+  auto sweep = [&] {
+    launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, B[l].u, nullptr, inv_h2, B[l].g, nullptr, lc, s);
+    launch_ext<double, double>(b->dim, EXT_SMOOTH, D.n, B[l].g, ext_addr(D), fracK_of<double>(D), B[l].f, B[l].u,
+                               (double*)nullptr, delta, 0.0, nullptr, ext_cfg(D), s, D.wd);
+  };
+  for (int k = 0; k < p.nu1; ++k) sweep();
+  // r = f - A (E u): v = E u into t, then r = f + E(N v) - delta v
+  launch_ext<double, double>(b->dim, EXT_PLAIN, D.n, B[l].u, ext_addr(D), fracK_of<double>(D), nullptr, nullptr,
+                             B[l].t, 0.0, 0.0, nullptr, ext_cfg(D), s);
+  launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, B[l].t, nullptr, inv_h2, B[l].g, nullptr, lc, s);
+  launch_ext<double, double>(b->dim, EXT_RESID, D.n, B[l].g, ext_addr(D), fracK_of<double>(D), B[l].f, B[l].t,
+                             B[l].r, delta, 0.0, nullptr, ext_cfg(D), s);
+  const DevLevel& C = b->dev[(size_t)(l + 1)];
+  launch_restrict<double>(b->dim, C.n, B[l].r, C.runR, fracR_of<double>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
+  vcycle_std(b, l + 1, B, p, s);
+  launch_prolong<double>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<double>(D), B[l].u, lc, s);
+  for (int k = 0; k < p.nu2; ++k) sweep();
+}
+
 // ||E f||_inf into scalar slot 1 (double)
 void enqueue_rhs_norm(const cpm_band b, const double* f, double* g, hipStream_t s) {
   const DevLevel& D = b->dev[0];
@@ -416,6 +471,18 @@ void enqueue_resid64(const cpm_band b, const double* f, const double* u, double*
 // One complete cycle of the solve loop on the band stream, ending with the residual
 // norm of the new iterate in slot 0.
 void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, double* u, void* work, hipStream_t s) {
+  if (p.smoother == CPM_SMOOTH_STANDARD) {
+    // slot 0 = ||u_new - u_old||_inf, slot 1 = ||u_new||_inf (the paper's stopping test)
+    LevelBufs<double> B[kMaxLevels];
+    carve_levels<double>(b, work, B, nullptr);
+    B[0].u = u;
+    B[0].f = const_cast<double*>(f);
+    launch_copy<double>(b->dev[0].n, u, B[0].p, s);
+    vcycle_std(b, 0, B, p, s);
+    launch_zero_u64(b->dscal, 2, s);
+    launch_incr(b->dev[0].n, u, B[0].p, b->dscal, s);
+    return;
+  }
   if (p.precision == CPM_F64) {
     LevelBufs<double> B[kMaxLevels];
     carve_levels<double>(b, work, B, nullptr);
@@ -438,6 +505,12 @@ void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, doubl
 // Prologue of a solve: ||E f|| (slot 1) and, in mixed precision, the first residual.
 void enqueue_prologue(const cpm_band b, const cpm_params& p, const double* f, const double* u, void* work,
                       hipStream_t s) {
+  if (p.smoother == CPM_SMOOTH_STANDARD) {
+    // ||f||_inf into slot 1 (the system is A u = f)
+    launch_zero_u64(b->dscal, 2, s);
+    launch_incr(b->dev[0].n, f, nullptr, b->dscal, s);
+    return;
+  }
   if (p.precision == CPM_F64) {
     LevelBufs<double> B[kMaxLevels];
     carve_levels<double>(b, work, B, nullptr);
@@ -528,8 +601,12 @@ cpm_status validate_params(const cpm_band b, const cpm_params* p) {
     set_error("unknown precision");
     return CPM_E_INVALID;
   }
-  if (p->smoother != CPM_SMOOTH_JACOBI && p->smoother != CPM_SMOOTH_LEARNED) {
+  if (p->smoother != CPM_SMOOTH_JACOBI && p->smoother != CPM_SMOOTH_LEARNED && p->smoother != CPM_SMOOTH_STANDARD) {
     set_error("unknown smoother");
+    return CPM_E_INVALID;
+  }
+  if (p->smoother == CPM_SMOOTH_STANDARD && p->precision != CPM_F64) {
+    set_error("the standard relaxation runs in double precision only");
     return CPM_E_INVALID;
   }
   if (p->precision == CPM_MIXED && b->L < 2) {
@@ -630,6 +707,8 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     std::vector<int32_t>().swap(H.patchRow);
     std::vector<uint32_t>().swap(H.patchMask);
     D.band_order = band_order;
+    if (st == CPM_OK) st = upload(&D.qdiag, H.qdiag);
+    std::vector<double>().swap(H.qdiag);
     if (st == CPM_OK) st = upload(&D.originX, H.originX);
     std::vector<int32_t>().swap(H.originX);
     D.fusedOK = H.fusedOK && D.originX != nullptr;
@@ -865,8 +944,8 @@ cpm_status cpm_vcycle(cpm_band band, const cpm_params* params, const double* f, 
   }
   cpm_status st = validate_params(band, params);
   if (st != CPM_OK) return st;
-  if (params->precision != CPM_F64 || params->smoother != CPM_SMOOTH_JACOBI) {
-    set_error("cpm_vcycle runs the plain double-precision cycle only");
+  if (params->precision != CPM_F64 || params->smoother == CPM_SMOOTH_LEARNED) {
+    set_error("cpm_vcycle runs the double-precision cycles (Jacobi or standard relaxation) only");
     return CPM_E_INVALID;
   }
   if (work_bytes < workspace_bytes(band, params->precision)) {
@@ -875,6 +954,8 @@ cpm_status cpm_vcycle(cpm_band band, const cpm_params* params, const double* f, 
   }
   if ((st = enter(band, stream)) != CPM_OK) return st;
   if ((st = ensure_coarse(band, params->c)) != CPM_OK) return st;
+  if (params->smoother == CPM_SMOOTH_STANDARD && (st = ensure_std(band, params->c, params->omega)) != CPM_OK)
+    return st;
   band->learned_active = false;
   if (relres_out) enqueue_prologue(band, *params, f, u, work, band->stream);
   enqueue_cycle(band, *params, f, u, work, band->stream);
@@ -906,6 +987,8 @@ cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, d
   auto t0 = std::chrono::steady_clock::now();
   if ((st = enter(band, stream)) != CPM_OK) return st;
   if ((st = ensure_coarse(band, params->c)) != CPM_OK) return st;
+  if (params->smoother == CPM_SMOOTH_STANDARD && (st = ensure_std(band, params->c, params->omega)) != CPM_OK)
+    return st;
   const cpm_params p = *params;
   band->learned_active = p.smoother == CPM_SMOOTH_LEARNED;
   enqueue_prologue(band, p, f, u, work, band->stream);
@@ -929,9 +1012,10 @@ cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, d
     const std::string key = graph_key("cycle", p, f, u, work, band->learned_active ? 1 : 0);
     cpm_status gs = graph_launch(band, key, [&](hipStream_t s) { enqueue_cycle(band, p, f, u, work, s); });
     if (gs != CPM_OK) return gs;
-    double rn = 0;
-    if ((gs = read_scalars(band, &rn, nullptr)) != CPM_OK) return gs;
-    const double rel = rn / bn;
+    double rn = 0, un = 0;
+    if ((gs = read_scalars(band, &rn, &un)) != CPM_OK) return gs;
+    // standard relaxation: the relative increment ||u_k - u_{k-1}|| / ||u_k|| (Sec. 4.6)
+    const double rel = p.smoother == CPM_SMOOTH_STANDARD ? (un > 0 ? rn / un : 0.0) : rn / bn;
     if (k < CPM_MAX_HISTORY) S->relres_history[k] = rel;
     S->cycles = k + 1;
     S->relres = rel;
@@ -972,6 +1056,8 @@ cpm_status cpm_run_cycles(cpm_band band, const cpm_params* params, const double*
   }
   if ((st = enter(band, stream)) != CPM_OK) return st;
   if ((st = ensure_coarse(band, params->c)) != CPM_OK) return st;
+  if (params->smoother == CPM_SMOOTH_STANDARD && (st = ensure_std(band, params->c, params->omega)) != CPM_OK)
+    return st;
   const cpm_params p = *params;
   band->learned_active = p.smoother == CPM_SMOOTH_LEARNED;
   launch_fill<int>(1, band->dcounter, 0, band->stream);

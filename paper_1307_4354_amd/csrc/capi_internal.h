@@ -22,6 +22,7 @@ struct LevelBufs {
   T* g = nullptr;  // f + N u
   T* r = nullptr;  // residual
   T* t = nullptr;  // second iterate of the fused sweep (it reads u while writing)
+  T* p = nullptr;  // level 0, FP64: previous iterate (increment of the standard relaxation)
 };
 
 }  // namespace cpm
@@ -39,6 +40,10 @@ struct cpm_band_s {
   // coarsest level: [A_c | Z] after Gauss-Jordan, Z = A_c^{-1} E_c at column offset n
   double coarse_c = 0.0 / 0.0;
   double* coarseM = nullptr;
+  // standard relaxation: [A_c | A_c^{-1}] for coarse_std_c, per-level omega / diag(A) for (std_c, std_omega)
+  double* coarseS = nullptr;
+  double coarse_std_c = 0.0 / 0.0;
+  double std_c = 0.0 / 0.0, std_omega = 0.0 / 0.0;
   double* gj_col = nullptr;
   int* gj_info = nullptr;
   // device scalars: [0] residual norm bits, [1] ||E f|| bits; relres history + counter

@@ -23,6 +23,7 @@ struct HostLevel {
   std::vector<int32_t> map;    // dense index box -> band index (-1 = not in band)
   // addressing, structure of arrays (slot-major: array[slot * n + i])
   std::vector<double> fracE;   // dim * n: frac(cp / h) for the cubic stencil
+  std::vector<double> qdiag;   // n: (E N)_ii, so that diag(A) = delta - qdiag
   std::vector<int32_t> runE;   // 4^(dim-1) * n: first node of each x-run of the cubic stencil
   std::vector<int32_t> nbr;    // 2*dim * n: -x,+x,-y,+y,-z,+z neighbours, -1 if absent
   // extension in stencil order: nodes sorted by the base of their cubic stencil (z, y, x);
@@ -112,6 +113,8 @@ struct DevLevel {
   double* fracR = nullptr;
   float* fracR32 = nullptr;
   int32_t* originX = nullptr;
+  double* qdiag = nullptr;  // (E N)_ii
+  double* wd = nullptr;     // omega / diag(A) of the standard relaxation (set per c, omega)
   bool fusedOK = false;
   bool fused = false;  // sweeps as one fused pass instead of neighbour sum + extension
   int32_t* patchRow = nullptr;

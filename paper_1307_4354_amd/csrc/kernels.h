@@ -61,7 +61,8 @@ void launch_nsum(int dim, int64_t m, const int32_t* ilist, const int32_t* nbrI, 
 // frac: fractions in stencil order.
 template <typename T, typename TO>
 void launch_ext(int dim, int mode, int64_t n, const T* g, const ExtAddr& a, const T* frac, const T* b, T* u,
-                TO* out, T delta, T w_over_delta, unsigned long long* nrm, const LaunchCfg& lc, hipStream_t s);
+                TO* out, T delta, T w_over_delta, unsigned long long* nrm, const LaunchCfg& lc, hipStream_t s,
+                const T* wd = nullptr);  // wd: per-node scale replacing w_over_delta (EXT_SMOOTH)
 
 template <typename T>
 void launch_restrict(int dim, int64_t nc, const T* rf, const int32_t* runR, const T* fracR, T* fc,
@@ -74,6 +75,12 @@ void launch_prolong(int dim, int64_t nf, const T* ec, const int32_t* runP, const
 // y = Z x with Z (n x n, leading dimension ld, double), x, y of type T.
 template <typename T>
 void launch_coarse_gemv(int n, const double* Z, int64_t ld, const T* x, T* y, hipStream_t s);
+
+// standard relaxation: wd = omega / (delta - q) per node
+void launch_std_scale(int64_t n, const double* q, double delta, double omega, double* wd, hipStream_t s);
+// slot[0] = max |u - p| (0 when p is null), slot[1] = max |u|, as bit patterns (atomicMax;
+// the slots must be cleared first)
+void launch_incr(int64_t n, const double* u, const double* p, unsigned long long* slot, hipStream_t s);
 
 // dst = src (n elements)
 template <typename T>
@@ -92,7 +99,7 @@ void launch_record_relres(const unsigned long long* nrm, const unsigned long lon
 
 // Dense coarse operator: M (n x 2n, row-major, ld = 2n) = [delta I - E N | E]
 void launch_assemble_coarse(int dim, int n, const int32_t* runE, const double* fracE, const int32_t* nbr,
-                            double delta, double inv_h2, double* M, hipStream_t s);
+                            double delta, double inv_h2, double* M, hipStream_t s, bool identity_rhs = false);
 // One Gauss-Jordan step with partial pivoting on column k of M (n x 2n).
 void launch_gj_step(int n, int k, double* M, double* col, int* info, hipStream_t s);
 

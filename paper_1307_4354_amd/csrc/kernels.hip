@@ -34,10 +34,11 @@ __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(6, 8)
                                                    const T* __restrict__ frac,
                                                    const T* __restrict__ b, T* __restrict__ u,
                                                    TO* __restrict__ out, T delta, T wod,
-                                                   unsigned long long* __restrict__ nrm, int remap) {
+                                                   unsigned long long* __restrict__ nrm, int remap,
+                                                   const T* __restrict__ wd) {
   const int64_t k = tile_of_block(remap) * blockDim.x + threadIdx.x;
   unsigned long long nv = 0ull;
-  if (k < n) nv = ext_node<D, T, TO, MODE>(k, n, g, perm, packed, origin, frac, b, u, out, delta, wod);
+  if (k < n) nv = ext_node<D, T, TO, MODE>(k, n, g, perm, packed, origin, frac, b, u, out, delta, wod, wd);
   if (MODE != EXT_APPLY && nrm) block_max_atomic(nv, nrm);
 }
 
@@ -65,7 +66,7 @@ __global__ __launch_bounds__(kExtBlock) void k_ext_lds(int64_t n, const T* __res
                                                        const T* __restrict__ frac, const T* __restrict__ b,
                                                        T* __restrict__ u, TO* __restrict__ out, T delta, T wod,
                                                        unsigned long long* __restrict__ nrm, int remap,
-                                                       int lo_offset) {
+                                                       int lo_offset, const T* __restrict__ wd) {
   constexpr int S = D == 2 ? 4 : 16;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   T* gl = (T*)smem;
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(kExtBlock) void k_ext_lds(int64_t n, const T* __res
   ext_stage<T>(blk, g, blkE, gidx, blkG, lorg, S, gl, lo);
   const int64_t k = blk * kExtBlock + threadIdx.x;
   unsigned long long nv = 0ull;
-  if (k < n) nv = ext_node_lds<D, T, TO, MODE>(k, n, gl, lo, perm, packedL, frac, b, u, out, delta, wod);
+  if (k < n) nv = ext_node_lds<D, T, TO, MODE>(k, n, gl, lo, perm, packedL, frac, b, u, out, delta, wod, wd);
   if (MODE != EXT_APPLY && nrm) block_max_atomic(nv, nrm);
 }
 
@@ -151,16 +152,18 @@ __global__ void k_record_relres(const unsigned long long* nrm, const unsigned lo
   }
 }
 
-// Row i of [delta I - E N | E] (one lane per row, so no two lanes write the same row).
+// Row i of [delta I - E N | E] ([delta I - E N | I] when identity_rhs; one lane per row, so no
+// two lanes write the same row).
 template <int D>
 __global__ void k_assemble_coarse(int n, const int32_t* __restrict__ runE,
                                   const double* __restrict__ fracE, const int32_t* __restrict__ nbr,
-                                  double delta, double inv_h2, double* __restrict__ M) {
+                                  double delta, double inv_h2, double* __restrict__ M, bool identity_rhs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int64_t ld = 2 * (int64_t)n;
   double* row = M + (int64_t)i * ld;
   row[i] += delta;
+  if (identity_rhs) row[n + i] = 1.0;
   double wx[4], wy[4], wz[4] = {1.0, 0.0, 0.0, 0.0};
   cubic_weights<double>(fracE[i], wx);
   cubic_weights<double>(fracE[n + i], wy);
@@ -172,7 +175,7 @@ __global__ void k_assemble_coarse(int n, const int32_t* __restrict__ runE,
     for (int a = 0; a < 4; ++a) {
       const int32_t j = j0 + a;
       const double w = wx[a] * wy[bb] * wz[c];
-      row[n + j] += w;
+      if (!identity_rhs) row[n + j] += w;
       for (int k = 0; k < 2 * D; ++k) {
         const int32_t m = nbr[(int64_t)k * n + j];
         if (m >= 0) row[m] -= w * inv_h2;
@@ -271,7 +274,7 @@ void launch_nsum(int dim, int64_t m, const int32_t* ilist, const int32_t* nbrI, 
 
 template <typename T, typename TO>
 void launch_ext(int dim, int mode, int64_t n, const T* g, const ExtAddr& a, const T* frac, const T* b, T* u,
-                TO* out, T delta, T wod, unsigned long long* nrm, const LaunchCfg& lc, hipStream_t s) {
+                TO* out, T delta, T wod, unsigned long long* nrm, const LaunchCfg& lc, hipStream_t s, const T* wd) {
   if (n <= 0) return;
   if (a.packedL) {
     // LDS-staged path: fixed workgroup of kExtBlock stencil slots (the staging tables are
@@ -283,7 +286,7 @@ void launch_ext(int dim, int mode, int64_t n, const T* g, const ExtAddr& a, cons
     const int rm = lc.xcd_remap;
 #define CPM_EXTL_CASE(DD, MM)                                                                         \
   k_ext_lds<DD, T, TO, MM><<<gl, kExtBlock, shm, s>>>(n, g, a.perm, a.packedL, a.blkE, a.gidx, a.blkG, a.lorg, \
-                                                       frac, b, u, out, delta, wod, nrm, rm, lo_off)
+                                                       frac, b, u, out, delta, wod, nrm, rm, lo_off, wd)
     if (dim == 2) {
       switch (mode) {
         case EXT_SMOOTH: CPM_EXTL_CASE(2, EXT_SMOOTH); break;
@@ -306,7 +309,7 @@ void launch_ext(int dim, int mode, int64_t n, const T* g, const ExtAddr& a, cons
   const int rm = lc.xcd_remap;
 #define CPM_EXT_CASE(DD, MM)                                                                        \
   k_ext<DD, T, TO, MM><<<gr, lc.block, 0, s>>>(n, g, a.perm, a.packed, a.origin, frac, b, u, out, delta, wod, \
-                                               nrm, rm)
+                                               nrm, rm, wd)
   if (dim == 2) {
     switch (mode) {
       case EXT_SMOOTH: CPM_EXT_CASE(2, EXT_SMOOTH); break;
@@ -390,12 +393,12 @@ void launch_record_relres(const unsigned long long* nrm, const unsigned long lon
 }
 
 void launch_assemble_coarse(int dim, int n, const int32_t* runE, const double* fracE, const int32_t* nbr,
-                            double delta, double inv_h2, double* M, hipStream_t s) {
+                            double delta, double inv_h2, double* M, hipStream_t s, bool identity_rhs) {
   launch_fill<double>(2 * (int64_t)n * n, M, 0.0, s);
   if (dim == 2)
-    k_assemble_coarse<2><<<grid_for(n, 128), 128, 0, s>>>(n, runE, fracE, nbr, delta, inv_h2, M);
+    k_assemble_coarse<2><<<grid_for(n, 128), 128, 0, s>>>(n, runE, fracE, nbr, delta, inv_h2, M, identity_rhs);
   else
-    k_assemble_coarse<3><<<grid_for(n, 128), 128, 0, s>>>(n, runE, fracE, nbr, delta, inv_h2, M);
+    k_assemble_coarse<3><<<grid_for(n, 128), 128, 0, s>>>(n, runE, fracE, nbr, delta, inv_h2, M, identity_rhs);
 }
 
 void launch_gj_step(int n, int k, double* M, double* col, int* info, hipStream_t s) {
@@ -423,6 +426,33 @@ void launch_sweep(int dim, int mode, int64_t n, const T* u, T* uo, const T* Ef, 
 #undef CPM_SWEEP_CASE
 }
 
+__global__ void k_std_scale(int64_t n, const double* __restrict__ q, double dc, double omega,
+                            double* __restrict__ wd) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) wd[i] = omega / (dc - q[i]);
+}
+
+void launch_std_scale(int64_t n, const double* q, double delta, double omega, double* wd, hipStream_t s) {
+  if (n > 0) k_std_scale<<<grid_for(n, 256), 256, 0, s>>>(n, q, delta, omega, wd);
+}
+
+// slot[0] = max |u - p| and slot[1] = max |u| (bit patterns, atomicMax); p may be null
+__global__ __launch_bounds__(256) void k_incr(int64_t n, const double* __restrict__ u, const double* __restrict__ p,
+                                              unsigned long long* __restrict__ slot) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  unsigned long long d = 0ull, m = 0ull;
+  if (i < n) {
+    m = abs_bits(u[i]);
+    if (p) d = abs_bits(u[i] - p[i]);
+  }
+  block_max_atomic(d, slot);
+  block_max_atomic(m, slot + 1);
+}
+
+void launch_incr(int64_t n, const double* u, const double* p, unsigned long long* slot, hipStream_t s) {
+  if (n > 0) k_incr<<<grid_for(n, 256), 256, 0, s>>>(n, u, p, slot);
+}
+
 // explicit instantiations
 template void launch_nsum<double>(int, int64_t, const int32_t*, const int32_t*, const double*, const double*, double,
                                   double*, unsigned long long*, const LaunchCfg&, hipStream_t);
@@ -430,13 +460,13 @@ template void launch_nsum<float>(int, int64_t, const int32_t*, const int32_t*, c
                                  float*, unsigned long long*, const LaunchCfg&, hipStream_t);
 template void launch_ext<double, double>(int, int, int64_t, const double*, const ExtAddr&, const double*,
                                          const double*, double*, double*, double, double,
-                                         unsigned long long*, const LaunchCfg&, hipStream_t);
+                                         unsigned long long*, const LaunchCfg&, hipStream_t, const double*);
 template void launch_ext<double, float>(int, int, int64_t, const double*, const ExtAddr&, const double*,
                                         const double*, double*, float*, double, double,
-                                        unsigned long long*, const LaunchCfg&, hipStream_t);
+                                        unsigned long long*, const LaunchCfg&, hipStream_t, const double*);
 template void launch_ext<float, float>(int, int, int64_t, const float*, const ExtAddr&, const float*,
                                        const float*, float*, float*, float, float, unsigned long long*,
-                                       const LaunchCfg&, hipStream_t);
+                                       const LaunchCfg&, hipStream_t, const float*);
 template void launch_sweep<double>(int, int, int64_t, const double*, double*, const double*, const double*,
                                    const SweepAddr&, const double*, double, double, double, const LaunchCfg&,
                                    hipStream_t);

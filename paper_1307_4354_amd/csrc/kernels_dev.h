@@ -101,7 +101,7 @@ __device__ __forceinline__ unsigned long long ext_node(int64_t k, int64_t n, con
                                                        const int32_t* __restrict__ origin,
                                                        const T* __restrict__ frac, const T* __restrict__ b,
                                                        T* __restrict__ u, TO* __restrict__ out, T delta,
-                                                       T wod) {
+                                                       T wod, const T* __restrict__ wd = nullptr) {
   constexpr int S = D == 2 ? 4 : 16;
   const int32_t i = perm ? perm[k] : (int32_t)k;  // null perm: band order
   const int32_t pk = packed[k];
@@ -128,7 +128,7 @@ __device__ __forceinline__ unsigned long long ext_node(int64_t k, int64_t n, con
     const T ui = u[i];
     T r = t - delta * ui;
     if (b) r += b[i];
-    u[i] = ui + wod * r;
+    u[i] = ui + (wd ? wd[i] : wod) * r;  // wd: per-node scale of the standard relaxation
     if (out) out[i] = (TO)t;  // optionally keep E g
     return abs_bits((double)r);
   } else if (MODE == EXT_RESID) {
@@ -274,7 +274,8 @@ __device__ __forceinline__ unsigned long long ext_node_lds(int64_t k, int64_t n,
                                                            const int32_t* __restrict__ perm,
                                                            const int32_t* __restrict__ packedL,
                                                            const T* __restrict__ frac, const T* __restrict__ b,
-                                                           T* __restrict__ u, TO* __restrict__ out, T delta, T wod) {
+                                                           T* __restrict__ u, TO* __restrict__ out, T delta, T wod,
+                                                           const T* __restrict__ wd = nullptr) {
   constexpr int S = D == 2 ? 4 : 16;
   const int32_t i = perm[k];
   const int32_t pk = packedL[k];
@@ -301,7 +302,7 @@ __device__ __forceinline__ unsigned long long ext_node_lds(int64_t k, int64_t n,
     const T ui = u[i];
     T r = t - delta * ui;
     if (b) r += b[i];
-    u[i] = ui + wod * r;
+    u[i] = ui + (wd ? wd[i] : wod) * r;  // wd: per-node scale of the standard relaxation
     if (out) out[i] = (TO)t;  // optionally keep E g
     return abs_bits((double)r);
   } else if (MODE == EXT_RESID) {
