@@ -14,6 +14,8 @@ Layout (each function cites the passage of the paper it follows):
                 coarsest direct solve, solve loop
 * ``direct``    assembled matrix A = cI - M of eq. (3.3) and sparse direct solves
 * ``mixed``     FP32-inner / FP64-outer iterative refinement of the same V-cycle
+* ``standard``  the V-cycle with standard relaxation: Jacobi on A, residual f - A(E u) (Sec. 4.5)
+* ``varcoef``   variable diffusion coefficients: flux-form L~ and its V-cycle
 * ``mlp``       reference forward / backward of the learned local smoother network
 * ``errors``    error evaluation on the surface by cubic interpolation (Sec. 3.4)
 

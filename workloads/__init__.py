@@ -105,6 +105,8 @@ class Problem:
     f: Callable[[np.ndarray], np.ndarray]
     u_exact: Optional[Callable[[np.ndarray], np.ndarray]]
     name: str = ""
+    # scalar diffusion coefficient a(y) of -div_S(a grad_S u) + c u = f (None: a = 1)
+    a: Optional[Callable[[np.ndarray], np.ndarray]] = None
 
 
 def circle_sin12(c: float = 1.0) -> Problem:
@@ -134,6 +136,24 @@ def sphere_l3(c: float = 1.0) -> Problem:
         return (12.0 + c) * u(Y)
 
     return Problem(s, c, f, u, "sphere_l3")
+
+
+def sphere_varcoef(c: float = 1.0) -> Problem:
+    """Unit sphere, variable diffusion a = cos(phi) + 1.5 and u = cos(phi), phi the polar
+    angle (cos(phi) = z): -div_S(a grad_S u) = 2 z (z + 1.5) - (1 - z^2)."""
+    s = unit_sphere()
+
+    def u(Y):
+        return _sphere_dirs(Y, s)[:, 2]
+
+    def a(Y):
+        return u(Y) + 1.5
+
+    def f(Y):
+        z = u(Y)
+        return 2.0 * z * (z + 1.5) - (1.0 - z * z) + c * z
+
+    return Problem(s, c, f, u, "sphere_varcoef", a=a)
 
 
 def sphere_l5_paper(c: float = 1.0) -> Problem:
@@ -273,6 +293,11 @@ def config_circle(h_inv: int = 64, levels: int = 4) -> SolverConfig:
 def config_sphere(h_inv: int = 64, levels: int = 5) -> SolverConfig:
     """3-D FP64 workload: unit sphere, l = 3 harmonic, h = 1/64 coarsened to 1/4 (5 levels)."""
     return SolverConfig("sphere_h%d" % h_inv, sphere_l3(), 1.0 / h_inv, levels, LAM2_3D)
+
+
+def config_sphere_varcoef(h_inv: int = 64, levels: int = 5) -> SolverConfig:
+    """Variable-coefficient workload: unit sphere, a = z + 1.5, u = z, h = 1/64 to 1/4."""
+    return SolverConfig("sphere_vc_h%d" % h_inv, sphere_varcoef(), 1.0 / h_inv, levels, LAM2_3D)
 
 
 def config_torus_mixed(h_inv: int = 256, levels: Optional[int] = None, seed_offset: int = 3) -> SolverConfig:
