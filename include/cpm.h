@@ -160,7 +160,20 @@ cpm_status cpm_apply(cpm_band band, int level, double c, const double* u, double
  * interpolation, Sec. 3.1).  double device vectors of length n(level), not overlapping. */
 cpm_status cpm_extend(cpm_band band, int level, const double* g, double* out, void* stream);
 
-/* One V(nu1, nu2) cycle in place on u (Algorithm 4.1) for right-hand side f.  work has
+/* Variable diffusion coefficient: -div_S(a grad_S u) + c u = f (Sec. 2.2; the variable-
+ * coefficient sphere example of the numerical section).  a is a host array of n(level)
+ * doubles, a(cp(x_i)) > 0 for the nodes of `level` in band order (closest points from
+ * cpm_band_export), copied.  The discrete operator is the flux form
+ * L~ = sum over axes of D^b diag(A^f a) D^f, smoothed with the Ruuth-Merriman step on
+ * cI - L~ (Jacobi, then the extension); a level's residual is r = D (E u~ - u), u~ the
+ * undamped Jacobi step and D = c + sigma its diagonal, and the coarsest level solves the
+ * smoother's fixed-point equation densely.  The coefficient takes effect once every level
+ * has one; a = NULL (any level) removes it from all levels.  While set, solves accept
+ * precision CPM_F64 with smoother CPM_SMOOTH_JACOBI only; relres is ||r|| / ||D E (f / D)||.
+ * cpm_apply and the batched solver keep the constant-coefficient operator.  Synchronous. */
+cpm_status cpm_set_diffusion(cpm_band band, int level, const double* a);
+
+/* One V(nu1, nu2) cycle in place on u (Algorithm 4.1) for right-hand side f./* One V(nu1, nu2) cycle in place on u (Algorithm 4.1) for right-hand side f.  work has
  * cpm_workspace_size bytes.  If relres_out is not NULL the call synchronizes the stream
  * and stores ||E f - A u||_inf / ||E f||_inf of the new iterate (the relative increment
  * for CPM_SMOOTH_STANDARD).  Only precision CPM_F64 with smoother CPM_SMOOTH_JACOBI or

@@ -93,6 +93,7 @@ def _load():
         "cpm_band_tuning": (c_int, [vp, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int),
                                     POINTER(c_int)]),
         "cpm_set_smoother_weights": (c_int, [vp, vp, c_double]),
+        "cpm_set_diffusion": (c_int, [vp, c_int, vp]),
         "cpm_mlp_forward": (c_int, [c_int64, vp, vp, vp, vp, vp]),
         "cpm_mlp_backward": (c_int, [c_int64, vp, vp, vp, vp, vp, vp, vp]),
         "cpm_mlp_adam": (c_int, [c_int, ctypes.c_float, vp, vp, vp, vp, vp, vp]),
@@ -232,6 +233,18 @@ def cpm_extend(band: Band, level: int, g, out, stream=None) -> None:
     _check(_lib.cpm_extend(band.handle, level, _ptr(g), _ptr(out), _stream(stream)))
 
 
+def cpm_set_diffusion(band: Band, level: int, a) -> None:
+    """Variable diffusion coefficient a(cp(x_i)) on one level (host float64 array of n(level)
+    values, copied); a = None removes it from every level."""
+    if a is None:
+        _check(_lib.cpm_set_diffusion(band.handle, int(level), None))
+        return
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    if arr.shape != (band.n(level),):
+        raise ValueError("coefficient must have n(level) = %d values" % band.n(level))
+    _check(_lib.cpm_set_diffusion(band.handle, int(level), arr.ctypes.data_as(c_void_p)))
+
+
 def cpm_vcycle(band: Band, params: cpm_params, f, u, work, work_bytes: int, want_relres: bool = False,
                stream=None) -> Optional[float]:
     rr = c_double(0.0)
@@ -253,6 +266,8 @@ def cpm_solve(band: Band, params: cpm_params, f, u, work, work_bytes: int, rtol:
 
 def cpm_run_cycles(band: Band, params: cpm_params, f, u, work, work_bytes: int, cycles: int,
                    cycles_per_launch: int, relres_dev, stream=None) -> None:
+    if hasattr(relres_dev, "numel") and relres_dev.numel() < cycles:
+        raise ValueError("relres_dev holds %d values, %d cycles record one each" % (relres_dev.numel(), cycles))
     _check(_lib.cpm_run_cycles(band.handle, byref(params), _ptr(f), _ptr(u), _ptr(work), work_bytes, int(cycles),
                                int(cycles_per_launch), _ptr(relres_dev), _stream(stream)))
 

@@ -89,7 +89,7 @@ static void free_dev(cpm_band b) {
     void* ps[] = {D.runE,  D.nbr,   D.fracE,  D.fracE32, D.runP,    D.fracP,  D.fracP32, D.runR,
                   D.fracR, D.fracR32, D.perm, D.packed, D.origin, D.fracK, D.fracK32, D.ilist, D.nbrI,
                   D.patchRow, D.patchMask, D.packedB, D.packedL, D.blkE, D.gidx, D.blkG, D.lorg, D.originX,
-                  D.qdiag, D.wd};
+                  D.qdiag, D.wd, D.acoef, D.vcD};
     for (void* p : ps)
       if (p) (void)hipFree(p);
   }
@@ -139,6 +139,8 @@ cpm_status check_launch(const char* what) {
 // partial pivoting on [A_c | E_c] on the device.  Cached per value of c.
 // Dense inverse on the coarsest level: Gauss-Jordan on [A_c | E_c] (-> A_c^{-1} E_c, the
 // Ruuth-Merriman cycles) or on [A_c | I] (-> A_c^{-1}, the standard relaxation).
+static cpm_status ensure_vc_diag(cpm_band b, double c);
+
 static cpm_status coarse_inverse(cpm_band b, double c, bool identity_rhs, double** M, double* cached_c) {
   if (*M && *cached_c == c) return CPM_OK;
   const int l = b->L - 1;
@@ -161,8 +163,14 @@ static cpm_status coarse_inverse(cpm_band b, double c, bool identity_rhs, double
   }
   hipStream_t s = b->stream;
   const double h = D.h;
-  launch_assemble_coarse(b->dim, n, D.runE, D.fracE, D.nbr, level_delta(b, l, c), 1.0 / (h * h), *M, s,
-                         identity_rhs);
+  if (b->vc_active && !identity_rhs) {
+    // variable coefficient: [I - E D^{-1} N~ | E D^{-1}]
+    if ((st = ensure_vc_diag(b, c)) != CPM_OK) return st;
+    launch_assemble_coarse_vc(b->dim, n, D.runE, D.fracE, D.nbr, D.acoef, D.vcD, 1.0 / (h * h), *M, s);
+  } else {
+    launch_assemble_coarse(b->dim, n, D.runE, D.fracE, D.nbr, level_delta(b, l, c), 1.0 / (h * h), *M, s,
+                           identity_rhs);
+  }
   launch_fill<int>(1, b->gj_info, 0, s);
   for (int k = 0; k < n; ++k) launch_gj_step(n, k, *M, b->gj_col, b->gj_info, s);
   if ((st = check_launch("coarse factorization")) != CPM_OK) return st;
@@ -182,6 +190,23 @@ static cpm_status coarse_inverse(cpm_band b, double c, bool identity_rhs, double
 }
 
 cpm_status ensure_coarse(cpm_band b, double c) { return coarse_inverse(b, c, false, &b->coarseM, &b->coarse_c); }
+
+// Variable coefficient: D = c + sigma on every level for this c.
+static cpm_status ensure_vc_diag(cpm_band b, double c) {
+  if (b->vc_c == c) return CPM_OK;
+  cpm_status st = CPM_OK;
+  for (int l = 0; l < b->L; ++l) {
+    DevLevel& D = b->dev[(size_t)l];
+    if (!D.vcD && !(D.vcD = dalloc<double>((size_t)D.n, &st))) {
+      set_error("device allocation of the variable-coefficient diagonal failed");
+      return st != CPM_OK ? st : CPM_E_NOMEM;
+    }
+    launch_vc_diag(b->dim, D.n, D.nbr, D.acoef, c, 1.0 / (D.h * D.h), D.vcD, b->stream);
+  }
+  if ((st = check_launch("variable-coefficient diagonal")) != CPM_OK) return st;
+  b->vc_c = c;
+  return CPM_OK;
+}
 
 // Standard relaxation: A_c^{-1} and omega / diag(A) on every level for (c, omega).
 static cpm_status ensure_std(cpm_band b, double c, double omega) {
@@ -313,6 +338,16 @@ void smooth_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g
   const DevLevel& D = b->dev[(size_t)l];
   const LaunchCfg lc = level_cfg(D);
   const double delta = level_delta(b, l, c);
+  if constexpr (sizeof(T) == 8) {
+    if (b->vc_active) {
+      // variable coefficient: g = (f + N~ u) / D, u <- u + omega (E g - u)
+      launch_nsum_var(b->dim, D.m, D.ilist, D.nbrI, u_zero ? nullptr : u, f, D.acoef, D.vcD, 1.0 / (D.h * D.h), g,
+                      lc, s);
+      launch_ext<T, T>(b->dim, EXT_SMOOTH, D.n, g, ext_addr(D), fracK_of<T>(D), rhsA, u, (T*)nullptr, (T)1.0,
+                       (T)omega, nrm, ext_cfg(D), s);
+      return;
+    }
+  }
   const T* gg = g;
   if (u_zero && f)
     gg = f;
@@ -395,7 +430,7 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
   const int nu2 = learned ? p.learned_sweeps : p.nu2;
   const bool u_zero = l > 0;  // the restriction into this level set u = 0
   const DevLevel& C = b->dev[(size_t)(l + 1)];
-  if (D.fused && D.fusedOK && !learned_here) {
+  if (D.fused && D.fusedOK && !learned_here && !b->vc_active) {
     T* cur = fused_pre<T>(b, l, B, f, rhsA, p, nu1, u_zero, s);
     launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
     vcycle_level<T>(b, l + 1, B, nullptr, p, s);
@@ -406,7 +441,19 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
   for (int k = 0; k < nu1; ++k)
     smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s, u_zero && k == 0);
   // residual r = b + E(f + N u) - delta u, restricted to the next level (where u := 0)
-  if (u_zero && nu1 == 0 && f) {
+  bool resid_done = false;
+  if constexpr (sizeof(T) == 8) {
+    if (b->vc_active) {
+      // variable coefficient: r = D (E g - u), g = (f + N~ u) / D
+      launch_nsum_var(b->dim, D.m, D.ilist, D.nbrI, (u_zero && nu1 == 0) ? nullptr : B[l].u, f, D.acoef, D.vcD,
+                      1.0 / (D.h * D.h), B[l].g, lc, s);
+      launch_ext<T, T>(b->dim, EXT_RESID, D.n, B[l].g, ext_addr(D), fracK_of<T>(D), rhsA, B[l].u, B[l].r, (T)1.0,
+                       (T)0, nullptr, ext_cfg(D), s, D.vcD);
+      resid_done = true;
+    }
+  }
+  if (resid_done) {
+  } else if (u_zero && nu1 == 0 && f) {
     launch_ext<T, T>(b->dim, EXT_RESID, D.n, f, ext_addr(D), fracK_of<T>(D), rhsA, B[l].u, B[l].r, (T)delta,
                      (T)0, nullptr, ext_cfg(D), s);
   } else {
@@ -454,6 +501,13 @@ static void vcycle_std(const cpm_band b, int l, LevelBufs<double>* B, const cpm_
 void enqueue_rhs_norm(const cpm_band b, const double* f, double* g, hipStream_t s) {
   const DevLevel& D = b->dev[0];
   launch_zero_u64(b->dscal + 1, 1, s);
+  if (b->vc_active) {
+    // ||D E (f / D)||_inf: g = f / D, then the residual form with delta = 0 scaled by D
+    launch_nsum_var(b->dim, D.m, D.ilist, D.nbrI, nullptr, f, D.acoef, D.vcD, 1.0 / (D.h * D.h), g, level_cfg(D), s);
+    launch_ext<double, double>(b->dim, EXT_RESID, D.n, g, ext_addr(D), fracK_of<double>(D), nullptr, g,
+                               (double*)nullptr, 0.0, 0.0, b->dscal + 1, ext_cfg(D), s, D.vcD);
+    return;
+  }
   launch_ext<double, double>(b->dim, EXT_PLAIN, D.n, f, ext_addr(D), fracK_of<double>(D), nullptr, nullptr, (double*)nullptr,
                              0.0, 0.0, b->dscal + 1, ext_cfg(D), s);
 }
@@ -463,6 +517,13 @@ void enqueue_resid64(const cpm_band b, const double* f, const double* u, double*
                      hipStream_t s) {
   const DevLevel& D = b->dev[0];
   const LaunchCfg lc = level_cfg(D);
+  if (b->vc_active) {
+    launch_zero_u64(b->dscal, 1, s);
+    launch_nsum_var(b->dim, D.m, D.ilist, D.nbrI, u, f, D.acoef, D.vcD, 1.0 / (D.h * D.h), g, lc, s);
+    launch_ext<double, float>(b->dim, EXT_RESID, D.n, g, ext_addr(D), fracK_of<double>(D), nullptr,
+                              const_cast<double*>(u), r32, 1.0, 0.0, b->dscal, ext_cfg(D), s, D.vcD);
+    return;
+  }
   launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, u, f, 1.0 / (D.h * D.h), g, b->dscal, lc, s);
   launch_ext<double, float>(b->dim, EXT_RESID, D.n, g, ext_addr(D), fracK_of<double>(D), nullptr, const_cast<double*>(u), r32,
                             level_delta(b, 0, c), 0.0, b->dscal, ext_cfg(D), s);
@@ -603,6 +664,10 @@ cpm_status validate_params(const cpm_band b, const cpm_params* p) {
   }
   if (p->smoother != CPM_SMOOTH_JACOBI && p->smoother != CPM_SMOOTH_LEARNED && p->smoother != CPM_SMOOTH_STANDARD) {
     set_error("unknown smoother");
+    return CPM_E_INVALID;
+  }
+  if (b->vc_active && (p->precision != CPM_F64 || p->smoother != CPM_SMOOTH_JACOBI)) {
+    set_error("a variable diffusion coefficient runs with precision CPM_F64 and smoother CPM_SMOOTH_JACOBI only");
     return CPM_E_INVALID;
   }
   if (p->smoother == CPM_SMOOTH_STANDARD && p->precision != CPM_F64) {
@@ -767,7 +832,7 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     std::vector<int32_t>().swap(H.runE);
     std::vector<int32_t>().swap(H.runP);
     std::vector<int32_t>().swap(H.runR);
-    std::vector<int32_t>().swap(H.nbr);
+    // H.nbr stays on the host: cpm_set_diffusion uploads it for levels that get a coefficient
     std::vector<int32_t>().swap(H.perm);
     std::vector<int32_t>().swap(H.packed);
     std::vector<int32_t>().swap(H.packedB);
@@ -934,6 +999,47 @@ cpm_status cpm_extend(cpm_band band, int level, const double* g, double* out, vo
                              nullptr, ext_cfg(D), band->stream);
   if ((st = check_launch("cpm_extend")) != CPM_OK) return st;
   return leave(band, stream);
+}
+
+cpm_status cpm_set_diffusion(cpm_band band, int level, const double* a) {
+  if (!band || level < 0 || level >= band->L) {
+    set_error("cpm_set_diffusion: invalid argument");
+    return CPM_E_INVALID;
+  }
+  if (hipStreamSynchronize(band->stream) != hipSuccess) {
+    set_error("cpm_set_diffusion: synchronization failed");
+    return CPM_E_HIP;
+  }
+  band->vc_c = NAN;
+  band->coarse_c = NAN;  // the coarsest inverse changes form
+  for (auto& kv : band->graphs) (void)hipGraphExecDestroy(kv.second);
+  band->graphs.clear();
+  if (!a) {
+    for (auto& D : band->dev) {
+      if (D.acoef) (void)hipFree(D.acoef);
+      D.acoef = nullptr;
+    }
+    band->vc_active = false;
+    return CPM_OK;
+  }
+  DevLevel& D = band->dev[(size_t)level];
+  const HostLevel& H = band->host[(size_t)level];
+  for (int64_t i = 0; i < D.n; ++i)
+    if (!(a[i] > 0.0) || !std::isfinite(a[i])) {
+      set_error("cpm_set_diffusion: the coefficient must be positive and finite");
+      return CPM_E_INVALID;
+    }
+  cpm_status st = CPM_OK;
+  if (!D.acoef && !(D.acoef = dalloc<double>((size_t)D.n, &st))) return st != CPM_OK ? st : CPM_E_NOMEM;
+  if (hipMemcpy(D.acoef, a, (size_t)D.n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("cpm_set_diffusion: copy failed");
+    return CPM_E_HIP;
+  }
+  if (!D.nbr && (st = upload(&D.nbr, H.nbr)) != CPM_OK) return st;
+  bool all = true;
+  for (auto& Dl : band->dev) all = all && Dl.acoef != nullptr;
+  band->vc_active = all;
+  return CPM_OK;
 }
 
 cpm_status cpm_vcycle(cpm_band band, const cpm_params* params, const double* f, double* u, void* work,

@@ -44,6 +44,9 @@ struct cpm_band_s {
   double* coarseS = nullptr;
   double coarse_std_c = 0.0 / 0.0;
   double std_c = 0.0 / 0.0, std_omega = 0.0 / 0.0;
+  // variable diffusion coefficient: set on every level (vc_active), diagonals valid for vc_c
+  bool vc_active = false;
+  double vc_c = 0.0 / 0.0;
   double* gj_col = nullptr;
   int* gj_info = nullptr;
   // device scalars: [0] residual norm bits, [1] ||E f|| bits; relres history + counter

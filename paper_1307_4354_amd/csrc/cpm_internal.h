@@ -114,6 +114,8 @@ struct DevLevel {
   float* fracR32 = nullptr;
   int32_t* originX = nullptr;
   double* qdiag = nullptr;  // (E N)_ii
+  double* acoef = nullptr;  // variable diffusion coefficient a(cp(x_i)) (cpm_set_diffusion)
+  double* vcD = nullptr;    // c + sigma_i of the flux-form operator, for vc_c
   double* wd = nullptr;     // omega / diag(A) of the standard relaxation (set per c, omega)
   bool fusedOK = false;
   bool fused = false;  // sweeps as one fused pass instead of neighbour sum + extension

@@ -62,7 +62,8 @@ void launch_nsum(int dim, int64_t m, const int32_t* ilist, const int32_t* nbrI, 
 template <typename T, typename TO>
 void launch_ext(int dim, int mode, int64_t n, const T* g, const ExtAddr& a, const T* frac, const T* b, T* u,
                 TO* out, T delta, T w_over_delta, unsigned long long* nrm, const LaunchCfg& lc, hipStream_t s,
-                const T* wd = nullptr);  // wd: per-node scale replacing w_over_delta (EXT_SMOOTH)
+                const T* wd = nullptr);  // wd: per-node factor: EXT_SMOOTH uses it in place of
+                                         // w_over_delta, EXT_RESID multiplies the residual by it
 
 template <typename T>
 void launch_restrict(int dim, int64_t nc, const T* rf, const int32_t* runR, const T* fracR, T* fc,
@@ -81,6 +82,16 @@ void launch_std_scale(int64_t n, const double* q, double delta, double omega, do
 // slot[0] = max |u - p| (0 when p is null), slot[1] = max |u|, as bit patterns (atomicMax;
 // the slots must be cleared first)
 void launch_incr(int64_t n, const double* u, const double* p, unsigned long long* slot, hipStream_t s);
+
+// Variable diffusion coefficient (flux form): g = (f + N~ u) / D on B_interp (u, f may be
+// null); D_i = c + sigma_i on every node; the coarsest level's [I - E D^{-1} N~ | E D^{-1}].
+void launch_nsum_var(int dim, int64_t m, const int32_t* ilist, const int32_t* nbrI, const double* u,
+                     const double* f, const double* a, const double* Dd, double inv_h2, double* g,
+                     const LaunchCfg& lc, hipStream_t s);
+void launch_vc_diag(int dim, int64_t n, const int32_t* nbr, const double* a, double c, double inv_h2, double* Dd,
+                    hipStream_t s);
+void launch_assemble_coarse_vc(int dim, int n, const int32_t* runE, const double* fracE, const int32_t* nbr,
+                               const double* a, const double* Dd, double inv_h2, double* M, hipStream_t s);
 
 // dst = src (n elements)
 template <typename T>

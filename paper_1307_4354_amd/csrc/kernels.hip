@@ -453,6 +453,87 @@ void launch_incr(int64_t n, const double* u, const double* p, unsigned long long
   if (n > 0) k_incr<<<grid_for(n, 256), 256, 0, s>>>(n, u, p, slot);
 }
 
+template <int D, typename T>
+__global__ __launch_bounds__(kMaxBlock) void k_nsum_var(int64_t m, const int32_t* __restrict__ ilist,
+                                                        const int32_t* __restrict__ nbrI, const T* __restrict__ u,
+                                                        const T* __restrict__ f, const T* __restrict__ a,
+                                                        const T* __restrict__ Dd, T inv_h2, T* __restrict__ g,
+                                                        int remap) {
+  const int64_t k = tile_of_block(remap) * blockDim.x + threadIdx.x;
+  if (k < m) nsum_var_node<D, T>(k, m, ilist, nbrI, u, f, a, Dd, inv_h2, g);
+}
+
+void launch_nsum_var(int dim, int64_t m, const int32_t* ilist, const int32_t* nbrI, const double* u,
+                     const double* f, const double* a, const double* Dd, double inv_h2, double* g,
+                     const LaunchCfg& lc, hipStream_t s) {
+  if (m <= 0) return;
+  const unsigned gr = grid_for(m, lc.block);
+  if (dim == 2)
+    k_nsum_var<2, double><<<gr, lc.block, 0, s>>>(m, ilist, nbrI, u, f, a, Dd, inv_h2, g, lc.xcd_remap);
+  else
+    k_nsum_var<3, double><<<gr, lc.block, 0, s>>>(m, ilist, nbrI, u, f, a, Dd, inv_h2, g, lc.xcd_remap);
+}
+
+// D_i = c + sigma_i, sigma_i = sum over the 2d axis directions of (a_i + a_q) / 2 / h^2, a
+// missing neighbour counting with a_i (so that a = 1 gives the 2d/h^2 of every row of L).
+__global__ void k_vc_diag(int64_t n, int nq, const int32_t* __restrict__ nbr, const double* __restrict__ a,
+                          double c, double inv_h2, double* __restrict__ Dd) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double ai = a[i];
+  double s = 0.0;
+  for (int q = 0; q < nq; ++q) {
+    const int32_t j = nbr[(int64_t)q * n + i];
+    s += j >= 0 ? 0.5 * (ai + a[j]) : ai;
+  }
+  Dd[i] = c + s * inv_h2;
+}
+
+void launch_vc_diag(int dim, int64_t n, const int32_t* nbr, const double* a, double c, double inv_h2, double* Dd,
+                    hipStream_t s) {
+  if (n > 0) k_vc_diag<<<grid_for(n, 256), 256, 0, s>>>(n, 2 * dim, nbr, a, c, inv_h2, Dd);
+}
+
+// Row i of [I - E D^{-1} N~ | E D^{-1}] on the coarsest level (variable coefficient): the
+// fixed-point equation of its Ruuth-Merriman smoother.  One lane per row.
+template <int D>
+__global__ void k_assemble_coarse_vc(int n, const int32_t* __restrict__ runE, const double* __restrict__ fracE,
+                                     const int32_t* __restrict__ nbr, const double* __restrict__ a,
+                                     const double* __restrict__ Dd, double inv_h2, double* __restrict__ M) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t ld = 2 * (int64_t)n;
+  double* row = M + (int64_t)i * ld;
+  row[i] += 1.0;
+  double wx[4], wy[4], wz[4] = {1.0, 0.0, 0.0, 0.0};
+  cubic_weights<double>(fracE[i], wx);
+  cubic_weights<double>(fracE[n + i], wy);
+  if (D == 3) cubic_weights<double>(fracE[2 * n + i], wz);
+  const int nruns = D == 2 ? 4 : 16;
+  for (int r = 0; r < nruns; ++r) {
+    const int bb = r & 3, c = r >> 2;
+    const int32_t j0 = runE[(int64_t)r * n + i];
+    for (int q = 0; q < 4; ++q) {
+      const int32_t j = j0 + q;
+      const double w = wx[q] * wy[bb] * wz[c] / Dd[j];
+      row[n + j] += w;
+      for (int k = 0; k < 2 * D; ++k) {
+        const int32_t mm = nbr[(int64_t)k * n + j];
+        if (mm >= 0) row[mm] -= w * 0.5 * (a[j] + a[mm]) * inv_h2;
+      }
+    }
+  }
+}
+
+void launch_assemble_coarse_vc(int dim, int n, const int32_t* runE, const double* fracE, const int32_t* nbr,
+                               const double* a, const double* Dd, double inv_h2, double* M, hipStream_t s) {
+  launch_fill<double>(2 * (int64_t)n * n, M, 0.0, s);
+  if (dim == 2)
+    k_assemble_coarse_vc<2><<<grid_for(n, 128), 128, 0, s>>>(n, runE, fracE, nbr, a, Dd, inv_h2, M);
+  else
+    k_assemble_coarse_vc<3><<<grid_for(n, 128), 128, 0, s>>>(n, runE, fracE, nbr, a, Dd, inv_h2, M);
+}
+
 // explicit instantiations
 template void launch_nsum<double>(int, int64_t, const int32_t*, const int32_t*, const double*, const double*, double,
                                   double*, unsigned long long*, const LaunchCfg&, hipStream_t);

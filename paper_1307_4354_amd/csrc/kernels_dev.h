@@ -71,6 +71,30 @@ __device__ __forceinline__ void nsum_node(int64_t k, int64_t m, const int32_t* _
   g[j] = gj;
 }
 
+// Variable coefficient: g_j = (f_j + sum_q abar_q u_q / h^2) / D_j at node k of B_interp,
+// abar_q = (a_j + a_q) / 2 over the 2d axis neighbours q (the flux form D^b diag(A^f a) D^f),
+// D_j = c + sigma_j precomputed.  u may be null (g = f / D), f may be null.
+template <int D, typename T>
+__device__ __forceinline__ void nsum_var_node(int64_t k, int64_t m, const int32_t* __restrict__ ilist,
+                                              const int32_t* __restrict__ nbrI, const T* __restrict__ u,
+                                              const T* __restrict__ f, const T* __restrict__ a,
+                                              const T* __restrict__ Dd, T inv_h2, T* __restrict__ g) {
+  const int32_t j = ilist[k];
+  T gj = T(0);
+  if (u) {
+    const T aj = a[j];
+    T s = (aj + a[j - 1]) * u[j - 1] + (aj + a[j + 1]) * u[j + 1];
+#pragma unroll
+    for (int q = 0; q < 2 * D - 2; ++q) {
+      const int32_t nq = nbrI[q * m + k];
+      s += (aj + a[nq]) * u[nq];
+    }
+    gj = T(0.5) * s * inv_h2;
+  }
+  if (f) gj += f[j];
+  g[j] = gj / Dd[j];
+}
+
 // Weighted sum of one x-run of 4 consecutive values, loaded with 16-byte vector loads
 // (the run start is only element aligned; global loads of several dwords need dword
 // alignment, which every double and float address has).
@@ -134,6 +158,7 @@ __device__ __forceinline__ unsigned long long ext_node(int64_t k, int64_t n, con
   } else if (MODE == EXT_RESID) {
     T r = t - delta * u[i];
     if (b) r += b[i];
+    if (wd) r *= wd[i];  // variable coefficient: residual brought to the units of f
     if (out) out[i] = (TO)r;
     return abs_bits((double)r);
   } else if (MODE == EXT_APPLY) {
@@ -308,6 +333,7 @@ __device__ __forceinline__ unsigned long long ext_node_lds(int64_t k, int64_t n,
   } else if (MODE == EXT_RESID) {
     T r = t - delta * u[i];
     if (b) r += b[i];
+    if (wd) r *= wd[i];  // variable coefficient: residual brought to the units of f
     if (out) out[i] = (TO)r;
     return abs_bits((double)r);
   } else if (MODE == EXT_APPLY) {
