@@ -89,7 +89,7 @@ def build_level(s: Surface, h: float, lam2: float) -> Level:
     if d == 2:
         YY, XX = np.meshgrid(ys, xs, indexing="ij")
         I = np.stack([XX.ravel(), YY.ravel()], axis=1)
-        cp, dist2 = closest_point_and_dist2(s, I.astype(np.float64) * h)
+        cp, dist2 = closest_point_and_dist2(s, I.astype(np.float64) * h, thr)
         keep = dist2 <= thr
         idx_parts.append(I[keep])
         cp_parts.append(cp[keep])
@@ -98,7 +98,7 @@ def build_level(s: Surface, h: float, lam2: float) -> Level:
         XY = np.stack([XX.ravel(), YY.ravel()], axis=1)
         for z in range(ilo[2], ihi[2] + 1):
             I = np.concatenate([XY, np.full((XY.shape[0], 1), z, dtype=np.int64)], axis=1)
-            cp, dist2 = closest_point_and_dist2(s, I.astype(np.float64) * h)
+            cp, dist2 = closest_point_and_dist2(s, I.astype(np.float64) * h, thr)
             keep = dist2 <= thr
             if keep.any():
                 idx_parts.append(I[keep])

@@ -30,6 +30,7 @@ import numpy as np
 CIRCLE = "circle"
 SPHERE = "sphere"
 TORUS = "torus"
+DZIUK = "dziuk"  # the level set (x1 - x3^2)^2 + x2^2 + x3^2 = 1 (Dziuk's surface)
 
 #: seed base for the random right-hand sides and batched problem draws
 SEED_BASE = 13074354
@@ -42,6 +43,7 @@ class Surface:
     circle: centre (cx, cy), radius R.            (embedding dimension 2)
     sphere: centre (cx, cy, cz), radius R.        (embedding dimension 3)
     torus:  centre (cx, cy, cz), axis along z, tube-centre radius R, tube radius r.
+    dziuk:  centre (cx, cy, cz) shifts the level set (x1 - x3^2)^2 + x2^2 + x3^2 = 1 (R, r unused).
     """
 
     kind: str
@@ -67,6 +69,10 @@ def unit_sphere() -> Surface:
 
 def torus(R: float, r: float) -> Surface:
     return Surface(TORUS, float(R), float(r), (0.0, 0.0, 0.0))
+
+
+def dziuk_surface() -> Surface:
+    return Surface(DZIUK, 1.0, 0.0, (0.0, 0.0, 0.0))
 
 
 # ----------------------------------------------------------------------------
@@ -154,6 +160,32 @@ def sphere_varcoef(c: float = 1.0) -> Problem:
         return 2.0 * z * (z + 1.5) - (1.0 - z * z) + c * z
 
     return Problem(s, c, f, u, "sphere_varcoef", a=a)
+
+
+def dziuk_x1x2(c: float = 1.0) -> Problem:
+    """Dziuk's level-set surface with u = x1 x2.  With n = grad(phi) / |grad(phi)| and
+    kappa = div(n) = Lap(phi) / |grad(phi)| - grad(phi)^T Hess(phi) grad(phi) / |grad(phi)|^3,
+    -Lap_S u = -Lap u + n^T Hess(u) n + kappa (n . grad u) = 2 n1 n2 + kappa (n1 x2 + n2 x1)."""
+    s = dziuk_surface()
+
+    def u(Y):
+        X = Y - s.c0()
+        return X[:, 0] * X[:, 1]
+
+    def f(Y):
+        X = Y - s.c0()
+        x1, x2, x3 = X[:, 0], X[:, 1], X[:, 2]
+        p = x1 - x3 * x3
+        g = np.stack([2.0 * p, 2.0 * x2, 2.0 * x3 - 4.0 * x3 * p], axis=1)
+        gn = np.sqrt(np.sum(g * g, axis=1))
+        n = g / gn[:, None]
+        h33 = 2.0 - 4.0 * p + 8.0 * x3 * x3
+        lap = 4.0 + h33
+        gHg = 2.0 * g[:, 0] ** 2 + 2.0 * g[:, 1] ** 2 + h33 * g[:, 2] ** 2 - 8.0 * x3 * g[:, 0] * g[:, 2]
+        kappa = lap / gn - gHg / gn ** 3
+        return 2.0 * n[:, 0] * n[:, 1] + kappa * (n[:, 0] * x2 + n[:, 1] * x1) + c * x1 * x2
+
+    return Problem(s, c, f, u, "dziuk_x1x2")
 
 
 def sphere_l5_paper(c: float = 1.0) -> Problem:
@@ -298,6 +330,11 @@ def config_sphere(h_inv: int = 64, levels: int = 5) -> SolverConfig:
 def config_sphere_varcoef(h_inv: int = 64, levels: int = 5) -> SolverConfig:
     """Variable-coefficient workload: unit sphere, a = z + 1.5, u = z, h = 1/64 to 1/4."""
     return SolverConfig("sphere_vc_h%d" % h_inv, sphere_varcoef(), 1.0 / h_inv, levels, LAM2_3D)
+
+
+def config_dziuk(h_inv: int = 64, levels: int = 3) -> SolverConfig:
+    """Level-set workload: Dziuk's surface, u = x1 x2, h = 1/64 coarsened to 1/16."""
+    return SolverConfig("dziuk_h%d" % h_inv, dziuk_x1x2(), 1.0 / h_inv, levels, LAM2_3D)
 
 
 def config_torus_mixed(h_inv: int = 256, levels: Optional[int] = None, seed_offset: int = 3) -> SolverConfig:
