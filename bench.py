@@ -404,6 +404,21 @@ def main():
                   "ms_per_cycle": 1000.0 * (time.perf_counter() - t0) / 50, "max_error_vs_exact": err}
         cpm.cpm_set_diffusion(band, 0, None)
 
+    # level-set surface (Dziuk's surface, Newton closest points): band build and solve
+    ls_res = None
+    if not args.no_solve:
+        pl = W.dziuk_x1x2()
+        t0 = time.perf_counter()
+        bl = _build(cpm, pl, 1.0 / 64, 4)
+        t_bl = time.perf_counter() - t0
+        _, cpl = bl.export(0)
+        fl = torch.as_tensor(pl.f(cpl)).to("cuda")
+        ul, rl = _solve(cpm, torch, bl, cpm.make_params(c=pl.c), fl)
+        ls_res = {"workload": "dziuk_h1/64_4levels", "n_per_level": bl.sizes(), "band_build_s": t_bl,
+                  "seconds_to_1e-10": rl["seconds"], "cycles": rl["cycles"], "contraction": rl["contraction"],
+                  "max_error_vs_exact": float((ul.cpu().numpy() - pl.u_exact(cpl)).__abs__().max())}
+        bl.free()
+
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
@@ -432,6 +447,7 @@ def main():
         "time_to_1e-10": tt,
         "standard_relaxation_to_increment_1e-10": std_res,
         "variable_coefficient_sphere": vc_res,
+        "levelset_surface": ls_res,
         "band_build_s": t_build,
         "autotune_s": t_tune,
         "tuning": [{"level": l, "lds": t[0], "ext_block": t[1], "nsum_block": t[2], "fused_sweep": t[3],

@@ -51,7 +51,10 @@ typedef enum {
   CPM_E_WORKSPACE = 7 /* workspace too small                                             */
 } cpm_status;
 
-typedef enum { CPM_CIRCLE = 0, CPM_SPHERE = 1, CPM_TORUS = 2 } cpm_surface_kind;
+/* CPM_DZIUK: the level set (x1 - x3^2)^2 + x2^2 + x3^2 = 1 shifted by center (R, r unused),
+ * the level-set example of the numerical section; its closest points are computed by
+ * Newton's method from the nearest of a fixed set of surface samples. */
+typedef enum { CPM_CIRCLE = 0, CPM_SPHERE = 1, CPM_TORUS = 2, CPM_DZIUK = 3 } cpm_surface_kind;
 
 /* Analytic surfaces of the paper's examples (Sec. 3.4, 4.6).  circle: 2-D, centre
  * center[0..1], radius R.  sphere: centre, radius R.  torus: centre, axis along z,

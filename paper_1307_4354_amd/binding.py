@@ -19,7 +19,7 @@ import numpy as np
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcpm.so")
 
 CPM_OK, CPM_E_INVALID, CPM_E_BAND, CPM_E_NOMEM, CPM_E_HIP, CPM_E_NOCONV, CPM_E_DIVERGED, CPM_E_WORKSPACE = range(8)
-CPM_CIRCLE, CPM_SPHERE, CPM_TORUS = 0, 1, 2
+CPM_CIRCLE, CPM_SPHERE, CPM_TORUS, CPM_DZIUK = 0, 1, 2, 3
 CPM_F64, CPM_MIXED = 0, 1
 CPM_SMOOTH_JACOBI, CPM_SMOOTH_LEARNED, CPM_SMOOTH_STANDARD = 0, 1, 2
 CPM_MAX_HISTORY = 256
@@ -140,7 +140,7 @@ def _stream(stream) -> Optional[int]:
     return stream.cuda_stream
 
 
-_KINDS = {"circle": CPM_CIRCLE, "sphere": CPM_SPHERE, "torus": CPM_TORUS}
+_KINDS = {"circle": CPM_CIRCLE, "sphere": CPM_SPHERE, "torus": CPM_TORUS, "dziuk": CPM_DZIUK}
 
 
 def make_surface(kind, R: float, r: float = 0.0, center=(0.0, 0.0, 0.0)) -> cpm_surface:

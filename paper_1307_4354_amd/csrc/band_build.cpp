@@ -10,6 +10,7 @@
 // to contain B_interp and B_edge of the cubic scheme.  Nodes are sorted x fastest.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <climits>
 #include <cstdlib>
 #include <cstring>
@@ -23,9 +24,155 @@ namespace {
 // Closest point and squared distance (Sec. 2.1) for the analytic surfaces.  Ties resolve
 // onto the surface: centre -> direction +x; torus axis -> radial direction +x; torus
 // tube-centre circle -> outward radial direction.
+// ---- level set: Dziuk's surface (y1 - y3^2)^2 + y2^2 + y3^2 = 1 -------------------------
+// Closest point by Newton's method on the stationarity conditions of |y - x|^2 under
+// phi(y) = 0 (the level-set example of the paper minimises the squared distance with
+// Newton's method), F = (y - x + mu grad(phi), phi), J = [[I + mu Hess(phi), g], [g^T, 0]];
+// the 3x3 block couples y1 and y3 only, so a step is solved in closed form.  The start is
+// the nearest of 6 K^2 surface samples (a global start: the coarse bands reach beyond the
+// surface's reach, where a local start can end at a stationary point that is not the
+// closest point and leave holes in the band).  A node that provably has no surface point
+// within the band radius is skipped (Lipschitz bound of phi on the ball); a node whose
+// iteration does not converge, or ends farther than its start, keeps the start sample.
+// Plain IEEE double operations in exactly this order (no contraction): the band is then
+// identical to the one the float64 reference computes.
+constexpr int kDziukK = 16;
+constexpr int kDziukNewton = 25;
+
+const std::vector<double>& dziuk_samples() {
+  static const std::vector<double> S = [] {
+    std::vector<double> out;
+    out.reserve((size_t)6 * kDziukK * kDziukK * 3);
+    double t[kDziukK];
+    for (int i = 0; i < kDziukK; ++i) t[i] = (2.0 * (double)i + 1.0) / (double)kDziukK - 1.0;
+    for (int face = 0; face < 6; ++face)
+      for (int i = 0; i < kDziukK; ++i)
+        for (int j = 0; j < kDziukK; ++j) {
+          const double u = t[i], v = t[j];
+          double P[3];
+          switch (face) {
+            case 0: P[0] = 1.0; P[1] = u; P[2] = v; break;
+            case 1: P[0] = -1.0; P[1] = u; P[2] = v; break;
+            case 2: P[0] = u; P[1] = 1.0; P[2] = v; break;
+            case 3: P[0] = u; P[1] = -1.0; P[2] = v; break;
+            case 4: P[0] = u; P[1] = v; P[2] = 1.0; break;
+            default: P[0] = u; P[1] = v; P[2] = -1.0; break;
+          }
+          const double r = std::sqrt((P[0] * P[0] + P[1] * P[1]) + P[2] * P[2]);
+          const double q0 = P[0] / r, q1 = P[1] / r, q2 = P[2] / r;
+          out.push_back(q0 + q2 * q2);
+          out.push_back(q1);
+          out.push_back(q2);
+        }
+    return out;
+  }();
+  return S;
+}
+
+// x relative to the surface centre; returns false when x is provably farther than sqrt(thr)
+bool dziuk_closest(const double* x, double thr, double* cp, double* dist2) {
+  const double x1 = x[0], x2 = x[1], x3 = x[2];
+  const double p0 = x1 - x3 * x3;
+  const double ph0 = (p0 * p0 + x2 * x2) + (x3 * x3 - 1.0);
+  const double r = std::sqrt(thr);
+  const double ax3 = std::fabs(x3);
+  const double P = ((std::fabs(p0) + r) + (2.0 * ax3) * r) + r * r;
+  const double Y2 = std::fabs(x2) + r;
+  const double Y3 = ax3 + r;
+  const double q = 2.0 + 4.0 * P;
+  const double G2 = (4.0 * (P * P) + 4.0 * (Y2 * Y2)) + (Y3 * Y3) * (q * q);
+  if (!(ph0 * ph0 <= G2 * thr)) return false;
+  const std::vector<double>& S = dziuk_samples();
+  const size_t M = S.size() / 3;
+  size_t best = 0;
+  double bd = 0.0;
+  for (size_t k = 0; k < M; ++k) {
+    const double d0 = S[3 * k] - x1, d1 = S[3 * k + 1] - x2, d2 = S[3 * k + 2] - x3;
+    const double d = (d0 * d0 + d1 * d1) + d2 * d2;
+    if (k == 0 || d < bd) {
+      bd = d;
+      best = k;
+    }
+  }
+  const double s1 = S[3 * best], s2 = S[3 * best + 1], s3 = S[3 * best + 2];
+  double y1 = s1, y2 = s2, y3 = s3;
+  double p = y1 - y3 * y3;
+  double g1 = 2.0 * p, g2 = 2.0 * y2, g3 = 2.0 * y3 - 4.0 * y3 * p;
+  double gg = (g1 * g1 + g2 * g2) + g3 * g3;
+  double mu = (((x1 - y1) * g1 + (x2 - y2) * g2) + (x3 - y3) * g3) / gg;
+  for (int it = 0; it < kDziukNewton; ++it) {
+    p = y1 - y3 * y3;
+    g1 = 2.0 * p;
+    g2 = 2.0 * y2;
+    g3 = 2.0 * y3 - 4.0 * y3 * p;
+    const double ph = (p * p + y2 * y2) + (y3 * y3 - 1.0);
+    const double F1 = (y1 - x1) + mu * g1;
+    const double F2 = (y2 - x2) + mu * g2;
+    const double F3 = (y3 - x3) + mu * g3;
+    const double h33 = (2.0 - 4.0 * p) + 8.0 * (y3 * y3);
+    const double a = 1.0 + 2.0 * mu;
+    const double b = (-4.0 * mu) * y3;
+    const double d = 1.0 + mu * h33;
+    const double det = a * d - b * b;
+    const double kf1 = (d * F1 - b * F3) / det;
+    const double kf3 = (a * F3 - b * F1) / det;
+    const double kf2 = F2 / a;
+    const double kg1 = (d * g1 - b * g3) / det;
+    const double kg3 = (a * g3 - b * g1) / det;
+    const double kg2 = g2 / a;
+    const double gkf = (g1 * kf1 + g2 * kf2) + g3 * kf3;
+    const double gkg = (g1 * kg1 + g2 * kg2) + g3 * kg3;
+    const double dmu = (ph - gkf) / gkg;
+    y1 = y1 - (kf1 + kg1 * dmu);
+    y2 = y2 - (kf2 + kg2 * dmu);
+    y3 = y3 - (kf3 + kg3 * dmu);
+    mu = mu + dmu;
+  }
+  p = y1 - y3 * y3;
+  const double ph = (p * p + y2 * y2) + (y3 * y3 - 1.0);
+  const double r1 = (y1 - x1) + mu * (2.0 * p);
+  const double r2 = (y2 - x2) + mu * (2.0 * y2);
+  const double r3 = (y3 - x3) + mu * (2.0 * y3 - 4.0 * y3 * p);
+  const double e1 = y1 - x1, e2 = y2 - x2, e3 = y3 - x3;
+  const double dn = (e1 * e1 + e2 * e2) + e3 * e3;
+  const bool conv = std::fabs(ph) <= 1e-12 && std::fabs(r1) <= 1e-12 && std::fabs(r2) <= 1e-12 &&
+                    std::fabs(r3) <= 1e-12;
+  const double f1 = s1 - x1, f2 = s2 - x2, f3 = s3 - x3;
+  const double ds = (f1 * f1 + f2 * f2) + f3 * f3;
+  if (conv && dn <= ds) {
+    cp[0] = y1;
+    cp[1] = y2;
+    cp[2] = y3;
+    *dist2 = dn;
+  } else {
+    cp[0] = s1;
+    cp[1] = s2;
+    cp[2] = s3;
+    *dist2 = ds;
+  }
+  return true;
+}
+
+// thr: squared band radius (used by the level set to skip far points and as the Newton
+// filter; the analytic surfaces ignore it)
 inline void closest_point(const cpm_surface& s, int dim, const double* x, double* cp,
-                          double* dist2) {
+                          double* dist2, double thr) {
   const double* c = s.center;
+  if (s.kind == CPM_DZIUK) {
+    const double xr[3] = {x[0] - c[0], x[1] - c[1], x[2] - c[2]};
+    double y[3];
+    if (!dziuk_closest(xr, thr, y, dist2)) {
+      *dist2 = std::numeric_limits<double>::infinity();
+      cp[0] = x[0];
+      cp[1] = x[1];
+      cp[2] = x[2];
+      return;
+    }
+    cp[0] = y[0] + c[0];
+    cp[1] = y[1] + c[1];
+    cp[2] = y[2] + c[2];
+    return;
+  }
   if (s.kind == CPM_CIRCLE || s.kind == CPM_SPHERE) {
     double dx = x[0] - c[0];
     double dy = x[1] - c[1];
@@ -107,6 +254,15 @@ inline void closest_point(const cpm_surface& s, int dim, const double* x, double
 }
 
 void bounding_box(const cpm_surface& s, int dim, double lo[3], double hi[3]) {
+  if (s.kind == CPM_DZIUK) {
+    // x1 = x3^2 +- sqrt(1 - x2^2 - x3^2) lies in [-1, 5/4]; |x2|, |x3| <= 1
+    const double l[3] = {-1.0, -1.0, -1.0}, u[3] = {1.25, 1.0, 1.0};
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = s.center[a] + l[a];
+      hi[a] = s.center[a] + u[a];
+    }
+    return;
+  }
   double ext[3];
   if (s.kind == CPM_TORUS) {
     ext[0] = ext[1] = s.R + s.r;
@@ -170,7 +326,7 @@ cpm_status enumerate_level(const cpm_surface& s, int dim, double h, double lam2,
         x[0] = (double)xi * h;
         x[1] = (double)y * h;
         x[2] = (double)z * h;
-        closest_point(s, dim, x, cp, &d2);
+        closest_point(s, dim, x, cp, &d2, thr);
         if (d2 <= thr) {
           P.push_back((int32_t)xi);
           P.push_back((int32_t)y);

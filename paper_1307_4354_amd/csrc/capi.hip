@@ -716,11 +716,12 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
   }
   *out = nullptr;
   const int kind = surface->kind;
-  if (kind != CPM_CIRCLE && kind != CPM_SPHERE && kind != CPM_TORUS) {
+  if (kind != CPM_CIRCLE && kind != CPM_SPHERE && kind != CPM_TORUS && kind != CPM_DZIUK) {
     set_error("unknown surface kind");
     return CPM_E_INVALID;
   }
-  if (!(surface->R > 0) || (kind == CPM_TORUS && !(surface->r > 0 && surface->r < surface->R))) {
+  if ((kind != CPM_DZIUK && !(surface->R > 0)) ||
+      (kind == CPM_TORUS && !(surface->r > 0 && surface->r < surface->R))) {
     set_error("invalid surface radii");
     return CPM_E_INVALID;
   }
