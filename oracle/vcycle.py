@@ -38,6 +38,7 @@ class Params:
     residual_mode: str = "consistent"  # or "verbatim"
     learned: Optional[np.ndarray] = None  # bf16 weights of the learned smoother (levels 0, 1)
     learned_sweeps: int = 0  # sweeps per side on the learned levels (0: nu1 / nu2)
+    gamma: int = 1  # cycle index: coarse-grid visits per level (1: V-cycle, 2: W-cycle)
 
 
 def delta(H: Hierarchy, l: int, c: float) -> float:
@@ -103,7 +104,10 @@ def vcycle(H: Hierarchy, l: int, u: np.ndarray, f: np.ndarray, p: Params,
         u = smooth(H, l, u, f, p)
     r = residual(H, l, u, f, p)  # step 2: residual, restriction, coarse solve
     fc = H.R[l] @ r
-    ec = vcycle(H, l + 1, np.zeros(H.levels[l + 1].n), fc, p, coarse)
+    ec = np.zeros(H.levels[l + 1].n)
+    # gamma recursive visits of the coarse level (the coarsest one is solved exactly once)
+    for _ in range(1 if l + 1 == len(H.levels) - 1 else max(1, p.gamma)):
+        ec = vcycle(H, l + 1, ec, fc, p, coarse)
     u = u + H.P[l] @ ec  # step 3: coarse-grid correction
     for _ in range(nu2):  # step 4: post-smoothing
         u = smooth(H, l, u, f, p)
@@ -126,8 +130,28 @@ def rhs_norm(H: Hierarchy, f: np.ndarray) -> float:
     return float(np.max(np.abs(H.E[0] @ f)))
 
 
+def fmg_start(H: Hierarchy, f: np.ndarray, p: Params, coarse: CoarseSolver) -> np.ndarray:
+    """Full-multigrid start (nested iteration): the right-hand side restricted to every level
+    with the closest-point restriction, the coarsest level solved exactly, then on each finer
+    level the coarse solution interpolated to the fine closest points and improved by one
+    cycle.  The nested-iteration interpolation is cubic (degree 3 closest-point
+    interpolation): with the cycle's linear prolongation the start misses the discretization
+    error by one to three orders of magnitude, with cubic it lands within a small factor of
+    it (the classical full-multigrid property)."""
+    from .band import interp_matrix
+
+    L = len(H.levels)
+    fs = [f]
+    for l in range(L - 1):
+        fs.append(H.R[l] @ fs[-1])
+    u = coarse(fs[L - 1])
+    for l in range(L - 2, -1, -1):
+        u = vcycle(H, l, interp_matrix(H.levels[l].cp, H.levels[l + 1], 3) @ u, fs[l], p, coarse)
+    return u
+
+
 def solve(H: Hierarchy, f: np.ndarray, p: Params, rtol: float = 1e-10, max_cycles: int = 60,
-          keep_iterates: bool = False, u0: Optional[np.ndarray] = None) -> SolveResult:
+          keep_iterates: bool = False, u0: Optional[np.ndarray] = None, fmg: bool = False) -> SolveResult:
     """Repeat V-cycles from u_0 = 0 until ||E f - A u||_inf / ||E f||_inf < rtol.
 
     In verbatim mode the residual of A u = f is reported instead and the loop stops on
@@ -135,6 +159,8 @@ def solve(H: Hierarchy, f: np.ndarray, p: Params, rtol: float = 1e-10, max_cycle
     coarse = CoarseSolver(H, p)
     u = np.zeros(H.levels[0].n) if u0 is None else u0.copy()
     consistent = Params(p.c, p.nu1, p.nu2, p.omega, "consistent")
+    if u0 is None and fmg:
+        u = fmg_start(H, f, p, coarse)
     bn = rhs_norm(H, f)
     res, inc, its = [], [], []
     for _ in range(max_cycles):
