@@ -333,7 +333,10 @@ def main():
 
     # time to 1e-10 from u = 0 (graph per cycle, one host check per cycle); first call warms up
     tt = {}
-    for name, p, nb in (() if args.no_solve else (("f64", p64, nb64), ("mixed", pmx, nbmx))):
+    p_fmg = cpm.make_params(c=cfg.problem.c, nu1=cfg.nu1, nu2=cfg.nu2, omega=cfg.omega, fmg=True)
+    p_w = cpm.make_params(c=cfg.problem.c, nu1=cfg.nu1, nu2=cfg.nu2, omega=cfg.omega, gamma=2)
+    for name, p, nb in (() if args.no_solve else (("f64", p64, nb64), ("mixed", pmx, nbmx),
+                                                  ("f64_fmg_start", p_fmg, nb64), ("f64_W_cycle", p_w, nb64))):
         ud.zero_()
         cpm.cpm_solve(band, p, fd, ud, work, nb, rtol=1e-10, max_cycles=80)
         ud.zero_()

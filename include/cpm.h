@@ -98,6 +98,13 @@ typedef struct {
   int smoother;
   int learned_sweeps; /* learned smoother: sweeps before and after the coarse correction on
                          the levels where it runs (0 = nu1 / nu2 as everywhere else) */
+  int gamma;          /* cycle index: visits of the next coarser level per level (1 = V-cycle,
+                         2 = W-cycle; 0 is taken as 1; the coarsest level is solved once) */
+  int fmg;            /* cpm_solve only: 1 = start from the full-multigrid (nested iteration)
+                         approximation instead of the given u: f restricted to every level,
+                         coarsest solved, then per finer level cubic closest-point
+                         interpolation of the coarser solution and one cycle (precision
+                         CPM_F64, smoother CPM_SMOOTH_JACOBI) */
 } cpm_params;
 
 #define CPM_MAX_HISTORY 256

@@ -38,6 +38,7 @@ class StdParams:
     nu2: int = 3
     omega: float = 2.0 / 3.0
     residual: str = "extended"  # r = f - A (E u); "plain": r = f - A u
+    gamma: int = 1  # cycle index (1: V-cycle, 2: W-cycle)
 
 
 def matrix_A(H: Hierarchy, l: int, c: float) -> sp.csr_matrix:
@@ -76,7 +77,9 @@ def vcycle(S: StdHierarchy, l: int, u: np.ndarray, f: np.ndarray) -> np.ndarray:
     for _ in range(S.p.nu1):
         u = smooth(S, l, u, f)
     fc = H.R[l] @ residual(S, l, u, f)
-    ec = vcycle(S, l + 1, np.zeros(H.levels[l + 1].n), fc)
+    ec = np.zeros(H.levels[l + 1].n)
+    for _ in range(1 if l + 1 == len(H.levels) - 1 else max(1, S.p.gamma)):
+        ec = vcycle(S, l + 1, ec, fc)
     u = u + H.P[l] @ ec
     for _ in range(S.p.nu2):
         u = smooth(S, l, u, f)

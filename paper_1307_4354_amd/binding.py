@@ -39,7 +39,8 @@ class cpm_grid(Structure):
 
 class cpm_params(Structure):
     _fields_ = [("c", c_double), ("nu1", c_int), ("nu2", c_int), ("omega", c_double),
-                ("precision", c_int), ("smoother", c_int), ("learned_sweeps", c_int)]
+                ("precision", c_int), ("smoother", c_int), ("learned_sweeps", c_int), ("gamma", c_int),
+                ("fmg", c_int)]
 
 
 class cpm_stats(Structure):
@@ -150,9 +151,10 @@ def make_surface(kind, R: float, r: float = 0.0, center=(0.0, 0.0, 0.0)) -> cpm_
 
 
 def make_params(c: float = 1.0, nu1: int = 3, nu2: int = 3, omega: float = 2.0 / 3.0,
-                precision: int = CPM_F64, smoother: int = CPM_SMOOTH_JACOBI, learned_sweeps: int = 0) -> cpm_params:
+                precision: int = CPM_F64, smoother: int = CPM_SMOOTH_JACOBI, learned_sweeps: int = 0,
+                gamma: int = 1, fmg: bool = False) -> cpm_params:
     return cpm_params(float(c), int(nu1), int(nu2), float(omega), int(precision), int(smoother),
-                      int(learned_sweeps))
+                      int(learned_sweeps), int(gamma), int(bool(fmg)))
 
 
 class Band:

@@ -813,6 +813,10 @@ cpm_status build_host_levels(const cpm_surface& s, const cpm_grid& g, int dim,
       err = os.str();
       return CPM_E_BAND;
     }
+    if (!stencil_runs(F, C, 3, F.runP3, F.fracP3, &bad)) {
+      std::vector<int32_t>().swap(F.runP3);  // no full-multigrid start on this band
+      std::vector<double>().swap(F.fracP3);
+    }
     if (!stencil_runs(C, F, 1, C.runR, C.fracR, &bad)) {
       std::ostringstream os;
       os << "restriction stencil of node " << bad << " (level " << l + 1 << ") leaves the band of level "

@@ -310,6 +310,10 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
     cpm_status st = validate_params(bands[p], params);
     if (st != CPM_OK) return st;
   }
+  if (params->gamma > 1 || params->fmg) {
+    set_error("cpm_solve_batched runs V-cycles from the given iterates (gamma <= 1, no fmg)");
+    return CPM_E_INVALID;
+  }
   if (params->precision != CPM_MIXED || params->smoother != CPM_SMOOTH_JACOBI) {
     set_error("cpm_solve_batched runs mixed precision with the Jacobi smoother");
     return CPM_E_INVALID;

@@ -89,7 +89,7 @@ static void free_dev(cpm_band b) {
     void* ps[] = {D.runE,  D.nbr,   D.fracE,  D.fracE32, D.runP,    D.fracP,  D.fracP32, D.runR,
                   D.fracR, D.fracR32, D.perm, D.packed, D.origin, D.fracK, D.fracK32, D.ilist, D.nbrI,
                   D.patchRow, D.patchMask, D.packedB, D.packedL, D.blkE, D.gidx, D.blkG, D.lorg, D.originX,
-                  D.qdiag, D.wd, D.acoef, D.vcD};
+                  D.qdiag, D.wd, D.acoef, D.vcD, D.runP3, D.fracP3};
     for (void* p : ps)
       if (p) (void)hipFree(p);
   }
@@ -414,7 +414,8 @@ static void fused_post(const cpm_band b, int l, LevelBufs<T>* B, T* cur, const T
 }
 
 template <typename T>
-void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const cpm_params& p, hipStream_t s) {
+void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const cpm_params& p, hipStream_t s,
+                  bool u_zero) {
   const DevLevel& D = b->dev[(size_t)l];
   const LaunchCfg lc = level_cfg(D);
   if (l == b->L - 1) {
@@ -428,12 +429,13 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
   const bool learned = learned_here && p.learned_sweeps > 0;
   const int nu1 = learned ? p.learned_sweeps : p.nu1;
   const int nu2 = learned ? p.learned_sweeps : p.nu2;
-  const bool u_zero = l > 0;  // the restriction into this level set u = 0
+  // u_zero: u is 0 on entry (the first visit after the restriction cleared it)
   const DevLevel& C = b->dev[(size_t)(l + 1)];
+  const int visits = l + 1 == b->L - 1 ? 1 : (p.gamma > 1 ? p.gamma : 1);  // cycle index
   if (D.fused && D.fusedOK && !learned_here && !b->vc_active) {
     T* cur = fused_pre<T>(b, l, B, f, rhsA, p, nu1, u_zero, s);
     launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
-    vcycle_level<T>(b, l + 1, B, nullptr, p, s);
+    for (int v = 0; v < visits; ++v) vcycle_level<T>(b, l + 1, B, nullptr, p, s, v == 0);
     launch_prolong<T>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<T>(D), cur, lc, s);
     fused_post<T>(b, l, B, cur, rhsA, p, nu2, s);
     return;
@@ -462,7 +464,7 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
                      (T)0, nullptr, ext_cfg(D), s);
   }
   launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
-  vcycle_level<T>(b, l + 1, B, nullptr, p, s);
+  for (int v = 0; v < visits; ++v) vcycle_level<T>(b, l + 1, B, nullptr, p, s, v == 0);
   launch_prolong<T>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<T>(D), B[l].u, lc, s);
   for (int k = 0; k < nu2; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s);
 }
@@ -492,9 +494,38 @@ static void vcycle_std(const cpm_band b, int l, LevelBufs<double>* B, const cpm_
                              B[l].r, delta, 0.0, nullptr, ext_cfg(D), s);
   const DevLevel& C = b->dev[(size_t)(l + 1)];
   launch_restrict<double>(b->dim, C.n, B[l].r, C.runR, fracR_of<double>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
-  vcycle_std(b, l + 1, B, p, s);
+  const int visits = l + 1 == b->L - 1 ? 1 : (p.gamma > 1 ? p.gamma : 1);
+  for (int v = 0; v < visits; ++v) vcycle_std(b, l + 1, B, p, s);
   launch_prolong<double>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<double>(D), B[l].u, lc, s);
   for (int k = 0; k < p.nu2; ++k) sweep();
+}
+
+// Full-multigrid start into u (nested iteration): f restricted down the hierarchy, the
+// coarsest level solved, then on each finer level the cubic closest-point interpolation of
+// the coarser solution improved by one cycle.
+static void enqueue_fmg(const cpm_band b, const cpm_params& p, const double* f, double* u, void* work,
+                        hipStream_t s) {
+  LevelBufs<double> B[kMaxLevels];
+  carve_levels<double>(b, work, B, nullptr);
+  B[0].u = u;
+  B[0].f = const_cast<double*>(f);
+  const int L = b->L;
+  for (int l = 0; l + 1 < L; ++l) {
+    const DevLevel& C = b->dev[(size_t)(l + 1)];
+    launch_restrict<double>(b->dim, C.n, B[l].f, C.runR, fracR_of<double>(C), B[l + 1].f, nullptr, level_cfg(C), s);
+  }
+  vcycle_level<double>(b, L - 1, B, nullptr, p, s, true);  // coarsest: exact
+  for (int l = L - 2; l >= 0; --l) {
+    const DevLevel& D = b->dev[(size_t)l];
+    launch_interp3(b->dim, D.n, B[l + 1].u, D.runP3, D.fracP3, B[l].u, s);
+    vcycle_level<double>(b, l, B, nullptr, p, s, false);
+  }
+}
+
+static bool fmg_ok(const cpm_band b) {
+  for (int l = 0; l + 1 < b->L; ++l)
+    if (!b->dev[(size_t)l].runP3) return false;
+  return true;
 }
 
 // ||E f||_inf into scalar slot 1 (double)
@@ -549,7 +580,7 @@ void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, doubl
     carve_levels<double>(b, work, B, nullptr);
     B[0].u = u;
     B[0].f = const_cast<double*>(f);
-    vcycle_level<double>(b, 0, B, nullptr, p, s);
+    vcycle_level<double>(b, 0, B, nullptr, p, s, false);
     enqueue_resid64(b, f, u, B[0].g, nullptr, p.c, s);
   } else {
     LevelBufs<float> B[kMaxLevels];
@@ -557,7 +588,7 @@ void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, doubl
     carve_levels<float>(b, work, B, &g64);
     // B[0].f holds the float32 copy of the double residual (A-space right-hand side)
     launch_fill<float>(b->dev[0].n, B[0].u, 0.0f, s);
-    vcycle_level<float>(b, 0, B, B[0].f, p, s);
+    vcycle_level<float>(b, 0, B, B[0].f, p, s, false);
     launch_axpy_f32_to_f64(b->dev[0].n, B[0].u, u, s);
     enqueue_resid64(b, f, u, g64, B[0].f, p.c, s);
   }
@@ -604,7 +635,8 @@ static std::string graph_key(const char* tag, const cpm_params& p, const void* a
                              int extra) {
   std::ostringstream os;
   os << tag << '|' << p.c << '|' << p.nu1 << '|' << p.nu2 << '|' << p.omega << '|' << p.precision << '|'
-     << p.smoother << '|' << p.learned_sweeps << '|' << a << '|' << bb << '|' << c << '|' << extra;
+     << p.smoother << '|' << p.learned_sweeps << '|' << p.gamma << '|' << a << '|' << bb << '|' << c << '|'
+     << extra;
   return os.str();
 }
 
@@ -668,6 +700,18 @@ cpm_status validate_params(const cpm_band b, const cpm_params* p) {
   }
   if (b->vc_active && (p->precision != CPM_F64 || p->smoother != CPM_SMOOTH_JACOBI)) {
     set_error("a variable diffusion coefficient runs with precision CPM_F64 and smoother CPM_SMOOTH_JACOBI only");
+    return CPM_E_INVALID;
+  }
+  if (p->gamma < 0 || p->gamma > 4) {
+    set_error("cycle index gamma must be in 0..4");
+    return CPM_E_INVALID;
+  }
+  if (p->fmg && (p->precision != CPM_F64 || p->smoother != CPM_SMOOTH_JACOBI)) {
+    set_error("the full-multigrid start runs with precision CPM_F64 and smoother CPM_SMOOTH_JACOBI");
+    return CPM_E_INVALID;
+  }
+  if (p->fmg && !fmg_ok(b)) {
+    set_error("no full-multigrid start on this band: a cubic interpolation stencil leaves a coarser band");
     return CPM_E_INVALID;
   }
   if (p->smoother == CPM_SMOOTH_STANDARD && p->precision != CPM_F64) {
@@ -823,6 +867,10 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     if (st == CPM_OK) st = upload(&D.runP, H.runP);
     if (st == CPM_OK) st = upload(&D.fracP, H.fracP);
     if (st == CPM_OK && !H.fracP.empty()) st = upload_f32(&D.fracP32, H.fracP);
+    if (st == CPM_OK) st = upload(&D.runP3, H.runP3);
+    if (st == CPM_OK) st = upload(&D.fracP3, H.fracP3);
+    std::vector<int32_t>().swap(H.runP3);
+    std::vector<double>().swap(H.fracP3);
     if (st == CPM_OK) st = upload(&D.runR, H.runR);
     if (st == CPM_OK) st = upload(&D.fracR, H.fracR);
     if (st == CPM_OK && !H.fracR.empty()) st = upload_f32(&D.fracR32, H.fracR);
@@ -1113,6 +1161,10 @@ cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, d
     (void)hipStreamSynchronize(band->stream);
     return leave(band, stream);
   }
+  if (p.fmg) {
+    enqueue_fmg(band, p, f, u, work, band->stream);
+    if ((st = check_launch("full-multigrid start")) != CPM_OK) return st;
+  }
   double prev = p.precision == CPM_F64 ? NAN : r0 / bn;
   st = CPM_E_NOCONV;
   for (int k = 0; k < max_cycles; ++k) {
@@ -1284,7 +1336,7 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
 
 namespace cpm {
 template void vcycle_level<double>(const cpm_band, int, LevelBufs<double>*, const double*, const cpm_params&,
-                                   hipStream_t);
+                                   hipStream_t, bool);
 template void vcycle_level<float>(const cpm_band, int, LevelBufs<float>*, const float*, const cpm_params&,
-                                  hipStream_t);
+                                  hipStream_t, bool);
 }  // namespace cpm

@@ -83,7 +83,8 @@ size_t workspace_bytes(const cpm_band b, int precision);
 template <typename T>
 void carve_levels(const cpm_band b, void* work, LevelBufs<T>* B, double** g64);
 template <typename T>
-void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const cpm_params& p, hipStream_t s);
+void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const cpm_params& p, hipStream_t s,
+                  bool u_zero);
 void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, double* u, void* work, hipStream_t s);
 void enqueue_prologue(const cpm_band b, const cpm_params& p, const double* f, const double* u, void* work,
                       hipStream_t s);

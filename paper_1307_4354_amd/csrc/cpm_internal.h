@@ -61,6 +61,11 @@ struct HostLevel {
   std::vector<uint32_t> patchMask;  // n
   bool patchOK = false;
   std::vector<double> fracP;   // dim * n: frac(cp / (2h)) (prolongation from level+1)
+  // cubic interpolation from level+1 at this level's closest points (4^(d-1) runs of 4, and
+  // the fractions), the nested-iteration step of the full-multigrid start; empty when some
+  // stencil leaves the coarse band
+  std::vector<int32_t> runP3;
+  std::vector<double> fracP3;
   std::vector<int32_t> runP;   // 2^(dim-1) * n: x-runs in level+1's band
   std::vector<double> fracR;   // dim * n: frac(cp / (h/2)) (restriction from level-1)
   std::vector<int32_t> runR;   // 2^(dim-1) * n: x-runs in level-1's band
@@ -113,6 +118,8 @@ struct DevLevel {
   double* fracR = nullptr;
   float* fracR32 = nullptr;
   int32_t* originX = nullptr;
+  int32_t* runP3 = nullptr;  // full-multigrid interpolation from level+1 (cubic)
+  double* fracP3 = nullptr;
   double* qdiag = nullptr;  // (E N)_ii
   double* acoef = nullptr;  // variable diffusion coefficient a(cp(x_i)) (cpm_set_diffusion)
   double* vcD = nullptr;    // c + sigma_i of the flux-form operator, for vc_c

@@ -93,6 +93,10 @@ void launch_vc_diag(int dim, int64_t n, const int32_t* nbr, const double* a, dou
 void launch_assemble_coarse_vc(int dim, int n, const int32_t* runE, const double* fracE, const int32_t* nbr,
                                const double* a, const double* Dd, double inv_h2, double* M, hipStream_t s);
 
+// out = cubic closest-point interpolation of the coarse vector v at the n fine nodes
+void launch_interp3(int dim, int64_t n, const double* v, const int32_t* runs, const double* frac, double* out,
+                    hipStream_t s);
+
 // dst = src (n elements)
 template <typename T>
 void launch_copy(int64_t n, const T* src, T* dst, hipStream_t s);

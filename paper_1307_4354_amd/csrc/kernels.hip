@@ -534,6 +534,23 @@ void launch_assemble_coarse_vc(int dim, int n, const int32_t* runE, const double
     k_assemble_coarse_vc<3><<<grid_for(n, 128), 128, 0, s>>>(n, runE, fracE, nbr, a, Dd, inv_h2, M);
 }
 
+template <int D>
+__global__ __launch_bounds__(256) void k_interp3(int64_t n, const double* __restrict__ v,
+                                                 const int32_t* __restrict__ runs, const double* __restrict__ frac,
+                                                 double* __restrict__ out) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] = cubic_node<D, double>(i, n, v, runs, frac);
+}
+
+void launch_interp3(int dim, int64_t n, const double* v, const int32_t* runs, const double* frac, double* out,
+                    hipStream_t s) {
+  if (n <= 0) return;
+  if (dim == 2)
+    k_interp3<2><<<grid_for(n, 256), 256, 0, s>>>(n, v, runs, frac, out);
+  else
+    k_interp3<3><<<grid_for(n, 256), 256, 0, s>>>(n, v, runs, frac, out);
+}
+
 // explicit instantiations
 template void launch_nsum<double>(int, int64_t, const int32_t*, const int32_t*, const double*, const double*, double,
                                   double*, unsigned long long*, const LaunchCfg&, hipStream_t);

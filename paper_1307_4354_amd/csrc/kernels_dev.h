@@ -363,4 +363,31 @@ __device__ __forceinline__ T linear_node(int64_t j, int64_t cnt, const T* __rest
   return (T(1) - az) * z0 + az * z1;
 }
 
+// Cubic closest-point interpolation of v at target node j (4^(D-1) runs of 4 consecutive
+// source entries, fractions per axis; the layout of the transfer runs).
+template <int D, typename T>
+__device__ __forceinline__ T cubic_node(int64_t j, int64_t cnt, const T* __restrict__ v,
+                                        const int32_t* __restrict__ runs, const T* __restrict__ frac) {
+  T wx[4], wy[4];
+  cubic_weights<T>(frac[j], wx);
+  cubic_weights<T>(frac[cnt + j], wy);
+  if (D == 2) {
+    T t = T(0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) t += wy[b] * run_dot(v + runs[b * cnt + j], wx);
+    return t;
+  }
+  T wz[4];
+  cubic_weights<T>(frac[2 * cnt + j], wz);
+  T t = T(0);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    T tc = T(0);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) tc += wy[b] * run_dot(v + runs[(b + 4 * c) * cnt + j], wx);
+    t += wz[c] * tc;
+  }
+  return t;
+}
+
 }  // namespace cpm
