@@ -52,7 +52,7 @@ typedef enum {
 } cpm_status;
 
 /* CPM_DZIUK: the level set (x1 - x3^2)^2 + x2^2 + x3^2 = 1 shifted by center (R, r unused),
- * the level-set example of the numerical section; its closest points are computed by
+ * the level-set example of Sec. 4.6.5; its closest points are computed by
  * Newton's method from the nearest of a fixed set of surface samples. */
 typedef enum { CPM_CIRCLE = 0, CPM_SPHERE = 1, CPM_TORUS = 2, CPM_DZIUK = 3 } cpm_surface_kind;
 
@@ -171,7 +171,7 @@ cpm_status cpm_apply(cpm_band band, int level, double c, const double* u, double
 cpm_status cpm_extend(cpm_band band, int level, const double* g, double* out, void* stream);
 
 /* Variable diffusion coefficient: -div_S(a grad_S u) + c u = f (Sec. 2.2; the variable-
- * coefficient sphere example of the numerical section).  a is a host array of n(level)
+ * coefficient sphere example, Sec. 4.6.6).  a is a host array of n(level)
  * doubles, a(cp(x_i)) > 0 for the nodes of `level` in band order (closest points from
  * cpm_band_export), copied.  The discrete operator is the flux form
  * L~ = sum over axes of D^b diag(A^f a) D^f, smoothed with the Ruuth-Merriman step on
@@ -194,8 +194,9 @@ cpm_status cpm_vcycle(cpm_band band, const cpm_params* params, const double* f, 
 /* Repeat cycles from the given u (set it to 0 for the paper's start) until
  * ||E f - A u||_inf / ||E f||_inf < rtol or max_cycles.  Synchronous on return.  In
  * CPM_MIXED precision each outer step is one float32 V-cycle on the correction equation
- * A e = r with r evaluated in double.  Returns CPM_E_NOCONV / CPM_E_DIVERGED with stats
- * filled. */
+ * A e = r with r evaluated in double.  With params->fmg the given u is replaced by the
+ * full-multigrid start first (its one cycle per level is not counted in stats->cycles).
+ * Returns CPM_E_NOCONV / CPM_E_DIVERGED with stats filled. */
 cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, double* u,
                      void* work, size_t work_bytes, double rtol, int max_cycles,
                      cpm_stats* stats, void* stream);

@@ -1,6 +1,6 @@
 """Closest-point functions (Sec. 2.1: cp maps a point of the tubular neighbourhood to a
 nearest surface point) for the analytic surfaces used in the paper's examples, and the
-Newton closest point of the level-set example (Dziuk's surface).
+Newton closest point of the level-set example (Dziuk's surface, Sec. 4.6.5).
 
 Floating-point convention (shared *as a convention* with the GPU library's band builder,
 so that band membership and stencil bases agree bit for bit): plain IEEE double

@@ -1,5 +1,5 @@
-"""Variable diffusion coefficients: -div_S(a grad_S u) + c u = f (Sec. 2.2 and the
-variable-coefficient sphere example of the numerical section).
+"""Variable diffusion coefficients: -div_S(a grad_S u) + c u = f (Sec. 2.2; the
+variable-coefficient sphere example, Sec. 4.6.6).
 
 Discretization (as the paper writes it): L~ = sum over axes of D^b diag(A^f a) D^f, with
 a_i = a(cp(x_i)), D^f / D^b forward / backward differences and A^f the average of two

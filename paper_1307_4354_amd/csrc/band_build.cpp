@@ -26,7 +26,7 @@ namespace {
 // tube-centre circle -> outward radial direction.
 // ---- level set: Dziuk's surface (y1 - y3^2)^2 + y2^2 + y3^2 = 1 -------------------------
 // Closest point by Newton's method on the stationarity conditions of |y - x|^2 under
-// phi(y) = 0 (the level-set example of the paper minimises the squared distance with
+// phi(y) = 0 (the level-set example, Sec. 4.6.5, minimises the squared distance with
 // Newton's method), F = (y - x + mu grad(phi), phi), J = [[I + mu Hess(phi), g], [g^T, 0]];
 // the 3x3 block couples y1 and y3 only, so a step is solved in closed form.  The start is
 // the nearest of 6 K^2 surface samples (a global start: the coarse bands reach beyond the

@@ -85,7 +85,7 @@ def test_band_h16_against_sampling():
     g = np.stack([2 * p, 2 * cp[:, 1], 2 * cp[:, 2] - 4 * cp[:, 2] * p], axis=1)
     cr = np.linalg.norm(np.cross(X - cp, g), axis=1) / np.linalg.norm(g, axis=1)
     assert np.mean(cr < 1e-11) > 0.999  # stationary points (the rest keep a surface sample)
-    T = cKDTree(_surface_points(1_000_000, 7))
+    T = cKDTree(_surface_points(600_000, 7))
     bf, _ = T.query(X)
     assert np.max(np.linalg.norm(X - cp, axis=1) - bf) < 2e-3
     box = np.stack(np.meshgrid(*[np.arange(lev.lo[a], lev.lo[a] + lev.ext[a]) for a in range(3)], indexing="ij"),

@@ -46,7 +46,7 @@ def test_diag_from_weights(cfg):
     assert np.any(np.abs(S.diag[0] - ov.delta(H, 0, 1.0)) > 1.0)
 
 
-@pytest.mark.parametrize("cfg", [W.config_circle(32, 3), W.config_sphere(16, 2)], ids=["circle32", "sphere16"])
+@pytest.mark.parametrize("cfg", [W.config_circle(32, 3), W.config_sphere(12, 2)], ids=["circle32", "sphere12"])
 def test_plain_residual_fixed_point_is_sparse_solve(cfg):
     H = _hier(cfg)
     f = cfg.problem.f(H.levels[0].cp)

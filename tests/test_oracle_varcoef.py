@@ -50,12 +50,16 @@ def test_flux_form_exact_for_linear_coefficient():
     assert np.max(np.abs(Lu[full] - exact[full])) <= 1e-9 * np.max(np.abs(exact))
 
 
-def test_fixed_point_is_direct_solve():
-    cfg = W.config_sphere(16, 2)
-    prob = W.sphere_varcoef()
+@pytest.mark.parametrize("cfg", [W.config_circle(64, 3), W.config_sphere(12, 2)], ids=["circle64", "sphere12"])
+def test_fixed_point_is_direct_solve(cfg):
     H = _hier(cfg)
-    a_lv = [prob.a(lev.cp) for lev in H.levels]
-    f = prob.f(H.levels[0].cp)
+    if H.levels[0].dim == 2:
+        a_lv = [1.2 + 0.5 * lev.cp[:, 0] - 0.3 * lev.cp[:, 1] for lev in H.levels]
+        f = cfg.problem.f(H.levels[0].cp)
+    else:
+        prob = W.sphere_varcoef()
+        a_lv = [prob.a(lev.cp) for lev in H.levels]
+        f = prob.f(H.levels[0].cp)
     res = vc.solve(H, a_lv, f, vc.VCParams(), rtol=1e-13, max_cycles=80)
     u_star = vc.fixed_point(H, a_lv, f, vc.VCParams())
     assert np.max(np.abs(res.u - u_star)) <= 1e-11 * np.max(np.abs(u_star))
