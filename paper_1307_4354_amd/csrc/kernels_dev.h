@@ -282,15 +282,37 @@ __device__ __forceinline__ T run_dot_lds(const T* p, const T w[4]) {
   return w[0] * p[0] + w[1] * p[1] + w[2] * p[2] + w[3] * p[3];
 }
 
-// Every thread of the workgroup must call it (it synchronizes the block).
+// Every thread of the workgroup must call it (it synchronizes the block).  The copies are
+// unrolled by kStageUnroll so that a thread issues all of its index loads, then all of its
+// value loads (two memory round trips instead of two per copy); a workgroup staging more
+// than kStageUnroll * blockDim values finishes in a plain loop.
+constexpr int kStageUnroll = 8;
+
 template <typename T>
 __device__ __forceinline__ void ext_stage(int64_t blk, const T* __restrict__ g, const int32_t* __restrict__ blkE,
                                           const int32_t* __restrict__ gidx, const int32_t* __restrict__ blkG,
                                           const int32_t* __restrict__ lorg, int S, T* gl, int32_t* lo) {
   const int32_t e0 = blkE[blk], e1 = blkE[blk + 1];
-  for (int32_t e = e0 + (int32_t)threadIdx.x; e < e1; e += (int32_t)blockDim.x) gl[e - e0] = g[gidx[e]];
   const int32_t q0 = blkG[blk] * S, q1 = blkG[blk + 1] * S;
-  for (int32_t q = q0 + (int32_t)threadIdx.x; q < q1; q += (int32_t)blockDim.x) lo[q - q0] = lorg[q];
+  const int32_t tid = (int32_t)threadIdx.x, bd = (int32_t)blockDim.x;
+  int32_t gi[kStageUnroll], lq[kStageUnroll];
+#pragma unroll
+  for (int j = 0; j < kStageUnroll; ++j) {
+    const int32_t e = e0 + tid + j * bd, q = q0 + tid + j * bd;
+    gi[j] = e < e1 ? gidx[e] : -1;
+    lq[j] = q < q1 ? lorg[q] : 0;
+  }
+  T gv[kStageUnroll];
+#pragma unroll
+  for (int j = 0; j < kStageUnroll; ++j) gv[j] = gi[j] >= 0 ? g[gi[j]] : T(0);
+#pragma unroll
+  for (int j = 0; j < kStageUnroll; ++j) {
+    const int32_t e = e0 + tid + j * bd, q = q0 + tid + j * bd;
+    if (e < e1) gl[e - e0] = gv[j];
+    if (q < q1) lo[q - q0] = lq[j];
+  }
+  for (int32_t e = e0 + tid + kStageUnroll * bd; e < e1; e += bd) gl[e - e0] = g[gidx[e]];
+  for (int32_t q = q0 + tid + kStageUnroll * bd; q < q1; q += bd) lo[q - q0] = lorg[q];
   __syncthreads();
 }
 
