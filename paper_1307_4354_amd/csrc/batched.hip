@@ -151,7 +151,18 @@ __global__ __launch_bounds__(256) void kb_coarse(const CoItem* __restrict__ it, 
     const int64_t row = t - pre[q];
     const double* zr = C.Z + row * C.ld;
     double s = 0.0;
-    for (int64_t j = threadIdx.x; j < C.n; j += blockDim.x) s += zr[j] * (double)C.f[j];
+    int64_t j = threadIdx.x;
+    for (; j + 7 * 256 < C.n; j += 8 * 256) {
+      double z[8], xv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        z[q] = zr[j + q * 256];
+        xv[q] = (double)C.f[j + q * 256];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) s += z[q] * xv[q];
+    }
+    for (; j < C.n; j += 256) s += zr[j] * (double)C.f[j];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
     __syncthreads();

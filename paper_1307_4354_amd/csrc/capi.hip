@@ -385,6 +385,9 @@ static T* fused_pre(const cpm_band b, int l, LevelBufs<T>* B, const T* f, const 
       launch_ext<T, T>(b->dim, EXT_PLAIN, D.n, f, ext_addr(D), fracK_of<T>(D), nullptr, nullptr, Ef, (T)0, (T)0,
                        nullptr, ext_cfg(D), s);
     }
+  } else if (u_zero && rhsA && nu > 0) {
+    launch_scale_add<T>(D.n, rhsA, wod, cur, false, s);
+    k0 = 1;
   }
   for (int k = k0; k < nu; ++k) {
     launch_sweep<T>(b->dim, EXT_SMOOTH, D.n, cur, oth, Ef, rhsA, sa, fracS_of<T>(D), inv_h2, (T)delta, wod,
@@ -413,9 +416,14 @@ static void fused_post(const cpm_band b, int l, LevelBufs<T>* B, T* cur, const T
   if (cur != B[l].u) launch_copy<T>(D.n, cur, B[l].u, s);
 }
 
+// r_first (finest level, split sweeps only): the residual E(f + N u) - delta u of the
+// entering iterate, already computed (the stopping test's) with the same two passes as a
+// sweep, so that the first pre-smoothing sweep is u += (omega/delta) r_first, bit for bit.
+// u_zero with an A-space right-hand side rhsA: the first sweep from u = 0 is
+// u = (omega/delta) rhsA, and u need not be cleared beforehand.
 template <typename T>
 void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const cpm_params& p, hipStream_t s,
-                  bool u_zero) {
+                  bool u_zero, const T* r_first) {
   const DevLevel& D = b->dev[(size_t)l];
   const LaunchCfg lc = level_cfg(D);
   if (l == b->L - 1) {
@@ -436,12 +444,20 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
     T* cur = fused_pre<T>(b, l, B, f, rhsA, p, nu1, u_zero, s);
     launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
     for (int v = 0; v < visits; ++v) vcycle_level<T>(b, l + 1, B, nullptr, p, s, v == 0);
-    launch_prolong<T>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<T>(D), cur, lc, s);
-    fused_post<T>(b, l, B, cur, rhsA, p, nu2, s);
+    // the post-smoothing alternates between u and t nu2 times: the prolongation writes
+    // u + P e into the buffer from which the last sweep lands in u
+    T* start = nu2 % 2 == 0 ? B[l].u : B[l].t;
+    launch_prolong<T>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<T>(D), start, lc, s, cur);
+    fused_post<T>(b, l, B, start, rhsA, p, nu2, s);
     return;
   }
-  for (int k = 0; k < nu1; ++k)
+  for (int k = 0; k < nu1; ++k) {
+    if (k == 0 && !learned_here && !b->vc_active && (r_first || (u_zero && rhsA && !f))) {
+      launch_scale_add<T>(D.n, r_first ? r_first : rhsA, (T)(p.omega / delta), B[l].u, r_first != nullptr, s);
+      continue;
+    }
     smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s, u_zero && k == 0);
+  }
   // residual r = b + E(f + N u) - delta u, restricted to the next level (where u := 0)
   bool resid_done = false;
   if constexpr (sizeof(T) == 8) {
@@ -543,9 +559,10 @@ void enqueue_rhs_norm(const cpm_band b, const double* f, double* g, hipStream_t 
                              0.0, 0.0, b->dscal + 1, ext_cfg(D), s);
 }
 
-// ||E(f + N u) - delta u||_inf into slot 0; optionally the residual as float into r32
+// ||E(f + N u) - delta u||_inf into slot 0; optionally the residual as float into r32 or as
+// double into r64
 void enqueue_resid64(const cpm_band b, const double* f, const double* u, double* g, float* r32, double c,
-                     hipStream_t s) {
+                     hipStream_t s, double* r64 = nullptr) {
   const DevLevel& D = b->dev[0];
   const LaunchCfg lc = level_cfg(D);
   if (b->vc_active) {
@@ -556,13 +573,30 @@ void enqueue_resid64(const cpm_band b, const double* f, const double* u, double*
     return;
   }
   launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, u, f, 1.0 / (D.h * D.h), g, b->dscal, lc, s);
-  launch_ext<double, float>(b->dim, EXT_RESID, D.n, g, ext_addr(D), fracK_of<double>(D), nullptr, const_cast<double*>(u), r32,
-                            level_delta(b, 0, c), 0.0, b->dscal, ext_cfg(D), s);
+  if (r64)
+    launch_ext<double, double>(b->dim, EXT_RESID, D.n, g, ext_addr(D), fracK_of<double>(D), nullptr,
+                               const_cast<double*>(u), r64, level_delta(b, 0, c), 0.0, b->dscal, ext_cfg(D), s);
+  else
+    launch_ext<double, float>(b->dim, EXT_RESID, D.n, g, ext_addr(D), fracK_of<double>(D), nullptr,
+                              const_cast<double*>(u), r32, level_delta(b, 0, c), 0.0, b->dscal, ext_cfg(D), s);
+}
+
+// Whether a cycle may start from the residual that the previous cycle's stopping test left
+// in the finest level's r: the Ruuth-Merriman FP64 cycle with constant coefficients whose
+// finest level sweeps in two passes (the fused pass forms the same residual in another
+// rounding order).
+static bool resid_reuse_ok(const cpm_band b, const cpm_params& p) {
+  const DevLevel& D = b->dev[0];
+  return p.precision == CPM_F64 && p.smoother == CPM_SMOOTH_JACOBI && !b->vc_active && !b->learned_active &&
+         p.nu1 > 0 && !(D.fused && D.fusedOK);
 }
 
 // One complete cycle of the solve loop on the band stream, ending with the residual
-// norm of the new iterate in slot 0.
-void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, double* u, void* work, hipStream_t s) {
+// norm of the new iterate in slot 0 (and, in FP64, the residual itself in the finest
+// level's r).  r_ready: that residual is the one of the entering u (the previous cycle of the
+// same solve left it), so the first smoothing sweep is taken from it.
+void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, double* u, void* work, hipStream_t s,
+                   bool r_ready) {
   if (p.smoother == CPM_SMOOTH_STANDARD) {
     // slot 0 = ||u_new - u_old||_inf, slot 1 = ||u_new||_inf (the paper's stopping test)
     LevelBufs<double> B[kMaxLevels];
@@ -580,15 +614,18 @@ void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, doubl
     carve_levels<double>(b, work, B, nullptr);
     B[0].u = u;
     B[0].f = const_cast<double*>(f);
-    vcycle_level<double>(b, 0, B, nullptr, p, s, false);
-    enqueue_resid64(b, f, u, B[0].g, nullptr, p.c, s);
+    const bool reuse = resid_reuse_ok(b, p);
+    vcycle_level<double>(b, 0, B, nullptr, p, s, false, reuse && r_ready ? B[0].r : nullptr);
+    enqueue_resid64(b, f, u, B[0].g, nullptr, p.c, s, reuse ? B[0].r : nullptr);
   } else {
     LevelBufs<float> B[kMaxLevels];
     double* g64 = nullptr;
     carve_levels<float>(b, work, B, &g64);
-    // B[0].f holds the float32 copy of the double residual (A-space right-hand side)
-    launch_fill<float>(b->dev[0].n, B[0].u, 0.0f, s);
-    vcycle_level<float>(b, 0, B, B[0].f, p, s, false);
+    // B[0].f holds the float32 copy of the double residual (A-space right-hand side); the
+    // correction starts from 0, and its first sweep (u = (omega/delta) B[0].f) writes all of u
+    const bool zero_start = p.nu1 > 0 && !b->learned_active;
+    if (!zero_start) launch_fill<float>(b->dev[0].n, B[0].u, 0.0f, s);
+    vcycle_level<float>(b, 0, B, B[0].f, p, s, zero_start);
     launch_axpy_f32_to_f64(b->dev[0].n, B[0].u, u, s);
     enqueue_resid64(b, f, u, g64, B[0].f, p.c, s);
   }
@@ -1168,8 +1205,11 @@ cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, d
   double prev = p.precision == CPM_F64 ? NAN : r0 / bn;
   st = CPM_E_NOCONV;
   for (int k = 0; k < max_cycles; ++k) {
-    const std::string key = graph_key("cycle", p, f, u, work, band->learned_active ? 1 : 0);
-    cpm_status gs = graph_launch(band, key, [&](hipStream_t s) { enqueue_cycle(band, p, f, u, work, s); });
+    // cycles after the first start from the residual the previous one left
+    const bool r_ready = k > 0;
+    const std::string key = graph_key(r_ready ? "cycle_r" : "cycle", p, f, u, work, band->learned_active ? 1 : 0);
+    cpm_status gs =
+        graph_launch(band, key, [&](hipStream_t s) { enqueue_cycle(band, p, f, u, work, s, r_ready); });
     if (gs != CPM_OK) return gs;
     double rn = 0, un = 0;
     if ((gs = read_scalars(band, &rn, &un)) != CPM_OK) return gs;
@@ -1224,11 +1264,13 @@ cpm_status cpm_run_cycles(cpm_band band, const cpm_params* params, const double*
   int done = 0;
   while (done < cycles) {
     const int k = std::min(cycles_per_launch, cycles - done);
-    const std::string key = graph_key("run", p, f, u, work, k * 4 + (band->learned_active ? 1 : 0)) +
+    // every cycle but the run's first starts from the residual the previous one left
+    const bool first = done == 0;
+    const std::string key = graph_key(first ? "run0" : "run", p, f, u, work, k * 4 + (band->learned_active ? 1 : 0)) +
                             std::to_string((uintptr_t)relres_dev);
     st = graph_launch(band, key, [&](hipStream_t s) {
       for (int j = 0; j < k; ++j) {
-        enqueue_cycle(band, p, f, u, work, s);
+        enqueue_cycle(band, p, f, u, work, s, !(first && j == 0));
         launch_record_relres(band->dscal, band->dscal + 1, relres_dev, band->dcounter, s);
       }
     });
@@ -1336,7 +1378,7 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
 
 namespace cpm {
 template void vcycle_level<double>(const cpm_band, int, LevelBufs<double>*, const double*, const cpm_params&,
-                                   hipStream_t, bool);
+                                   hipStream_t, bool, const double*);
 template void vcycle_level<float>(const cpm_band, int, LevelBufs<float>*, const float*, const cpm_params&,
-                                  hipStream_t, bool);
+                                  hipStream_t, bool, const float*);
 }  // namespace cpm

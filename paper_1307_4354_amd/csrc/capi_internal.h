@@ -84,8 +84,9 @@ template <typename T>
 void carve_levels(const cpm_band b, void* work, LevelBufs<T>* B, double** g64);
 template <typename T>
 void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const cpm_params& p, hipStream_t s,
-                  bool u_zero);
-void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, double* u, void* work, hipStream_t s);
+                  bool u_zero, const T* r_first = nullptr);
+void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, double* u, void* work, hipStream_t s,
+                   bool r_ready = false);
 void enqueue_prologue(const cpm_band b, const cpm_params& p, const double* f, const double* u, void* work,
                       hipStream_t s);
 cpm_status read_scalars(cpm_band b, double* r0, double* r1);

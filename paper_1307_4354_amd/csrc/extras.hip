@@ -6,6 +6,7 @@
 // faster form for the level.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "capi_internal.h"
@@ -14,16 +15,23 @@ using namespace cpm;
 
 namespace {
 
+// Average launch time of fn over reps back-to-back calls, the minimum of three trials after
+// a warm-up: small levels run a few microseconds per launch, where one short trial is
+// easily off by more than the difference between two candidates.
 template <typename Fn>
 float time_us(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int reps, Fn fn) {
-  fn();  // warm-up
-  (void)hipEventRecord(e0, s);
-  for (int r = 0; r < reps; ++r) fn();
-  (void)hipEventRecord(e1, s);
-  (void)hipEventSynchronize(e1);
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  return 1000.f * ms / reps;
+  for (int r = 0; r < 3; ++r) fn();  // warm-up
+  float best = 1e30f;
+  for (int trial = 0; trial < 3; ++trial) {
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) fn();
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    best = std::min(best, 1000.f * ms / reps);
+  }
+  return best;
 }
 
 }  // namespace
@@ -53,7 +61,7 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
   const int blocks[3] = {128, 256, 512};
   for (int l = 0; l < band->L; ++l) {
     DevLevel& D = band->dev[(size_t)l];
-    const int reps = D.n > (1 << 20) ? 5 : 20;
+    const int reps = D.n > (1 << 20) ? 10 : 50;
     const double delta = level_delta(band, l, 1.0);
     const double inv_h2 = 1.0 / (D.h * D.h);
     float best = 1e30f;

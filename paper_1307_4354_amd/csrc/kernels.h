@@ -69,9 +69,10 @@ template <typename T>
 void launch_restrict(int dim, int64_t nc, const T* rf, const int32_t* runR, const T* fracR, T* fc,
                      T* uc, const LaunchCfg& lc, hipStream_t s);
 
+// uf = src + P ec (src = nullptr: in place, uf += P ec)
 template <typename T>
 void launch_prolong(int dim, int64_t nf, const T* ec, const int32_t* runP, const T* fracP, T* uf,
-                    const LaunchCfg& lc, hipStream_t s);
+                    const LaunchCfg& lc, hipStream_t s, const T* src = nullptr);
 
 // y = Z x with Z (n x n, leading dimension ld, double), x, y of type T.
 template <typename T>
@@ -105,6 +106,9 @@ template <typename T>
 void launch_fill(int64_t n, T* p, T v, hipStream_t s);
 
 void launch_axpy_f32_to_f64(int64_t n, const float* e, double* u, hipStream_t s);
+// y = a x, or y += a x with accumulate
+template <typename T>
+void launch_scale_add(int64_t n, const T* x, T a, T* y, bool accumulate, hipStream_t s);
 void launch_cast_f64_to_f32(int64_t n, const double* a, float* b, hipStream_t s);
 void launch_zero_u64(unsigned long long* p, int count, hipStream_t s);
 

@@ -96,22 +96,35 @@ __global__ __launch_bounds__(kMaxBlock) void k_restrict(int64_t nc, const T* __r
 template <int D, typename T>
 __global__ __launch_bounds__(kMaxBlock) void k_prolong(int64_t nf, const T* __restrict__ ec,
                                                        const int32_t* __restrict__ runP,
-                                                       const T* __restrict__ fracP,
-                                                       T* __restrict__ uf, int remap) {
+                                                       const T* __restrict__ fracP, const T* src,
+                                                       T* uf, int remap) {
   const int64_t i = tile_of_block(remap) * blockDim.x + threadIdx.x;
   if (i >= nf) return;
-  uf[i] += linear_node<D, T>(i, nf, ec, runP, fracP);
+  uf[i] = src[i] + linear_node<D, T>(i, nf, ec, runP, fracP);  // src may be uf
 }
 
-// y = Z x, one workgroup per row (coalesced row reads spread over 256 lanes, so that many
-// loads are in flight), wavefront shuffle + LDS reduction.
+// y = Z x, one workgroup per row (coalesced row reads spread over 256 lanes), wavefront
+// shuffle + LDS reduction.  Each lane issues eight row loads before it accumulates them
+// (in the order j = lane, lane + 256, ...), so that the matrix streams at the memory's rate
+// rather than one load latency per element.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemv(int n, const double* __restrict__ Z, int64_t ld,
                                               const T* __restrict__ x, T* __restrict__ y) {
   const int row = blockIdx.x;
   const double* zr = Z + (int64_t)row * ld;
   double s = 0.0;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) s += zr[j] * (double)x[j];
+  int j = threadIdx.x;
+  for (; j + 7 * 256 < n; j += 8 * 256) {
+    double z[8], xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      z[q] = zr[j + q * 256];
+      xv[q] = (double)x[j + q * 256];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) s += z[q] * xv[q];
+  }
+  for (; j < n; j += 256) s += zr[j] * (double)x[j];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   __shared__ double part[4];
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
@@ -129,6 +142,13 @@ __global__ void k_fill(int64_t n, T* __restrict__ p, T v) {
 __global__ void k_axpy_f32_f64(int64_t n, const float* __restrict__ e, double* __restrict__ u) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) u[i] += (double)e[i];
+}
+
+// y = a x (ACC false) or y = y + a x (ACC true): a Jacobi step whose residual is at hand
+template <typename T, bool ACC>
+__global__ void k_scale_add(int64_t n, const T* __restrict__ x, T a, T* __restrict__ y) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) y[i] = ACC ? y[i] + a * x[i] : a * x[i];
 }
 
 __global__ void k_cast_f64_f32(int64_t n, const double* __restrict__ a, float* __restrict__ b) {
@@ -341,13 +361,14 @@ void launch_restrict(int dim, int64_t nc, const T* rf, const int32_t* runR, cons
 
 template <typename T>
 void launch_prolong(int dim, int64_t nf, const T* ec, const int32_t* runP, const T* fracP, T* uf,
-                    const LaunchCfg& lc, hipStream_t s) {
+                    const LaunchCfg& lc, hipStream_t s, const T* src) {
   if (nf <= 0) return;
+  if (!src) src = uf;
   const unsigned gr = grid_for(nf, lc.block);
   if (dim == 2)
-    k_prolong<2, T><<<gr, lc.block, 0, s>>>(nf, ec, runP, fracP, uf, lc.xcd_remap);
+    k_prolong<2, T><<<gr, lc.block, 0, s>>>(nf, ec, runP, fracP, src, uf, lc.xcd_remap);
   else
-    k_prolong<3, T><<<gr, lc.block, 0, s>>>(nf, ec, runP, fracP, uf, lc.xcd_remap);
+    k_prolong<3, T><<<gr, lc.block, 0, s>>>(nf, ec, runP, fracP, src, uf, lc.xcd_remap);
 }
 
 template <typename T>
@@ -373,6 +394,15 @@ void launch_fill(int64_t n, T* p, T v, hipStream_t s) {
   int64_t gr = (n + 255) / 256;
   if (gr > 65536) gr = 65536;
   k_fill<T><<<(unsigned)gr, 256, 0, s>>>(n, p, v);
+}
+
+template <typename T>
+void launch_scale_add(int64_t n, const T* x, T a, T* y, bool accumulate, hipStream_t s) {
+  if (n <= 0) return;
+  if (accumulate)
+    k_scale_add<T, true><<<grid_for(n, 256), 256, 0, s>>>(n, x, a, y);
+  else
+    k_scale_add<T, false><<<grid_for(n, 256), 256, 0, s>>>(n, x, a, y);
 }
 
 void launch_axpy_f32_to_f64(int64_t n, const float* e, double* u, hipStream_t s) {
@@ -575,11 +605,13 @@ template void launch_restrict<double>(int, int64_t, const double*, const int32_t
 template void launch_restrict<float>(int, int64_t, const float*, const int32_t*, const float*, float*,
                                      float*, const LaunchCfg&, hipStream_t);
 template void launch_prolong<double>(int, int64_t, const double*, const int32_t*, const double*, double*,
-                                     const LaunchCfg&, hipStream_t);
+                                     const LaunchCfg&, hipStream_t, const double*);
 template void launch_prolong<float>(int, int64_t, const float*, const int32_t*, const float*, float*,
-                                    const LaunchCfg&, hipStream_t);
+                                    const LaunchCfg&, hipStream_t, const float*);
 template void launch_coarse_gemv<double>(int, const double*, int64_t, const double*, double*, hipStream_t);
 template void launch_coarse_gemv<float>(int, const double*, int64_t, const float*, float*, hipStream_t);
+template void launch_scale_add<double>(int64_t, const double*, double, double*, bool, hipStream_t);
+template void launch_scale_add<float>(int64_t, const float*, float, float*, bool, hipStream_t);
 template void launch_copy<double>(int64_t, const double*, double*, hipStream_t);
 template void launch_copy<float>(int64_t, const float*, float*, hipStream_t);
 template void launch_fill<double>(int64_t, double*, double, hipStream_t);

@@ -173,10 +173,13 @@ def test_mixed_precision_matches_oracle(name, cfg, sweep, monkeypatch):
     assert rel_inf(host(ud), ref64.u) < 1e-9
 
 
-def test_graph_replays_match_eager_cycles():
-    """cpm_run_cycles (captured graph, replayed) gives the same iterates as eager cycles."""
+@pytest.mark.parametrize("sweep", ["split", "fused"])
+def test_graph_replays_match_eager_cycles(sweep, monkeypatch):
+    """cpm_run_cycles (captured graph, replayed) gives the same iterates as eager cycles, bit
+    for bit, also where its later cycles start from the residual the previous cycle left."""
     import paper_1307_4354_amd as cpm
 
+    monkeypatch.setenv("CPM_SWEEP", sweep)
     torch = torch_cuda()
     cfg = W.config_sphere(32, 4)
     H = oracle_for(cfg)
