@@ -454,7 +454,7 @@ def main():
         "band_build_s": t_build,
         "autotune_s": t_tune,
         "tuning": [{"level": l, "lds": t[0], "ext_block": t[1], "nsum_block": t[2], "fused_sweep": t[3],
-                    "sweep_block": t[4]} for l, t in enumerate(tuning)],
+                    "sweep_block": t[4], "sweep_lds": t[5]} for l, t in enumerate(tuning)],
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

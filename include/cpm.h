@@ -237,16 +237,27 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
 /* Autotuner: for every level, time the two passes of a smoothing sweep with each candidate
  * launch configuration on this band's addressing (extension: gathers with workgroups of
  * 128 / 256 / 512 lanes or LDS-staged; neighbour sum: 128 / 256 / 512 lanes), then the fused
- * one-pass sweep (E f + (E N) u, 128 / 256 / 512 lanes; levels up to 2^21 nodes) against that
- * pair, and keep the fastest in the handle.  The environment variable CPM_SWEEP=fused|split,
- * read when the band is built, pins the sweep form instead.  Allocates two temporary
- * vectors; synchronous. */
+ * one-pass sweep (E f + (E N) u, levels up to 2^21 nodes: gathers with 128 / 256 / 512 lanes
+ * or LDS-staged) against that pair, and keep the fastest in the handle.  The environment
+ * variables CPM_SWEEP=fused|split and CPM_SWEEP_LDS=0, read when the band is built, pin the
+ * sweep form and keep the fused pass off LDS.  Allocates two temporary vectors;
+ * synchronous. */
 cpm_status cpm_autotune(cpm_band band, void* stream);
 
 /* Launch configuration chosen for one level (after cpm_autotune, or the defaults); any
- * output pointer may be NULL.  fused = 1 when the level sweeps with the fused pass. */
+ * output pointer may be NULL.  fused = 1 when the level sweeps with the fused pass;
+ * sweep_lds = 1 when that pass is LDS-staged (sweep_block is then its fixed 256 lanes). */
 cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_block, int* nsum_block, int* fused,
-                           int* sweep_block);
+                           int* sweep_block, int* sweep_lds);
+
+/* Set one level's launch configuration by hand (for instance one found by cpm_autotune in
+ * an earlier process): use_lds = LDS-staged extension (levels that have its tables),
+ * ext_block / nsum_block / sweep_block in {128, 256, 512}, fused = sweep with the fused pass
+ * (levels that have its addressing), sweep_lds = that pass LDS-staged (levels that have its
+ * tables; its workgroup is then 256).  CPM_E_INVALID, with nothing changed, for a
+ * configuration the level does not support.  Drops the band's captured cycle graphs. */
+cpm_status cpm_set_band_tuning(cpm_band band, int level, int use_lds, int ext_block, int nsum_block, int fused,
+                               int sweep_block, int sweep_lds);
 
 /* ---- learned smoother ---------------------------------------------------------------
  * Network (per node): x = [r_patch / s (27 values: residual on the 3x3x3 grid patch

@@ -91,8 +91,9 @@ def _load():
         "cpm_solve_batched": (c_int, [c_int, POINTER(vp), POINTER(cpm_params), POINTER(vp), POINTER(vp), vp,
                                       c_size_t, c_double, c_int, POINTER(cpm_stats), vp]),
         "cpm_autotune": (c_int, [vp, vp]),
+        "cpm_set_band_tuning": (c_int, [vp, c_int, c_int, c_int, c_int, c_int, c_int, c_int]),
         "cpm_band_tuning": (c_int, [vp, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int),
-                                    POINTER(c_int)]),
+                                    POINTER(c_int), POINTER(c_int)]),
         "cpm_set_smoother_weights": (c_int, [vp, vp, c_double]),
         "cpm_set_diffusion": (c_int, [vp, c_int, vp]),
         "cpm_mlp_forward": (c_int, [c_int64, vp, vp, vp, vp, vp]),
@@ -333,8 +334,16 @@ def cpm_mlp_adam(step: int, lr: float, w_master, m1, m2, G, w_bf16, stream=None)
                              _stream(stream)))
 
 
+def cpm_set_band_tuning(band: Band, level: int, use_lds: bool, ext_block: int, nsum_block: int, fused: bool,
+                        sweep_block: int, sweep_lds: bool) -> None:
+    """Pin one level's launch configuration (the fields cpm_band_tuning reports)."""
+    _check(_lib.cpm_set_band_tuning(band.handle, int(level), int(bool(use_lds)), int(ext_block), int(nsum_block),
+                                    int(bool(fused)), int(sweep_block), int(bool(sweep_lds))))
+
+
 def cpm_band_tuning(band: Band, level: int):
-    """(use_lds, ext_block, nsum_block, fused, sweep_block) chosen for one level."""
-    a, b, c, d, e = c_int(), c_int(), c_int(), c_int(), c_int()
-    _check(_lib.cpm_band_tuning(band.handle, int(level), byref(a), byref(b), byref(c), byref(d), byref(e)))
-    return bool(a.value), b.value, c.value, bool(d.value), e.value
+    """(use_lds, ext_block, nsum_block, fused, sweep_block, sweep_lds) chosen for one level."""
+    a, b, c, d, e, g = c_int(), c_int(), c_int(), c_int(), c_int(), c_int()
+    _check(_lib.cpm_band_tuning(band.handle, int(level), byref(a), byref(b), byref(c), byref(d), byref(e),
+                                byref(g)))
+    return bool(a.value), b.value, c.value, bool(d.value), e.value, bool(g.value)

@@ -423,11 +423,51 @@ bool stencil_runs(const HostLevel& src, const HostLevel& target, int p, std::vec
   return bad < 0;
 }
 
+// One workgroup's staged set: the [start, end) intervals of band indices that its rows read,
+// merged into segments laid out one after another in LDS.  lds_of(x) is the LDS offset of
+// band index x, which must lie in one of the intervals.
+struct StageSet {
+  std::vector<int32_t> seg_g, seg_e, seg_l;
+  int32_t size = 0;
+  void build(std::vector<std::pair<int32_t, int32_t>>& iv) {
+    std::sort(iv.begin(), iv.end());
+    seg_g.clear();
+    seg_e.clear();
+    seg_l.clear();
+    size = 0;
+    for (auto& v : iv) {
+      if (!seg_g.empty() && v.first <= seg_e.back()) {
+        if (v.second > seg_e.back()) {
+          size += v.second - seg_e.back();
+          seg_e.back() = v.second;
+        }
+      } else {
+        seg_g.push_back(v.first);
+        seg_e.push_back(v.second);
+        seg_l.push_back(size);
+        size += v.second - v.first;
+      }
+    }
+  }
+  void append_indices(std::vector<int32_t>& gidx) const {
+    for (size_t j = 0; j < seg_g.size(); ++j)
+      for (int32_t x = seg_g[j]; x < seg_e[j]; ++x) gidx.push_back(x);
+  }
+  // LDS offset that band index o maps to, o + lo being a staged index (segments are sorted
+  // and disjoint)
+  int32_t lds_of(int32_t o, int32_t lo) const {
+    const size_t j = (size_t)(std::upper_bound(seg_g.begin(), seg_g.end(), o + lo) - seg_g.begin()) - 1;
+    return seg_l[j] + (o - seg_g[j]);
+  }
+};
+
 // LDS staging tables of the extension (see HostLevel): for every workgroup of kExtBlock
 // consecutive stencil slots, merge the x-runs its nodes read into segments of consecutive
 // band indices, lay the segments out one after another in LDS and record, per local group
-// (a group cut at the workgroup boundary), where each x-run starts in LDS.
-void build_lds_tables(HostLevel& Lv, int S) {
+// (a group cut at the workgroup boundary), where each x-run starts in LDS.  Levels with the
+// fused-sweep addressing also get the fused sweep's tables on the same workgroups: rows
+// widened by one node on each side in x, plus the cross rows.
+void build_lds_tables(HostLevel& Lv, int S, int SX) {
   const int64_t n = Lv.n;
   const int64_t nb = (n + kExtBlock - 1) / kExtBlock;
   const int32_t xmask = (1 << kXoffBits) - 1;
@@ -438,7 +478,13 @@ void build_lds_tables(HostLevel& Lv, int S) {
   Lv.packedL.assign((size_t)n, 0);
   Lv.maxE = 0;
   Lv.maxG = 0;
+  const bool sweep = Lv.fusedOK && !Lv.originX.empty();
+  Lv.blkE2.assign(sweep ? (size_t)nb + 1 : 0, 0);
+  Lv.gidx2.clear();
+  Lv.lorg2.clear();
+  Lv.maxE2 = 0;
   std::vector<std::pair<int32_t, int32_t>> iv;  // [start, end) intervals of band indices
+  StageSet set2;
   for (int64_t b = 0; b < nb; ++b) {
     const int64_t k0 = b * kExtBlock, k1 = std::min<int64_t>(n, k0 + kExtBlock);
     // local groups: runs of equal global group id
@@ -494,6 +540,28 @@ void build_lds_tables(HostLevel& Lv, int S) {
     Lv.blkG[(size_t)b + 1] = Lv.blkG[(size_t)b] + (int32_t)lg_gid.size();
     Lv.maxE = std::max(Lv.maxE, off);
     Lv.maxG = std::max(Lv.maxG, (int32_t)lg_gid.size());
+    if (!sweep) continue;
+    // fused sweep: rows x0-1 .. x0+4 of every node, cross rows x0 .. x0+3
+    iv.clear();
+    for (size_t q = 0; q < lg_gid.size(); ++q) {
+      for (int s = 0; s < S; ++s) {
+        const int32_t o = Lv.origin[(size_t)lg_gid[q] * S + s];
+        iv.emplace_back(o + lg_xmin[q] - 1, o + lg_xmax[q] + 5);
+      }
+      for (int s = 0; s < SX; ++s) {
+        const int32_t o = Lv.originX[(size_t)lg_gid[q] * SX + s];
+        iv.emplace_back(o + lg_xmin[q], o + lg_xmax[q] + 4);
+      }
+    }
+    set2.build(iv);
+    set2.append_indices(Lv.gidx2);
+    for (size_t q = 0; q < lg_gid.size(); ++q) {
+      for (int s = 0; s < S; ++s)
+        Lv.lorg2.push_back(set2.lds_of(Lv.origin[(size_t)lg_gid[q] * S + s], lg_xmin[q] - 1));
+      for (int s = 0; s < SX; ++s) Lv.lorg2.push_back(set2.lds_of(Lv.originX[(size_t)lg_gid[q] * SX + s], lg_xmin[q]));
+    }
+    Lv.blkE2[(size_t)b + 1] = Lv.blkE2[(size_t)b] + set2.size;
+    Lv.maxE2 = std::max(Lv.maxE2, set2.size);
   }
 }
 
@@ -623,7 +691,7 @@ cpm_status build_stencil_order(HostLevel& Lv, int level, std::string& err) {
     for (int a = 0; a < dim; ++a) Lv.fracK[(size_t)(a * n + k)] = Lv.fracE[(size_t)(a * n + i)];
   }
   Lv.ngroups = g + 1;
-  build_lds_tables(Lv, S);
+  build_lds_tables(Lv, S, SX);
   Lv.packedB.assign((size_t)n, 0);
   for (int64_t k = 0; k < n; ++k) Lv.packedB[(size_t)order[(size_t)k]] = Lv.packed[(size_t)k];
   // B_interp (every node of some cubic stencil) with its +-y, +-z neighbours

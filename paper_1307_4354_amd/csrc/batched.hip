@@ -688,12 +688,14 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
   // ---- capture one batched cycle
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+  // captured on the private stream (the caller's may be the legacy default stream),
+  // launched on the caller's
+  if (hipStreamBeginCapture(b0->own, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     set_error("hipStreamBeginCapture failed");
     return CPM_E_HIP;
   }
-  cycle(s);
-  if (hipStreamEndCapture(s, &graph) != hipSuccess || !graph ||
+  cycle(b0->own);
+  if (hipStreamEndCapture(b0->own, &graph) != hipSuccess || !graph ||
       hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
     set_error("batched graph capture failed");

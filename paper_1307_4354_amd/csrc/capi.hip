@@ -89,7 +89,7 @@ static void free_dev(cpm_band b) {
     void* ps[] = {D.runE,  D.nbr,   D.fracE,  D.fracE32, D.runP,    D.fracP,  D.fracP32, D.runR,
                   D.fracR, D.fracR32, D.perm, D.packed, D.origin, D.fracK, D.fracK32, D.ilist, D.nbrI,
                   D.patchRow, D.patchMask, D.packedB, D.packedL, D.blkE, D.gidx, D.blkG, D.lorg, D.originX,
-                  D.qdiag, D.wd, D.acoef, D.vcD, D.runP3, D.fracP3};
+                  D.qdiag, D.wd, D.acoef, D.vcD, D.runP3, D.fracP3, D.blkE2, D.gidx2, D.lorg2};
     for (void* p : ps)
       if (p) (void)hipFree(p);
   }
@@ -111,18 +111,19 @@ double level_delta(const cpm_band b, int l, double c) {
   return c + 2.0 * b->dim / (h * h);
 }
 
-// Enter / leave the band's private stream (ordered after / before the caller's stream).
+// A call enqueues its work on the caller's stream itself, so that it is ordered with the
+// caller's work without events.  (Handing the results back through an event that the
+// caller's stream waits on while the private stream still holds a long queue of cycle
+// launches slowed those launches by a sixth on MI355X.)  Only graph capture uses the
+// private stream.
 cpm_status enter(cpm_band b, void* user) {
-  hipStream_t us = (hipStream_t)user;
-  if (hipEventRecord(b->ev_in, us) != hipSuccess) return CPM_E_HIP;
-  if (hipStreamWaitEvent(b->stream, b->ev_in, 0) != hipSuccess) return CPM_E_HIP;
+  b->stream = (hipStream_t)user;
   return CPM_OK;
 }
 
 cpm_status leave(cpm_band b, void* user) {
-  hipStream_t us = (hipStream_t)user;
-  if (hipEventRecord(b->ev_out, b->stream) != hipSuccess) return CPM_E_HIP;
-  if (hipStreamWaitEvent(us, b->ev_out, 0) != hipSuccess) return CPM_E_HIP;
+  (void)user;
+  b->stream = b->own;
   return CPM_OK;
 }
 
@@ -302,6 +303,19 @@ ExtAddr ext_addr(const DevLevel& D) {
   }
   return a;
 }
+SweepAddr sweep_addr(const DevLevel& D) {
+  SweepAddr a{D.perm, D.packed, D.origin, D.originX};
+  if (D.sweep_lds && D.use_sweep_lds) {
+    a.packedL = D.packedL;
+    a.blkE = D.blkE2;
+    a.gidx = D.gidx2;
+    a.blkG = D.blkG;
+    a.lorg = D.lorg2;
+    a.maxE = D.maxE2;
+    a.maxG = D.maxG;
+  }
+  return a;
+}
 template <typename T>
 static const T* fracK_of(const DevLevel& D);
 template <>
@@ -369,7 +383,7 @@ static T* fused_pre(const cpm_band b, int l, LevelBufs<T>* B, const T* f, const 
   const DevLevel& D = b->dev[(size_t)l];
   const double delta = level_delta(b, l, p.c);
   const T wod = (T)(p.omega / delta), inv_h2 = (T)(1.0 / (D.h * D.h));
-  const SweepAddr sa{D.perm, D.packed, D.origin, D.originX};
+  const SweepAddr sa = sweep_addr(D);
   T* Ef = nullptr;
   T* cur = B[l].u;
   T* oth = B[l].t;
@@ -405,7 +419,7 @@ static void fused_post(const cpm_band b, int l, LevelBufs<T>* B, T* cur, const T
   const DevLevel& D = b->dev[(size_t)l];
   const double delta = level_delta(b, l, p.c);
   const T wod = (T)(p.omega / delta), inv_h2 = (T)(1.0 / (D.h * D.h));
-  const SweepAddr sa{D.perm, D.packed, D.origin, D.originX};
+  const SweepAddr sa = sweep_addr(D);
   const T* Ef = rhsA ? nullptr : B[l].g;
   T* oth = cur == B[l].u ? B[l].t : B[l].u;
   for (int k = 0; k < nu; ++k) {
@@ -677,7 +691,8 @@ static std::string graph_key(const char* tag, const cpm_params& p, const void* a
   return os.str();
 }
 
-// Capture `fn` on the band stream once per key and launch the executable graph.
+// Capture `fn` on the private stream once per key and launch the executable graph on the
+// current stream.
 template <typename Fn>
 cpm_status graph_launch(cpm_band b, const std::string& key, Fn fn) {
   auto it = b->graphs.find(key);
@@ -687,12 +702,12 @@ cpm_status graph_launch(cpm_band b, const std::string& key, Fn fn) {
       b->graphs.clear();
     }
     hipGraph_t graph = nullptr;
-    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    if (hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       set_error("hipStreamBeginCapture failed");
       return CPM_E_HIP;
     }
-    fn(b->stream);
-    hipError_t e = hipStreamEndCapture(b->stream, &graph);
+    fn(b->own);
+    hipError_t e = hipStreamEndCapture(b->own, &graph);
     if (e != hipSuccess || !graph) {
       set_error(std::string("graph capture failed: ") + hipGetErrorString(e));
       return CPM_E_HIP;
@@ -711,6 +726,93 @@ cpm_status graph_launch(cpm_band b, const std::string& key, Fn fn) {
     return CPM_E_HIP;
   }
   return CPM_OK;
+}
+
+// For every level that has the fused pass (and whose form no environment variable pins),
+// time FP64 V-cycles of the paper's parameters (nu1 = nu2 = 3, omega = 2/3, c = 1) on a
+// constant right-hand side with the level sweeping in two passes, fused with gathers, and
+// fused from LDS, the other levels as they stand, and keep the fastest.
+cpm_status tune_sweep_forms(cpm_band b) {
+  if (b->vc_active) return CPM_OK;  // variable coefficients always sweep in two passes
+  cpm_status st = ensure_coarse(b, 1.0);
+  if (st != CPM_OK) return st;
+  const int64_t n0 = b->dev[0].n;
+  const size_t wb = workspace_bytes(b, CPM_F64);
+  double *f = nullptr, *u = nullptr;
+  void* work = nullptr;
+  if (hipMalloc((void**)&f, n0 * sizeof(double)) != hipSuccess ||
+      hipMalloc((void**)&u, n0 * sizeof(double)) != hipSuccess || hipMalloc(&work, wb) != hipSuccess) {
+    if (f) (void)hipFree(f);
+    if (u) (void)hipFree(u);
+    set_error("autotune: allocation failed");
+    return CPM_E_NOMEM;
+  }
+  hipStream_t s = b->stream;
+  launch_fill<double>(n0, f, 1.0, s);
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  cpm_params p{};
+  p.c = 1.0;
+  p.nu1 = 3;
+  p.nu2 = 3;
+  p.omega = 2.0 / 3.0;
+  p.precision = CPM_F64;
+  p.smoother = CPM_SMOOTH_JACOBI;
+  p.gamma = 1;
+  const bool learned = b->learned_active;
+  b->learned_active = false;
+  // Each candidate is captured once into a graph of kCyc cycles; the candidates are then
+  // timed in turn over several rounds (the minimum per candidate), so that slow drifts of
+  // the clock do not favour the one measured first.
+  constexpr int kCyc = 4, kReps = 4, kRounds = 4;
+  auto body = [&](hipStream_t st2) {
+    for (int j = 0; j < kCyc; ++j) enqueue_cycle(b, p, f, u, work, st2, j > 0);
+  };
+  for (int l = 0; l < b->L - 1 && st == CPM_OK; ++l) {
+    DevLevel& D = b->dev[(size_t)l];
+    if (!D.fusedOK || D.sweep_forced) continue;
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+    launch_fill<double>(n0, u, 0.0, s);
+    bool have[3] = {false, false, false};
+    for (int cand = 0; cand < 3 && st == CPM_OK; ++cand) {
+      if (cand == 2 && !D.sweep_lds) continue;
+      D.fused = cand > 0;
+      D.use_sweep_lds = cand == 2;
+      st = graph_launch(b, "autotune" + std::to_string(cand), body);  // capture + warm-up
+      have[cand] = st == CPM_OK;
+    }
+    float best[3] = {1e30f, 1e30f, 1e30f};
+    for (int round = 0; round < kRounds && st == CPM_OK; ++round)
+      for (int cand = 0; cand < 3 && st == CPM_OK; ++cand) {
+        if (!have[cand]) continue;
+        const std::string key = "autotune" + std::to_string(cand);
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < kReps && st == CPM_OK; ++r) st = graph_launch(b, key, body);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        best[cand] = std::min(best[cand], 1000.f * ms / (kCyc * kReps));
+      }
+    int pick = 0;
+    for (int cand = 1; cand < 3; ++cand)
+      if (have[cand] && best[cand] < best[pick]) pick = cand;
+    D.fused = pick > 0;
+    D.use_sweep_lds = pick == 2;
+  }
+  b->learned_active = learned;
+  (void)hipStreamSynchronize(s);
+  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(f);
+  (void)hipFree(u);
+  (void)hipFree(work);
+  if (st != CPM_OK) return st;
+  return check_launch("autotune (whole cycles)");
 }
 
 cpm_status validate_params(const cpm_band b, const cpm_params* p) {
@@ -824,13 +926,12 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     delete b;
     return st;
   }
-  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
-    set_error("stream / event creation failed");
+  if (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess) {
+    set_error("stream creation failed");
     delete b;
     return CPM_E_HIP;
   }
+  b->stream = b->own;
   b->dev.resize((size_t)b->L);
   // order in which the extension visits nodes: stencil order (default) or band order
   const char* ord = std::getenv("CPM_EXT_ORDER");
@@ -885,6 +986,22 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
       if (st == CPM_OK) st = upload(&D.blkG, H.blkG);
       if (st == CPM_OK) st = upload(&D.lorg, H.lorg);
     }
+    // LDS-staged fused sweep (on the extension's workgroups) unless disabled by
+    // CPM_SWEEP_LDS=0 or a workgroup would stage too many values; it is the default form of
+    // the fused pass where present
+    const char* slds_env = std::getenv("CPM_SWEEP_LDS");
+    D.sweep_lds = D.lds && D.fusedOK && !H.blkE2.empty() && H.maxE2 <= kMaxStaged &&
+                  !(slds_env && std::strcmp(slds_env, "0") == 0);
+    D.use_sweep_lds = D.sweep_lds;
+    D.maxE2 = H.maxE2;
+    if (D.sweep_lds) {
+      if (st == CPM_OK) st = upload(&D.blkE2, H.blkE2);
+      if (st == CPM_OK) st = upload(&D.gidx2, H.gidx2);
+      if (st == CPM_OK) st = upload(&D.lorg2, H.lorg2);
+    }
+    std::vector<int32_t>().swap(H.blkE2);
+    std::vector<int32_t>().swap(H.gidx2);
+    std::vector<int32_t>().swap(H.lorg2);
     std::vector<int32_t>().swap(H.packedL);
     std::vector<int32_t>().swap(H.blkE);
     std::vector<int32_t>().swap(H.gidx);
@@ -947,11 +1064,9 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
 
 cpm_status cpm_band_free(cpm_band band) {
   if (!band) return CPM_OK;
-  (void)hipStreamSynchronize(band->stream);
+  (void)hipDeviceSynchronize();  // work of earlier calls runs on the callers' streams
   free_dev(band);
-  if (band->ev_in) (void)hipEventDestroy(band->ev_in);
-  if (band->ev_out) (void)hipEventDestroy(band->ev_out);
-  if (band->stream) (void)hipStreamDestroy(band->stream);
+  if (band->own) (void)hipStreamDestroy(band->own);
   delete band;
   return CPM_OK;
 }
@@ -1349,7 +1464,7 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
           // u -> t and back, reading E f from g
           const bool odd = r & 1;
           launch_sweep<T>(band->dim, EXT_SMOOTH, D.n, odd ? B[level].t : uu, odd ? uu : B[level].t, B[level].g,
-                          (const T*)nullptr, SweepAddr{D.perm, D.packed, D.origin, D.originX}, fracS_of<T>(D),
+                          (const T*)nullptr, sweep_addr(D), fracS_of<T>(D),
                           (T)(1.0 / (D.h * D.h)), (T)delta, (T)(params->omega / delta), sweep_cfg(D), s);
         } else {
           launch_learned<T>(band, level, B[level].r, uu, params->c, s);

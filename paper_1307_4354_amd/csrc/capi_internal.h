@@ -34,9 +34,11 @@ struct cpm_band_s {
   int L = 0;
   std::vector<cpm::HostLevel> host;
   std::vector<cpm::DevLevel> dev;
+  // `stream`: where the current call enqueues its work (the caller's stream between enter()
+  // and leave(), the private stream otherwise); `own`: the private stream, which also
+  // captures the cycle graphs (the legacy default stream cannot be captured)
   hipStream_t stream = nullptr;
-  hipEvent_t ev_in = nullptr;
-  hipEvent_t ev_out = nullptr;
+  hipStream_t own = nullptr;
   // coarsest level: [A_c | Z] after Gauss-Jordan, Z = A_c^{-1} E_c at column offset n
   double coarse_c = 0.0 / 0.0;
   double* coarseM = nullptr;
@@ -74,6 +76,9 @@ LaunchCfg level_cfg(const DevLevel& D);
 LaunchCfg ext_cfg(const DevLevel& D);
 LaunchCfg sweep_cfg(const DevLevel& D);
 ExtAddr ext_addr(const DevLevel& D);
+SweepAddr sweep_addr(const DevLevel& D);
+// Whole-cycle choice of every level's sweep form (second stage of cpm_autotune).
+cpm_status tune_sweep_forms(cpm_band b);
 double level_delta(const cpm_band b, int l, double c);
 cpm_status enter(cpm_band b, void* user);
 cpm_status leave(cpm_band b, void* user);

@@ -54,6 +54,13 @@ struct HostLevel {
   // (y0+4) in 2-D).  fusedOK is false when some node's cross rows do not follow that pattern.
   std::vector<int32_t> originX;
   bool fusedOK = false;
+  // LDS staging of the fused sweep, on the extension's workgroups and local groups (blkG,
+  // packedL): the u values the widened stencils read (gidx2) and, per local group, the LDS
+  // offsets of its 4^(dim-1) rows (widened to 6 nodes) then of its cross rows (lorg2)
+  std::vector<int32_t> blkE2;   // nblocks + 1: prefix of staged values
+  std::vector<int32_t> gidx2;   // staged u indices
+  std::vector<int32_t> lorg2;   // local groups * (4^(dim-1) + cross rows)
+  int32_t maxE2 = 0;            // largest staged set of one workgroup
   // learned smoother (two finest levels): 3^dim grid patch of every node, in band order;
   // row (dy, dz) holds the band index of (x - 1, y + dy, z + dz) (virtual when that
   // node is absent), mask bit (dx+1) + 3 (dy+1) + 9 (dz+1) marks nodes that are present
@@ -118,6 +125,12 @@ struct DevLevel {
   double* fracR = nullptr;
   float* fracR32 = nullptr;
   int32_t* originX = nullptr;
+  bool sweep_lds = false;      // LDS staging tables of the fused sweep present
+  bool use_sweep_lds = false;  // fused sweep runs LDS-staged (else gathers through L1)
+  int32_t maxE2 = 0;
+  int32_t* blkE2 = nullptr;
+  int32_t* gidx2 = nullptr;
+  int32_t* lorg2 = nullptr;
   int32_t* runP3 = nullptr;  // full-multigrid interpolation from level+1 (cubic)
   double* fracP3 = nullptr;
   double* qdiag = nullptr;  // (E N)_ii

@@ -2,8 +2,10 @@
 // configurations of the two passes of a smoothing sweep on the band's own addressing and
 // keeps the fastest (the extension: gathers through the vector caches with workgroups of
 // 128 / 256 / 512 lanes, or LDS-staged; the neighbour sum: 128 / 256 / 512 lanes), then
-// times the fused one-pass sweep (128 / 256 / 512 lanes) against that pair and keeps the
-// faster form for the level.
+// times the fused one-pass sweep (gathers with 128 / 256 / 512 lanes, or LDS-staged) against
+// that pair.  Back-to-back launches of one kernel run on warm caches, which flatters the
+// two-pass form on mid-sized levels, so a second stage settles each level's form (two
+// passes, fused with gathers, fused from LDS) by timing whole V-cycles.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -107,12 +109,16 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
       launch_ext<double, double>(band->dim, EXT_SMOOTH, D.n, g, ext_addr(D), D.band_order ? D.fracE : D.fracK,
                                  nullptr, u, (double*)nullptr, delta, 0.5 / delta, nullptr, ext_cfg(D), s);
     });
-    const SweepAddr sa{D.perm, D.packed, D.origin, D.originX};
-    float t_fused = 1e30f;
-    int best_s = D.sweep_block;
-    for (int bi = 0; bi < 3; ++bi) {
+    float t_fused = 1e30f, t_gather = 1e30f;
+    int best_g = D.sweep_block;
+    bool best_slds = D.use_sweep_lds;
+    for (int cand = 0; cand < 4; ++cand) {
+      const bool slds = cand == 3;  // LDS-staged (fixed workgroup), else gathers
+      if (slds && !D.sweep_lds) continue;
+      D.use_sweep_lds = slds;
+      const SweepAddr sa = sweep_addr(D);
       LaunchCfg lc;
-      lc.block = blocks[bi];
+      lc.block = slds ? kExtBlock : blocks[cand];
       // u -> g and g -> u alternately, like the solver's ping-pong
       int flip = 0;
       const float t = time_us(s, e0, e1, reps, [&] {
@@ -122,12 +128,17 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
         launch_sweep<double>(band->dim, EXT_SMOOTH, D.n, src, dst, src, nullptr, sa, D.fracK, inv_h2, delta,
                              0.5 / delta, lc, s);
       });
+      if (!slds && t < t_gather) {
+        t_gather = t;
+        best_g = lc.block;
+      }
       if (t < t_fused) {
         t_fused = t;
-        best_s = blocks[bi];
+        best_slds = slds;
       }
     }
-    D.sweep_block = best_s;
+    D.sweep_block = best_g;  // the gather form's workgroup (the LDS form's is fixed)
+    D.use_sweep_lds = best_slds;
     if (!D.sweep_forced) D.fused = t_fused < t_split;
   }
   (void)hipEventDestroy(e0);
@@ -139,11 +150,13 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
   for (auto& kv : band->graphs) (void)hipGraphExecDestroy(kv.second);
   band->graphs.clear();
   if ((st = check_launch("cpm_autotune")) != CPM_OK) return st;
+  // second stage: each level's sweep form decided on whole cycles
+  if ((st = tune_sweep_forms(band)) != CPM_OK) return st;
   return leave(band, stream);
 }
 
 cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_block, int* nsum_block, int* fused,
-                           int* sweep_block) {
+                           int* sweep_block, int* sweep_lds) {
   if (!band || level < 0 || level >= band->L) {
     set_error("cpm_band_tuning: invalid argument");
     return CPM_E_INVALID;
@@ -153,7 +166,34 @@ cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_bloc
   if (ext_block) *ext_block = D.use_lds ? kExtBlock : D.ext_block;
   if (nsum_block) *nsum_block = D.nsum_block;
   if (fused) *fused = D.fused && D.fusedOK ? 1 : 0;
-  if (sweep_block) *sweep_block = D.sweep_block;
+  const bool slds = D.sweep_lds && D.use_sweep_lds;
+  if (sweep_block) *sweep_block = slds ? kExtBlock : D.sweep_block;
+  if (sweep_lds) *sweep_lds = slds ? 1 : 0;
+  return CPM_OK;
+}
+
+cpm_status cpm_set_band_tuning(cpm_band band, int level, int use_lds, int ext_block, int nsum_block, int fused,
+                               int sweep_block, int sweep_lds) {
+  if (!band || level < 0 || level >= band->L) {
+    set_error("cpm_set_band_tuning: invalid argument");
+    return CPM_E_INVALID;
+  }
+  DevLevel& D = band->dev[(size_t)level];
+  auto blk_ok = [](int b) { return b == 128 || b == 256 || b == 512; };
+  if ((use_lds && !D.lds) || (fused && !D.fusedOK) || (sweep_lds && !D.sweep_lds) || !blk_ok(ext_block) ||
+      !blk_ok(nsum_block) || !blk_ok(sweep_block)) {
+    set_error("cpm_set_band_tuning: configuration not supported on this level");
+    return CPM_E_INVALID;
+  }
+  D.use_lds = use_lds != 0;
+  D.ext_block = ext_block;
+  D.nsum_block = nsum_block;
+  D.fused = fused != 0;
+  D.sweep_block = sweep_block;
+  D.use_sweep_lds = sweep_lds != 0;
+  // captured graphs hold the old launch configurations
+  for (auto& kv : band->graphs) (void)hipGraphExecDestroy(kv.second);
+  band->graphs.clear();
   return CPM_OK;
 }
 

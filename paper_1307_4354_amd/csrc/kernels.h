@@ -38,12 +38,20 @@ struct ExtAddr {
 };
 
 // Fused sweep addressing (stencil order): ExtAddr's perm, packed, origin plus the cross-row
-// origins of the widened stencil.
+// origins of the widened stencil; with packedL set, the LDS staging tables of the fused
+// sweep instead (blkE, gidx, lorg of the widened rows; blkG, packedL of the extension).
 struct SweepAddr {
   const int32_t* perm;
   const int32_t* packed;
   const int32_t* origin;
   const int32_t* originX;
+  const int32_t* packedL = nullptr;
+  const int32_t* blkE = nullptr;
+  const int32_t* gidx = nullptr;
+  const int32_t* blkG = nullptr;
+  const int32_t* lorg = nullptr;
+  int32_t maxE = 0;
+  int32_t maxG = 0;
 };
 
 // mode EXT_SMOOTH: uo = u + (omega/delta)(b + E f + (E N) u - delta u); EXT_RESID: uo = that

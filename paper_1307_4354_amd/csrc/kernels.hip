@@ -55,6 +55,28 @@ __global__ __launch_bounds__(kMaxBlock) void k_sweep(int64_t n, const T* __restr
   if (k < n) sweep_node<D, T, MODE>(k, n, u, uo, Ef, b, perm, packed, origin, originX, frac, inv_h2, delta, wod);
 }
 
+// Fused sweep, LDS-staged: the workgroup of kExtBlock stencil slots copies the u values its
+// widened stencils read into LDS, then sweeps from there.
+template <int D, typename T, int MODE>
+__global__ __launch_bounds__(kExtBlock) void k_sweep_lds(int64_t n, const T* __restrict__ u, T* __restrict__ uo,
+                                                         const T* __restrict__ Ef, const T* __restrict__ b,
+                                                         const int32_t* __restrict__ perm,
+                                                         const int32_t* __restrict__ packedL,
+                                                         const int32_t* __restrict__ blkE,
+                                                         const int32_t* __restrict__ gidx,
+                                                         const int32_t* __restrict__ blkG,
+                                                         const int32_t* __restrict__ lorg, const T* __restrict__ frac,
+                                                         T inv_h2, T delta, T wod, int remap, int lo_offset) {
+  constexpr int SR = D == 2 ? 4 + 2 : 16 + 16;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  T* gl = (T*)smem;
+  int32_t* lo = (int32_t*)(smem + lo_offset);
+  const int64_t blk = tile_of_block(remap);
+  ext_stage<T>(blk, u, blkE, gidx, blkG, lorg, SR, gl, lo);
+  const int64_t k = blk * kExtBlock + threadIdx.x;
+  if (k < n) sweep_node_lds<D, T, MODE>(k, n, gl, lo, u, uo, Ef, b, perm, packedL, frac, inv_h2, delta, wod);
+}
+
 template <int D, typename T, typename TO, int MODE>
 __global__ __launch_bounds__(kExtBlock) void k_ext_lds(int64_t n, const T* __restrict__ g,
                                                        const int32_t* __restrict__ perm,
@@ -443,6 +465,25 @@ template <typename T>
 void launch_sweep(int dim, int mode, int64_t n, const T* u, T* uo, const T* Ef, const T* b, const SweepAddr& a,
                   const T* frac, T inv_h2, T delta, T wod, const LaunchCfg& lc, hipStream_t s) {
   if (n <= 0) return;
+  if (a.packedL) {
+    // LDS-staged: fixed workgroup of kExtBlock stencil slots; dynamic LDS = staged values +
+    // the local groups' row offsets
+    const int SR = dim == 2 ? 6 : 32;
+    const int lo_off = (int)(((size_t)a.maxE * sizeof(T) + 15) & ~(size_t)15);
+    const size_t shm = (size_t)lo_off + (size_t)a.maxG * SR * sizeof(int32_t);
+    const unsigned gl = (unsigned)((n + kExtBlock - 1) / kExtBlock);
+    const int rm = lc.xcd_remap;
+#define CPM_SWEEPL_CASE(DD, MM)                                                                                   \
+  k_sweep_lds<DD, T, MM><<<gl, kExtBlock, shm, s>>>(n, u, uo, Ef, b, a.perm, a.packedL, a.blkE, a.gidx, a.blkG, \
+                                                    a.lorg, frac, inv_h2, delta, wod, rm, lo_off)
+    if (dim == 2) {
+      if (mode == EXT_SMOOTH) CPM_SWEEPL_CASE(2, EXT_SMOOTH); else CPM_SWEEPL_CASE(2, EXT_RESID);
+    } else {
+      if (mode == EXT_SMOOTH) CPM_SWEEPL_CASE(3, EXT_SMOOTH); else CPM_SWEEPL_CASE(3, EXT_RESID);
+    }
+#undef CPM_SWEEPL_CASE
+    return;
+  }
   const unsigned gr = grid_for(n, lc.block);
   const int rm = lc.xcd_remap;
 #define CPM_SWEEP_CASE(DD, MM)                                                                                  \

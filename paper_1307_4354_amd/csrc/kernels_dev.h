@@ -272,6 +272,34 @@ __device__ __forceinline__ void sweep_node(int64_t k, int64_t n, const T* __rest
   uo[i] = MODE == EXT_SMOOTH ? ui + wod * r : r;
 }
 
+// The fused sweep at slot k from LDS: gl holds the workgroup's staged u values, lo the LDS
+// offsets of the local groups' rows (4^(D-1) widened rows, then the cross rows), packedL
+// the node's local group and x offset.  The arithmetic is sweep_node's, term for term.
+template <int D, typename T, int MODE>
+__device__ __forceinline__ void sweep_node_lds(int64_t k, int64_t n, const T* gl, const int32_t* lo,
+                                               const T* __restrict__ u, T* __restrict__ uo,
+                                               const T* __restrict__ Ef, const T* __restrict__ b,
+                                               const int32_t* __restrict__ perm,
+                                               const int32_t* __restrict__ packedL, const T* __restrict__ frac,
+                                               T inv_h2, T delta, T wod) {
+  constexpr int S = D == 2 ? 4 : 16;
+  constexpr int SX = D == 2 ? 2 : 16;
+  const int32_t i = perm[k];
+  const int32_t pk = packedL[k];
+  const int32_t* org = lo + (pk >> kXoffBits) * (S + SX);
+  const T* ux = gl + (pk & ((1 << kXoffBits) - 1));
+  T wx[4], wy[4], wz[4] = {T(0), T(0), T(0), T(0)};
+  cubic_weights<T>(frac[k], wx);
+  cubic_weights<T>(frac[n + k], wy);
+  if (D == 3) cubic_weights<T>(frac[2 * n + k], wz);
+  T t = en_node<D, T>(ux, org, org + S, wx, wy, wz) * inv_h2;
+  if (Ef) t += Ef[i];
+  const T ui = u[i];
+  T r = t - delta * ui;
+  if (b) r += b[i];
+  uo[i] = MODE == EXT_SMOOTH ? ui + wod * r : r;
+}
+
 // ---- LDS-staged extension ---------------------------------------------------------
 // A workgroup of kExtBlock consecutive stencil slots first copies the g values its
 // stencils read into LDS (a few hundred values instead of 64 gathers per node through the

@@ -207,6 +207,45 @@ def test_graph_replays_match_eager_cycles(sweep, monkeypatch):
     assert np.all(ho[:6] > 0) and np.all(np.diff(ho[:6]) < 0)
 
 
+@pytest.mark.parametrize("name,cfg", [
+    ("circle128", W.config_circle(128, 5)),
+    ("sphere32", W.config_sphere(32, 4)),
+    ("torus32", W.config_torus_mixed(32, 3)),
+], ids=["circle128", "sphere32", "torus32"])
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_fused_sweep_lds_equals_gathers(name, cfg, precision, monkeypatch):
+    """The LDS-staged fused sweep does the gather form's arithmetic term for term: cycles
+    with either form on every level give the same iterates, bit for bit."""
+    log("fused sweep LDS vs gathers: %s %s" % (name, precision))
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    prec = cpm.CPM_F64 if precision == "f64" else cpm.CPM_MIXED
+    out = {}
+    fd = None
+    for lds in ("1", "0"):
+        monkeypatch.setenv("CPM_SWEEP", "fused")
+        monkeypatch.setenv("CPM_SWEEP_LDS", lds)
+        band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+        if fd is None:
+            fd = dev(cfg.problem.f(band.export(0)[1]))
+        tun = [cpm.cpm_band_tuning(band, l) for l in range(band.levels - 1)]
+        assert all(t[3] for t in tun)
+        assert all(t[5] == (lds == "1") for t in tun)
+        p = cpm.make_params(c=cfg.problem.c, precision=prec)
+        work, nbytes = workspace(band, p)
+        ud = torch.zeros_like(fd)
+        hist = torch.zeros(8, dtype=torch.float64, device="cuda")
+        its = []
+        for _ in range(4):
+            cpm.cpm_run_cycles(band, p, fd, ud, work, nbytes, 1, 1, hist)
+            its.append(host(ud).copy())
+        out[lds] = its
+        del work, band
+    for k in range(4):
+        assert np.array_equal(out["1"][k], out["0"][k]), k
+
+
 def test_error_paths():
     import paper_1307_4354_amd as cpm
 
@@ -276,8 +315,9 @@ def test_autotuned_solve_matches_oracle():
     band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
     cpm.cpm_autotune(band)
     for l in range(band.levels):
-        lds, eb, nb, fused, sb = cpm.cpm_band_tuning(band, l)
+        lds, eb, nb, fused, sb, slds = cpm.cpm_band_tuning(band, l)
         assert eb in (128, 256, 512) and nb in (128, 256, 512) and sb in (128, 256, 512)
+        assert sb == 256 or not slds
     p = cpm.make_params()
     work, nbytes = workspace(band, p)
     fd = dev(f)
