@@ -121,11 +121,14 @@ def run_batched256(args):
     items = W.batch_problems(args.nprob)
     t0 = time.perf_counter()
     bands, fs = [], []
-    for it in items:
+    for k, it in enumerate(items):
         b = _build(cpm, it.problem, it.h0, it.levels, it.lam2)
         _, cp = b.export(0)
         bands.append(b)
         fs.append(torch.as_tensor(it.problem.f(cp)).to("cuda"))
+        if (k + 1) % 32 == 0:  # the host build takes minutes: report progress on stderr
+            print("built %d of %d bands (%.0f s)" % (k + 1, len(items), time.perf_counter() - t0),
+                  file=sys.stderr, flush=True)
     t_build = time.perf_counter() - t0
     sizes = [b.n(0) for b in bands]
     p = cpm.make_params(precision=cpm.CPM_MIXED)
