@@ -246,6 +246,60 @@ def test_fused_sweep_lds_equals_gathers(name, cfg, precision, monkeypatch):
         assert np.array_equal(out["1"][k], out["0"][k]), k
 
 
+def test_calls_run_on_the_callers_stream():
+    """Cycles enqueued on a side stream are ordered with that stream's later work (no
+    synchronisation in between) and give the default stream's iterates bit for bit."""
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    cfg = W.config_sphere(32, 4)
+    band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+    fd = dev(cfg.problem.f(band.export(0)[1]))
+    p = cpm.make_params()
+    work, nbytes = workspace(band, p)
+    hist = torch.zeros(16, dtype=torch.float64, device="cuda")
+    ua = torch.zeros_like(fd)
+    cpm.cpm_run_cycles(band, p, fd, ua, work, nbytes, 5, 5, hist)
+    ref = host(ua).copy()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ub = torch.zeros_like(fd)
+        cpm.cpm_run_cycles(band, p, fd, ub, work, nbytes, 5, 5, hist, stream=side)
+        snap = ub.clone()  # runs after the cycles on the same stream
+    torch.cuda.synchronize()
+    assert np.array_equal(host(snap), ref)
+
+
+def test_set_band_tuning():
+    """cpm_set_band_tuning applies a configuration (read back by cpm_band_tuning), rejects
+    one the level cannot run, and the pinned configuration still solves to the oracle."""
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    cfg = W.config_sphere(32, 4)
+    H = oracle_for(cfg)
+    f = cfg.problem.f(H.levels[0].cp)
+    band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+    for l in range(band.levels - 1):
+        cpm.cpm_set_band_tuning(band, l, False, 128, 512, True, 512, False)
+        assert cpm.cpm_band_tuning(band, l) == (False, 128, 512, True, 512, False)
+    with pytest.raises(cpm.CpmError):
+        cpm.cpm_set_band_tuning(band, 0, True, 100, 256, False, 256, False)  # workgroup size
+    before = cpm.cpm_band_tuning(band, 0)
+    with pytest.raises(cpm.CpmError):
+        cpm.cpm_set_band_tuning(band, band.levels, True, 256, 256, False, 256, False)  # no such level
+    assert cpm.cpm_band_tuning(band, 0) == before
+    ref = ov.solve(H, f, ov.Params(), rtol=1e-10, max_cycles=60)
+    p = cpm.make_params()
+    work, nbytes = workspace(band, p)
+    fd = dev(f)
+    ud = torch.zeros_like(fd)
+    st = cpm.cpm_solve(band, p, fd, ud, work, nbytes, rtol=1e-10, max_cycles=60)
+    assert st.cycles == ref.cycles
+    assert rel_inf(host(ud), ref.u) < 1e-12
+
+
 def test_error_paths():
     import paper_1307_4354_amd as cpm
 
