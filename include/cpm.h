@@ -183,7 +183,7 @@ cpm_status cpm_extend(cpm_band band, int level, const double* g, double* out, vo
  * cpm_apply and the batched solver keep the constant-coefficient operator.  Synchronous. */
 cpm_status cpm_set_diffusion(cpm_band band, int level, const double* a);
 
-/* One V(nu1, nu2) cycle in place on u (Algorithm 4.1) for right-hand side f./* One V(nu1, nu2) cycle in place on u (Algorithm 4.1) for right-hand side f.  work has
+/* One V(nu1, nu2) cycle in place on u (Algorithm 4.1) for right-hand side f.  work has
  * cpm_workspace_size bytes.  If relres_out is not NULL the call synchronizes the stream
  * and stores ||E f - A u||_inf / ||E f||_inf of the new iterate (the relative increment
  * for CPM_SMOOTH_STANDARD).  Only precision CPM_F64 with smoother CPM_SMOOTH_JACOBI or
