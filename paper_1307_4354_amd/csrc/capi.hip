@@ -432,7 +432,8 @@ static void fused_post(const cpm_band b, int l, LevelBufs<T>* B, T* cur, const T
 
 // r_first (finest level, split sweeps only): the residual E(f + N u) - delta u of the
 // entering iterate, already computed (the stopping test's) with the same two passes as a
-// sweep, so that the first pre-smoothing sweep is u += (omega/delta) r_first, bit for bit.
+// sweep, so that the first pre-smoothing sweep is u += (omega/delta) r_first, or the learned
+// update applied to r_first, bit for bit.
 // u_zero with an A-space right-hand side rhsA: the first sweep from u = 0 is
 // u = (omega/delta) rhsA, and u need not be cleared beforehand.
 template <typename T>
@@ -466,6 +467,10 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
     return;
   }
   for (int k = 0; k < nu1; ++k) {
+    if (k == 0 && learned_here && r_first) {  // the network's update from the residual at hand
+      launch_learned<T>(b, l, r_first, B[l].u, p.c, s);
+      continue;
+    }
     if (k == 0 && !learned_here && !b->vc_active && (r_first || (u_zero && rhsA && !f))) {
       launch_scale_add<T>(D.n, r_first ? r_first : rhsA, (T)(p.omega / delta), B[l].u, r_first != nullptr, s);
       continue;
@@ -596,13 +601,15 @@ void enqueue_resid64(const cpm_band b, const double* f, const double* u, double*
 }
 
 // Whether a cycle may start from the residual that the previous cycle's stopping test left
-// in the finest level's r: the Ruuth-Merriman FP64 cycle with constant coefficients whose
-// finest level sweeps in two passes (the fused pass forms the same residual in another
-// rounding order).
+// in the finest level's r: the FP64 cycle with constant coefficients whose finest level sweeps
+// in two passes (the fused pass forms the same residual in another rounding order), with the
+// Ruuth-Merriman step or the learned update (which is applied to that residual).
 static bool resid_reuse_ok(const cpm_band b, const cpm_params& p) {
   const DevLevel& D = b->dev[0];
-  return p.precision == CPM_F64 && p.smoother == CPM_SMOOTH_JACOBI && !b->vc_active && !b->learned_active &&
-         p.nu1 > 0 && !(D.fused && D.fusedOK);
+  if (p.precision != CPM_F64 || b->vc_active || p.smoother == CPM_SMOOTH_STANDARD) return false;
+  const bool learned0 = b->learned_active && b->mlpW && D.patchRow;  // never fused
+  const int nu1 = learned0 && p.learned_sweeps > 0 ? p.learned_sweeps : p.nu1;
+  return nu1 > 0 && (learned0 || !(D.fused && D.fusedOK));
 }
 
 // One complete cycle of the solve loop on the band stream, ending with the residual
