@@ -366,7 +366,7 @@ def main():
                    "status": st.status}
 
     # dominant kernel: finest-level extension + smoothing pass, timed with HIP events on the
-    # band's stream.  Algorithmic bytes per node: 3 closest-point fractions (24 B), u read (8),
+    # stream it runs on.  Algorithmic bytes per node: 3 closest-point fractions (24 B), u read (8),
     # u write (8), one read of g (8) = 48 B (FP64, 3-D).
     ud.zero_()
     avg_us = cpm.cpm_time_kernel(band, p64, 0, 0, args.kernel_reps, fd, ud, work, nb64)

@@ -210,7 +210,7 @@ cpm_status cpm_run_cycles(cpm_band band, const cpm_params* params, const double*
                           double* relres_dev, void* stream);
 
 /* Average duration in microseconds of one launch of a V-cycle kernel on one level, timed
- * with HIP events on the band's stream over `reps` back-to-back launches: which = 0 the
+ * with HIP events on `stream` over `reps` back-to-back launches: which = 0 the
  * extension pass fused with Jacobi smoothing (the dominant kernel), 1 the neighbour-sum
  * pass, 2 restriction into `level` (level >= 1), 3 prolongation from level+1 into `level`
  * (level < levels-1), 4 the fused learned-smoother update from a fixed residual (level < 2,

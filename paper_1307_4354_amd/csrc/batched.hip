@@ -340,7 +340,7 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
   cpm_status st = enter(b0, stream);
   if (st != CPM_OK) return st;
   hipStream_t s = b0->stream;
-  // coarsest-level inverses (each on its own band stream, then joined)
+  // coarsest-level inverses (each band's on its own stream, synchronously)
   for (int p = 0; p < nprob; ++p) {
     if ((st = ensure_coarse(bands[p], P.c)) != CPM_OK) return st;
   }

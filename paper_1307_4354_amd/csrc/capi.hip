@@ -612,7 +612,7 @@ static bool resid_reuse_ok(const cpm_band b, const cpm_params& p) {
   return nu1 > 0 && (learned0 || !(D.fused && D.fusedOK));
 }
 
-// One complete cycle of the solve loop on the band stream, ending with the residual
+// One complete cycle of the solve loop on stream s, ending with the residual
 // norm of the new iterate in slot 0 (and, in FP64, the residual itself in the finest
 // level's r).  r_ready: that residual is the one of the entering u (the previous cycle of the
 // same solve left it), so the first smoothing sweep is taken from it.
