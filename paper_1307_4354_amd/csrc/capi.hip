@@ -741,6 +741,10 @@ cpm_status graph_launch(cpm_band b, const std::string& key, Fn fn) {
 // fused from LDS, the other levels as they stand, and keep the fastest.
 cpm_status tune_sweep_forms(cpm_band b) {
   if (b->vc_active) return CPM_OK;  // variable coefficients always sweep in two passes
+  bool any = false;  // a level that could sweep either way
+  for (int l = 0; l + 1 < b->L; ++l) any = any || (b->dev[(size_t)l].fusedOK && !b->dev[(size_t)l].sweep_forced);
+  // bands that cannot run cycles (coarsest level beyond the dense solve) keep the first stage
+  if (!any || b->dev[(size_t)(b->L - 1)].n > kMaxCoarse) return CPM_OK;
   cpm_status st = ensure_coarse(b, 1.0);
   if (st != CPM_OK) return st;
   const int64_t n0 = b->dev[0].n;

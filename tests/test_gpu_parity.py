@@ -300,6 +300,24 @@ def test_set_band_tuning():
     assert rel_inf(host(ud), ref.u) < 1e-12
 
 
+def test_autotune_on_bands_that_cannot_cycle():
+    """Autotuning needs no cycle: a one-level band whose single level exceeds the dense
+    coarsest solve tunes its passes, and only the solve reports the size limit."""
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    cfg = W.config_sphere(32, 1)
+    band = build_gpu(cfg.problem.surface, cfg.h0, 1, cfg.lam2)
+    assert band.n(0) > 12000
+    cpm.cpm_autotune(band)
+    assert len(cpm.cpm_band_tuning(band, 0)) == 6
+    fd = dev(cfg.problem.f(band.export(0)[1]))
+    p = cpm.make_params()
+    work, nbytes = workspace(band, p)
+    with pytest.raises(cpm.CpmError):
+        cpm.cpm_solve(band, p, fd, torch.zeros_like(fd), work, nbytes, rtol=1e-10, max_cycles=5)
+
+
 def test_error_paths():
     import paper_1307_4354_amd as cpm
 
