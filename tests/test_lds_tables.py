@@ -1,0 +1,26 @@
+"""The band builder's LDS staging tables (host code, no GPU): compiles a checker against the
+builder with g++ and runs it.  For circles, spheres (centred and off-centre), a torus and
+Dziuk's surface it checks, on every level and for every node, that each LDS address the
+LDS-staged extension and fused sweep form lies in its workgroup's staged range and holds the
+band index the gather form of the same pass reads (so the two forms read the same values)."""
+import os
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_1307_4354_amd", "csrc")
+
+
+def test_lds_staging_tables(tmp_path):
+    exe = str(tmp_path / "lds_tables_check")
+    cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-ffp-contract=off", "-I" + CSRC,
+           os.path.join(HERE, "lds_tables_check.cpp"), os.path.join(CSRC, "band_build.cpp"), "-o", exe]
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        pytest.fail("build failed:\n" + r.stdout[-3000:])
+    out = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=600)
+    assert out.returncode == 0 and "ALL OK" in out.stdout, out.stdout[-3000:]
+    # the fused sweep's tables exist on the levels that have its addressing
+    assert "sweep tables present" in out.stdout
