@@ -117,6 +117,28 @@ __global__ __launch_bounds__(kMaxBlock) void kb_ext(const LvItem* __restrict__ i
   }
 }
 
+// First pre-smoothing sweep of a level from u = 0 (every level starts a cycle there): on a
+// problem's finest level, with its A-space right-hand side b, the sweep is u = wod b; on a
+// coarser level g = f + N 0 = f, so the sweep extends f itself and skips the neighbour sum.
+// Bit for bit the two-pass sweep from zero.
+template <int D>
+__global__ __launch_bounds__(kMaxBlock) void kb_first(const LvItem* __restrict__ it, const int64_t* __restrict__ pre,
+                                                      int ni, const int* __restrict__ done) {
+  const int64_t total = pre[ni];
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int q = find_item(pre, ni, t);
+    const LvItem& B = it[q];
+    if (done[B.prob]) continue;
+    const int64_t k = (t - pre[q]) * blockDim.x + threadIdx.x;
+    if (k >= B.n) continue;
+    if (B.rhsA)
+      B.u[k] = B.wod * B.rhsA[k];
+    else
+      (void)ext_node<D, float, float, EXT_SMOOTH>(k, B.n, B.f, B.perm, B.packed, B.origin, B.frac, nullptr, B.u,
+                                                  B.r, B.delta, B.wod);
+  }
+}
+
 template <int D, int RESTRICT>
 __global__ __launch_bounds__(kMaxBlock) void kb_transfer(const TrItem* __restrict__ it,
                                                          const int64_t* __restrict__ pre, int ni,
@@ -571,6 +593,14 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
       kb_ext<3, EXT_SMOOTH><<<grid(pe.total, gm), bs, 0, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
     }
   };
+  auto enqueue_first = [&](const PhaseSet& S, int bs, int gm, int a, hipStream_t st2) {
+    const DevPhase& pe = S.ext[a];
+    if (!pe.ni) return;
+    if (dim == 2)
+      kb_first<2><<<grid(pe.total, gm), bs, 0, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
+    else
+      kb_first<3><<<grid(pe.total, gm), bs, 0, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
+  };
   // ---- tile-size autotuning: time one smoothing sweep of the largest phase per candidate
   {
     int abig = 0;
@@ -655,7 +685,13 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
   auto cycle = [&](hipStream_t st2) {
     top(2, st2);  // e = 0 on every finest level
     for (int a = plan.A - 1; a >= 1; --a) {
-      for (int k = 0; k < P.nu1; ++k) enqueue_sweep(S, bs, gm, a, st2);
+      // every level enters from u = 0 (finest: cleared above; coarser: by the restriction)
+      for (int k = 0; k < P.nu1; ++k) {
+        if (k == 0)
+          enqueue_first(S, bs, gm, a, st2);
+        else
+          enqueue_sweep(S, bs, gm, a, st2);
+      }
       const DevPhase& pn = S.nsum[a];
       const DevPhase& pe = S.ext[a];
       if (pn.ni) {
