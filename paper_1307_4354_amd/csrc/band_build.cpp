@@ -759,7 +759,54 @@ cpm_status build_patches(HostLevel& Lv, int level, std::string& err) {
   if (gap) {
     std::vector<int32_t>().swap(Lv.patchRow);
     std::vector<uint32_t>().swap(Lv.patchMask);
+    return CPM_OK;
   }
+  // Group consecutive nodes whose present rows all continue the group's rows (row r of node
+  // t of the group = base_r + t).  A row with no present node is loaded but masked out, so
+  // its base is free: it is fixed by the first node of the group that has the row.
+  std::vector<int32_t> bases;  // groups x rows
+  std::vector<int32_t> base((size_t)rows, 0);
+  std::vector<char> fixed((size_t)rows, 0);
+  Lv.patchPk.assign((size_t)n, 0);
+  int64_t g = -1;
+  int t = 0;
+  auto flush = [&]() {
+    for (int r = 0; r < rows; ++r) bases.push_back(fixed[(size_t)r] ? base[(size_t)r] : 0);
+  };
+  for (int64_t i = 0; i < n; ++i) {
+    const uint32_t mask = Lv.patchMask[(size_t)i];
+    bool fresh = g < 0 || t + 1 >= kPatchRun;
+    for (int r = 0; r < rows && !fresh; ++r)
+      if (((mask >> (3 * r)) & 7u) && fixed[(size_t)r] && Lv.patchRow[(size_t)(r * n + i)] != base[(size_t)r] + t + 1)
+        fresh = true;
+    if (fresh) {
+      if (g >= 0) flush();
+      ++g;
+      t = 0;
+      std::fill(fixed.begin(), fixed.end(), 0);
+    } else {
+      ++t;
+    }
+    for (int r = 0; r < rows; ++r)
+      if (((mask >> (3 * r)) & 7u) && !fixed[(size_t)r]) {
+        base[(size_t)r] = Lv.patchRow[(size_t)(r * n + i)] - t;
+        fixed[(size_t)r] = 1;
+      }
+    Lv.patchPk[(size_t)i] = (int32_t)((g << kPatchBits) | t);
+  }
+  if (g >= 0) flush();
+  const int64_t G = g + 1;
+  if (G >= ((int64_t)1 << (31 - kPatchBits))) {  // too many groups to pack: no learned smoother here
+    Lv.patchOK = false;
+    std::vector<int32_t>().swap(Lv.patchRow);
+    std::vector<uint32_t>().swap(Lv.patchMask);
+    std::vector<int32_t>().swap(Lv.patchPk);
+    return CPM_OK;
+  }
+  Lv.patchGroups = G;
+  Lv.patchBase.assign((size_t)(rows * G), 0);
+  for (int64_t q = 0; q < G; ++q)
+    for (int r = 0; r < rows; ++r) Lv.patchBase[(size_t)(r * G + q)] = bases[(size_t)(q * rows + r)];
   return CPM_OK;
 }
 

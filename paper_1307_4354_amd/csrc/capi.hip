@@ -88,7 +88,7 @@ static void free_dev(cpm_band b) {
   for (auto& D : b->dev) {
     void* ps[] = {D.runE,  D.nbr,   D.fracE,  D.fracE32, D.runP,    D.fracP,  D.fracP32, D.runR,
                   D.fracR, D.fracR32, D.perm, D.packed, D.origin, D.fracK, D.fracK32, D.ilist, D.nbrI,
-                  D.patchRow, D.patchMask, D.packedB, D.packedL, D.blkE, D.gidx, D.blkG, D.lorg, D.originX,
+                  D.patchRow, D.patchPk, D.patchMask, D.packedB, D.packedL, D.blkE, D.gidx, D.blkG, D.lorg, D.originX,
                   D.qdiag, D.wd, D.acoef, D.vcD, D.runP3, D.fracP3, D.blkE2, D.gidx2, D.lorg2};
     for (void* p : ps)
       if (p) (void)hipFree(p);
@@ -961,9 +961,15 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     if (st == CPM_OK) st = upload_f32(&D.fracK32, H.fracK);
     if (st == CPM_OK) st = upload(&D.ilist, H.ilist);
     if (st == CPM_OK) st = upload(&D.nbrI, H.nbrI);
-    if (st == CPM_OK) st = upload(&D.patchRow, H.patchRow);
-    if (st == CPM_OK) st = upload(&D.patchMask, H.patchMask);
+    if (H.patchOK && !H.patchBase.empty()) {
+      if (st == CPM_OK) st = upload(&D.patchRow, H.patchBase);
+      if (st == CPM_OK) st = upload(&D.patchPk, H.patchPk);
+      if (st == CPM_OK) st = upload(&D.patchMask, H.patchMask);
+      D.patchGroups = H.patchGroups;
+    }
     std::vector<int32_t>().swap(H.patchRow);
+    std::vector<int32_t>().swap(H.patchBase);
+    std::vector<int32_t>().swap(H.patchPk);
     std::vector<uint32_t>().swap(H.patchMask);
     D.band_order = band_order;
     if (st == CPM_OK) st = upload(&D.qdiag, H.qdiag);

@@ -67,6 +67,12 @@ struct HostLevel {
   std::vector<int32_t> patchRow;  // 3^(dim-1) * n
   std::vector<uint32_t> patchMask;  // n
   bool patchOK = false;
+  // the same rows stored once per group of consecutive nodes whose present rows all shift by
+  // one band entry per node: patchBase[r * ngroups + g] + t is row r of the t-th node of
+  // group g (t < kPatchRun); patchPk[i] = (group << kPatchBits) | t
+  std::vector<int32_t> patchBase;
+  std::vector<int32_t> patchPk;
+  int64_t patchGroups = 0;
   std::vector<double> fracP;   // dim * n: frac(cp / (2h)) (prolongation from level+1)
   // cubic interpolation from level+1 at this level's closest points (4^(d-1) runs of 4, and
   // the fractions), the nested-iteration step of the full-multigrid start; empty when some
@@ -79,6 +85,8 @@ struct HostLevel {
 };
 
 constexpr int kXoffBits = 10;
+constexpr int kPatchBits = 8;  // node offset bits of a learned-smoother patch group
+constexpr int kPatchRun = 1 << kPatchBits;
 constexpr int kExtBlock = 256;      // workgroup size of the LDS-staged extension
 constexpr int kMaxStaged = 8192;    // staged values per workgroup above which a level keeps the gather path
 constexpr int kMaxGroups = 1 << (31 - kXoffBits);
@@ -139,7 +147,9 @@ struct DevLevel {
   double* wd = nullptr;     // omega / diag(A) of the standard relaxation (set per c, omega)
   bool fusedOK = false;
   bool fused = false;  // sweeps as one fused pass instead of neighbour sum + extension
-  int32_t* patchRow = nullptr;
+  int32_t* patchRow = nullptr;   // grouped rows (HostLevel::patchBase), rows x patchGroups
+  int32_t* patchPk = nullptr;    // per node (group << kPatchBits) | offset
+  int64_t patchGroups = 0;
   uint32_t* patchMask = nullptr;
 };
 

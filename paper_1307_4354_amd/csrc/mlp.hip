@@ -107,17 +107,22 @@ __device__ float mlp_wave(const uint16_t* X, int valid, const uint16_t* __restri
 // NOUT bf16 into xrow; returns s.
 template <int D, typename T, int NOUT = kIn>
 __device__ __forceinline__ float node_features(int64_t k, int64_t n, const T* __restrict__ r,
-                                               const int32_t* __restrict__ prow, const uint32_t* __restrict__ pmask,
+                                               const int32_t* __restrict__ prow, const int32_t* __restrict__ ppk,
+                                               int64_t groups, const uint32_t* __restrict__ pmask,
                                                const T* __restrict__ frac, uint16_t* xrow) {
   constexpr int R = D == 2 ? 3 : 9;
   constexpr int P = 3 * R;
   const uint32_t mask = pmask[k];
+  // the node's rows: its group's rows (one per group of consecutive nodes) plus its offset
+  const int32_t pk = ppk[k];
+  const int32_t* grow = prow + (pk >> kPatchBits);
+  const int32_t toff = pk & (kPatchRun - 1);
   // every load is issued unconditionally (the index clamped into the array, the value of an
   // absent node discarded below), so the 3^D loads are in flight together
   T patch[P];
 #pragma unroll
   for (int q = 0; q < R; ++q) {
-    const int32_t base = prow[q * n + k];
+    const int32_t base = grow[q * groups] + toff;
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
       int64_t a = (int64_t)base + dx;
@@ -151,12 +156,13 @@ __device__ __forceinline__ float node_features(int64_t k, int64_t n, const T* __
 // Features of every node of a level, in band order (patch tables and band-order fractions).
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_features(int64_t n, const T* __restrict__ r, const int32_t* __restrict__ prow,
+                                                  const int32_t* __restrict__ ppk, int64_t groups,
                                                   const uint32_t* __restrict__ pmask, const T* __restrict__ frac,
                                                   uint16_t* __restrict__ X, float* __restrict__ scale) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint16_t xr[kIn];
-  const float s = node_features<D, T>(i, n, r, prow, pmask, frac, xr);
+  const float s = node_features<D, T>(i, n, r, prow, ppk, groups, pmask, frac, xr);
   uint64_t* dst = (uint64_t*)(X + (int64_t)i * kIn);
 #pragma unroll
   for (int q = 0; q < kIn / 4; ++q)
@@ -179,6 +185,7 @@ __global__ __launch_bounds__(256) void k_features(int64_t n, const T* __restrict
 // columns of W1 (with b1) and w2 are staged once per workgroup in LDS.
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_learned(int64_t n, const T* __restrict__ r, const int32_t* __restrict__ prow,
+                                                 const int32_t* __restrict__ ppk, int64_t groups,
                                                  const uint32_t* __restrict__ pmask, const T* __restrict__ frac,
                                                  const uint16_t* __restrict__ W, T inv_delta, T* __restrict__ u) {
   constexpr int NF = (D == 2 ? 9 : 27) + 4 * D;  // features in use
@@ -204,7 +211,7 @@ __global__ __launch_bounds__(256) void k_learned(int64_t n, const T* __restrict_
   {
     uint16_t xs[8 * KS];
     if (k < n) {
-      s = node_features<D, T, 8 * KS>(k, n, r, prow, pmask, frac, xs);
+      s = node_features<D, T, 8 * KS>(k, n, r, prow, ppk, groups, pmask, frac, xs);
     } else {
 #pragma unroll
       for (int q = 0; q < 8 * KS; ++q) xs[q] = 0;
@@ -393,9 +400,11 @@ void launch_learned(const cpm_band b, int l, const T* r, T* u, double c, hipStre
   const double delta = level_delta(b, l, c);
   const unsigned gr = (unsigned)((D.n + 255) / 256);  // 64 nodes per wavefront, 4 per block
   if (b->dim == 2)
-    k_learned<2, T><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchMask, frac_b<T>(D), b->mlpW, (T)(1.0 / delta), u);
+    k_learned<2, T><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchPk, D.patchGroups, D.patchMask, frac_b<T>(D),
+                                       b->mlpW, (T)(1.0 / delta), u);
   else
-    k_learned<3, T><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchMask, frac_b<T>(D), b->mlpW, (T)(1.0 / delta), u);
+    k_learned<3, T><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchPk, D.patchGroups, D.patchMask, frac_b<T>(D),
+                                       b->mlpW, (T)(1.0 / delta), u);
 }
 
 // r = b + E g - delta u into B.r, then the fused network update of u.
@@ -503,9 +512,11 @@ cpm_status cpm_smoother_features(cpm_band band, int level, double c, const doubl
                              const_cast<double*>(u), r, level_delta(band, level, c), 0.0, nullptr, lc, s);
   const unsigned gr = (unsigned)((D.n + 255) / 256);
   if (band->dim == 2)
-    k_features<2, double><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchMask, D.fracE, X, scale);
+    k_features<2, double><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchPk, D.patchGroups, D.patchMask, D.fracE, X,
+                                             scale);
   else
-    k_features<3, double><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchMask, D.fracE, X, scale);
+    k_features<3, double><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchPk, D.patchGroups, D.patchMask, D.fracE, X,
+                                             scale);
   if ((st = check_launch("cpm_smoother_features")) != CPM_OK) return st;
   return leave(band, stream);
 }

@@ -1,7 +1,7 @@
 // Host-side check of the LDS staging tables the band builder makes for the extension and the
 // fused sweep: for every workgroup, every LDS address that the kernels form for a node lies
 // inside the workgroup's staged range and holds the band index that the gather form of the
-// same pass reads.  Prints one line per level and "ALL OK" or "FAIL"; exit status 1 on a
+// same pass reads.  Also checks the grouped patch rows of the learned smoother.  Prints one line per level and "ALL OK" or "FAIL"; exit status 1 on a
 // mismatch.
 #include <cstdio>
 #include <string>
@@ -49,6 +49,26 @@ static long check_level(const HostLevel& H, int dim) {
   return bad;
 }
 
+// Learned-smoother patch rows in grouped form: for every node and every row with a present
+// node, the group's row plus the node's offset is the node's own row.
+static long check_patches(const HostLevel& H, int dim) {
+  if (!H.patchOK) return 0;
+  const int rows = dim == 2 ? 3 : 9;
+  const int64_t n = H.n, G = H.patchGroups;
+  long bad = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t g = H.patchPk[i] >> kPatchBits;
+    const int32_t t = H.patchPk[i] & (kPatchRun - 1);
+    if (g < 0 || g >= G) {
+      ++bad;
+      continue;
+    }
+    for (int r = 0; r < rows; ++r)
+      if ((H.patchMask[i] >> (3 * r)) & 7u) bad += H.patchBase[(size_t)(r * G + g)] + t != H.patchRow[(size_t)(r * n + i)];
+  }
+  return bad;
+}
+
 int main() {
   struct Case {
     cpm_surface s;
@@ -73,9 +93,10 @@ int main() {
       return 1;
     }
     for (size_t l = 0; l < lv.size(); ++l) {
-      const long bad = check_level(lv[l], c.dim);
-      std::printf("kind %d h = 1/%g level %zu: n = %ld, sweep tables %s, mismatches %ld\n", c.s.kind, 1.0 / c.h, l,
-                  (long)lv[l].n, lv[l].blkE2.empty() ? "absent" : "present", bad);
+      const long bad = check_level(lv[l], c.dim) + check_patches(lv[l], c.dim);
+      std::printf("kind %d h = 1/%g level %zu: n = %ld, sweep tables %s, patch groups %ld, mismatches %ld\n",
+                  c.s.kind, 1.0 / c.h, l, (long)lv[l].n, lv[l].blkE2.empty() ? "absent" : "present",
+                  (long)lv[l].patchGroups, bad);
       fails += bad;
     }
   }

@@ -2,7 +2,8 @@
 builder with g++ and runs it.  For circles, spheres (centred and off-centre), a torus and
 Dziuk's surface it checks, on every level and for every node, that each LDS address the
 LDS-staged extension and fused sweep form lies in its workgroup's staged range and holds the
-band index the gather form of the same pass reads (so the two forms read the same values)."""
+band index the gather form of the same pass reads (so the two forms read the same values), and
+that the learned smoother's grouped patch rows give back every node's own rows."""
 import os
 import subprocess
 
@@ -24,3 +25,4 @@ def test_lds_staging_tables(tmp_path):
     assert out.returncode == 0 and "ALL OK" in out.stdout, out.stdout[-3000:]
     # the fused sweep's tables exist on the levels that have its addressing
     assert "sweep tables present" in out.stdout
+    assert "patch groups 0," not in out.stdout.split("level 0:")[1].split("\n")[0]
