@@ -359,6 +359,7 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
   auto t_start = std::chrono::steady_clock::now();
   const cpm_params P = *params;
   cpm_band b0 = bands[0];
+  StreamScope stream_scope(b0);
   cpm_status st = enter(b0, stream);
   if (st != CPM_OK) return st;
   hipStream_t s = b0->stream;

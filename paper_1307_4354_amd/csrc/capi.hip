@@ -1195,6 +1195,7 @@ cpm_status cpm_apply(cpm_band band, int level, double c, const double* u, double
     return CPM_E_INVALID;
   }
   const DevLevel& D = band->dev[(size_t)level];
+  StreamScope stream_scope(band);
   cpm_status st = enter(band, stream);
   if (st != CPM_OK) return st;
   const LaunchCfg lc = level_cfg(D);
@@ -1211,6 +1212,7 @@ cpm_status cpm_extend(cpm_band band, int level, const double* g, double* out, vo
     return CPM_E_INVALID;
   }
   const DevLevel& D = band->dev[(size_t)level];
+  StreamScope stream_scope(band);
   cpm_status st = enter(band, stream);
   if (st != CPM_OK) return st;
   launch_ext<double, double>(band->dim, EXT_PLAIN, D.n, g, ext_addr(D), fracK_of<double>(D), nullptr, nullptr, out, 0.0, 0.0,
@@ -1276,6 +1278,7 @@ cpm_status cpm_vcycle(cpm_band band, const cpm_params* params, const double* f, 
     set_error("workspace too small");
     return CPM_E_WORKSPACE;
   }
+  StreamScope stream_scope(band);
   if ((st = enter(band, stream)) != CPM_OK) return st;
   if ((st = ensure_coarse(band, params->c)) != CPM_OK) return st;
   if (params->smoother == CPM_SMOOTH_STANDARD && (st = ensure_std(band, params->c, params->omega)) != CPM_OK)
@@ -1309,6 +1312,7 @@ cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, d
   std::memset(S, 0, sizeof(cpm_stats));
   S->fallback_cycle = -1;
   auto t0 = std::chrono::steady_clock::now();
+  StreamScope stream_scope(band);
   if ((st = enter(band, stream)) != CPM_OK) return st;
   if ((st = ensure_coarse(band, params->c)) != CPM_OK) return st;
   if (params->smoother == CPM_SMOOTH_STANDARD && (st = ensure_std(band, params->c, params->omega)) != CPM_OK)
@@ -1385,6 +1389,7 @@ cpm_status cpm_run_cycles(cpm_band band, const cpm_params* params, const double*
     set_error("workspace too small");
     return CPM_E_WORKSPACE;
   }
+  StreamScope stream_scope(band);
   if ((st = enter(band, stream)) != CPM_OK) return st;
   if ((st = ensure_coarse(band, params->c)) != CPM_OK) return st;
   if (params->smoother == CPM_SMOOTH_STANDARD && (st = ensure_std(band, params->c, params->omega)) != CPM_OK)
@@ -1440,6 +1445,7 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
     set_error("cpm_time_kernel: no fused-sweep addressing on this level");
     return CPM_E_INVALID;
   }
+  StreamScope stream_scope(band);
   if ((st = enter(band, stream)) != CPM_OK) return st;
   hipStream_t s = band->stream;
   const DevLevel& D = band->dev[(size_t)level];

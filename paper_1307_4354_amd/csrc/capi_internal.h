@@ -70,6 +70,20 @@ struct cpm_band_s {
 };
 
 namespace cpm {
+// Restores a band's private stream when an entry point returns, on every path (enter() makes
+// the caller's stream current; a later call that takes no stream must not find it there).
+struct StreamScope {
+  cpm_band b;
+  explicit StreamScope(cpm_band band) : b(band) {}
+  ~StreamScope() {
+    if (b) b->stream = b->own;
+  }
+  StreamScope(const StreamScope&) = delete;
+  StreamScope& operator=(const StreamScope&) = delete;
+};
+}  // namespace cpm
+
+namespace cpm {
 
 LaunchCfg band_cfg(const cpm_band b, int64_t n);
 LaunchCfg level_cfg(const DevLevel& D);

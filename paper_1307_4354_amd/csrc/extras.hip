@@ -45,6 +45,7 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
     set_error("cpm_autotune: null band");
     return CPM_E_INVALID;
   }
+  StreamScope stream_scope(band);
   cpm_status st = enter(band, stream);
   if (st != CPM_OK) return st;
   hipStream_t s = band->stream;

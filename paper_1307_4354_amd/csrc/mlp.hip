@@ -501,6 +501,7 @@ cpm_status cpm_smoother_features(cpm_band band, int level, double c, const doubl
     set_error("cpm_smoother_features: no patch addressing on this level");
     return CPM_E_INVALID;
   }
+  StreamScope stream_scope(band);
   cpm_status st = enter(band, stream);
   if (st != CPM_OK) return st;
   hipStream_t s = band->stream;
