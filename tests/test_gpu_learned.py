@@ -119,6 +119,30 @@ def test_learned_vcycle_matches_oracle():
     assert err < 1e-4, err
 
 
+def test_learned_cycles_from_the_stopping_residual():
+    """Cycles after the first take the learned update of their first sweep from the residual
+    the previous cycle's stopping test computed: five graph-replayed cycles give the iterate of
+    five separate one-cycle runs (where no residual is carried over) bit for bit."""
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    cfg = _learned_case()
+    band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+    cpm.cpm_set_smoother_weights(band, _rand_weights(9, scale=0.05), 10.0)
+    fd = dev(cfg.problem.f(band.export(0)[1]))
+    p = cpm.make_params(smoother=cpm.CPM_SMOOTH_LEARNED)
+    work, nbytes = workspace(band, p)
+    hist = torch.zeros(8, dtype=torch.float64, device="cuda")
+    ua = torch.zeros_like(fd)
+    for _ in range(5):
+        cpm.cpm_run_cycles(band, p, fd, ua, work, nbytes, 1, 1, hist)
+    ub = torch.zeros_like(fd)
+    cpm.cpm_run_cycles(band, p, fd, ub, work, nbytes, 5, 5, hist)
+    a, b = host(ua), host(ub)
+    assert np.all(np.isfinite(a)) and np.max(np.abs(a)) > 0
+    assert np.array_equal(a, b)
+
+
 def test_jacobi_network_reproduces_plain_solve():
     """With the weights of the damped Jacobi network the learned solve matches the plain one."""
     import paper_1307_4354_amd as cpm
