@@ -94,13 +94,15 @@ def features(lev: Level, r: np.ndarray):
         ok = j >= 0
         P[ok, q] = r[j[ok]]
     s = np.max(np.abs(P), axis=1)
-    safe = np.where(s > 0, s, 1.0)
-    X = np.zeros((n, N_IN))
-    X[:, :off.shape[0]] = np.where(s[:, None] > 0, P / safe[:, None], 0.0)
+    X = np.zeros((n, N_IN), dtype=np.float32)
+    # the normalised patch is a quantised input (bfloat16): its rounding is decided in the
+    # precision the kernels take it in, float32(r) * (1 / float32(s)) in float32
+    s32 = s.astype(np.float32)
+    inv = np.where(s32 > 0, np.float32(1.0) / np.where(s32 > 0, s32, np.float32(1.0)), np.float32(0.0))
+    X[:, :off.shape[0]] = P.astype(np.float32) * inv[:, None]
     _, W1d, _ = stencil(lev.cp, lev.h, 3)  # (n, d, 4)
-    X[:, off.shape[0]:off.shape[0] + 4 * d] = W1d.reshape(n, 4 * d)
-    # the kernels form patch / s in float32 before rounding to bfloat16
-    return bf16_round(X.astype(np.float32)), s
+    X[:, off.shape[0]:off.shape[0] + 4 * d] = W1d.reshape(n, 4 * d).astype(np.float32)
+    return bf16_round(X), s
 
 
 def forward_params(X: np.ndarray, W1, b1, w2, b2):
@@ -135,23 +137,29 @@ def loss_and_grad(X: np.ndarray, T: np.ndarray, w_bits: np.ndarray):
     return loss_and_grad_params(X, T, *unpack(w_bits))
 
 
-def patch_has_gap(lev: Level) -> bool:
-    """True if some row of a node's 3^d patch has its two outer nodes in the band but not the
-    middle one.  Such a level keeps the Jacobi smoother (its patches cannot be addressed by
-    one reference index per row in the GPU layout)."""
-    cached = getattr(lev, "_patch_gap", None)
-    if cached is not None:
-        return cached
-    off = patch_offsets(lev.dim)
-    pres = np.stack([lev.lookup(lev.idx + o) >= 0 for o in off], axis=1)
-    rows = pres.reshape(lev.n, -1, 3)
-    gap = bool(np.any(rows[:, :, 0] & ~rows[:, :, 1] & rows[:, :, 2]))
-    lev._patch_gap = gap
-    return gap
-
-
 def learned_update(lev: Level, r: np.ndarray, delta: float, w_bits: np.ndarray) -> np.ndarray:
     """Correction (s/delta) y of one learned smoothing step."""
     X, s = features(lev, r)
     y, _ = forward(X, w_bits)
     return s / delta * y
+
+
+def backward_bf16(X: np.ndarray, w_bits: np.ndarray, H: np.ndarray, Y: np.ndarray, T: np.ndarray):
+    """Gradient of (1/m) sum (y - t)^2 given the forward pass's hidden activations H and
+    outputs Y (float32), with the layer-1 weight gradient taken from bfloat16 inputs: the
+    per-node output error dy = (2/m)(y - t) and the hidden error dh = dy w2 [h > 0] are formed
+    in float32, dh is rounded to bfloat16 (the matrix cores' input type), and
+    dW1 = sum_i dh_i x_i^T is summed exactly (float64).  b1, w2, b2 take the unrounded float32
+    dh, dy.  Returns the gradient in packing order (float64)."""
+    _, _, w2, _ = unpack(w_bits)
+    m = X.shape[0]
+    f32 = np.float32
+    H32 = np.asarray(H, dtype=f32)
+    dy = (f32(2.0) / f32(m)) * (np.asarray(Y, dtype=f32) - np.asarray(T, dtype=f32))
+    dh = np.where(H32 > 0, dy[:, None] * w2.astype(f32)[None, :], f32(0.0)).astype(f32)
+    dh_bf = bf16_round(dh).astype(np.float64)
+    gW1 = dh_bf.T @ np.asarray(X, dtype=np.float64)
+    gb1 = dh.astype(np.float64).sum(axis=0)
+    gw2 = H32.astype(np.float64).T @ dy.astype(np.float64)
+    gb2 = float(dy.astype(np.float64).sum())
+    return np.concatenate([gW1.ravel(), gb1, gw2, [gb2]])

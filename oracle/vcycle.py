@@ -51,10 +51,9 @@ def smooth(H: Hierarchy, l: int, u: np.ndarray, f: np.ndarray, p: Params) -> np.
     finest levels the learned local step replaces it when weights are given."""
     dl = delta(H, l, p.c)
     if p.learned is not None and l < 2:
-        from .mlp import learned_update, patch_has_gap
+        from .mlp import learned_update
 
-        if not patch_has_gap(H.levels[l]):
-            return u + learned_update(H.levels[l], residual(H, l, u, f, p), dl, p.learned)
+        return u + learned_update(H.levels[l], residual(H, l, u, f, p), dl, p.learned)
     g = f + H.N[l] @ u
     return (1.0 - p.omega) * u + p.omega * (H.E[l] @ g) / dl
 
@@ -96,10 +95,7 @@ def vcycle(H: Hierarchy, l: int, u: np.ndarray, f: np.ndarray, p: Params,
         return coarse(f)
     nu1, nu2 = p.nu1, p.nu2
     if p.learned is not None and l < 2 and p.learned_sweeps > 0:
-        from .mlp import patch_has_gap
-
-        if not patch_has_gap(H.levels[l]):
-            nu1 = nu2 = p.learned_sweeps
+        nu1 = nu2 = p.learned_sweeps
     for _ in range(nu1):  # step 1: pre-smoothing
         u = smooth(H, l, u, f, p)
     r = residual(H, l, u, f, p)  # step 2: residual, restriction, coarse solve

@@ -94,3 +94,35 @@ def test_learned_update_with_jacobi_weights_is_jacobi_step():
     du = om.learned_update(H.levels[0], r, d0, om.jacobi_weights(2.0 / 3.0, 3))
     ref = (2.0 / 3.0) / d0 * r
     assert np.max(np.abs(du - ref)) <= 2 ** -7 * np.max(np.abs(ref))
+
+
+def test_backward_bf16_is_the_gradient_within_bf16_rounding():
+    """The gradient with the hidden error rounded to bfloat16 differs from the exact gradient
+    (itself pinned by finite differences) by at most the rounding of each term, 2^-8 of the
+    sum of the terms' magnitudes; the other parameters' gradients equal it to float32 rounding."""
+    rng = np.random.default_rng(4)
+    m = 300
+    X = om.bf16_round(rng.uniform(-1, 1, (m, om.N_IN)).astype(np.float32))
+    T = rng.standard_normal(m).astype(np.float32)
+    w = om.pack(rng.standard_normal((64, 64)) * 0.3, rng.standard_normal(64) * 0.1,
+                rng.standard_normal(64) * 0.3, 0.25)
+    y, Hh = om.forward(X, w)
+    H32, Y32 = Hh.astype(np.float32), y.astype(np.float32)
+    g = om.backward_bf16(X, w, H32, Y32, T)
+    # exact gradient at the same (float32-rounded) forward values
+    W1, b1, w2, b2 = om.unpack(w)
+    dy = 2.0 * (Y32.astype(np.float64) - T.astype(np.float64)) / m
+    dH = np.outer(dy, w2) * (H32 > 0)
+    gW1 = dH.T @ X.astype(np.float64)
+    bound = np.abs(dH).T @ np.abs(X.astype(np.float64))
+    o = 64 * 64
+    assert np.all(np.abs(g[:o] - gW1.ravel()) <= 2 ** -8 * bound.ravel() * (1 + 1e-6) + 1e-12)
+    assert np.max(np.abs(g[o:o + 64] - dH.sum(axis=0))) <= 1e-5 * np.max(np.abs(dH.sum(axis=0)))
+    # exactly representable hidden errors are not rounded: then dW1 is exact
+    w2x = np.zeros(64)
+    w2x[:8] = 0.5
+    wx = om.pack(W1, b1, w2x, b2)
+    Tx = (Y32 - np.float32(m) / np.float32(2.0) * np.float32(0.25)).astype(np.float32)  # dy = 0.25 exactly
+    gx = om.backward_bf16(X, wx, H32, Y32, Tx)
+    dHx = np.outer(np.full(m, 0.25), om.unpack(wx)[2]) * (H32 > 0)
+    assert np.allclose(gx[:o], (dHx.T @ X.astype(np.float64)).ravel(), rtol=1e-12, atol=1e-12)
