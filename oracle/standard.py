@@ -39,6 +39,7 @@ class StdParams:
     omega: float = 2.0 / 3.0
     residual: str = "extended"  # r = f - A (E u); "plain": r = f - A u
     gamma: int = 1  # cycle index (1: V-cycle, 2: W-cycle)
+    smoother: str = "jacobi"  # or "redblack": two-colour Gauss-Seidel ordering of the same step
 
 
 def matrix_A(H: Hierarchy, l: int, c: float) -> sp.csr_matrix:
@@ -47,19 +48,42 @@ def matrix_A(H: Hierarchy, l: int, c: float) -> sp.csr_matrix:
     return (delta(H, l, c) * sp.identity(n, format="csr") - H.E[l] @ H.N[l]).tocsr()
 
 
+def red_nodes(lev) -> np.ndarray:
+    """Colour of the two-colour ordering: nodes whose grid indices sum to an even number."""
+    return (np.sum(lev.idx, axis=1) % 2) == 0
+
+
 class StdHierarchy:
-    """The assembled A_l, their diagonals and the LU factors of the coarsest A_c."""
+    """The assembled A_l, their diagonals, node colours and the LU factors of the coarsest A_c."""
 
     def __init__(self, H: Hierarchy, p: StdParams):
         self.H = H
         self.p = p
         self.A = [matrix_A(H, l, p.c) for l in range(len(H.levels))]
         self.diag = [A.diagonal() for A in self.A]
+        self.red = [red_nodes(lev) for lev in H.levels]
         self.lu = sla.lu_factor(self.A[-1].toarray())
 
 
+def two_colour_sweep(A, diag: np.ndarray, red: np.ndarray, u: np.ndarray, f: np.ndarray,
+                     omega: float) -> np.ndarray:
+    """Gauss-Seidel in two-colour (red-black) order: the damped Jacobi correction
+    omega (f - A u) / diag(A) applied to the red rows from the current iterate, then to the
+    black rows from the iterate the red half-sweep left (Sec. 4.5 names Gauss-Seidel as an
+    alternative to Jacobi).  Rows of one colour that couple to each other (A = delta I - E N
+    couples a node to the nodes of its stencil) are updated together, as Jacobi does."""
+    u = u.copy()
+    for colour in (red, ~red):
+        r = f - A @ u
+        u[colour] += omega * r[colour] / diag[colour]
+    return u
+
+
 def smooth(S: StdHierarchy, l: int, u: np.ndarray, f: np.ndarray) -> np.ndarray:
-    """One damped Jacobi step on A_l u = f (Sec. 4.1, the iteration of Sec. 4.5)."""
+    """One damped Jacobi step on A_l u = f (Sec. 4.1, the iteration of Sec. 4.5), or one
+    red-black Gauss-Seidel sweep of it."""
+    if S.p.smoother == "redblack":
+        return two_colour_sweep(S.A[l], S.diag[l], S.red[l], u, f, S.p.omega)
     return u + S.p.omega * (f - S.A[l] @ u) / S.diag[l]
 
 

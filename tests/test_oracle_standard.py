@@ -88,3 +88,36 @@ def test_extended_residual_sphere():
     err_rm = np.max(np.abs(ref.u - cfg.problem.u_exact(cp)))
     # same discretization accuracy as the Ruuth-Merriman solver's limit
     assert err < 2.0 * err_rm and err_rm < 2.0 * err, (err, err_rm)
+
+
+def test_two_colour_sweep_on_a_red_black_coupled_matrix():
+    """On the 1-D Laplacian (red rows couple only to black ones) the red half-sweep with
+    omega = 1 zeroes the red rows of the residual exactly, and the black half-sweep then the
+    black rows: the textbook red-black Gauss-Seidel step."""
+    import scipy.sparse as sp
+
+    n = 41
+    A = sp.diags([-np.ones(n - 1), 2.0 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1], format="csr")
+    red = (np.arange(n) % 2) == 0
+    f = np.random.default_rng(0).standard_normal(n)
+    u0 = np.random.default_rng(1).standard_normal(n)
+    diag = A.diagonal()
+    u_red = u0.copy()
+    u_red[red] += (f - A @ u0)[red] / diag[red]
+    assert np.max(np.abs((f - A @ u_red)[red])) < 1e-13
+    u1 = os_.two_colour_sweep(A, diag, red, u0, f, 1.0)
+    assert np.array_equal(u1[red], u_red[red])
+    assert np.max(np.abs((f - A @ u1)[~red])) < 1e-13
+    # the black half-sweep used the updated red values (Jacobi from u0 would not zero them)
+    u_jac = u0 + (f - A @ u0) / diag
+    assert np.max(np.abs((f - A @ u_jac)[~red])) > 1e-3
+
+
+@pytest.mark.parametrize("cfg", [W.config_circle(32, 3), W.config_sphere(12, 2)], ids=["circle32", "sphere12"])
+def test_redblack_plain_residual_fixed_point_is_sparse_solve(cfg):
+    H = _hier(cfg)
+    f = cfg.problem.f(H.levels[0].cp)
+    res = os_.solve(H, f, os_.StdParams(residual="plain", smoother="redblack"), rtol=1e-14, max_cycles=120)
+    A = os_.matrix_A(H, 0, 1.0)
+    u_star = spla.spsolve(A.tocsc(), f)
+    assert np.max(np.abs(res.u - u_star)) <= 1e-10 * np.max(np.abs(u_star))
