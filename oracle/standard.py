@@ -13,6 +13,10 @@ residual r = f - A u is kept as ``residual="plain"``.  Every level solves for a 
 of its own system A_l e = f_l (f-space right-hand sides, no extension in front of them),
 and the coarsest level is solved exactly, e = A_c^{-1} f_c.
 
+The operator may also be the sparser one of Remark 3.2, A = c I - (E_1 L - gamma (I - E_3))
+with linear interpolation in front of the Laplacian (``el_degree=1``), which the paper uses
+for its direct solves (Table 3.1); the extended residual keeps the cubic E.
+
 The stopping test is the paper's (Sec. 4.6): the relative increment
 ||u_{k+1} - u_k||_inf / ||u_{k+1}||_inf.  With the extended residual the cycle's fixed point
 is not the solution of A u = f (the residual f - A u stalls at the size of the
@@ -28,6 +32,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 from .band import Hierarchy
+from .direct import assemble_A
 from .vcycle import delta
 
 
@@ -40,10 +45,15 @@ class StdParams:
     residual: str = "extended"  # r = f - A (E u); "plain": r = f - A u
     gamma: int = 1  # cycle index (1: V-cycle, 2: W-cycle)
     smoother: str = "jacobi"  # or "redblack": two-colour Gauss-Seidel ordering of the same step
+    el_degree: int = 3  # degree p of the interpolation in front of L (1: Remark 3.2's sparser M)
 
 
-def matrix_A(H: Hierarchy, l: int, c: float) -> sp.csr_matrix:
-    """A = delta I - E N on level l (eq. (3.3) with p = q = 3)."""
+def matrix_A(H: Hierarchy, l: int, c: float, el_degree: int = 3) -> sp.csr_matrix:
+    """A = c I - M on level l, M = E_p L - gamma (I - E_3) (eq. (3.3)); with p = 3 this is
+    delta I - E N.  p = 1 is the sparser operator of Remark 3.2 (linear interpolation in front
+    of the Laplacian, the one of Table 3.1), assembled by the direct-solve module."""
+    if el_degree == 1:
+        return assemble_A(H.levels[l], c, p=1, q=3)
     n = H.levels[l].n
     return (delta(H, l, c) * sp.identity(n, format="csr") - H.E[l] @ H.N[l]).tocsr()
 
@@ -59,7 +69,7 @@ class StdHierarchy:
     def __init__(self, H: Hierarchy, p: StdParams):
         self.H = H
         self.p = p
-        self.A = [matrix_A(H, l, p.c) for l in range(len(H.levels))]
+        self.A = [matrix_A(H, l, p.c, p.el_degree) for l in range(len(H.levels))]
         self.diag = [A.diagonal() for A in self.A]
         self.red = [red_nodes(lev) for lev in H.levels]
         self.lu = sla.lu_factor(self.A[-1].toarray())

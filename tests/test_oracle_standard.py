@@ -121,3 +121,23 @@ def test_redblack_plain_residual_fixed_point_is_sparse_solve(cfg):
     A = os_.matrix_A(H, 0, 1.0)
     u_star = spla.spsolve(A.tocsc(), f)
     assert np.max(np.abs(res.u - u_star)) <= 1e-10 * np.max(np.abs(u_star))
+
+
+def test_linear_el_operator_vcycle_reaches_table_3_1():
+    """Remark 3.2's operator (p = 1 in front of L, q = 3) under the standard-relaxation V-cycle
+    with the plain residual: the fixed point is the sparse direct solve of A u = f, and its
+    error on the circle reproduces Table 3.1 (dx = 0.025, 0.0125) within 1 %."""
+    from oracle import direct as od
+    from oracle import errors as oe
+
+    prob = W.circle_sin12()
+    table = dict((round(1 / dx), e) for dx, e in [(0.025, 4.76e-3), (0.0125, 1.19e-3)])
+    for h_inv, ref in table.items():
+        H = ob.build_hierarchy(prob.surface, 1.0 / h_inv, 3, W.LAM2_2D)
+        f = prob.f(H.levels[0].cp)
+        res = os_.solve(H, f, os_.StdParams(residual="plain", el_degree=1), rtol=1e-13, max_cycles=120)
+        A = od.assemble_A(H.levels[0], 1.0, p=1, q=3)
+        u_star = spla.spsolve(A.tocsc(), f)
+        assert np.max(np.abs(res.u - u_star)) <= 1e-10 * np.max(np.abs(u_star))
+        e = oe.surface_error(H.levels[0], res.u, prob.u_exact, 20000)
+        assert abs(e - ref) / ref < 0.01, (h_inv, e, ref)
