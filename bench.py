@@ -1,19 +1,24 @@
 """Throughput of the CPM multigrid V-cycle on one MI355X.
 
 One step = one V(3,3) cycle of the whole hot path (smoothing, residual, restriction,
-coarsest solve, prolongation on every level, plus the stopping residual) on the unit
-sphere, h = 1/64, 5 levels (424,510 finest band nodes), FP64, with all inputs resident in
-HBM.  value = finest-level band DOFs x cycles / second.  Also reported: time to a 1e-10
-relative residual from u = 0 in FP64 and mixed precision, the roofline of the dominant
-kernel (extension + smoothing pass on the finest level) and the CPU oracle's rate.
+coarsest solve, prolongation on every level, plus the stopping residual) on the torus
+R = 1, r = 0.4 at h = 1/256 (6 levels down to h = 1/8, 8,531,440 finest band nodes, a
+seeded 16-mode right-hand side), FP64, with all inputs resident in HBM.
+value = finest-level band DOFs x cycles / second.  Also reported: the same cycles in mixed
+precision (float32 inner cycles, float64 outer refinement), time to a 1e-10 relative
+residual from u = 0 (FP64, mixed, FP64 with the full-multigrid start, W-cycles), the
+mixed solution's error against the float64 oracle at h = 1/64, the roofline of the
+dominant kernel (the finest level's smoothing pass) and the CPU oracle's rate.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload torus256|sphere64|...]
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -22,22 +27,25 @@ if REPO not in sys.path:
     sys.path.insert(0, REPO)
 
 HBM_PEAK_GBS = 8000.0
+PER_LAUNCH = 10  # cycles per captured graph launch in the throughput runs
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=100)
-    ap.add_argument("--kernel-reps", type=int, default=200)
+    ap.add_argument("--cpu-cycles", type=int, default=20)
+    ap.add_argument("--kernel-reps", type=int, default=100)
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-tolerance solves")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the oracle comparison at h = 1/64 and the secondary surfaces")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
-    ap.add_argument("--workload", default="sphere64",
-                    choices=["sphere64", "torus256", "batched256", "learned"],
-                    help="sphere64 (default, the headline line); the others are secondary measurements")
+    ap.add_argument("--workload", default="torus256",
+                    choices=["torus256", "sphere64", "batched256", "learned"],
+                    help="torus256 (default, the headline line); the others are secondary measurements")
     ap.add_argument("--nprob", type=int, default=256, help="batched256: number of problems")
     ap.add_argument("--train-steps", type=int, default=3000, help="learned: Adam steps")
     return ap.parse_args()
@@ -68,46 +76,241 @@ def _solve(cpm, torch, band, p, fd, rtol=1e-10, max_cycles=120, repeat=True):
                 "worst_cycle_contraction": worst, "fallback_cycle": st.fallback_cycle, "status": st.status}
 
 
-def run_torus256(args):
-    """Mixed precision (float32 inner, float64 outer) vs FP64 on the torus R = 1, r = 0.4 at
-    h = 1/256 (6 levels), and the error of the mixed solution against the FP64 oracle at 1/64."""
+def _host_info():
+    """Cores, CPU model and thread environment of the host that runs the CPU baseline."""
+    model = platform.processor() or ""
+    try:
+        out = subprocess.run(["lscpu"], stdout=subprocess.PIPE, stderr=subprocess.DEVNULL, text=True,
+                             timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    env = {k: os.environ.get(k) for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")}
+    return {"nproc": os.cpu_count(), "cpu_model": model, "thread_env": env}
+
+
+# Dominant kernel of a level's smoothing pass for a tuning (cpm_band_tuning's fields): (kernel
+# name as the profiler prints it, launch grid in work-items, algorithmic bytes per node,
+# cpm_time_kernel selector, description).  The extension pass moves 3 closest-point fractions
+# (24 B), one read of g (8), u read and write (16): 48 B per node in FP64; the fused one-pass
+# sweep moves the fractions, u and E f read, u' written: 56 B; the tiled pass the fractions,
+# u and f read, u' written: 48 B.
+def _dominant_kernel(tuning, n0, ntiles=0):
+    use_lds, ext_block, _, fused, sweep_block, sweep_lds, tiled, prefetch = tuning
+    if tiled:
+        return ("k_tile<double, double, 0>", ntiles * 256, 48.0, 6,
+                "tiled Ruuth-Merriman sweep (f + N u in LDS, extension, Jacobi step), level 0")
+    if fused:
+        name = ("k_sweep_lds" if sweep_lds else "k_sweep") + "<3, double, 0>"
+        blk = 256 if sweep_lds else sweep_block
+        return name, -(-n0 // blk) * blk, 56.0, 5, "fused one-pass sweep E f + (E N) u (Jacobi step), level 0"
+    name = ("k_ext_ldsp" if prefetch else ("k_ext_lds" if use_lds else "k_ext")) + "<3, double, double, 0>"
+    blk = 256 if use_lds else ext_block
+    return name, -(-n0 // blk) * blk, 48.0, 0, "extension + Jacobi smoothing pass, level 0"
+
+
+def _traffic_file(workload):
+    return os.path.join(REPO, "profiles", "traffic_level0_sweep_%s.json" % workload)
+
+
+def headline_torus256(args):
+    """The headline line: FP64 V(3,3) cycles on the torus at h = 1/256, mixed beside it."""
     import numpy as np
     import torch
 
     import paper_1307_4354_amd as cpm
     import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    cfg = W.config_torus_mixed(256)
+    s = cfg.problem.surface
+    t0 = time.perf_counter()
+    band = cpm.cpm_build_band(cpm.make_surface(s.kind, s.R, s.r, s.center), cfg.h0, cfg.levels, cfg.lam2)
+    t_build = time.perf_counter() - t0
+    sizes = band.sizes()
+    n0 = sizes[0]
+    print("band built: %s in %.1f s" % (sizes, t_build), file=sys.stderr, flush=True)
+    _, cp = band.export(0)
+    fd = torch.as_tensor(cfg.problem.f(cp)).to("cuda")
+    p64 = cpm.make_params(c=cfg.problem.c, nu1=cfg.nu1, nu2=cfg.nu2, omega=cfg.omega)
+    pmx = cpm.make_params(c=cfg.problem.c, nu1=cfg.nu1, nu2=cfg.nu2, omega=cfg.omega, precision=cpm.CPM_MIXED)
+    nb64 = cpm.cpm_workspace_size(band, p64)
+    nbmx = cpm.cpm_workspace_size(band, pmx)
+    work = torch.empty(max(nb64, nbmx), dtype=torch.uint8, device="cuda")
+    t0 = time.perf_counter()
+    cpm.cpm_autotune(band)  # per-level launch configurations (setup, like the band build)
+    t_tune = time.perf_counter() - t0
+    tuning = [cpm.cpm_band_tuning(band, l) for l in range(band.levels)]
+    ud = torch.zeros_like(fd)
+    K, Wm = args.steps, max(args.warmup, 1)
+    hist = torch.zeros(max(K, Wm) + 8, dtype=torch.float64, device="cuda")
+
+    def run(p, nb, k):
+        cpm.cpm_run_cycles(band, p, fd, ud, work, nb, k, PER_LAUNCH, hist)
+
+    def timed(p, nb):
+        # warm-up: W cycles, then the timed run's exact launch pattern once, so that every
+        # graph it launches (first launch, full launches, remainder) is captured beforehand
+        ud.zero_()
+        run(p, nb, Wm)
+        run(p, nb, K)
+        ud.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(p, nb, K)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    dt = timed(p64, nb64)
+    dt_mx = timed(pmx, nbmx)
+    print("cycles: f64 %.3f ms, mixed %.3f ms" % (1e3 * dt / K, 1e3 * dt_mx / K), file=sys.stderr, flush=True)
+
+    # time to 1e-10 from u = 0 (one graph per cycle, one host check per cycle); the first
+    # call of each warms its graphs
+    tt, sol = {}, {}
+    if not args.no_solve:
+        for name, p in (("f64", p64), ("mixed", pmx),
+                        ("f64_fmg_start", cpm.make_params(c=cfg.problem.c, fmg=True)),
+                        ("f64_W_cycle", cpm.make_params(c=cfg.problem.c, gamma=2))):
+            sol[name], tt[name] = _solve(cpm, torch, band, p, fd, max_cycles=80)
+        tt["speedup_mixed_over_f64"] = tt["f64"]["seconds"] / tt["mixed"]["seconds"]
+        tt["mixed_vs_f64_max_rel_diff"] = float((sol["mixed"] - sol["f64"]).abs().max() / sol["f64"].abs().max())
+        _, tt["standard_relaxation_to_increment_1e-10"] = _solve(
+            cpm, torch, band, cpm.make_params(c=cfg.problem.c, smoother=cpm.CPM_SMOOTH_STANDARD), fd, max_cycles=80)
+        sol.clear()
+
+    # dominant kernel: the finest level's smoothing pass, timed with HIP events on the stream
+    # it is launched on
+    kname, grid0, bpn, which, what = _dominant_kernel(tuning[0], n0)
+    ud.zero_()
+    avg_us = cpm.cpm_time_kernel(band, p64, which, 0, args.kernel_reps, fd, ud, work, nb64)
+    alg_bytes = bpn * n0
+    achieved = alg_bytes / (avg_us * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": _measured_traffic(_traffic_file("torus256"), kname, grid0),
+                "kernel": "%s (%s)" % (kname, what), "grid": grid0, "avg_launch_us": round(avg_us, 3),
+                "alg_bytes_per_node": bpn, "alg_bytes_per_launch": int(alg_bytes)}
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)  # reads and writes exactly 1 GiB
+        torch.cuda.synchronize()
+        del a, b
+    del work, hist
+    band.free()
+
+    line = {
+        "metric": "band DOF*V-cycles/s and time to 1e-10 rel residual: FP64 vs mixed/learned",
+        "value": n0 * K / dt,
+        "unit": "DOF*V-cycles/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * dt / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (torus R=1, r=0.4; f = seeded mix of 16 torus Fourier modes, sampled at closest points)",
+        "config": {"workload": "torus_R1_r0.4_h1/256_6levels_V(3,3)_omega2/3_fp64", "n_per_level": sizes,
+                   "levels": cfg.levels, "band_radius": "sqrt(17) h", "c": cfg.problem.c,
+                   "cycles_per_graph_launch": PER_LAUNCH},
+        "mixed": {"value": n0 * K / dt_mx, "ms_per_step": 1000.0 * dt_mx / K, "dtype": "f32+f64",
+                  "speedup_over_f64": dt / dt_mx},
+        "time_to_1e-10": tt,
+        "band_build_s": t_build,
+        "autotune_s": t_tune,
+        "tuning": [{"level": l, "lds": t[0], "ext_block": t[1], "nsum_block": t[2], "fused_sweep": t[3],
+                    "sweep_block": t[4], "sweep_lds": t[5], "tiled": t[6], "ext_prefetch": t[7]}
+                   for l, t in enumerate(tuning)],
+        "roofline": roofline,
+    }
+    if not args.no_extras:
+        line["h1/64_oracle"] = oracle_at_64(args, cpm, torch)
+        line["extras"] = secondary_surfaces(cpm, torch)
+    print(json.dumps(line), flush=True)
+
+
+def oracle_at_64(args, cpm, torch):
+    """The same torus and right-hand side at h = 1/64 (4 levels, 531,968 nodes): the GPU's
+    mixed and FP64 solutions against the float64 oracle's, and the oracle's own V-cycle rate
+    on one core (the CPU baseline)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import workloads as W
     from oracle import band as ob
     from oracle import vcycle as ov
 
-    cfg = W.config_torus_mixed(256)
-    t0 = time.perf_counter()
-    band = _build(cpm, cfg.problem, cfg.h0, cfg.levels)
-    t_build = time.perf_counter() - t0
-    cpm.cpm_autotune(band)
-    _, cp = band.export(0)
-    fd = torch.as_tensor(cfg.problem.f(cp)).to("cuda")
-    n0 = band.n(0)
-    out = {"workload": "torus_R1_r0.4_h1/256_6levels", "n_per_level": band.sizes(), "band_build_s": t_build}
-    u64, out["f64"] = _solve(cpm, torch, band, cpm.make_params(), fd)
-    umx, out["mixed"] = _solve(cpm, torch, band, cpm.make_params(precision=cpm.CPM_MIXED), fd)
-    out["mixed_vs_f64_max_rel_diff"] = float((umx - u64).abs().max() / u64.abs().max())
-    out["speedup_mixed_over_f64"] = out["f64"]["seconds"] / out["mixed"]["seconds"]
-    for k in ("f64", "mixed"):
-        out[k]["dof_cycles_per_s"] = n0 * out[k]["cycles"] / out[k]["seconds"]
-    band.free()
-    # error against the FP64 oracle at h = 1/64 (same torus, same right-hand side)
     c64 = W.config_torus_mixed(64)
+    t0 = time.perf_counter()
     H = ob.build_hierarchy(c64.problem.surface, c64.h0, c64.levels, c64.lam2)
     f = c64.problem.f(H.levels[0].cp)
-    ref = ov.solve(H, f, ov.Params(), rtol=1e-10, max_cycles=80)
-    b64 = _build(cpm, c64.problem, c64.h0, c64.levels)
-    ug, st = _solve(cpm, torch, b64, cpm.make_params(precision=cpm.CPM_MIXED), torch.as_tensor(f).to("cuda"),
-                    repeat=False)
-    ugh = ug.cpu().numpy()
-    out["h1/64_mixed_vs_fp64_oracle"] = {"n": H.levels[0].n, "max_rel_diff": float(np.max(np.abs(ugh - ref.u)) /
-                                                                                  np.max(np.abs(ref.u))),
-                                         "oracle_cycles": ref.cycles, "gpu_cycles": st["cycles"]}
-    print(json.dumps({"metric": "time to 1e-10 rel residual, FP64 vs mixed", **out}), flush=True)
+    ref = ov.solve(H, f, ov.Params(c=c64.problem.c), rtol=1e-10, max_cycles=80)
+    print("oracle at h=1/64: %d cycles in %.1f s" % (ref.cycles, time.perf_counter() - t0), file=sys.stderr,
+          flush=True)
+    band = _build(cpm, c64.problem, c64.h0, c64.levels, c64.lam2)
+    fd = torch.as_tensor(f).to("cuda")
+    out = {"workload": "torus_R1_r0.4_h1/64_4levels", "n": H.levels[0].n, "oracle_cycles": ref.cycles}
+    for name, p in (("mixed", cpm.make_params(precision=cpm.CPM_MIXED)), ("f64", cpm.make_params())):
+        ug, st = _solve(cpm, torch, band, p, fd, repeat=False)
+        out[name] = {"gpu_cycles": st["cycles"], "relres": st["relres"],
+                     "max_rel_diff_vs_fp64_oracle": float(np.max(np.abs(ug.cpu().numpy() - ref.u)) /
+                                                          np.max(np.abs(ref.u)))}
+    band.free()
+    if not args.no_cpu_baseline:
+        with threadpool_limits(limits=1):
+            p = ov.Params(c=c64.problem.c)
+            coarse = ov.CoarseSolver(H, p)
+            u = np.zeros(H.levels[0].n)
+            t0 = time.perf_counter()
+            for _ in range(args.cpu_cycles):
+                u = ov.vcycle(H, 0, u, f, p, coarse)
+            dt = time.perf_counter() - t0
+        n0 = H.levels[0].n
+        out["cpu_baseline"] = {
+            "value": n0 * args.cpu_cycles / dt, "unit": "DOF*V-cycles/s", "cores": 1, "kind": "oracle",
+            "sample": "%d V(3,3) cycles of the same torus and right-hand side at h = 1/64 (4 levels, %d finest "
+                      "DOFs; the oracle's cost per cycle is proportional to the DOFs), scipy CSR mat-vecs, 1 thread, "
+                      "setup excluded; %.2f s" % (args.cpu_cycles, n0, dt),
+            **_host_info()}
+    return out
+
+
+def secondary_surfaces(cpm, torch):
+    """The variable-coefficient sphere example and Dziuk's level-set surface at h = 1/64."""
+    import workloads as W
+
+    out = {}
+    pv = W.sphere_varcoef()
+    cfg = W.config_sphere(64, 5)
+    band = _build(cpm, pv, cfg.h0, cfg.levels, cfg.lam2)
+    for l in range(band.levels):
+        _, cpl = band.export(l)
+        cpm.cpm_set_diffusion(band, l, pv.a(cpl))
+    _, cp = band.export(0)
+    u, r = _solve(cpm, torch, band, cpm.make_params(c=pv.c), torch.as_tensor(pv.f(cp)).to("cuda"))
+    out["variable_coefficient_sphere_h1/64"] = {
+        "seconds_to_1e-10": r["seconds"], "cycles": r["cycles"], "relres": r["relres"],
+        "max_error_vs_exact": float(abs(u.cpu().numpy() - pv.u_exact(cp)).max())}
+    band.free()
+    pl = W.dziuk_x1x2()
+    t0 = time.perf_counter()
+    bl = _build(cpm, pl, 1.0 / 64, 4)
+    t_bl = time.perf_counter() - t0
+    _, cpl = bl.export(0)
+    ul, rl = _solve(cpm, torch, bl, cpm.make_params(c=pl.c), torch.as_tensor(pl.f(cpl)).to("cuda"))
+    out["levelset_dziuk_h1/64"] = {"n_per_level": bl.sizes(), "band_build_s": t_bl,
+                                   "seconds_to_1e-10": rl["seconds"], "cycles": rl["cycles"],
+                                   "contraction": rl["contraction"],
+                                   "max_error_vs_exact": float(abs(ul.cpu().numpy() - pl.u_exact(cpl)).max())}
+    bl.free()
+    return out
 
 
 def run_batched256(args):
@@ -120,15 +323,15 @@ def run_batched256(args):
 
     items = W.batch_problems(args.nprob)
     t0 = time.perf_counter()
-    bands, fs = [], []
-    for k, it in enumerate(items):
-        b = _build(cpm, it.problem, it.h0, it.levels, it.lam2)
+    # all bands at once on the host's cores (one band per thread)
+    surfs = [cpm.make_surface(it.problem.surface.kind, it.problem.surface.R, it.problem.surface.r,
+                              it.problem.surface.center) for it in items]
+    bands = cpm.cpm_build_bands(surfs, [(it.h0, it.levels, it.lam2) for it in items])
+    print("built %d bands in %.1f s" % (len(bands), time.perf_counter() - t0), file=sys.stderr, flush=True)
+    fs = []
+    for it, b in zip(items, bands):
         _, cp = b.export(0)
-        bands.append(b)
         fs.append(torch.as_tensor(it.problem.f(cp)).to("cuda"))
-        if (k + 1) % 32 == 0:  # the host build takes minutes: report progress on stderr
-            print("built %d of %d bands (%.0f s)" % (k + 1, len(items), time.perf_counter() - t0),
-                  file=sys.stderr, flush=True)
     t_build = time.perf_counter() - t0
     sizes = [b.n(0) for b in bands]
     p = cpm.make_params(precision=cpm.CPM_MIXED)
@@ -162,6 +365,7 @@ def run_batched256(args):
                       "cycles_min": min(s.cycles for s in stats), "cycles_max": max(s.cycles for s in stats),
                       "max_relres": max(s.relres for s in stats), "tile_block": stats[0].tile_block,
                       "tile_blocks_per_cu": stats[0].tile_blocks_per_cu, "band_build_s": t_build,
+                      "cycles_per_graph_launch": stats[0].cycles_per_launch, "host_syncs": stats[0].host_syncs,
                       "unbatched_sample": {"problems": sample, "seconds": seq_t,
                                            "dof_cycles_per_s": sample_n / seq_t, "same_cycles_as_batched": same_cycles,
                                            "max_rel_diff_to_batched": max_diff}}),
@@ -228,17 +432,14 @@ def run_learned(args):
     print(json.dumps(out), flush=True)
 
 
-TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic_ext_smooth_sphere64.json")
-
-
-def _measured_traffic(kernel: str, grid: int):
-    """HBM bytes per launch of the dominant kernel from the committed FETCH_SIZE / WRITE_SIZE
+def _measured_traffic(path: str, kernel: str, grid: int):
+    """HBM bytes per launch of the dominant kernel from a committed FETCH_SIZE / WRITE_SIZE
     summary, or None when there is none, it is for another kernel or launch shape, or the
     kernel's sources have changed since the counters were taken."""
     from paper_1307_4354_amd import prof_summary
 
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -281,16 +482,22 @@ def main():
         print("bench.py measures one GPU only: the CPM solver runs each problem on a single device "
               "(multi-GPU sharding is a design note, not an implemented path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    {"torus256": headline_torus256, "sphere64": run_sphere64, "batched256": run_batched256,
+     "learned": run_learned}[args.workload](args)
+
+
+def run_sphere64(args):
+    """The unit sphere at h = 1/64 (5 levels, 424,510 nodes): cycle rates, time to 1e-10 and
+    the standard relaxation on a level set whose working set fits the 256 MB last-level cache."""
     import numpy as np
     import torch
 
     import paper_1307_4354_amd as cpm
     import workloads as W
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.workload != "sphere64":
-        {"torus256": run_torus256, "batched256": run_batched256, "learned": run_learned}[args.workload](args)
-        return
     cfg = W.config_sphere(64, 5)
     s = cfg.problem.surface
     t0 = time.perf_counter()
@@ -311,13 +518,13 @@ def main():
     tuning = [cpm.cpm_band_tuning(band, l) for l in range(band.levels)]
     ud = torch.zeros_like(fd)
     hist = torch.zeros(max(args.steps, args.warmup) + 8, dtype=torch.float64, device="cuda")
-    per_launch = 10
-
     def run(p, nb, k):
-        cpm.cpm_run_cycles(band, p, fd, ud, work, nb, k, min(per_launch, max(k, 1)), hist)
+        cpm.cpm_run_cycles(band, p, fd, ud, work, nb, k, PER_LAUNCH, hist)
 
     # FP64 throughput: warm-up (graph capture, coarse factorization), then exactly K timed cycles
-    run(p64, nb64, args.warmup)
+    run(p64, nb64, max(args.warmup, 1))
+    run(p64, nb64, args.steps)  # the timed run's launch pattern, so its graphs are captured
+    ud.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run(p64, nb64, args.steps)
@@ -327,7 +534,9 @@ def main():
 
     # mixed-precision throughput (same cycles, float32 inner / float64 outer)
     ud.zero_()
-    run(pmx, nbmx, args.warmup)
+    run(pmx, nbmx, max(args.warmup, 1))
+    run(pmx, nbmx, args.steps)
+    ud.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run(pmx, nbmx, args.steps)
@@ -365,19 +574,16 @@ def main():
         std_res = {"seconds": time.perf_counter() - t0, "cycles": st.cycles, "final_increment": st.relres,
                    "status": st.status}
 
-    # dominant kernel: finest-level extension + smoothing pass, timed with HIP events on the
-    # stream it runs on.  Algorithmic bytes per node: 3 closest-point fractions (24 B), u read (8),
-    # u write (8), one read of g (8) = 48 B (FP64, 3-D).
+    # dominant kernel: the finest level's smoothing pass, timed with HIP events on the stream it
+    # runs on
+    kname, grid0, bpn, which, _ = _dominant_kernel(tuning[0], n0)
     ud.zero_()
-    avg_us = cpm.cpm_time_kernel(band, p64, 0, 0, args.kernel_reps, fd, ud, work, nb64)
-    alg_bytes = 48.0 * n0
+    avg_us = cpm.cpm_time_kernel(band, p64, which, 0, args.kernel_reps, fd, ud, work, nb64)
+    alg_bytes = bpn * n0
     achieved = alg_bytes / (avg_us * 1e-6) / 1e9
-    lds0, blk0 = tuning[0][0], (256 if tuning[0][0] else tuning[0][1])
-    kname = ("k_ext_lds" if lds0 else "k_ext") + "<3, double, double, 0>"
-    grid0 = -(-n0 // blk0) * blk0
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": _measured_traffic(kname, grid0),
+                "traffic": _measured_traffic(_traffic_file("sphere64"), kname, grid0),
                 "kernel": kname + " (extension + Jacobi smoothing, level 0)", "grid": grid0,
                 "avg_launch_us": round(avg_us, 3), "alg_bytes_per_launch": int(alg_bytes)}
 
@@ -435,7 +641,7 @@ def main():
         del a, b
 
     line = {
-        "metric": "band DOF*V-cycles/s and time to 1e-10 rel residual: FP64 vs mixed/learned",
+        "metric": "band DOF*V-cycles/s, sphere h=1/64 (secondary workload)",
         "value": value,
         "unit": "DOF*V-cycles/s",
         "n_gpus": 1,
@@ -457,7 +663,8 @@ def main():
         "band_build_s": t_build,
         "autotune_s": t_tune,
         "tuning": [{"level": l, "lds": t[0], "ext_block": t[1], "nsum_block": t[2], "fused_sweep": t[3],
-                    "sweep_block": t[4], "sweep_lds": t[5]} for l, t in enumerate(tuning)],
+                    "sweep_block": t[4], "sweep_lds": t[5], "tiled": t[6], "ext_prefetch": t[7]}
+                   for l, t in enumerate(tuning)],
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -75,7 +75,12 @@ typedef struct {
 } cpm_grid;
 
 typedef enum { CPM_F64 = 0, CPM_MIXED = 1 } cpm_precision;
-typedef enum { CPM_SMOOTH_JACOBI = 0, CPM_SMOOTH_LEARNED = 1, CPM_SMOOTH_STANDARD = 2 } cpm_smoother;
+typedef enum {
+  CPM_SMOOTH_JACOBI = 0,
+  CPM_SMOOTH_LEARNED = 1,
+  CPM_SMOOTH_STANDARD = 2,
+  CPM_SMOOTH_STANDARD_RB = 3
+} cpm_smoother;
 
 /* Solver parameters.  precision CPM_MIXED: float32 smoothing / extension / transfers on
  * every level, float64 outer residual, refinement update and coarsest solve.
@@ -88,7 +93,12 @@ typedef enum { CPM_SMOOTH_JACOBI = 0, CPM_SMOOTH_LEARNED = 1, CPM_SMOOTH_STANDAR
  * and solves the coarsest level with A_c^{-1}; its progress is measured by the relative
  * increment ||u_k - u_{k-1}||_inf / ||u_k||_inf (the paper's stopping test), which is what
  * relres / relres_history / relres_out and rtol then refer to (the cycle's fixed point does
- * not make f - A u vanish). */
+ * not make f - A u vanish).
+ * smoother CPM_SMOOTH_STANDARD_RB: the same standard relaxation with Gauss-Seidel in red-black
+ * order instead of Jacobi (Sec. 4.5 names Gauss-Seidel as the alternative): each sweep applies
+ * the damped correction omega diag(A)^{-1} (f - A u) to the nodes whose grid index sum is even,
+ * then, from that iterate, to the others (nodes of one colour that A couples are updated
+ * together).  Everything else as for CPM_SMOOTH_STANDARD. */
 typedef struct {
   double c;
   int nu1;
@@ -105,7 +115,25 @@ typedef struct {
                          coarsest solved, then per finer level cubic closest-point
                          interpolation of the coarser solution and one cycle (precision
                          CPM_F64, smoother CPM_SMOOTH_JACOBI) */
+  int residual_mode;  /* CPM_RESIDUAL_CONSISTENT (0): the residual passed to the coarse grid
+                         is E f - A u (= E(f + N u) - delta u), whose fixed point solves
+                         A u = E f.  CPM_RESIDUAL_VERBATIM (1): Algorithm 4.1 step 2 as printed,
+                         r = f - (cI - L) u = f + N u - delta u at every node, and the coarsest
+                         level solves A_c e = f_c; its residual stagnates at the extension's
+                         discretization error (Sec. 4.6.1 notes this), so progress is the
+                         relative increment ||u_k - u_{k-1}||_inf / ||u_k||_inf (the paper's
+                         stopping test), which relres and rtol then refer to (precision
+                         CPM_F64, smoother CPM_SMOOTH_JACOBI, constant coefficient).  With
+                         the standard relaxation it selects the plain residual f - A u (the
+                         printed step with A in place of A~) instead of f - A (E u); the fixed
+                         point then solves A u = f */
+  int el_degree;      /* degree p of the interpolation in front of L in M = E_p L - gamma
+                         (I - E_3): 3 (or 0) the cubic of every cycle; 1 the sparser operator of
+                         Remark 3.2 (Table 3.1), with the standard relaxation only */
 } cpm_params;
+
+#define CPM_RESIDUAL_CONSISTENT 0
+#define CPM_RESIDUAL_VERBATIM 1
 
 #define CPM_MAX_HISTORY 256
 
@@ -119,9 +147,22 @@ typedef struct {
   int tile_block;                           /* batched: workgroup size chosen by the
                                                autotuner (0 for single solves)           */
   int tile_blocks_per_cu;                   /* batched: resident workgroups per CU       */
+  int host_syncs;                           /* batched: host synchronizations of the
+                                               solve loop (one per graph launch)          */
+  int cycles_per_launch;                    /* batched: cycles captured per graph launch */
 } cpm_stats;
 
 typedef struct cpm_band_s* cpm_band;
+
+/* Device allocator for the arrays a band owns (index tables, closest-point fractions,
+ * coarsest-level matrices, scalars, smoother weights): alloc(ctx, bytes) returns device
+ * memory or NULL, release(ctx, p) frees it, so a framework's caching allocator (torch's) can
+ * back a band.  Bands use the allocator registered when they are built, until they are
+ * freed; NULL for both restores hipMalloc / hipFree.  Process-wide; set it before building
+ * bands, not while another thread builds one.  CPM_E_INVALID if only one function is given.
+ * (Workspaces and vectors are the caller's own memory and never go through it.) */
+cpm_status cpm_set_allocator(void* (*alloc)(void* ctx, size_t bytes), void (*release)(void* ctx, void* ptr),
+                             void* ctx);
 
 /* Build the band hierarchy (Sec. 3.1, Sec. 4.3): band nodes, closest points, cubic
  * extension stencils, Laplacian neighbours and the linear restriction / prolongation
@@ -133,14 +174,26 @@ typedef struct cpm_band_s* cpm_band;
 cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void* stream,
                           cpm_band* out);
 
+/* Build `count` band hierarchies (surfaces[k], grids[k]) as cpm_build_band does, several
+ * at once on the host's cores (each band single-threaded), for batches of problems.  out
+ * receives count handles; on failure none is left allocated and the error names the first
+ * failing band. */
+cpm_status cpm_build_bands(int count, const cpm_surface* surfaces, const cpm_grid* grids, void* stream,
+                           cpm_band* out);
+
 /* Release a handle and all device memory it owns.  NULL is accepted. */
 cpm_status cpm_band_free(cpm_band band);
 
 /* Number of levels, embedding dimension. */
 cpm_status cpm_band_levels(cpm_band band, int* levels, int* dim);
 
-/* Size n and spacing h of one level. */
-cpm_status cpm_band_info(cpm_band band, int level, int64_t* n, double* h);
+/* Size n and spacing h of one level (any output may be NULL), and flags:
+ * CPM_BAND_BEYOND_REACH when the band radius sqrt(lam2) h of the level reaches the surface's
+ * reach (Sec. 2.1: the closest point is unique only within it; radius R for a circle or
+ * sphere, min(r, R - r) for a torus, the smallest radius of curvature for the level set).
+ * Such coarse levels are allowed: nodes at a tie take the documented closest point on S. */
+#define CPM_BAND_BEYOND_REACH 1
+cpm_status cpm_band_info(cpm_band band, int level, int64_t* n, double* h, int* flags);
 
 /* Copy one level's grid multi-indices (n x dim int32, row-major) and closest points
  * (n x dim double, row-major) into caller-owned host buffers (either may be NULL). */
@@ -160,11 +213,22 @@ cpm_status cpm_band_export_stencils(cpm_band band, int level, int32_t* runE, int
 /* Bytes of device workspace a vcycle / solve with these parameters needs. */
 cpm_status cpm_workspace_size(cpm_band band, const cpm_params* params, size_t* bytes);
 
-/* Au = (c + 2d/h^2) u - E (N u) on one level (eq. (3.3), matrix-free).  u and Au are
- * double device vectors of length n(level) that must not overlap; work is a device
- * buffer of at least n(level) doubles. */
-cpm_status cpm_apply(cpm_band band, int level, double c, const double* u, double* Au,
-                     double* work, void* stream);
+typedef enum { CPM_DTYPE_F64 = 0, CPM_DTYPE_F32 = 1 } cpm_dtype;
+
+/* Au = (c + 2d/h^2) u - E (N u) on one level (eq. (3.3), matrix-free).  u and Au are device
+ * vectors of length n(level) of type dtype (CPM_DTYPE_F64: double, CPM_DTYPE_F32: float,
+ * the arithmetic then in float) that must not overlap; work is a device buffer of at least
+ * n(level) elements of that type. */
+cpm_status cpm_apply(cpm_band band, int level, int dtype, double c, const void* u, void* Au, void* work,
+                     void* stream);
+
+/* A u for the family of Sec. 3.1: A = c I - M, M = E_p L - gamma (I - E_3), gamma = 2d/h^2,
+ * p = 3 (cpm_apply) or p = 1 (Remark 3.2: linear interpolation in front of the Laplacian, a
+ * sparser matrix with the same second order, the operator of Table 3.1):
+ * A u = delta u - E_1 (N u) + gamma (E_1 u - E_3 u).  double device vectors of length
+ * n(level), u and Au not overlapping; work holds n(level) doubles. */
+cpm_status cpm_apply_pq(cpm_band band, int level, int p, double c, const double* u, double* Au, double* work,
+                        void* stream);
 
 /* One application of the extension: out = E g on one level (degree-3 closest-point
  * interpolation, Sec. 3.1).  double device vectors of length n(level), not overlapping. */
@@ -186,8 +250,8 @@ cpm_status cpm_set_diffusion(cpm_band band, int level, const double* a);
 /* One V(nu1, nu2) cycle in place on u (Algorithm 4.1) for right-hand side f.  work has
  * cpm_workspace_size bytes.  If relres_out is not NULL the call synchronizes the stream
  * and stores ||E f - A u||_inf / ||E f||_inf of the new iterate (the relative increment
- * for CPM_SMOOTH_STANDARD).  Only precision CPM_F64 with smoother CPM_SMOOTH_JACOBI or
- * CPM_SMOOTH_STANDARD is accepted here. */
+ * for the standard relaxation and CPM_RESIDUAL_VERBATIM).  Only precision CPM_F64 with smoother
+ * CPM_SMOOTH_JACOBI, CPM_SMOOTH_STANDARD or CPM_SMOOTH_STANDARD_RB is accepted here. */
 cpm_status cpm_vcycle(cpm_band band, const cpm_params* params, const double* f, double* u,
                       void* work, size_t work_bytes, double* relres_out, void* stream);
 
@@ -215,18 +279,24 @@ cpm_status cpm_run_cycles(cpm_band band, const cpm_params* params, const double*
  * pass, 2 restriction into `level` (level >= 1), 3 prolongation from level+1 into `level`
  * (level < levels-1), 4 the fused learned-smoother update from a fixed residual (level < 2,
  * weights set, CPM_E_INVALID otherwise), 5 the fused one-pass sweep (levels that have its
- * addressing, CPM_E_INVALID otherwise).  Level 0 runs on f and u, other levels on workspace vectors; the
+ * addressing, CPM_E_INVALID otherwise), 6 the tiled sweep (levels that have its tables,
+ * CPM_E_INVALID otherwise).  Level 0 runs on f and u, other levels on workspace vectors; the
  * values left in u are those of repeated smoothing.  Synchronous. */
 cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, int level, int reps,
                            const double* f, double* u, void* work, size_t work_bytes, double* avg_us,
                            void* stream);
 
 /* Batched solve of nprob independent problems (different surfaces, spacings and sizes)
- * with the same parameters: every phase of the V-cycle runs as one launch over the tiles
- * of all problems, and one V-cycle of the whole batch is one captured HIP graph.  f[k],
- * u[k] are device vectors of problem k; work has cpm_workspace_size_batched bytes.
- * precision must be CPM_MIXED or CPM_F64.  stats: nprob entries (NULL allowed).
- * Returns CPM_E_NOCONV if any problem missed rtol. */
+ * with the same parameters (the mixed-precision iterative refinement of cpm_solve, Jacobi
+ * smoother, V-cycles): every phase of the V-cycle runs as one launch over the tiles of all
+ * problems, and 8 consecutive V-cycles of the whole batch are one captured HIP graph.
+ * Each problem stops on the device, through its own flag, when it reaches rtol or
+ * max_cycles, so it performs exactly the cycles of its own solve; the host reads the
+ * number of finished problems once per graph launch.  A problem with E f = 0 gets u = 0
+ * and no cycle.  f[k], u[k] are device vectors of problem k (u[k]: the start, normally 0);
+ * work has cpm_workspace_size_batched bytes.  precision must be CPM_MIXED.  stats: nprob
+ * entries (NULL allowed).  Returns CPM_E_NOCONV if any problem missed rtol,
+ * CPM_E_DIVERGED if any residual was not finite.  Synchronous on return. */
 cpm_status cpm_workspace_size_batched(int nprob, const cpm_band* bands, const cpm_params* params,
                                       size_t* bytes);
 cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params* params,
@@ -246,18 +316,24 @@ cpm_status cpm_autotune(cpm_band band, void* stream);
 
 /* Launch configuration chosen for one level (after cpm_autotune, or the defaults); any
  * output pointer may be NULL.  fused = 1 when the level sweeps with the fused pass;
- * sweep_lds = 1 when that pass is LDS-staged (sweep_block is then its fixed 256 lanes). */
+ * sweep_lds = 1 when that pass is LDS-staged (sweep_block is then its fixed 256 lanes);
+ * tiled = 1 when the level sweeps with the tiled pass (3-D levels of 2^18 nodes or more whose
+ * tables exist: f + N u formed in LDS over each tile's box, then the extension, one pass);
+ * ext_prefetch = 1 when the LDS-staged extension loads each node's own data (band index, run
+ * offsets, fractions, u) before its workgroup stages the interpolated values. */
 cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_block, int* nsum_block, int* fused,
-                           int* sweep_block, int* sweep_lds);
+                           int* sweep_block, int* sweep_lds, int* tiled, int* ext_prefetch);
 
 /* Set one level's launch configuration by hand (for instance one found by cpm_autotune in
  * an earlier process): use_lds = LDS-staged extension (levels that have its tables),
  * ext_block / nsum_block / sweep_block in {128, 256, 512}, fused = sweep with the fused pass
  * (levels that have its addressing), sweep_lds = that pass LDS-staged (levels that have its
- * tables; its workgroup is then 256).  CPM_E_INVALID, with nothing changed, for a
- * configuration the level does not support.  Drops the band's captured cycle graphs. */
+ * tables; its workgroup is then 256), tiled = sweep with the tiled pass (levels that have its
+ * tables; not together with fused), ext_prefetch = the LDS-staged extension's early loads
+ * (with use_lds only).  CPM_E_INVALID, with nothing changed, for a configuration the level
+ * does not support.  Drops the band's captured cycle graphs. */
 cpm_status cpm_set_band_tuning(cpm_band band, int level, int use_lds, int ext_block, int nsum_block, int fused,
-                               int sweep_block, int sweep_lds);
+                               int sweep_block, int sweep_lds, int tiled, int ext_prefetch);
 
 /* ---- learned smoother ---------------------------------------------------------------
  * Network (per node): x = [r_patch / s (27 values: residual on the 3x3x3 grid patch
@@ -302,6 +378,18 @@ cpm_status cpm_mlp_adam(int step, float lr, float* w_master, float* m1, float* m
 cpm_status cpm_smoother_features(cpm_band band, int level, double c, const double* f,
                                  const double* u, uint16_t* X, float* s, void* work,
                                  void* stream);
+
+/* Training pairs of the learned smoother at every node of level 0 or 1: X and s as
+ * cpm_smoother_features, and the target T (n floats, device) = r_i / s_i clipped to
+ * [-clip, clip] (0 where s_i = 0), the undamped Ruuth-Merriman correction of u_i (eqs.
+ * (4.2a)-(4.2b): u_i moves by r_i / delta with r = E f - A u, eq. (3.3)) in the network's
+ * units.  work: at least 2 n(level) doubles (it keeps the residual in its second half). */
+cpm_status cpm_smoother_pairs(cpm_band band, int level, double c, const double* f, const double* u, uint16_t* X,
+                              float* T, float* s, double clip, void* work, void* stream);
+
+/* Mean squared loss (1/m) sum (Y - T)^2 of m outputs against targets (device floats), summed
+ * in double in a fixed order, into one device double. */
+cpm_status cpm_mlp_loss(int64_t m, const float* Y, const float* T, double* loss, void* stream);
 
 const char* cpm_status_string(int status);
 const char* cpm_last_error(void);

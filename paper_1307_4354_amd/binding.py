@@ -21,7 +21,10 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libcpm.so")
 CPM_OK, CPM_E_INVALID, CPM_E_BAND, CPM_E_NOMEM, CPM_E_HIP, CPM_E_NOCONV, CPM_E_DIVERGED, CPM_E_WORKSPACE = range(8)
 CPM_CIRCLE, CPM_SPHERE, CPM_TORUS, CPM_DZIUK = 0, 1, 2, 3
 CPM_F64, CPM_MIXED = 0, 1
-CPM_SMOOTH_JACOBI, CPM_SMOOTH_LEARNED, CPM_SMOOTH_STANDARD = 0, 1, 2
+CPM_DTYPE_F64, CPM_DTYPE_F32 = 0, 1
+CPM_BAND_BEYOND_REACH = 1
+CPM_RESIDUAL_CONSISTENT, CPM_RESIDUAL_VERBATIM = 0, 1
+CPM_SMOOTH_JACOBI, CPM_SMOOTH_LEARNED, CPM_SMOOTH_STANDARD, CPM_SMOOTH_STANDARD_RB = 0, 1, 2, 3
 CPM_MAX_HISTORY = 256
 CPM_MLP_IN = 64
 CPM_MLP_HIDDEN = 64
@@ -40,13 +43,13 @@ class cpm_grid(Structure):
 class cpm_params(Structure):
     _fields_ = [("c", c_double), ("nu1", c_int), ("nu2", c_int), ("omega", c_double),
                 ("precision", c_int), ("smoother", c_int), ("learned_sweeps", c_int), ("gamma", c_int),
-                ("fmg", c_int)]
+                ("fmg", c_int), ("residual_mode", c_int), ("el_degree", c_int)]
 
 
 class cpm_stats(Structure):
     _fields_ = [("cycles", c_int), ("relres", c_double), ("relres_history", c_double * CPM_MAX_HISTORY),
                 ("fallback_cycle", c_int), ("seconds", c_double), ("tile_block", c_int),
-                ("tile_blocks_per_cu", c_int)]
+                ("tile_blocks_per_cu", c_int), ("host_syncs", c_int), ("cycles_per_launch", c_int)]
 
     def history(self):
         return [self.relres_history[k] for k in range(min(self.cycles, CPM_MAX_HISTORY))]
@@ -74,12 +77,15 @@ def _load():
         "cpm_last_error": (c_char_p, []),
         "cpm_build_band": (c_int, [POINTER(cpm_surface), POINTER(cpm_grid), vp, POINTER(vp)]),
         "cpm_band_free": (c_int, [vp]),
+        "cpm_build_bands": (c_int, [c_int, POINTER(cpm_surface), POINTER(cpm_grid), vp, POINTER(vp)]),
         "cpm_band_levels": (c_int, [vp, POINTER(c_int), POINTER(c_int)]),
-        "cpm_band_info": (c_int, [vp, c_int, POINTER(c_int64), POINTER(c_double)]),
+        "cpm_band_info": (c_int, [vp, c_int, POINTER(c_int64), POINTER(c_double), POINTER(c_int)]),
+        "cpm_set_allocator": (c_int, [vp, vp, vp]),
         "cpm_band_export": (c_int, [vp, c_int, vp, vp]),
         "cpm_band_export_stencils": (c_int, [vp, c_int, vp, vp, vp, vp]),
         "cpm_workspace_size": (c_int, [vp, POINTER(cpm_params), POINTER(c_size_t)]),
-        "cpm_apply": (c_int, [vp, c_int, c_double, vp, vp, vp, vp]),
+        "cpm_apply": (c_int, [vp, c_int, c_int, c_double, vp, vp, vp, vp]),
+        "cpm_apply_pq": (c_int, [vp, c_int, c_int, c_double, vp, vp, vp, vp]),
         "cpm_extend": (c_int, [vp, c_int, vp, vp, vp]),
         "cpm_vcycle": (c_int, [vp, POINTER(cpm_params), vp, vp, vp, c_size_t, POINTER(c_double), vp]),
         "cpm_solve": (c_int, [vp, POINTER(cpm_params), vp, vp, vp, c_size_t, c_double, c_int,
@@ -91,15 +97,17 @@ def _load():
         "cpm_solve_batched": (c_int, [c_int, POINTER(vp), POINTER(cpm_params), POINTER(vp), POINTER(vp), vp,
                                       c_size_t, c_double, c_int, POINTER(cpm_stats), vp]),
         "cpm_autotune": (c_int, [vp, vp]),
-        "cpm_set_band_tuning": (c_int, [vp, c_int, c_int, c_int, c_int, c_int, c_int, c_int]),
+        "cpm_set_band_tuning": (c_int, [vp, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int]),
         "cpm_band_tuning": (c_int, [vp, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int),
-                                    POINTER(c_int), POINTER(c_int)]),
+                                    POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
         "cpm_set_smoother_weights": (c_int, [vp, vp, c_double]),
         "cpm_set_diffusion": (c_int, [vp, c_int, vp]),
         "cpm_mlp_forward": (c_int, [c_int64, vp, vp, vp, vp, vp]),
         "cpm_mlp_backward": (c_int, [c_int64, vp, vp, vp, vp, vp, vp, vp]),
         "cpm_mlp_adam": (c_int, [c_int, ctypes.c_float, vp, vp, vp, vp, vp, vp]),
         "cpm_smoother_features": (c_int, [vp, c_int, c_double, vp, vp, vp, vp, vp, vp]),
+        "cpm_smoother_pairs": (c_int, [vp, c_int, c_double, vp, vp, vp, vp, vp, c_double, vp, vp]),
+        "cpm_mlp_loss": (c_int, [c_int64, vp, vp, vp, vp]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -153,9 +161,9 @@ def make_surface(kind, R: float, r: float = 0.0, center=(0.0, 0.0, 0.0)) -> cpm_
 
 def make_params(c: float = 1.0, nu1: int = 3, nu2: int = 3, omega: float = 2.0 / 3.0,
                 precision: int = CPM_F64, smoother: int = CPM_SMOOTH_JACOBI, learned_sweeps: int = 0,
-                gamma: int = 1, fmg: bool = False) -> cpm_params:
+                gamma: int = 1, fmg: bool = False, residual_mode: int = 0, el_degree: int = 0) -> cpm_params:
     return cpm_params(float(c), int(nu1), int(nu2), float(omega), int(precision), int(smoother),
-                      int(learned_sweeps), int(gamma), int(bool(fmg)))
+                      int(learned_sweeps), int(gamma), int(bool(fmg)), int(residual_mode), int(el_degree))
 
 
 class Band:
@@ -169,14 +177,19 @@ class Band:
         self.dim = d.value
 
     def n(self, level: int = 0) -> int:
-        n, h = c_int64(), c_double()
-        _check(_lib.cpm_band_info(self.handle, level, byref(n), byref(h)))
+        n = c_int64()
+        _check(_lib.cpm_band_info(self.handle, level, byref(n), None, None))
         return n.value
 
     def h(self, level: int = 0) -> float:
-        n, h = c_int64(), c_double()
-        _check(_lib.cpm_band_info(self.handle, level, byref(n), byref(h)))
+        h = c_double()
+        _check(_lib.cpm_band_info(self.handle, level, None, byref(h), None))
         return h.value
+
+    def flags(self, level: int = 0) -> int:
+        fl = c_int()
+        _check(_lib.cpm_band_info(self.handle, level, None, None, byref(fl)))
+        return fl.value
 
     def sizes(self):
         return [self.n(l) for l in range(self.levels)]
@@ -210,12 +223,59 @@ class Band:
             pass
 
 
+_ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_void_p, c_size_t)
+_FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+_allocator_keepalive = None
+
+
+def cpm_set_allocator(alloc, release, ctx=None) -> None:
+    """Register device allocation functions (C function pointers as ints, ctypes callbacks, or
+    None for both to restore hipMalloc / hipFree) for the arrays of bands built afterwards."""
+    a = ctypes.cast(alloc, c_void_p) if alloc is not None else None
+    r = ctypes.cast(release, c_void_p) if release is not None else None
+    _check(_lib.cpm_set_allocator(a, r, ctx))
+
+
+def use_torch_allocator(enable: bool = True) -> None:
+    """Back the arrays of bands built afterwards with torch's caching allocator (or restore
+    hipMalloc / hipFree).  The callbacks only forward the sizes and addresses."""
+    global _allocator_keepalive
+    if not enable:
+        cpm_set_allocator(None, None)
+        _allocator_keepalive = None
+        return
+    import torch
+
+    def _alloc(ctx, nbytes):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except RuntimeError:
+            return None
+
+    def _free(ctx, ptr):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    fa, ff = _ALLOC_FN(_alloc), _FREE_FN(_free)
+    _allocator_keepalive = (fa, ff)  # the library keeps the raw pointers
+    cpm_set_allocator(fa, ff)
+
+
 def cpm_build_band(surface: cpm_surface, h0: float, levels: int, lam2: float = 0.0, stream=None) -> Band:
     g = cpm_grid(float(h0), int(levels), float(lam2))
     out = c_void_p()
     _check(_lib.cpm_build_band(byref(surface), byref(g), _stream(stream) if stream is not None else None,
                                byref(out)))
     return Band(out.value)
+
+
+def cpm_build_bands(surfaces: Sequence[cpm_surface], grids: Sequence[tuple], stream=None):
+    """Build several bands at once; grids are (h0, levels, lam2) tuples."""
+    n = len(surfaces)
+    sa = (cpm_surface * n)(*surfaces)
+    ga = (cpm_grid * n)(*[cpm_grid(float(h0), int(L), float(lam2)) for h0, L, lam2 in grids])
+    out = (c_void_p * n)()
+    _check(_lib.cpm_build_bands(n, sa, ga, _stream(stream) if stream is not None else None, out))
+    return [Band(out[k]) for k in range(n)]
 
 
 def cpm_band_free(band: Band) -> None:
@@ -229,7 +289,16 @@ def cpm_workspace_size(band: Band, params: cpm_params) -> int:
 
 
 def cpm_apply(band: Band, level: int, c: float, u, Au, work, stream=None) -> None:
-    _check(_lib.cpm_apply(band.handle, level, float(c), _ptr(u), _ptr(Au), _ptr(work), _stream(stream)))
+    """Au = A u on one level; the vectors' element type (float64 or float32 tensors) selects
+    the precision."""
+    import torch
+
+    dt = CPM_DTYPE_F32 if getattr(u, "dtype", None) == torch.float32 else CPM_DTYPE_F64
+    _check(_lib.cpm_apply(band.handle, level, dt, float(c), _ptr(u), _ptr(Au), _ptr(work), _stream(stream)))
+
+
+def cpm_apply_pq(band: Band, level: int, p: int, c: float, u, Au, work, stream=None) -> None:
+    _check(_lib.cpm_apply_pq(band.handle, level, int(p), float(c), _ptr(u), _ptr(Au), _ptr(work), _stream(stream)))
 
 
 def cpm_extend(band: Band, level: int, g, out, stream=None) -> None:
@@ -320,6 +389,15 @@ def cpm_smoother_features(band: Band, level: int, c: float, f, u, X, s, work, st
                                       _stream(stream)))
 
 
+def cpm_smoother_pairs(band: Band, level: int, c: float, f, u, X, T, s, clip: float, work, stream=None) -> None:
+    _check(_lib.cpm_smoother_pairs(band.handle, level, float(c), _ptr(f), _ptr(u), _ptr(X), _ptr(T), _ptr(s),
+                                   float(clip), _ptr(work), _stream(stream)))
+
+
+def cpm_mlp_loss(m: int, Y, T, loss, stream=None) -> None:
+    _check(_lib.cpm_mlp_loss(int(m), _ptr(Y), _ptr(T), _ptr(loss), _stream(stream)))
+
+
 def cpm_time_kernel(band: Band, params: cpm_params, which: int, level: int, reps: int, f, u, work,
                     work_bytes: int, stream=None) -> float:
     """Average launch duration (microseconds) of one V-cycle kernel, timed with HIP events."""
@@ -335,15 +413,16 @@ def cpm_mlp_adam(step: int, lr: float, w_master, m1, m2, G, w_bf16, stream=None)
 
 
 def cpm_set_band_tuning(band: Band, level: int, use_lds: bool, ext_block: int, nsum_block: int, fused: bool,
-                        sweep_block: int, sweep_lds: bool) -> None:
+                        sweep_block: int, sweep_lds: bool, tiled: bool = False, ext_prefetch: bool = False) -> None:
     """Pin one level's launch configuration (the fields cpm_band_tuning reports)."""
     _check(_lib.cpm_set_band_tuning(band.handle, int(level), int(bool(use_lds)), int(ext_block), int(nsum_block),
-                                    int(bool(fused)), int(sweep_block), int(bool(sweep_lds))))
+                                    int(bool(fused)), int(sweep_block), int(bool(sweep_lds)), int(bool(tiled)),
+                                    int(bool(ext_prefetch))))
 
 
 def cpm_band_tuning(band: Band, level: int):
-    """(use_lds, ext_block, nsum_block, fused, sweep_block, sweep_lds) chosen for one level."""
-    a, b, c, d, e, g = c_int(), c_int(), c_int(), c_int(), c_int(), c_int()
-    _check(_lib.cpm_band_tuning(band.handle, int(level), byref(a), byref(b), byref(c), byref(d), byref(e),
-                                byref(g)))
-    return bool(a.value), b.value, c.value, bool(d.value), e.value, bool(g.value)
+    """(use_lds, ext_block, nsum_block, fused, sweep_block, sweep_lds, tiled, ext_prefetch) of one level."""
+    v = [c_int() for _ in range(8)]
+    _check(_lib.cpm_band_tuning(band.handle, int(level), *[byref(x) for x in v]))
+    a, b, c, d, e, g, t, pf = [x.value for x in v]
+    return bool(a), b, c, bool(d), e, bool(g), bool(t), bool(pf)

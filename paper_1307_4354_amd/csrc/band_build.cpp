@@ -14,6 +14,7 @@
 #include <climits>
 #include <cstdlib>
 #include <cstring>
+#include <omp.h>
 #include <sstream>
 
 #include "cpm_internal.h"
@@ -719,48 +720,52 @@ cpm_status build_stencil_order(HostLevel& Lv, int level, std::string& err) {
   return CPM_OK;
 }
 
-// 3^dim patch addressing (stencil order) for the learned smoother.
+// 3^dim patch addressing for the learned smoother, in band order.  Row (dy, dz) of node i
+// is addressed by one reference index ref: the present node at x offset dx (-1, 0, 1) sits at
+// ref + (dx + 1), except in a row whose middle node is absent while both outer ones are
+// present, where the +1 node follows the -1 node directly (ref + 1): band order is x fastest,
+// so the present nodes of one grid row are consecutive band entries.  The kernels read that
+// case from the presence mask.
 cpm_status build_patches(HostLevel& Lv, int level, std::string& err) {
   const int dim = Lv.dim;
   const int64_t n = Lv.n;
   const int rows = dim == 2 ? 3 : 9;
   Lv.patchRow.assign((size_t)(rows * n), 0);
   Lv.patchMask.assign((size_t)n, 0u);
-  bool gap = false;
-#pragma omp parallel for reduction(|| : gap)
+  bool bad = false;
+#pragma omp parallel for reduction(|| : bad)
   for (int64_t i = 0; i < n; ++i) {  // band order: the network visits nodes as stored
     const int32_t* m = &Lv.idx[(size_t)(i * dim)];
     uint32_t mask = 0;
     for (int r = 0; r < rows; ++r) {
       const int dy = r % 3 - 1, dz = dim == 3 ? r / 3 - 1 : 0;
-      int32_t ref = 0;
-      bool have = false;
+      int32_t j3[3];
+      uint32_t rm = 0;
       for (int dx = -1; dx <= 1; ++dx) {
-        const int32_t j = lookup(Lv, (int64_t)m[0] + dx, (int64_t)m[1] + dy, dim == 3 ? (int64_t)m[2] + dz : 0);
-        if (j < 0) continue;
-        const int32_t cand = j - (dx + 1);
-        if (!have) {
-          ref = cand;
-          have = true;
-        } else if (cand != ref) {
-          gap = true;  // present nodes of the row are not consecutive band entries
-        }
-        mask |= 1u << ((dx + 1) + 3 * r);
+        j3[dx + 1] = lookup(Lv, (int64_t)m[0] + dx, (int64_t)m[1] + dy, dim == 3 ? (int64_t)m[2] + dz : 0);
+        if (j3[dx + 1] >= 0) rm |= 1u << (dx + 1);
       }
+      int32_t ref = 0;
+      for (int q = 0; q < 3; ++q)
+        if (rm & (1u << q)) {
+          ref = j3[q] - q;
+          break;
+        }
+      const bool gap = rm == 5u;
+      for (int q = 0; q < 3; ++q)
+        if ((rm & (1u << q)) && j3[q] != ref + q - (gap && q == 2 ? 1 : 0)) bad = true;
+      mask |= rm << (3 * r);
       Lv.patchRow[(size_t)(r * n + i)] = ref;
     }
     Lv.patchMask[(size_t)i] = mask;
   }
-  // A row whose present nodes are not consecutive band entries cannot be addressed by one
-  // reference index; the learned smoother is then not used on this level (Jacobi instead).
-  (void)level;
-  (void)err;
-  Lv.patchOK = !gap;
-  if (gap) {
-    std::vector<int32_t>().swap(Lv.patchRow);
-    std::vector<uint32_t>().swap(Lv.patchMask);
-    return CPM_OK;
+  if (bad) {
+    std::ostringstream os;
+    os << "internal: learned-smoother patch rows of level " << level << " are not consecutive band entries";
+    err = os.str();
+    return CPM_E_BAND;
   }
+  Lv.patchOK = true;
   // Group consecutive nodes whose present rows all continue the group's rows (row r of node
   // t of the group = base_r + t).  A row with no present node is loaded but masked out, so
   // its base is free: it is fixed by the first node of the group that has the row.
@@ -796,7 +801,9 @@ cpm_status build_patches(HostLevel& Lv, int level, std::string& err) {
   }
   if (g >= 0) flush();
   const int64_t G = g + 1;
-  if (G >= ((int64_t)1 << (31 - kPatchBits))) {  // too many groups to pack: no learned smoother here
+  if (G >= ((int64_t)1 << (31 - kPatchBits))) {
+    // too many groups to pack: the level has no learned-smoother addressing, and a learned
+    // solve on this band is refused (cpm_solve reports it)
     Lv.patchOK = false;
     std::vector<int32_t>().swap(Lv.patchRow);
     std::vector<uint32_t>().swap(Lv.patchMask);
@@ -821,41 +828,213 @@ inline void cubic_basis(double a, double w[4]) {
 
 // (E N)_ii for every node: the weights of node i's own cubic stencil at the stencil nodes
 // that are axis neighbours of node i, summed and divided by h^2.  diag(A) = delta - (E N)_ii
-// is the divisor of the standard Jacobi relaxation (Sec. 4.1, Sec. 4.5).
+// is the divisor of the standard Jacobi relaxation (Sec. 4.1, Sec. 4.5).  Also the same
+// quantity for Remark 3.2's operator A = delta I - E_1 N + gamma (E_1 - E_3):
+// q1 = (E_1 N)_ii - gamma (E_1)_ii + gamma (E_3)_ii, so that diag(A) = delta - q1.
 void build_en_diagonal(HostLevel& Lv) {
   const int dim = Lv.dim;
   const int64_t n = Lv.n;
   const double ih2 = 1.0 / (Lv.h * Lv.h);
+  const double gamma = 2.0 * dim * ih2;
   Lv.qdiag.assign((size_t)n, 0.0);
+  Lv.q1diag.assign((size_t)n, 0.0);
 #pragma omp parallel for
   for (int64_t i = 0; i < n; ++i) {
     const int32_t j0 = Lv.runE[(size_t)i];  // run (0, 0) starts at the stencil base
     int32_t base[3] = {0, 0, 0}, me[3] = {0, 0, 0};
     double w[3][4] = {{1.0, 0.0, 0.0, 0.0}, {1.0, 0.0, 0.0, 0.0}, {1.0, 0.0, 0.0, 0.0}};
+    // linear weights on the same 4 positions: (0, 1 - a, a, 0) (its base is the cubic's + 1)
+    double w1[3][4] = {{1.0, 0.0, 0.0, 0.0}, {1.0, 0.0, 0.0, 0.0}, {1.0, 0.0, 0.0, 0.0}};
     for (int a = 0; a < dim; ++a) {
       base[a] = Lv.idx[(size_t)(j0 * dim + a)];
       me[a] = Lv.idx[(size_t)(i * dim + a)];
-      cubic_basis(Lv.fracE[(size_t)(a * n + i)], w[a]);
+      const double fr = Lv.fracE[(size_t)(a * n + i)];
+      cubic_basis(fr, w[a]);
+      w1[a][0] = 0.0;
+      w1[a][1] = 1.0 - fr;
+      w1[a][2] = fr;
+      w1[a][3] = 0.0;
     }
-    double q = 0.0;
+    // weight of the grid node at offset off from node i in the stencil with 1-D weights ww
+    auto weight = [&](const double (*ww)[4], const int* off) {
+      double prod = 1.0;
+      for (int b = 0; b < dim; ++b) {
+        const int rel = me[b] + off[b] - base[b];
+        if (rel < 0 || rel > 3) return 0.0;
+        prod *= ww[b][rel];
+      }
+      return prod;
+    };
+    double q = 0.0, q1n = 0.0;
     for (int a = 0; a < dim; ++a)
       for (int sg = -1; sg <= 1; sg += 2) {
-        double prod = 1.0;
-        bool inside = true;
-        for (int b = 0; b < dim && inside; ++b) {
-          const int rel = me[b] + (b == a ? sg : 0) - base[b];
-          if (rel < 0 || rel > 3)
-            inside = false;
-          else
-            prod *= w[b][rel];
-        }
-        if (inside) q += prod;
+        int off[3] = {0, 0, 0};
+        off[a] = sg;
+        q += weight(w, off);
+        q1n += weight(w1, off);
       }
+    const int zero[3] = {0, 0, 0};
     Lv.qdiag[(size_t)i] = q * ih2;
+    Lv.q1diag[(size_t)i] = (q1n * ih2 - gamma * weight(w1, zero)) + gamma * weight(w, zero);
   }
 }
 
+// Tiled-sweep tables (HostLevel::tileSlot ...).  A box row is stored as the band index of its
+// first in-band node and the presence mask of its cells: the in-band nodes of one grid row are
+// consecutive band entries (x fastest), so the node at box x is at
+// first + popcount(mask & ((1 << x) - 1)), also where the row crosses the band twice.
+void build_tiles(HostLevel& Lv) {
+  Lv.ntiles = 0;
+  std::vector<int32_t>().swap(Lv.tileSlot);
+  std::vector<int32_t>().swap(Lv.tileOrg);
+  std::vector<int32_t>().swap(Lv.tileRow);
+  std::vector<int32_t>().swap(Lv.tperm);
+  std::vector<int32_t>().swap(Lv.tloc);
+  std::vector<double>().swap(Lv.fracT);
+  int64_t min_nodes = kTileMinNodes;  // CPM_TILE_MIN_NODES lowers it (tests on small bands)
+  if (const char* e = std::getenv("CPM_TILE_MIN_NODES")) min_nodes = std::atoll(e);
+  if (Lv.dim != 3 || Lv.n < min_nodes) return;
+  const int64_t n = Lv.n;
+  auto fdiv = [](int32_t a, int32_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+  std::vector<int32_t> tc((size_t)(3 * n));
+  int32_t mn[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, mx[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+  const int32_t T[3] = {kTileX, kTileY, kTileZ};
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t j = Lv.runE[(size_t)i];  // run (0, 0) starts at the stencil base
+    for (int a = 0; a < 3; ++a) {
+      const int32_t t = fdiv(Lv.idx[(size_t)(j * 3 + a)], T[a]);
+      tc[(size_t)(3 * i + a)] = t;
+      mn[a] = std::min(mn[a], t);
+      mx[a] = std::max(mx[a], t);
+    }
+  }
+  const uint64_t NX = (uint64_t)(mx[0] - mn[0] + 1), NY = (uint64_t)(mx[1] - mn[1] + 1);
+  std::vector<std::pair<uint64_t, int32_t>> key((size_t)n);
+#pragma omp parallel for
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t k = ((uint64_t)(tc[(size_t)(3 * i + 2)] - mn[2]) * NY + (uint64_t)(tc[(size_t)(3 * i + 1)] - mn[1])) * NX +
+                       (uint64_t)(tc[(size_t)(3 * i)] - mn[0]);
+    key[(size_t)i] = {k, (int32_t)i};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int64_t> first;  // first slot of every tile
+  for (int64_t k = 0; k < n; ++k)
+    if (k == 0 || key[(size_t)k].first != key[(size_t)(k - 1)].first) first.push_back(k);
+  const int64_t nt = (int64_t)first.size();
+  first.push_back(n);
+  Lv.tileSlot.resize((size_t)nt + 1);
+  Lv.tileOrg.resize((size_t)(3 * nt));
+  Lv.tileRow.assign((size_t)(2 * kBoxRows * nt), 0);
+  Lv.tperm.resize((size_t)n);
+  Lv.tloc.resize((size_t)n);
+  Lv.fracT.resize((size_t)(3 * n));
+  bool ok = true;
+#pragma omp parallel for schedule(dynamic, 64) reduction(&& : ok)
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t k0 = first[(size_t)t], k1 = first[(size_t)t + 1];
+    const int32_t i0 = key[(size_t)k0].second;
+    int32_t o[3];
+    for (int a = 0; a < 3; ++a) o[a] = tc[(size_t)(3 * i0 + a)] * T[a] - 1;
+    Lv.tileSlot[(size_t)t] = (int32_t)k0;
+    for (int a = 0; a < 3; ++a) Lv.tileOrg[(size_t)(3 * t + a)] = o[a];
+    for (int r = 0; r < kBoxRows; ++r) {
+      const int64_t y = (int64_t)o[1] + r % kBoxY, z = (int64_t)o[2] + r / kBoxY;
+      int32_t first = -1, prev = -1;
+      uint32_t mask = 0;
+      for (int x = 0; x < kBoxX; ++x) {
+        const int32_t j = lookup(Lv, (int64_t)o[0] + x, y, z);
+        if (j < 0) continue;
+        if (first < 0) first = j;
+        else if (j != prev + 1) ok = false;  // in-band nodes of a grid row are consecutive entries
+        prev = j;
+        mask |= 1u << x;
+      }
+      int32_t* row = &Lv.tileRow[(size_t)(2 * (t * kBoxRows + r))];
+      row[0] = first < 0 ? 0 : first;
+      row[1] = (int32_t)mask;
+    }
+    for (int64_t k = k0; k < k1; ++k) {
+      const int32_t i = key[(size_t)k].second;
+      const int32_t jb = Lv.runE[(size_t)i];
+      int32_t loc = 0;
+      bool inbox = true;
+      for (int a = 0; a < 3; ++a) {
+        const int32_t lb = Lv.idx[(size_t)(jb * 3 + a)] - (o[a] + 1);  // base within the tile
+        const int32_t c = Lv.idx[(size_t)(i * 3 + a)] - o[a];       // own cell in the box
+        const int32_t ext = a == 0 ? kBoxX : (a == 1 ? kBoxY : kBoxZ);
+        if (lb < 0 || lb >= T[a]) ok = false;
+        inbox = inbox && c >= 0 && c < ext;
+        loc |= (lb & 31) << (5 * a);
+        loc |= (inbox ? (c & 31) : 0) << (15 + 5 * a);
+      }
+      if (!inbox) loc &= (1 << 15) - 1;
+      if (inbox) loc |= 1 << 30;
+      Lv.tperm[(size_t)k] = i;
+      Lv.tloc[(size_t)k] = loc;
+      for (int a = 0; a < 3; ++a) Lv.fracT[(size_t)(a * n + k)] = Lv.fracE[(size_t)(a * n + i)];
+    }
+  }
+  Lv.tileSlot[(size_t)nt] = (int32_t)n;
+  if (!ok) {
+    std::vector<int32_t>().swap(Lv.tileSlot);
+    std::vector<int32_t>().swap(Lv.tileOrg);
+    std::vector<int32_t>().swap(Lv.tileRow);
+    std::vector<int32_t>().swap(Lv.tperm);
+    std::vector<int32_t>().swap(Lv.tloc);
+    std::vector<double>().swap(Lv.fracT);
+    return;
+  }
+  Lv.ntiles = nt;
+}
+
 }  // namespace
+
+// Reach of the surface (Sec. 2.1: the closest point is unique within it): the radius for a
+// circle or sphere, min(r, R - r) for a torus (tube-centre circle and axis); for Dziuk's
+// surface the smallest radius of curvature over the fixed surface samples, 1 / max |kappa|
+// with the principal curvatures of the level set phi from its Hessian projected on the
+// tangent plane (a local bound: the reach is no larger).
+double surface_reach(const cpm_surface& s) {
+  if (s.kind == CPM_CIRCLE || s.kind == CPM_SPHERE) return s.R;
+  if (s.kind == CPM_TORUS) return std::min(s.r, s.R - s.r);
+  const std::vector<double>& S = dziuk_samples();
+  double kmax = 0.0;
+  for (size_t k = 0; k < S.size() / 3; ++k) {
+    const double x1 = S[3 * k], x2 = S[3 * k + 1], x3 = S[3 * k + 2];
+    const double p = x1 - x3 * x3;
+    const double g[3] = {2.0 * p, 2.0 * x2, 2.0 * x3 - 4.0 * x3 * p};
+    const double H[3][3] = {{2.0, 0.0, -4.0 * x3}, {0.0, 2.0, 0.0}, {-4.0 * x3, 0.0, (2.0 - 4.0 * p) + 8.0 * x3 * x3}};
+    const double gn = std::sqrt((g[0] * g[0] + g[1] * g[1]) + g[2] * g[2]);
+    const double n[3] = {g[0] / gn, g[1] / gn, g[2] / gn};
+    // shape operator P H P / |grad phi|, P = I - n n^T; its eigenvalues are 0 (along n) and
+    // the two principal curvatures
+    double P[3][3], PH[3][3], W[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) P[i][j] = (i == j ? 1.0 : 0.0) - n[i] * n[j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        PH[i][j] = 0.0;
+        for (int q = 0; q < 3; ++q) PH[i][j] += P[i][q] * H[q][j];
+      }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        W[i][j] = 0.0;
+        for (int q = 0; q < 3; ++q) W[i][j] += PH[i][q] * P[q][j];
+        W[i][j] /= gn;
+      }
+    // the two non-zero eigenvalues: trace and the sum of principal 2x2 minors
+    const double tr = W[0][0] + W[1][1] + W[2][2];
+    const double m2 = (W[0][0] * W[1][1] - W[0][1] * W[1][0]) + (W[0][0] * W[2][2] - W[0][2] * W[2][0]) +
+                      (W[1][1] * W[2][2] - W[1][2] * W[2][1]);
+    const double disc = std::sqrt(std::max(0.0, tr * tr - 4.0 * m2));
+    kmax = std::max(kmax, std::max(std::fabs(0.5 * (tr + disc)), std::fabs(0.5 * (tr - disc))));
+  }
+  return kmax > 0.0 ? 1.0 / kmax : std::numeric_limits<double>::infinity();
+}
+
+// Threads of the calling thread's OpenMP parallel regions (a batch of bands is built by
+// several host threads at once, each single-threaded inside).
+void set_host_build_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 cpm_status build_host_levels(const cpm_surface& s, const cpm_grid& g, int dim,
                              std::vector<HostLevel>& levels, std::string& err) {
@@ -915,6 +1094,7 @@ cpm_status build_host_levels(const cpm_surface& s, const cpm_grid& g, int dim,
   for (int l = 0; l < L; ++l) {
     cpm_status st = build_stencil_order(levels[(size_t)l], l, err);
     if (st != CPM_OK) return st;
+    build_tiles(levels[(size_t)l]);
     if (l < 2 && (st = build_patches(levels[(size_t)l], l, err)) != CPM_OK) return st;
   }
   for (int l = 0; l + 1 < L; ++l) {

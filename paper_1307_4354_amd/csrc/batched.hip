@@ -226,10 +226,11 @@ __global__ __launch_bounds__(kMaxBlock) void kb_top(const TopItem* __restrict__ 
   }
 }
 
-// per problem: relres = nrm / bnorm, history, stopping decision, clear nrm for the next cycle
+// per problem: relres = nrm / bnorm, history, stopping decision, clear nrm for the next cycle.
+// done[p]: 1 converged (or E f = 0), 2 diverged, 3 stopped at max_cycles.
 __global__ void kb_finalize(int nprob, unsigned long long* __restrict__ slots, int* __restrict__ done,
                             int* __restrict__ cycles, double* __restrict__ hist, int hcap, int count, double rtol,
-                            int* __restrict__ ndone) {
+                            int max_cycles, int* __restrict__ ndone) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nprob || done[p]) return;
   const double num = __longlong_as_double((long long)slots[2 * p]);
@@ -243,13 +244,31 @@ __global__ void kb_finalize(int nprob, unsigned long long* __restrict__ slots, i
   }
   slots[2 * p] = 0ull;
   const bool bad = !(rel == rel) || rel > 1e300;
-  if (rel < rtol || bad) {
-    done[p] = bad ? 2 : 1;
+  if (rel < rtol || bad || c >= max_cycles) {
+    done[p] = bad ? 2 : (rel < rtol ? 1 : 3);
     atomicAdd(ndone, 1);
   }
 }
 
+// E f = 0: the problem's solution is u = 0 (its prologue marked it done with relres 0)
+template <int D>
+__global__ __launch_bounds__(kMaxBlock) void kb_zero_trivial(const TopItem* __restrict__ it,
+                                                             const int64_t* __restrict__ pre, int ni,
+                                                             const unsigned long long* __restrict__ slots) {
+  const int64_t total = pre[ni];
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int q = find_item(pre, ni, t);
+    const TopItem& B = it[q];
+    if (slots[2 * B.prob + 1] != 0ull) continue;
+    const int64_t k = (t - pre[q]) * blockDim.x + threadIdx.x;
+    if (k < B.n) B.u[k] = 0.0;
+  }
+}
+
 inline int64_t tiles(int64_t n, int per) { return (n + per - 1) / per; }
+
+// batched cycles captured in one graph (one host synchronization per graph launch)
+constexpr int kBatchCycles = 8;
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -665,7 +684,7 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
   };
   auto finalize = [&](int count, hipStream_t st2) {
     kb_finalize<<<(nprob + 255) / 256, 256, 0, st2>>>(nprob, slots, done, cyc, hist, CPM_MAX_HISTORY, count, rtol,
-                                                     ndone);
+                                                     max_cycles, ndone);
   };
   auto transfer = [&](const DevPhase& ph, int restrict_, hipStream_t st2) {
     if (!ph.ni) return;
@@ -716,13 +735,22 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
     top(1, st2);  // r -> b32, norms
     finalize(1, st2);
   };
-  // ---- prologue: ||E f|| and the first residual per problem
+  // ---- prologue: ||E f|| and the first residual per problem; u = 0 where E f = 0
   top(4, s);
   top(0, s);
   top(1, s);
   finalize(0, s);
+  {
+    const TopItem* it = (const TopItem*)S.top_n.items;
+    if (dim == 2)
+      kb_zero_trivial<2><<<grid(S.top_n.total, gm), bs, 0, s>>>(it, S.top_n.pre, S.top_n.ni, slots);
+    else
+      kb_zero_trivial<3><<<grid(S.top_n.total, gm), bs, 0, s>>>(it, S.top_n.pre, S.top_n.ni, slots);
+  }
   if ((st = check_launch("cpm_solve_batched prologue")) != CPM_OK) return st;
-  // ---- capture one batched cycle
+  // ---- capture kBatchCycles batched cycles in one graph: problems that converge (or reach
+  // max_cycles) inside it are skipped by every later kernel through their done flag, so the
+  // host reads the count of finished problems once per graph launch
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // captured on the private stream (the caller's may be the legacy default stream),
@@ -731,7 +759,7 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
     set_error("hipStreamBeginCapture failed");
     return CPM_E_HIP;
   }
-  cycle(b0->own);
+  for (int j = 0; j < kBatchCycles; ++j) cycle(b0->own);
   if (hipStreamEndCapture(b0->own, &graph) != hipSuccess || !graph ||
       hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
@@ -740,7 +768,7 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
   }
   (void)hipGraphDestroy(graph);
   int* hnd = (int*)b0->hpinned;
-  int k = 0;
+  int launches = 0, syncs = 0;
   st = CPM_OK;
   while (true) {
     if (hipMemcpyAsync(hnd, ndone, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -749,13 +777,16 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
       set_error("batched solve: synchronization failed");
       break;
     }
-    if (*hnd >= nprob || k >= max_cycles) break;
+    ++syncs;
+    // every launch advances each unfinished problem by kBatchCycles cycles, and finalize stops
+    // a problem at max_cycles, so the loop ends after at most ceil(max_cycles / kBatchCycles)
+    if (*hnd >= nprob || (int64_t)launches * kBatchCycles >= max_cycles) break;
     if (hipGraphLaunch(exec, s) != hipSuccess) {
       st = CPM_E_HIP;
       set_error("batched solve: graph launch failed");
       break;
     }
-    ++k;
+    ++launches;
   }
   (void)hipGraphExecDestroy(exec);
   if (st != CPM_OK) return st;
@@ -783,6 +814,8 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
       S2.seconds = secs;
       S2.tile_block = bs;
       S2.tile_blocks_per_cu = gm;
+      S2.host_syncs = syncs;
+      S2.cycles_per_launch = kBatchCycles;
     }
   }
   if (st == CPM_E_NOCONV) set_error("some problems did not reach the tolerance");

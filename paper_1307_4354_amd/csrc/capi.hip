@@ -3,6 +3,8 @@
 // refinement, solve loops (eager or as captured HIP graphs).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdlib>
 #include <cmath>
@@ -10,6 +12,7 @@
 #include <map>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "capi_internal.h"
@@ -44,6 +47,7 @@ LaunchCfg level_cfg(const DevLevel& D) {
 LaunchCfg ext_cfg(const DevLevel& D) {
   LaunchCfg c;
   c.block = D.ext_block;
+  c.prefetch = D.ext_prefetch ? 1 : 0;
   return c;
 }
 
@@ -53,11 +57,30 @@ LaunchCfg sweep_cfg(const DevLevel& D) {
   return c;
 }
 
-template <typename T>
-static T* dalloc(size_t count, cpm_status* st) {
-  if (count == 0) return nullptr;
+// Device allocations of a band go through the allocator registered when it was built
+// (cpm_set_allocator; hipMalloc / hipFree by default).
+static cpm::DeviceAllocator g_allocator{};
+
+void* dev_alloc(const cpm_band b, size_t bytes) {
+  if (bytes == 0) return nullptr;
+  if (b->allocator.alloc) return b->allocator.alloc(b->allocator.ctx, bytes);
   void* p = nullptr;
-  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+  return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+
+void dev_free(const cpm_band b, void* p) {
+  if (!p) return;
+  if (b->allocator.free)
+    b->allocator.free(b->allocator.ctx, p);
+  else
+    (void)hipFree(p);
+}
+
+template <typename T>
+static T* dalloc(const cpm_band b, size_t count, cpm_status* st) {
+  if (count == 0) return nullptr;
+  void* p = dev_alloc(b, count * sizeof(T));
+  if (!p) {
     *st = CPM_E_NOMEM;
     return nullptr;
   }
@@ -65,23 +88,23 @@ static T* dalloc(size_t count, cpm_status* st) {
 }
 
 template <typename T>
-static cpm_status upload(T** dst, const std::vector<T>& src) {
+static cpm_status upload(const cpm_band b, T** dst, const std::vector<T>& src) {
   if (src.empty()) {
     *dst = nullptr;
     return CPM_OK;
   }
   cpm_status st = CPM_OK;
-  *dst = dalloc<T>(src.size(), &st);
+  *dst = dalloc<T>(b, src.size(), &st);
   if (st != CPM_OK) return st;
   if (hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
     return CPM_E_HIP;
   return CPM_OK;
 }
 
-static cpm_status upload_f32(float** dst, const std::vector<double>& src) {
+static cpm_status upload_f32(const cpm_band b, float** dst, const std::vector<double>& src) {
   std::vector<float> tmp(src.size());
   for (size_t i = 0; i < src.size(); ++i) tmp[i] = (float)src[i];
-  return upload(dst, tmp);
+  return upload(b, dst, tmp);
 }
 
 static void free_dev(cpm_band b) {
@@ -89,17 +112,17 @@ static void free_dev(cpm_band b) {
     void* ps[] = {D.runE,  D.nbr,   D.fracE,  D.fracE32, D.runP,    D.fracP,  D.fracP32, D.runR,
                   D.fracR, D.fracR32, D.perm, D.packed, D.origin, D.fracK, D.fracK32, D.ilist, D.nbrI,
                   D.patchRow, D.patchPk, D.patchMask, D.packedB, D.packedL, D.blkE, D.gidx, D.blkG, D.lorg, D.originX,
-                  D.qdiag, D.wd, D.acoef, D.vcD, D.runP3, D.fracP3, D.blkE2, D.gidx2, D.lorg2};
-    for (void* p : ps)
-      if (p) (void)hipFree(p);
+                  D.qdiag, D.wd, D.acoef, D.vcD, D.runP3, D.fracP3, D.blkE2, D.gidx2, D.lorg2,
+                  D.tileSlot, D.tileRow, D.tperm, D.tloc, D.fracT, D.fracT32, D.parity, D.wdR, D.wdB, D.q1diag, D.wd1};
+    for (void* p : ps) dev_free(b, p);
   }
   b->dev.clear();
-  void* ps[] = {b->coarseM, b->coarseS, b->gj_col, b->gj_info, b->dscal, b->dcounter, b->dhist, b->mlpW};
+  void* ps[] = {b->coarseM, b->coarseS, b->coarseS1, b->gj_col, b->gj_info, b->dscal, b->dcounter, b->dhist, b->mlpW};
   b->mlpW = nullptr;
-  for (void* p : ps)
-    if (p) (void)hipFree(p);
+  for (void* p : ps) dev_free(b, p);
   b->coarseM = nullptr;
   b->coarseS = nullptr;
+  b->coarseS1 = nullptr;
   if (b->hpinned) (void)hipHostFree(b->hpinned);
   b->hpinned = nullptr;
   for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -142,7 +165,10 @@ cpm_status check_launch(const char* what) {
 // Ruuth-Merriman cycles) or on [A_c | I] (-> A_c^{-1}, the standard relaxation).
 static cpm_status ensure_vc_diag(cpm_band b, double c);
 
-static cpm_status coarse_inverse(cpm_band b, double c, bool identity_rhs, double** M, double* cached_c) {
+// kind: 0 [A_c | E_c] (Ruuth-Merriman cycles), 1 [A_c | I] (standard relaxation), 2 [A_c | I]
+// for Remark 3.2's operator (linear interpolation in front of L)
+static cpm_status coarse_inverse(cpm_band b, double c, int kind, double** M, double* cached_c) {
+  const bool identity_rhs = kind != 0;
   if (*M && *cached_c == c) return CPM_OK;
   const int l = b->L - 1;
   const DevLevel& D = b->dev[(size_t)l];
@@ -155,16 +181,19 @@ static cpm_status coarse_inverse(cpm_band b, double c, bool identity_rhs, double
     return CPM_E_INVALID;
   }
   cpm_status st = CPM_OK;
-  if (!*M) *M = dalloc<double>((size_t)2 * n * n, &st);
-  if (!b->gj_col) b->gj_col = dalloc<double>((size_t)n, &st);
-  if (!b->gj_info) b->gj_info = dalloc<int>(1, &st);
+  if (!*M) *M = dalloc<double>(b, (size_t)2 * n * n, &st);
+  if (!b->gj_col) b->gj_col = dalloc<double>(b, (size_t)n, &st);
+  if (!b->gj_info) b->gj_info = dalloc<int>(b, 1, &st);
   if (st != CPM_OK) {
     set_error("device allocation of the coarse matrix failed");
     return st;
   }
   hipStream_t s = b->stream;
   const double h = D.h;
-  if (b->vc_active && !identity_rhs) {
+  if (kind == 2) {
+    launch_assemble_coarse_p1(b->dim, n, D.runE, D.fracE, D.nbr, level_delta(b, l, c), 2.0 * b->dim / (h * h),
+                              1.0 / (h * h), *M, s);
+  } else if (b->vc_active && !identity_rhs) {
     // variable coefficient: [I - E D^{-1} N~ | E D^{-1}]
     if ((st = ensure_vc_diag(b, c)) != CPM_OK) return st;
     launch_assemble_coarse_vc(b->dim, n, D.runE, D.fracE, D.nbr, D.acoef, D.vcD, 1.0 / (h * h), *M, s);
@@ -190,7 +219,7 @@ static cpm_status coarse_inverse(cpm_band b, double c, bool identity_rhs, double
   return CPM_OK;
 }
 
-cpm_status ensure_coarse(cpm_band b, double c) { return coarse_inverse(b, c, false, &b->coarseM, &b->coarse_c); }
+cpm_status ensure_coarse(cpm_band b, double c) { return coarse_inverse(b, c, 0, &b->coarseM, &b->coarse_c); }
 
 // Variable coefficient: D = c + sigma on every level for this c.
 static cpm_status ensure_vc_diag(cpm_band b, double c) {
@@ -198,7 +227,7 @@ static cpm_status ensure_vc_diag(cpm_band b, double c) {
   cpm_status st = CPM_OK;
   for (int l = 0; l < b->L; ++l) {
     DevLevel& D = b->dev[(size_t)l];
-    if (!D.vcD && !(D.vcD = dalloc<double>((size_t)D.n, &st))) {
+    if (!D.vcD && !(D.vcD = dalloc<double>(b, (size_t)D.n, &st))) {
       set_error("device allocation of the variable-coefficient diagonal failed");
       return st != CPM_OK ? st : CPM_E_NOMEM;
     }
@@ -209,22 +238,62 @@ static cpm_status ensure_vc_diag(cpm_band b, double c) {
   return CPM_OK;
 }
 
-// Standard relaxation: A_c^{-1} and omega / diag(A) on every level for (c, omega).
-static cpm_status ensure_std(cpm_band b, double c, double omega) {
-  cpm_status st = coarse_inverse(b, c, true, &b->coarseS, &b->coarse_std_c);
+// Standard relaxation: A_c^{-1} and omega / diag(A) on every level for (c, omega); for the
+// red-black sweeps also the two half-sweeps' factors (omega / diag(A) on one colour, 0 on the
+// other; colours by the parity of the grid index sum).
+static cpm_status ensure_std(cpm_band b, const cpm_params& p) {
+  const double c = p.c, omega = p.omega;
+  const bool rb = p.smoother == CPM_SMOOTH_STANDARD_RB;
+  const int el = p.el_degree == 1 ? 1 : 3;
+  cpm_status st = el == 1 ? coarse_inverse(b, c, 2, &b->coarseS1, &b->coarse_std1_c)
+                          : coarse_inverse(b, c, 1, &b->coarseS, &b->coarse_std_c);
   if (st != CPM_OK) return st;
-  if (b->std_c == c && b->std_omega == omega) return CPM_OK;
+  if (b->std_c == c && b->std_omega == omega && b->std_el == el && (!rb || b->std_rb)) return CPM_OK;
   for (int l = 0; l < b->L; ++l) {
     DevLevel& D = b->dev[(size_t)l];
-    if (!D.wd && !(D.wd = dalloc<double>((size_t)D.n, &st))) {
+    if (!D.wd && !(D.wd = dalloc<double>(b, (size_t)D.n, &st))) {
       set_error("device allocation of the relaxation weights failed");
       return st != CPM_OK ? st : CPM_E_NOMEM;
     }
-    launch_std_scale(D.n, D.qdiag, level_delta(b, l, c), omega, D.wd, b->stream);
+    launch_std_scale(D.n, el == 1 ? D.q1diag : D.qdiag, level_delta(b, l, c), omega, D.wd, b->stream);
+    if (!rb) continue;
+    if (!D.parity) {
+      const HostLevel& H = b->host[(size_t)l];
+      std::vector<uint8_t> par((size_t)D.n);
+      for (int64_t i = 0; i < D.n; ++i) {
+        int64_t sum = 0;
+        for (int a = 0; a < b->dim; ++a) sum += H.idx[(size_t)(i * b->dim + a)];
+        par[(size_t)i] = (uint8_t)(sum & 1);
+      }
+      if ((st = upload(b, &D.parity, par)) != CPM_OK) return st;
+    }
+    if ((!D.wdR && !(D.wdR = dalloc<double>(b, (size_t)D.n, &st))) ||
+        (!D.wdB && !(D.wdB = dalloc<double>(b, (size_t)D.n, &st)))) {
+      set_error("device allocation of the relaxation weights failed");
+      return st != CPM_OK ? st : CPM_E_NOMEM;
+    }
+    launch_split_colours(D.n, D.wd, D.parity, D.wdR, D.wdB, b->stream);
   }
   if ((st = check_launch("relaxation weights")) != CPM_OK) return st;
   b->std_c = c;
   b->std_omega = omega;
+  b->std_rb = rb;  // the half-sweep factors match (c, omega) only when just recomputed
+  b->std_el = el;
+  return CPM_OK;
+}
+
+// Verbatim residual (Algorithm 4.1 step 2 as printed): A_c^{-1} on the coarsest level and
+// every level's full neighbour table.
+static cpm_status ensure_verbatim(cpm_band b, double c) {
+  cpm_status st = coarse_inverse(b, c, 1, &b->coarseS, &b->coarse_std_c);
+  if (st != CPM_OK) return st;
+  for (int l = 0; l + 1 < b->L; ++l) {
+    DevLevel& D = b->dev[(size_t)l];
+    if (!D.nbr && (st = upload(b, &D.nbr, b->host[(size_t)l].nbr)) != CPM_OK) {
+      set_error("upload of the neighbour table failed");
+      return st;
+    }
+  }
   return CPM_OK;
 }
 
@@ -316,6 +385,19 @@ SweepAddr sweep_addr(const DevLevel& D) {
   }
   return a;
 }
+TileAddr tile_addr(const DevLevel& D) { return TileAddr{D.tileSlot, D.tileRow, D.tperm, D.tloc, D.ntiles}; }
+template <typename T>
+static const T* fracT_of(const DevLevel& D);
+template <>
+const double* fracT_of<double>(const DevLevel& D) { return D.fracT; }
+template <>
+const float* fracT_of<float>(const DevLevel& D) { return D.fracT32; }
+static bool tiled(const DevLevel& D) { return D.use_tile && D.ntiles > 0; }
+// the standard relaxation (Sec. 4.5), with Jacobi or red-black Gauss-Seidel sweeps
+static bool standard(const cpm_params& p) {
+  return p.smoother == CPM_SMOOTH_STANDARD || p.smoother == CPM_SMOOTH_STANDARD_RB;
+}
+
 template <typename T>
 static const T* fracK_of(const DevLevel& D);
 template <>
@@ -430,6 +512,51 @@ static void fused_post(const cpm_band b, int l, LevelBufs<T>* B, T* cur, const T
   if (cur != B[l].u) launch_copy<T>(D.n, cur, B[l].u, s);
 }
 
+// The level's smoothing and residual with the tiled pass (f + N u formed in LDS per tile, then
+// the extension, one launch per sweep), alternating between u and t.  r_first: the first
+// sweep is u += (omega/delta) r_first (the residual of the entering u, bit for bit what the
+// tiled residual pass computes); u_zero with an A-space right-hand side: u = (omega/delta) b.
+// Returns the vector holding the iterate; the residual is left in B[l].r.
+template <typename T>
+static T* tile_pre(const cpm_band b, int l, LevelBufs<T>* B, const T* f, const T* rhsA, const cpm_params& p, int nu,
+                   bool u_zero, const T* r_first, hipStream_t s) {
+  const DevLevel& D = b->dev[(size_t)l];
+  const double delta = level_delta(b, l, p.c);
+  const T wod = (T)(p.omega / delta), inv_h2 = (T)(1.0 / (D.h * D.h));
+  const TileAddr ta = tile_addr(D);
+  T* cur = B[l].u;
+  T* oth = B[l].t;
+  int k0 = 0;
+  if (nu > 0 && r_first) {
+    launch_scale_add<T>(D.n, r_first, wod, cur, true, s);
+    k0 = 1;
+  } else if (nu > 0 && u_zero && rhsA && !f) {
+    launch_scale_add<T>(D.n, rhsA, wod, cur, false, s);
+    k0 = 1;
+  }
+  for (int k = k0; k < nu; ++k) {
+    launch_tile<T, T>(EXT_SMOOTH, D.n, ta, fracT_of<T>(D), cur, f, rhsA, oth, inv_h2, (T)delta, wod, nullptr, s);
+    std::swap(cur, oth);
+  }
+  launch_tile<T, T>(EXT_RESID, D.n, ta, fracT_of<T>(D), cur, f, rhsA, B[l].r, inv_h2, (T)delta, (T)0, nullptr, s);
+  return cur;
+}
+
+template <typename T>
+static void tile_post(const cpm_band b, int l, LevelBufs<T>* B, T* cur, const T* f, const T* rhsA,
+                      const cpm_params& p, int nu, hipStream_t s) {
+  const DevLevel& D = b->dev[(size_t)l];
+  const double delta = level_delta(b, l, p.c);
+  const T wod = (T)(p.omega / delta), inv_h2 = (T)(1.0 / (D.h * D.h));
+  const TileAddr ta = tile_addr(D);
+  T* oth = cur == B[l].u ? B[l].t : B[l].u;
+  for (int k = 0; k < nu; ++k) {
+    launch_tile<T, T>(EXT_SMOOTH, D.n, ta, fracT_of<T>(D), cur, f, rhsA, oth, inv_h2, (T)delta, wod, nullptr, s);
+    std::swap(cur, oth);
+  }
+  if (cur != B[l].u) launch_copy<T>(D.n, cur, B[l].u, s);
+}
+
 // r_first (finest level, split sweeps only): the residual E(f + N u) - delta u of the
 // entering iterate, already computed (the stopping test's) with the same two passes as a
 // sweep, so that the first pre-smoothing sweep is u += (omega/delta) r_first, or the learned
@@ -455,6 +582,17 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
   // u_zero: u is 0 on entry (the first visit after the restriction cleared it)
   const DevLevel& C = b->dev[(size_t)(l + 1)];
   const int visits = l + 1 == b->L - 1 ? 1 : (p.gamma > 1 ? p.gamma : 1);  // cycle index
+  if (tiled(D) && !learned_here && !b->vc_active) {
+    T* cur = tile_pre<T>(b, l, B, f, rhsA, p, nu1, u_zero, r_first, s);
+    launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
+    for (int v = 0; v < visits; ++v) vcycle_level<T>(b, l + 1, B, nullptr, p, s, v == 0);
+    // the post-smoothing alternates between u and t nu2 times: the prolongation writes
+    // u + P e into the buffer from which the last sweep lands in u
+    T* start = nu2 % 2 == 0 ? B[l].u : B[l].t;
+    launch_prolong<T>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<T>(D), start, lc, s, cur);
+    tile_post<T>(b, l, B, start, f, rhsA, p, nu2, s);
+    return;
+  }
   if (D.fused && D.fusedOK && !learned_here && !b->vc_active) {
     T* cur = fused_pre<T>(b, l, B, f, rhsA, p, nu1, u_zero, s);
     launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
@@ -504,33 +642,85 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
   for (int k = 0; k < nu2; ++k) smooth_sweep<T>(b, l, B[l].u, f, rhsA, B[l].g, B[l].r, p.c, p.omega, nullptr, s);
 }
 
-// V-cycle with the standard relaxation (Sec. 4.5): Jacobi on A_l e = f_l in steps 1 and 4,
-// u <- u + (omega / diag(A)) (f - A u) with f - A u = f + E(N u) - delta u, and the residual
-// r = f - A (E u) passed to the coarse grid; the coarsest level is solved with A_c^{-1}.
-static void vcycle_std(const cpm_band b, int l, LevelBufs<double>* B, const cpm_params& p, hipStream_t s) {
+// V-cycle with the residual of Algorithm 4.1 step 2 as printed: the Ruuth-Merriman sweeps of
+// the consistent cycle (two passes), r = f + N u - delta u at every node restricted to the
+// coarse grid, and A_c e = f_c solved with A_c^{-1} on the coarsest level.
+static void vcycle_verbatim(const cpm_band b, int l, LevelBufs<double>* B, const cpm_params& p, hipStream_t s,
+                            bool u_zero) {
   const DevLevel& D = b->dev[(size_t)l];
   if (l == b->L - 1) {
     launch_coarse_gemv<double>((int)D.n, b->coarseS + D.n, 2 * D.n, B[l].f, B[l].u, s);
     return;
   }
   const LaunchCfg lc = level_cfg(D);
-  const double delta = level_delta(b, l, p.c), inv_h2 = 1.0 / (D.h * D.h);
-  auto sweep = [&] {
-    launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, B[l].u, nullptr, inv_h2, B[l].g, nullptr, lc, s);
-    launch_ext<double, double>(b->dim, EXT_SMOOTH, D.n, B[l].g, ext_addr(D), fracK_of<double>(D), B[l].f, B[l].u,
-                               (double*)nullptr, delta, 0.0, nullptr, ext_cfg(D), s, D.wd);
-  };
-  for (int k = 0; k < p.nu1; ++k) sweep();
-  // r = f - A (E u): v = E u into t, then r = f + E(N v) - delta v
-  launch_ext<double, double>(b->dim, EXT_PLAIN, D.n, B[l].u, ext_addr(D), fracK_of<double>(D), nullptr, nullptr,
-                             B[l].t, 0.0, 0.0, nullptr, ext_cfg(D), s);
-  launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, B[l].t, nullptr, inv_h2, B[l].g, nullptr, lc, s);
-  launch_ext<double, double>(b->dim, EXT_RESID, D.n, B[l].g, ext_addr(D), fracK_of<double>(D), B[l].f, B[l].t,
-                             B[l].r, delta, 0.0, nullptr, ext_cfg(D), s);
+  for (int k = 0; k < p.nu1; ++k)
+    smooth_sweep<double>(b, l, B[l].u, B[l].f, nullptr, B[l].g, B[l].r, p.c, p.omega, nullptr, s, u_zero && k == 0);
+  launch_resid_verbatim(b->dim, D.n, D.nbr, B[l].u, B[l].f, level_delta(b, l, p.c), 1.0 / (D.h * D.h), B[l].r, s);
   const DevLevel& C = b->dev[(size_t)(l + 1)];
   launch_restrict<double>(b->dim, C.n, B[l].r, C.runR, fracR_of<double>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
   const int visits = l + 1 == b->L - 1 ? 1 : (p.gamma > 1 ? p.gamma : 1);
-  for (int v = 0; v < visits; ++v) vcycle_std(b, l + 1, B, p, s);
+  for (int v = 0; v < visits; ++v) vcycle_verbatim(b, l + 1, B, p, s, v == 0);
+  launch_prolong<double>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<double>(D), B[l].u, lc, s);
+  for (int k = 0; k < p.nu2; ++k)
+    smooth_sweep<double>(b, l, B[l].u, B[l].f, nullptr, B[l].g, B[l].r, p.c, p.omega, nullptr, s);
+}
+
+// V-cycle with the standard relaxation (Sec. 4.5): Jacobi on A_l e = f_l in steps 1 and 4,
+// u <- u + (omega / diag(A)) (f - A u) with f - A u = f + E(N u) - delta u (or its red-black
+// Gauss-Seidel ordering), the residual r = f - A (E u) passed to the coarse grid (the plain
+// f - A u with CPM_RESIDUAL_VERBATIM); the coarsest level is solved with A_c^{-1}.  With
+// el_degree 1 the operator is Remark 3.2's A = delta I - E_1 N + gamma (E_1 - E_3), whose
+// sweeps read u at the stencil nodes and so write into t first.
+static void vcycle_std(const cpm_band b, int l, LevelBufs<double>* B, const cpm_params& p, hipStream_t s) {
+  const DevLevel& D = b->dev[(size_t)l];
+  const bool el1 = p.el_degree == 1;
+  if (l == b->L - 1) {
+    const double* Z = el1 ? b->coarseS1 : b->coarseS;
+    launch_coarse_gemv<double>((int)D.n, Z + D.n, 2 * D.n, B[l].f, B[l].u, s);
+    return;
+  }
+  const LaunchCfg lc = level_cfg(D);
+  const double delta = level_delta(b, l, p.c), inv_h2 = 1.0 / (D.h * D.h), gamma = 2.0 * b->dim * inv_h2;
+  const ExtAddr ea{D.perm, D.packed, D.origin};
+  // one Jacobi sweep, or the red then the black half-sweep (the cubic-E extension pass updates
+  // only the node it visits, so each half-sweep is in place; the black one reads the new reds)
+  auto half = [&](const double* wd) {
+    launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, B[l].u, nullptr, inv_h2, B[l].g, nullptr, lc, s);
+    if (el1) {
+      launch_p1(b->dim, EXT_SMOOTH, D.n, B[l].g, B[l].u, ea, D.fracK, B[l].f, wd, B[l].t, delta, gamma, ext_cfg(D),
+                s);
+      launch_copy<double>(D.n, B[l].t, B[l].u, s);
+    } else {
+      launch_ext<double, double>(b->dim, EXT_SMOOTH, D.n, B[l].g, ext_addr(D), fracK_of<double>(D), B[l].f, B[l].u,
+                                 (double*)nullptr, delta, 0.0, nullptr, ext_cfg(D), s, wd);
+    }
+  };
+  auto sweep = [&] {
+    if (p.smoother == CPM_SMOOTH_STANDARD_RB) {
+      half(D.wdR);
+      half(D.wdB);
+    } else {
+      half(D.wd);
+    }
+  };
+  for (int k = 0; k < p.nu1; ++k) sweep();
+  // r = f - A v with v = E u (into t), or v = u for the plain residual
+  const double* v = B[l].u;
+  if (p.residual_mode != CPM_RESIDUAL_VERBATIM) {
+    launch_ext<double, double>(b->dim, EXT_PLAIN, D.n, B[l].u, ext_addr(D), fracK_of<double>(D), nullptr, nullptr,
+                               B[l].t, 0.0, 0.0, nullptr, ext_cfg(D), s);
+    v = B[l].t;
+  }
+  launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, v, nullptr, inv_h2, B[l].g, nullptr, lc, s);
+  if (el1)
+    launch_p1(b->dim, EXT_RESID, D.n, B[l].g, v, ea, D.fracK, B[l].f, nullptr, B[l].r, delta, gamma, ext_cfg(D), s);
+  else
+    launch_ext<double, double>(b->dim, EXT_RESID, D.n, B[l].g, ext_addr(D), fracK_of<double>(D), B[l].f,
+                               const_cast<double*>(v), B[l].r, delta, 0.0, nullptr, ext_cfg(D), s);
+  const DevLevel& C = b->dev[(size_t)(l + 1)];
+  launch_restrict<double>(b->dim, C.n, B[l].r, C.runR, fracR_of<double>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
+  const int visits = l + 1 == b->L - 1 ? 1 : (p.gamma > 1 ? p.gamma : 1);
+  for (int vv = 0; vv < visits; ++vv) vcycle_std(b, l + 1, B, p, s);
   launch_prolong<double>(b->dim, D.n, B[l + 1].u, D.runP, fracP_of<double>(D), B[l].u, lc, s);
   for (int k = 0; k < p.nu2; ++k) sweep();
 }
@@ -591,6 +781,16 @@ void enqueue_resid64(const cpm_band b, const double* f, const double* u, double*
                               const_cast<double*>(u), r32, 1.0, 0.0, b->dscal, ext_cfg(D), s, D.vcD);
     return;
   }
+  if (tiled(D)) {
+    launch_zero_u64(b->dscal, 1, s);
+    if (r64)
+      launch_tile<double, double>(EXT_RESID, D.n, tile_addr(D), D.fracT, u, f, nullptr, r64, 1.0 / (D.h * D.h),
+                                  level_delta(b, 0, c), 0.0, b->dscal, s);
+    else
+      launch_tile<double, float>(EXT_RESID, D.n, tile_addr(D), D.fracT, u, f, nullptr, r32, 1.0 / (D.h * D.h),
+                                 level_delta(b, 0, c), 0.0, b->dscal, s);
+    return;
+  }
   launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, u, f, 1.0 / (D.h * D.h), g, b->dscal, lc, s);
   if (r64)
     launch_ext<double, double>(b->dim, EXT_RESID, D.n, g, ext_addr(D), fracK_of<double>(D), nullptr,
@@ -606,10 +806,12 @@ void enqueue_resid64(const cpm_band b, const double* f, const double* u, double*
 // Ruuth-Merriman step or the learned update (which is applied to that residual).
 static bool resid_reuse_ok(const cpm_band b, const cpm_params& p) {
   const DevLevel& D = b->dev[0];
-  if (p.precision != CPM_F64 || b->vc_active || p.smoother == CPM_SMOOTH_STANDARD) return false;
+  if (p.precision != CPM_F64 || b->vc_active || standard(p) ||
+      p.residual_mode == CPM_RESIDUAL_VERBATIM)
+    return false;
   const bool learned0 = b->learned_active && b->mlpW && D.patchRow;  // never fused
   const int nu1 = learned0 && p.learned_sweeps > 0 ? p.learned_sweeps : p.nu1;
-  return nu1 > 0 && (learned0 || !(D.fused && D.fusedOK));
+  return nu1 > 0 && (learned0 || tiled(D) || !(D.fused && D.fusedOK));
 }
 
 // One complete cycle of the solve loop on stream s, ending with the residual
@@ -618,14 +820,17 @@ static bool resid_reuse_ok(const cpm_band b, const cpm_params& p) {
 // same solve left it), so the first smoothing sweep is taken from it.
 void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, double* u, void* work, hipStream_t s,
                    bool r_ready) {
-  if (p.smoother == CPM_SMOOTH_STANDARD) {
+  if (standard(p) || p.residual_mode == CPM_RESIDUAL_VERBATIM) {
     // slot 0 = ||u_new - u_old||_inf, slot 1 = ||u_new||_inf (the paper's stopping test)
     LevelBufs<double> B[kMaxLevels];
     carve_levels<double>(b, work, B, nullptr);
     B[0].u = u;
     B[0].f = const_cast<double*>(f);
     launch_copy<double>(b->dev[0].n, u, B[0].p, s);
-    vcycle_std(b, 0, B, p, s);
+    if (standard(p))
+      vcycle_std(b, 0, B, p, s);  // verbatim: the plain residual f - A u
+    else
+      vcycle_verbatim(b, 0, B, p, s, false);
     launch_zero_u64(b->dscal, 2, s);
     launch_incr(b->dev[0].n, u, B[0].p, b->dscal, s);
     return;
@@ -655,7 +860,7 @@ void enqueue_cycle(const cpm_band b, const cpm_params& p, const double* f, doubl
 // Prologue of a solve: ||E f|| (slot 1) and, in mixed precision, the first residual.
 void enqueue_prologue(const cpm_band b, const cpm_params& p, const double* f, const double* u, void* work,
                       hipStream_t s) {
-  if (p.smoother == CPM_SMOOTH_STANDARD) {
+  if (standard(p) || p.residual_mode == CPM_RESIDUAL_VERBATIM) {
     // ||f||_inf into slot 1 (the system is A u = f)
     launch_zero_u64(b->dscal, 2, s);
     launch_incr(b->dev[0].n, f, nullptr, b->dscal, s);
@@ -693,8 +898,8 @@ static std::string graph_key(const char* tag, const cpm_params& p, const void* a
                              int extra) {
   std::ostringstream os;
   os << tag << '|' << p.c << '|' << p.nu1 << '|' << p.nu2 << '|' << p.omega << '|' << p.precision << '|'
-     << p.smoother << '|' << p.learned_sweeps << '|' << p.gamma << '|' << a << '|' << bb << '|' << c << '|'
-     << extra;
+     << p.smoother << '|' << p.learned_sweeps << '|' << p.gamma << '|' << p.residual_mode << '|' << p.el_degree << '|' << a << '|' << bb
+     << '|' << c << '|' << extra;
   return os.str();
 }
 
@@ -741,20 +946,24 @@ cpm_status graph_launch(cpm_band b, const std::string& key, Fn fn) {
 // fused from LDS, the other levels as they stand, and keep the fastest.
 cpm_status tune_sweep_forms(cpm_band b) {
   if (b->vc_active) return CPM_OK;  // variable coefficients always sweep in two passes
-  bool any = false;  // a level that could sweep either way
-  for (int l = 0; l + 1 < b->L; ++l) any = any || (b->dev[(size_t)l].fusedOK && !b->dev[(size_t)l].sweep_forced);
+  bool any = false;  // a level that could sweep more than one way
+  for (int l = 0; l + 1 < b->L; ++l) {
+    const DevLevel& D = b->dev[(size_t)l];
+    any = any || ((D.fusedOK || D.ntiles > 0) && !D.sweep_forced);
+  }
   // bands that cannot run cycles (coarsest level beyond the dense solve) keep the first stage
   if (!any || b->dev[(size_t)(b->L - 1)].n > kMaxCoarse) return CPM_OK;
   cpm_status st = ensure_coarse(b, 1.0);
   if (st != CPM_OK) return st;
   const int64_t n0 = b->dev[0].n;
   const size_t wb = workspace_bytes(b, CPM_F64);
-  double *f = nullptr, *u = nullptr;
-  void* work = nullptr;
-  if (hipMalloc((void**)&f, n0 * sizeof(double)) != hipSuccess ||
-      hipMalloc((void**)&u, n0 * sizeof(double)) != hipSuccess || hipMalloc(&work, wb) != hipSuccess) {
-    if (f) (void)hipFree(f);
-    if (u) (void)hipFree(u);
+  double* f = (double*)dev_alloc(b, n0 * sizeof(double));
+  double* u = (double*)dev_alloc(b, n0 * sizeof(double));
+  void* work = dev_alloc(b, wb);
+  if (!f || !u || !work) {
+    dev_free(b, f);
+    dev_free(b, u);
+    dev_free(b, work);
     set_error("autotune: allocation failed");
     return CPM_E_NOMEM;
   }
@@ -782,21 +991,23 @@ cpm_status tune_sweep_forms(cpm_band b) {
   };
   for (int l = 0; l < b->L - 1 && st == CPM_OK; ++l) {
     DevLevel& D = b->dev[(size_t)l];
-    if (!D.fusedOK || D.sweep_forced) continue;
+    if ((!D.fusedOK && D.ntiles <= 0) || D.sweep_forced) continue;
     for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
     b->graphs.clear();
     launch_fill<double>(n0, u, 0.0, s);
-    bool have[3] = {false, false, false};
-    for (int cand = 0; cand < 3 && st == CPM_OK; ++cand) {
-      if (cand == 2 && !D.sweep_lds) continue;
-      D.fused = cand > 0;
+    // candidates: 0 two passes, 1 fused with gathers, 2 fused from LDS, 3 tiled
+    bool have[4] = {false, false, false, false};
+    for (int cand = 0; cand < 4 && st == CPM_OK; ++cand) {
+      if ((cand == 1 && !D.fusedOK) || (cand == 2 && !D.sweep_lds) || (cand == 3 && D.ntiles <= 0)) continue;
+      D.fused = cand == 1 || cand == 2;
       D.use_sweep_lds = cand == 2;
+      D.use_tile = cand == 3;
       st = graph_launch(b, "autotune" + std::to_string(cand), body);  // capture + warm-up
       have[cand] = st == CPM_OK;
     }
-    float best[3] = {1e30f, 1e30f, 1e30f};
+    float best[4] = {1e30f, 1e30f, 1e30f, 1e30f};
     for (int round = 0; round < kRounds && st == CPM_OK; ++round)
-      for (int cand = 0; cand < 3 && st == CPM_OK; ++cand) {
+      for (int cand = 0; cand < 4 && st == CPM_OK; ++cand) {
         if (!have[cand]) continue;
         const std::string key = "autotune" + std::to_string(cand);
         (void)hipEventRecord(e0, s);
@@ -808,10 +1019,11 @@ cpm_status tune_sweep_forms(cpm_band b) {
         best[cand] = std::min(best[cand], 1000.f * ms / (kCyc * kReps));
       }
     int pick = 0;
-    for (int cand = 1; cand < 3; ++cand)
+    for (int cand = 1; cand < 4; ++cand)
       if (have[cand] && best[cand] < best[pick]) pick = cand;
-    D.fused = pick > 0;
+    D.fused = pick == 1 || pick == 2;
     D.use_sweep_lds = pick == 2;
+    D.use_tile = pick == 3;
   }
   b->learned_active = learned;
   (void)hipStreamSynchronize(s);
@@ -819,9 +1031,9 @@ cpm_status tune_sweep_forms(cpm_band b) {
   b->graphs.clear();
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  (void)hipFree(f);
-  (void)hipFree(u);
-  (void)hipFree(work);
+  dev_free(b, f);
+  dev_free(b, u);
+  dev_free(b, work);
   if (st != CPM_OK) return st;
   return check_launch("autotune (whole cycles)");
 }
@@ -844,12 +1056,31 @@ cpm_status validate_params(const cpm_band b, const cpm_params* p) {
     set_error("unknown precision");
     return CPM_E_INVALID;
   }
-  if (p->smoother != CPM_SMOOTH_JACOBI && p->smoother != CPM_SMOOTH_LEARNED && p->smoother != CPM_SMOOTH_STANDARD) {
+  if (p->smoother != CPM_SMOOTH_JACOBI && p->smoother != CPM_SMOOTH_LEARNED && p->smoother != CPM_SMOOTH_STANDARD &&
+      p->smoother != CPM_SMOOTH_STANDARD_RB) {
     set_error("unknown smoother");
     return CPM_E_INVALID;
   }
   if (b->vc_active && (p->precision != CPM_F64 || p->smoother != CPM_SMOOTH_JACOBI)) {
     set_error("a variable diffusion coefficient runs with precision CPM_F64 and smoother CPM_SMOOTH_JACOBI only");
+    return CPM_E_INVALID;
+  }
+  if (p->residual_mode != CPM_RESIDUAL_CONSISTENT && p->residual_mode != CPM_RESIDUAL_VERBATIM) {
+    set_error("unknown residual mode");
+    return CPM_E_INVALID;
+  }
+  if (p->residual_mode == CPM_RESIDUAL_VERBATIM &&
+      (p->precision != CPM_F64 || !(p->smoother == CPM_SMOOTH_JACOBI || standard(*p)) || b->vc_active || p->fmg)) {
+    set_error("the verbatim residual runs with precision CPM_F64, the Jacobi or standard-relaxation smoother, a "
+              "constant coefficient and no full-multigrid start");
+    return CPM_E_INVALID;
+  }
+  if (p->el_degree != 0 && p->el_degree != 1 && p->el_degree != 3) {
+    set_error("el_degree must be 1 or 3 (0 = 3)");
+    return CPM_E_INVALID;
+  }
+  if (p->el_degree == 1 && !standard(*p)) {
+    set_error("the linear interpolation in front of L (Remark 3.2) runs with the standard relaxation");
     return CPM_E_INVALID;
   }
   if (p->gamma < 0 || p->gamma > 4) {
@@ -864,7 +1095,7 @@ cpm_status validate_params(const cpm_band b, const cpm_params* p) {
     set_error("no full-multigrid start on this band: a cubic interpolation stencil leaves a coarser band");
     return CPM_E_INVALID;
   }
-  if (p->smoother == CPM_SMOOTH_STANDARD && p->precision != CPM_F64) {
+  if (standard(*p) && p->precision != CPM_F64) {
     set_error("the standard relaxation runs in double precision only");
     return CPM_E_INVALID;
   }
@@ -876,6 +1107,13 @@ cpm_status validate_params(const cpm_band b, const cpm_params* p) {
     set_error("learned smoother selected but no weights were set");
     return CPM_E_INVALID;
   }
+  if (p->smoother == CPM_SMOOTH_LEARNED)
+    for (int l = 0; l < 2 && l + 1 < b->L; ++l)
+      if (!b->dev[(size_t)l].patchRow) {
+        set_error("learned smoother unavailable: level " + std::to_string(l) +
+                  " has too many patch groups to address (more than 2^23)");
+        return CPM_E_INVALID;
+      }
   return CPM_OK;
 }
 
@@ -903,6 +1141,16 @@ const char* cpm_status_string(int status) {
 
 const char* cpm_last_error(void) { return cpm::g_last_error.c_str(); }
 
+cpm_status cpm_set_allocator(void* (*alloc)(void* ctx, size_t bytes), void (*release)(void* ctx, void* ptr),
+                             void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr)) {
+    set_error("cpm_set_allocator: give both functions or neither");
+    return CPM_E_INVALID;
+  }
+  g_allocator = cpm::DeviceAllocator{alloc, release, ctx};
+  return CPM_OK;
+}
+
 cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void* stream, cpm_band* out) {
   if (!surface || !grid || !out) {
     set_error("null argument");
@@ -928,6 +1176,7 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
   if (!b) return CPM_E_NOMEM;
   b->surf = *surface;
   b->grid = *grid;
+  b->allocator = g_allocator;
   b->dim = dim;
   b->L = grid->levels;
   std::string err;
@@ -954,17 +1203,17 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     D.h = H.h;
     D.m = (int64_t)H.ilist.size();
     D.ngroups = H.ngroups;
-    if (st == CPM_OK) st = upload(&D.perm, H.perm);
-    if (st == CPM_OK) st = upload(&D.packed, H.packed);
-    if (st == CPM_OK) st = upload(&D.origin, H.origin);
-    if (st == CPM_OK) st = upload(&D.fracK, H.fracK);
-    if (st == CPM_OK) st = upload_f32(&D.fracK32, H.fracK);
-    if (st == CPM_OK) st = upload(&D.ilist, H.ilist);
-    if (st == CPM_OK) st = upload(&D.nbrI, H.nbrI);
+    if (st == CPM_OK) st = upload(b, &D.perm, H.perm);
+    if (st == CPM_OK) st = upload(b, &D.packed, H.packed);
+    if (st == CPM_OK) st = upload(b, &D.origin, H.origin);
+    if (st == CPM_OK) st = upload(b, &D.fracK, H.fracK);
+    if (st == CPM_OK) st = upload_f32(b, &D.fracK32, H.fracK);
+    if (st == CPM_OK) st = upload(b, &D.ilist, H.ilist);
+    if (st == CPM_OK) st = upload(b, &D.nbrI, H.nbrI);
     if (H.patchOK && !H.patchBase.empty()) {
-      if (st == CPM_OK) st = upload(&D.patchRow, H.patchBase);
-      if (st == CPM_OK) st = upload(&D.patchPk, H.patchPk);
-      if (st == CPM_OK) st = upload(&D.patchMask, H.patchMask);
+      if (st == CPM_OK) st = upload(b, &D.patchRow, H.patchBase);
+      if (st == CPM_OK) st = upload(b, &D.patchPk, H.patchPk);
+      if (st == CPM_OK) st = upload(b, &D.patchMask, H.patchMask);
       D.patchGroups = H.patchGroups;
     }
     std::vector<int32_t>().swap(H.patchRow);
@@ -972,9 +1221,11 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     std::vector<int32_t>().swap(H.patchPk);
     std::vector<uint32_t>().swap(H.patchMask);
     D.band_order = band_order;
-    if (st == CPM_OK) st = upload(&D.qdiag, H.qdiag);
+    if (st == CPM_OK) st = upload(b, &D.qdiag, H.qdiag);
+    if (st == CPM_OK) st = upload(b, &D.q1diag, H.q1diag);
     std::vector<double>().swap(H.qdiag);
-    if (st == CPM_OK) st = upload(&D.originX, H.originX);
+    std::vector<double>().swap(H.q1diag);
+    if (st == CPM_OK) st = upload(b, &D.originX, H.originX);
     std::vector<int32_t>().swap(H.originX);
     D.fusedOK = H.fusedOK && D.originX != nullptr;
     {
@@ -994,14 +1245,18 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     D.lds = !band_order && H.maxE <= kMaxStaged && !(lds_env && std::strcmp(lds_env, "0") == 0);
     // default before autotuning: LDS staging pays on levels up to ~2M nodes
     D.use_lds = D.lds && H.n < (int64_t)(2 << 20);
+    if (const char* pe = std::getenv("CPM_EXT_PREFETCH")) {
+      D.ext_prefetch = std::strcmp(pe, "1") == 0;
+      D.prefetch_forced = true;
+    }
     D.maxE = H.maxE;
     D.maxG = H.maxG;
     if (D.lds) {
-      if (st == CPM_OK) st = upload(&D.packedL, H.packedL);
-      if (st == CPM_OK) st = upload(&D.blkE, H.blkE);
-      if (st == CPM_OK) st = upload(&D.gidx, H.gidx);
-      if (st == CPM_OK) st = upload(&D.blkG, H.blkG);
-      if (st == CPM_OK) st = upload(&D.lorg, H.lorg);
+      if (st == CPM_OK) st = upload(b, &D.packedL, H.packedL);
+      if (st == CPM_OK) st = upload(b, &D.blkE, H.blkE);
+      if (st == CPM_OK) st = upload(b, &D.gidx, H.gidx);
+      if (st == CPM_OK) st = upload(b, &D.blkG, H.blkG);
+      if (st == CPM_OK) st = upload(b, &D.lorg, H.lorg);
     }
     // LDS-staged fused sweep (on the extension's workgroups) unless disabled by
     // CPM_SWEEP_LDS=0 or a workgroup would stage too many values; it is the default form of
@@ -1012,10 +1267,33 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     D.use_sweep_lds = D.sweep_lds;
     D.maxE2 = H.maxE2;
     if (D.sweep_lds) {
-      if (st == CPM_OK) st = upload(&D.blkE2, H.blkE2);
-      if (st == CPM_OK) st = upload(&D.gidx2, H.gidx2);
-      if (st == CPM_OK) st = upload(&D.lorg2, H.lorg2);
+      if (st == CPM_OK) st = upload(b, &D.blkE2, H.blkE2);
+      if (st == CPM_OK) st = upload(b, &D.gidx2, H.gidx2);
+      if (st == CPM_OK) st = upload(b, &D.lorg2, H.lorg2);
     }
+    // tiled sweep tables: a candidate of cpm_autotune (measured slower than the two passes on
+    // the large levels it is built for), or forced with CPM_SWEEP=tile
+    if (H.ntiles > 0) {
+      D.ntiles = H.ntiles;
+      if (st == CPM_OK) st = upload(b, &D.tileSlot, H.tileSlot);
+      if (st == CPM_OK) st = upload(b, &D.tileRow, H.tileRow);
+      if (st == CPM_OK) st = upload(b, &D.tperm, H.tperm);
+      if (st == CPM_OK) st = upload(b, &D.tloc, H.tloc);
+      if (st == CPM_OK) st = upload(b, &D.fracT, H.fracT);
+      if (st == CPM_OK) st = upload_f32(b, &D.fracT32, H.fracT);
+      const char* e = std::getenv("CPM_SWEEP");
+      D.use_tile = e && std::strcmp(e, "tile") == 0;
+      if (D.use_tile) {
+        D.sweep_forced = true;
+        D.fused = false;
+      }
+    }
+    std::vector<int32_t>().swap(H.tileSlot);
+    std::vector<int32_t>().swap(H.tileOrg);
+    std::vector<int32_t>().swap(H.tileRow);
+    std::vector<int32_t>().swap(H.tperm);
+    std::vector<int32_t>().swap(H.tloc);
+    std::vector<double>().swap(H.fracT);
     std::vector<int32_t>().swap(H.blkE2);
     std::vector<int32_t>().swap(H.gidx2);
     std::vector<int32_t>().swap(H.lorg2);
@@ -1027,24 +1305,24 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     // band-order fractions: band-order extension, the learned smoother's weights features,
     // and the coarsest level's matrix assembly
     const bool learned_level = D.patchRow != nullptr;
-    if (band_order && st == CPM_OK) st = upload(&D.packedB, H.packedB);
-    if ((band_order || learned_level) && st == CPM_OK) st = upload_f32(&D.fracE32, H.fracE);
-    if ((band_order || learned_level || l == b->L - 1) && st == CPM_OK) st = upload(&D.fracE, H.fracE);
+    if (band_order && st == CPM_OK) st = upload(b, &D.packedB, H.packedB);
+    if ((band_order || learned_level) && st == CPM_OK) st = upload_f32(b, &D.fracE32, H.fracE);
+    if ((band_order || learned_level || l == b->L - 1) && st == CPM_OK) st = upload(b, &D.fracE, H.fracE);
     if (l == b->L - 1) {
       // band-order addressing of the coarsest level, used to assemble its dense matrix
-      if (st == CPM_OK) st = upload(&D.runE, H.runE);
-      if (st == CPM_OK) st = upload(&D.nbr, H.nbr);
+      if (st == CPM_OK) st = upload(b, &D.runE, H.runE);
+      if (st == CPM_OK) st = upload(b, &D.nbr, H.nbr);
     }
-    if (st == CPM_OK) st = upload(&D.runP, H.runP);
-    if (st == CPM_OK) st = upload(&D.fracP, H.fracP);
-    if (st == CPM_OK && !H.fracP.empty()) st = upload_f32(&D.fracP32, H.fracP);
-    if (st == CPM_OK) st = upload(&D.runP3, H.runP3);
-    if (st == CPM_OK) st = upload(&D.fracP3, H.fracP3);
+    if (st == CPM_OK) st = upload(b, &D.runP, H.runP);
+    if (st == CPM_OK) st = upload(b, &D.fracP, H.fracP);
+    if (st == CPM_OK && !H.fracP.empty()) st = upload_f32(b, &D.fracP32, H.fracP);
+    if (st == CPM_OK) st = upload(b, &D.runP3, H.runP3);
+    if (st == CPM_OK) st = upload(b, &D.fracP3, H.fracP3);
     std::vector<int32_t>().swap(H.runP3);
     std::vector<double>().swap(H.fracP3);
-    if (st == CPM_OK) st = upload(&D.runR, H.runR);
-    if (st == CPM_OK) st = upload(&D.fracR, H.fracR);
-    if (st == CPM_OK && !H.fracR.empty()) st = upload_f32(&D.fracR32, H.fracR);
+    if (st == CPM_OK) st = upload(b, &D.runR, H.runR);
+    if (st == CPM_OK) st = upload(b, &D.fracR, H.fracR);
+    if (st == CPM_OK && !H.fracR.empty()) st = upload_f32(b, &D.fracR32, H.fracR);
     // keep only what export needs on the host
     std::vector<double>().swap(H.fracE);
     std::vector<double>().swap(H.fracP);
@@ -1062,9 +1340,9 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     std::vector<int32_t>().swap(H.nbrI);
   }
   if (st == CPM_OK) {
-    b->dscal = dalloc<unsigned long long>(8, &st);
-    b->dcounter = dalloc<int>(4, &st);
-    b->dhist = dalloc<double>(CPM_MAX_HISTORY, &st);
+    b->dscal = dalloc<unsigned long long>(b, 8, &st);
+    b->dcounter = dalloc<int>(b, 4, &st);
+    b->dhist = dalloc<double>(b, CPM_MAX_HISTORY, &st);
     if (st == CPM_OK && hipHostMalloc((void**)&b->hpinned, 8 * sizeof(unsigned long long), 0) != hipSuccess)
       st = CPM_E_NOMEM;
   }
@@ -1076,6 +1354,47 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
   }
   (void)stream;
   *out = b;
+  return CPM_OK;
+}
+
+cpm_status cpm_build_bands(int count, const cpm_surface* surfaces, const cpm_grid* grids, void* stream,
+                           cpm_band* out) {
+  if (count < 0 || (count > 0 && (!surfaces || !grids || !out))) {
+    set_error("cpm_build_bands: invalid argument");
+    return CPM_E_INVALID;
+  }
+  for (int k = 0; k < count; ++k) out[k] = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    set_error("cpm_build_bands: no current device");
+    return CPM_E_HIP;
+  }
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nthr = (int)std::min<unsigned>(hw, (unsigned)std::max(count, 1));
+  std::atomic<int> next{0};
+  std::vector<cpm_status> sts((size_t)count, CPM_OK);
+  std::vector<std::string> errs((size_t)count);
+  auto worker = [&]() {
+    (void)hipSetDevice(dev);
+    set_host_build_threads(1);  // parallel over bands, not inside one
+    for (int k = next++; k < count; k = next++) {
+      sts[(size_t)k] = cpm_build_band(&surfaces[k], &grids[k], stream, &out[k]);
+      if (sts[(size_t)k] != CPM_OK) errs[(size_t)k] = g_last_error;
+    }
+  };
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nthr; ++t) pool.emplace_back(worker);
+  for (auto& th : pool) th.join();
+  for (int k = 0; k < count; ++k)
+    if (sts[(size_t)k] != CPM_OK) {
+      set_error("band " + std::to_string(k) + ": " + errs[(size_t)k]);
+      const cpm_status st = sts[(size_t)k];
+      for (int j = 0; j < count; ++j) {
+        (void)cpm_band_free(out[j]);
+        out[j] = nullptr;
+      }
+      return st;
+    }
   return CPM_OK;
 }
 
@@ -1098,13 +1417,18 @@ cpm_status cpm_band_levels(cpm_band band, int* levels, int* dim) {
   return CPM_OK;
 }
 
-cpm_status cpm_band_info(cpm_band band, int level, int64_t* n, double* h) {
+cpm_status cpm_band_info(cpm_band band, int level, int64_t* n, double* h, int* flags) {
   if (!band || level < 0 || level >= band->L) {
     set_error("null band or level out of range");
     return CPM_E_INVALID;
   }
-  if (n) *n = band->dev[(size_t)level].n;
-  if (h) *h = band->dev[(size_t)level].h;
+  const DevLevel& D = band->dev[(size_t)level];
+  if (n) *n = D.n;
+  if (h) *h = D.h;
+  if (flags) {
+    const double lam2 = band->grid.lam2 > 0 ? band->grid.lam2 : (band->dim == 2 ? 13.0 : 17.0);
+    *flags = std::sqrt(lam2) * D.h >= surface_reach(band->surf) ? CPM_BAND_BEYOND_REACH : 0;
+  }
   return CPM_OK;
 }
 
@@ -1189,8 +1513,10 @@ cpm_status cpm_workspace_size(cpm_band band, const cpm_params* params, size_t* b
   return CPM_OK;
 }
 
-cpm_status cpm_apply(cpm_band band, int level, double c, const double* u, double* Au, double* work, void* stream) {
-  if (!band || level < 0 || level >= band->L || !u || !Au || !work || !(c > 0.0)) {
+cpm_status cpm_apply(cpm_band band, int level, int dtype, double c, const void* u, void* Au, void* work,
+                     void* stream) {
+  if (!band || level < 0 || level >= band->L || !u || !Au || !work || !(c > 0.0) ||
+      (dtype != CPM_DTYPE_F64 && dtype != CPM_DTYPE_F32)) {
     set_error("cpm_apply: invalid argument");
     return CPM_E_INVALID;
   }
@@ -1199,10 +1525,39 @@ cpm_status cpm_apply(cpm_band band, int level, double c, const double* u, double
   cpm_status st = enter(band, stream);
   if (st != CPM_OK) return st;
   const LaunchCfg lc = level_cfg(D);
-  launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, u, nullptr, 1.0 / (D.h * D.h), work, nullptr, lc, band->stream);
-  launch_ext<double, double>(band->dim, EXT_APPLY, D.n, work, ext_addr(D), fracK_of<double>(D), nullptr, const_cast<double*>(u),
-                             Au, level_delta(band, level, c), 0.0, nullptr, ext_cfg(D), band->stream);
+  if (dtype == CPM_DTYPE_F64) {
+    launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, (const double*)u, nullptr, 1.0 / (D.h * D.h), (double*)work,
+                        nullptr, lc, band->stream);
+    launch_ext<double, double>(band->dim, EXT_APPLY, D.n, (const double*)work, ext_addr(D), fracK_of<double>(D),
+                               nullptr, (double*)u, (double*)Au, level_delta(band, level, c), 0.0, nullptr, ext_cfg(D),
+                               band->stream);
+  } else {
+    launch_nsum<float>(band->dim, D.m, D.ilist, D.nbrI, (const float*)u, nullptr, (float)(1.0 / (D.h * D.h)),
+                       (float*)work, nullptr, lc, band->stream);
+    launch_ext<float, float>(band->dim, EXT_APPLY, D.n, (const float*)work, ext_addr(D), fracK_of<float>(D), nullptr,
+                             (float*)u, (float*)Au, (float)level_delta(band, level, c), 0.0f, nullptr, ext_cfg(D),
+                             band->stream);
+  }
   if ((st = check_launch("cpm_apply")) != CPM_OK) return st;
+  return leave(band, stream);
+}
+
+cpm_status cpm_apply_pq(cpm_band band, int level, int p, double c, const double* u, double* Au, double* work,
+                        void* stream) {
+  if (p == 3) return cpm_apply(band, level, CPM_DTYPE_F64, c, u, Au, work, stream);
+  if (!band || level < 0 || level >= band->L || !u || !Au || !work || !(c > 0.0) || p != 1) {
+    set_error("cpm_apply_pq: invalid argument (p must be 1 or 3)");
+    return CPM_E_INVALID;
+  }
+  const DevLevel& D = band->dev[(size_t)level];
+  StreamScope stream_scope(band);
+  cpm_status st = enter(band, stream);
+  if (st != CPM_OK) return st;
+  const double inv_h2 = 1.0 / (D.h * D.h);
+  launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, u, nullptr, inv_h2, work, nullptr, level_cfg(D), band->stream);
+  launch_p1(band->dim, EXT_APPLY, D.n, work, u, ExtAddr{D.perm, D.packed, D.origin}, D.fracK, nullptr, nullptr, Au,
+            level_delta(band, level, c), 2.0 * band->dim * inv_h2, ext_cfg(D), band->stream);
+  if ((st = check_launch("cpm_apply_pq")) != CPM_OK) return st;
   return leave(band, stream);
 }
 
@@ -1236,7 +1591,7 @@ cpm_status cpm_set_diffusion(cpm_band band, int level, const double* a) {
   band->graphs.clear();
   if (!a) {
     for (auto& D : band->dev) {
-      if (D.acoef) (void)hipFree(D.acoef);
+      dev_free(band, D.acoef);
       D.acoef = nullptr;
     }
     band->vc_active = false;
@@ -1250,12 +1605,12 @@ cpm_status cpm_set_diffusion(cpm_band band, int level, const double* a) {
       return CPM_E_INVALID;
     }
   cpm_status st = CPM_OK;
-  if (!D.acoef && !(D.acoef = dalloc<double>((size_t)D.n, &st))) return st != CPM_OK ? st : CPM_E_NOMEM;
+  if (!D.acoef && !(D.acoef = dalloc<double>(band, (size_t)D.n, &st))) return st != CPM_OK ? st : CPM_E_NOMEM;
   if (hipMemcpy(D.acoef, a, (size_t)D.n * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
     set_error("cpm_set_diffusion: copy failed");
     return CPM_E_HIP;
   }
-  if (!D.nbr && (st = upload(&D.nbr, H.nbr)) != CPM_OK) return st;
+  if (!D.nbr && (st = upload(band, &D.nbr, H.nbr)) != CPM_OK) return st;
   bool all = true;
   for (auto& Dl : band->dev) all = all && Dl.acoef != nullptr;
   band->vc_active = all;
@@ -1281,7 +1636,10 @@ cpm_status cpm_vcycle(cpm_band band, const cpm_params* params, const double* f, 
   StreamScope stream_scope(band);
   if ((st = enter(band, stream)) != CPM_OK) return st;
   if ((st = ensure_coarse(band, params->c)) != CPM_OK) return st;
-  if (params->smoother == CPM_SMOOTH_STANDARD && (st = ensure_std(band, params->c, params->omega)) != CPM_OK)
+  if (standard(*params) && (st = ensure_std(band, *params)) != CPM_OK)
+    return st;
+  if (params->residual_mode == CPM_RESIDUAL_VERBATIM && !standard(*params) &&
+      (st = ensure_verbatim(band, params->c)) != CPM_OK)
     return st;
   band->learned_active = false;
   if (relres_out) enqueue_prologue(band, *params, f, u, work, band->stream);
@@ -1315,7 +1673,10 @@ cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, d
   StreamScope stream_scope(band);
   if ((st = enter(band, stream)) != CPM_OK) return st;
   if ((st = ensure_coarse(band, params->c)) != CPM_OK) return st;
-  if (params->smoother == CPM_SMOOTH_STANDARD && (st = ensure_std(band, params->c, params->omega)) != CPM_OK)
+  if (standard(*params) && (st = ensure_std(band, *params)) != CPM_OK)
+    return st;
+  if (params->residual_mode == CPM_RESIDUAL_VERBATIM && !standard(*params) &&
+      (st = ensure_verbatim(band, params->c)) != CPM_OK)
     return st;
   const cpm_params p = *params;
   band->learned_active = p.smoother == CPM_SMOOTH_LEARNED;
@@ -1350,7 +1711,8 @@ cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, d
     double rn = 0, un = 0;
     if ((gs = read_scalars(band, &rn, &un)) != CPM_OK) return gs;
     // standard relaxation: the relative increment ||u_k - u_{k-1}|| / ||u_k|| (Sec. 4.6)
-    const double rel = p.smoother == CPM_SMOOTH_STANDARD ? (un > 0 ? rn / un : 0.0) : rn / bn;
+    const bool incr = standard(p) || p.residual_mode == CPM_RESIDUAL_VERBATIM;
+    const double rel = incr ? (un > 0 ? rn / un : 0.0) : rn / bn;
     if (k < CPM_MAX_HISTORY) S->relres_history[k] = rel;
     S->cycles = k + 1;
     S->relres = rel;
@@ -1392,7 +1754,10 @@ cpm_status cpm_run_cycles(cpm_band band, const cpm_params* params, const double*
   StreamScope stream_scope(band);
   if ((st = enter(band, stream)) != CPM_OK) return st;
   if ((st = ensure_coarse(band, params->c)) != CPM_OK) return st;
-  if (params->smoother == CPM_SMOOTH_STANDARD && (st = ensure_std(band, params->c, params->omega)) != CPM_OK)
+  if (standard(*params) && (st = ensure_std(band, *params)) != CPM_OK)
+    return st;
+  if (params->residual_mode == CPM_RESIDUAL_VERBATIM && !standard(*params) &&
+      (st = ensure_verbatim(band, params->c)) != CPM_OK)
     return st;
   const cpm_params p = *params;
   band->learned_active = p.smoother == CPM_SMOOTH_LEARNED;
@@ -1423,7 +1788,7 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
                            const double* f, double* u, void* work, size_t work_bytes, double* avg_us,
                            void* stream) {
   if (!band || !f || !u || !work || !avg_us || reps < 1 || level < 0 || level >= band->L || which < 0 ||
-      which > 5) {
+      which > 6) {
     set_error("cpm_time_kernel: invalid argument");
     return CPM_E_INVALID;
   }
@@ -1443,6 +1808,10 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
   }
   if (which == 5 && !band->dev[(size_t)level].fusedOK) {
     set_error("cpm_time_kernel: no fused-sweep addressing on this level");
+    return CPM_E_INVALID;
+  }
+  if (which == 6 && band->dev[(size_t)level].ntiles <= 0) {
+    set_error("cpm_time_kernel: no tiled-sweep tables on this level");
     return CPM_E_INVALID;
   }
   StreamScope stream_scope(band);
@@ -1483,6 +1852,12 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
           launch_restrict<T>(band->dim, D.n, B[level - 1].g, D.runR, fracR_of<T>(D), B[level].r, nullptr, lc, s);
         } else if (which == 3) {
           launch_prolong<T>(band->dim, D.n, B[level + 1].g, D.runP, fracP_of<T>(D), B[level].r, lc, s);
+        } else if (which == 6) {
+          // u -> t and back, with the right-hand side f
+          const bool odd = r & 1;
+          launch_tile<T, T>(EXT_SMOOTH, D.n, tile_addr(D), fracT_of<T>(D), odd ? B[level].t : uu, ff, nullptr,
+                            odd ? uu : B[level].t, (T)(1.0 / (D.h * D.h)), (T)delta, (T)(params->omega / delta),
+                            nullptr, s);
         } else if (which == 5) {
           // u -> t and back, reading E f from g
           const bool odd = r & 1;

@@ -15,6 +15,13 @@ namespace cpm {
 constexpr int kMaxLevels = 12;
 constexpr int kMaxCoarse = 12000;  // largest coarsest level for the dense direct solve
 
+// A registered device allocator (cpm_set_allocator); null functions: hipMalloc / hipFree.
+struct DeviceAllocator {
+  void* (*alloc)(void* ctx, size_t bytes) = nullptr;
+  void (*free)(void* ctx, void* p) = nullptr;
+  void* ctx = nullptr;
+};
+
 template <typename T>
 struct LevelBufs {
   T* u = nullptr;  // iterate (correction on coarse levels)
@@ -29,6 +36,7 @@ struct LevelBufs {
 
 struct cpm_band_s {
   cpm_surface surf{};
+  cpm::DeviceAllocator allocator;  // the one registered when the band was built
   cpm_grid grid{};
   int dim = 0;
   int L = 0;
@@ -46,6 +54,11 @@ struct cpm_band_s {
   double* coarseS = nullptr;
   double coarse_std_c = 0.0 / 0.0;
   double std_c = 0.0 / 0.0, std_omega = 0.0 / 0.0;
+  bool std_rb = false;  // the red-black half-sweep factors are current too
+  int std_el = 3;       // degree of the E in front of L the factors are for
+  // Remark 3.2's operator: [A_c | A_c^{-1}] for coarse_std1_c
+  double* coarseS1 = nullptr;
+  double coarse_std1_c = 0.0 / 0.0;
   // variable diffusion coefficient: set on every level (vc_active), diagonals valid for vc_c
   bool vc_active = false;
   double vc_c = 0.0 / 0.0;
@@ -86,11 +99,15 @@ struct StreamScope {
 namespace cpm {
 
 LaunchCfg band_cfg(const cpm_band b, int64_t n);
+// device memory of a band through its allocator
+void* dev_alloc(const cpm_band b, size_t bytes);
+void dev_free(const cpm_band b, void* p);
 LaunchCfg level_cfg(const DevLevel& D);
 LaunchCfg ext_cfg(const DevLevel& D);
 LaunchCfg sweep_cfg(const DevLevel& D);
 ExtAddr ext_addr(const DevLevel& D);
 SweepAddr sweep_addr(const DevLevel& D);
+TileAddr tile_addr(const DevLevel& D);
 // Whole-cycle choice of every level's sweep form (second stage of cpm_autotune).
 cpm_status tune_sweep_forms(cpm_band b);
 double level_delta(const cpm_band b, int l, double c);

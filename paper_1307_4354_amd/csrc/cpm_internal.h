@@ -24,6 +24,7 @@ struct HostLevel {
   // addressing, structure of arrays (slot-major: array[slot * n + i])
   std::vector<double> fracE;   // dim * n: frac(cp / h) for the cubic stencil
   std::vector<double> qdiag;   // n: (E N)_ii, so that diag(A) = delta - qdiag
+  std::vector<double> q1diag;  // n: the same for Remark 3.2's operator (linear E in front of L)
   std::vector<int32_t> runE;   // 4^(dim-1) * n: first node of each x-run of the cubic stencil
   std::vector<int32_t> nbr;    // 2*dim * n: -x,+x,-y,+y,-z,+z neighbours, -1 if absent
   // extension in stencil order: nodes sorted by the base of their cubic stencil (z, y, x);
@@ -73,6 +74,19 @@ struct HostLevel {
   std::vector<int32_t> patchBase;
   std::vector<int32_t> patchPk;
   int64_t patchGroups = 0;
+  // tiled sweep (3-D levels of at least kTileMinNodes nodes): nodes grouped by the tile of
+  // kTileX x kTileY x kTileZ grid cells that holds their stencil base; one workgroup per tile
+  // stages u (and f) over the tile's box, the stencils widened by the Laplacian's reach, in
+  // LDS, forms f + N u there and interpolates it.  Per tile: slot range, box origin, and per
+  // box row (y, z) the band index of its first in-band node and the presence mask of its
+  // cells.  Per slot: band index, local coordinates, and the fractions in slot order.
+  int64_t ntiles = 0;
+  std::vector<int32_t> tileSlot;  // ntiles + 1
+  std::vector<int32_t> tileOrg;   // 3 * ntiles: box origin (x, y, z)
+  std::vector<int32_t> tileRow;   // 2 * kBoxRows * ntiles: {first band index, cell mask}
+  std::vector<int32_t> tperm;     // n: slot -> band index
+  std::vector<int32_t> tloc;      // n: local base (5 bits per axis), own box cell, in-box flag
+  std::vector<double> fracT;      // 3 * n: fractions in slot order
   std::vector<double> fracP;   // dim * n: frac(cp / (2h)) (prolongation from level+1)
   // cubic interpolation from level+1 at this level's closest points (4^(d-1) runs of 4, and
   // the fractions), the nested-iteration step of the full-multigrid start; empty when some
@@ -95,6 +109,17 @@ constexpr int64_t kFusedMaxNodes = 2 << 20;
 // levels up to this size sweep with the fused pass unless the autotuner decides otherwise
 constexpr int64_t kFusedDefaultNodes = 128 << 10;
 
+// tiled sweep geometry: tile of kTileX x kTileY x kTileZ stencil bases; its box spans the
+// stencils (+3) widened by one cell on each side (the Laplacian of the stencil nodes)
+constexpr int kTileX = 8, kTileY = 8, kTileZ = 8;
+constexpr int kBoxX = kTileX + 5, kBoxY = kTileY + 5, kBoxZ = kTileZ + 5;
+constexpr int kBoxRows = kBoxY * kBoxZ;
+constexpr int kBoxCells = kBoxX * kBoxRows;
+constexpr int kGX = kBoxX - 2, kGY = kBoxY - 2, kGZ = kBoxZ - 2;  // the stencils' box
+constexpr int kGCells = kGX * kGY * kGZ;
+constexpr int64_t kTileMinNodes = 1 << 18;
+constexpr int kTileBlock = 256;
+
 // Device copies of one level's addressing.
 struct DevLevel {
   int64_t n = 0;
@@ -105,6 +130,8 @@ struct DevLevel {
   bool lds = false;         // LDS-staged extension tables present
   bool use_lds = false;     // extension runs LDS-staged (else gathers through L1)
   int ext_block = 256;      // workgroup size of the gather extension
+  bool ext_prefetch = false;  // LDS-staged extension loads the node's own data before staging
+  bool prefetch_forced = false;  // set by CPM_EXT_PREFETCH
   int nsum_block = 256;     // workgroup size of the neighbour sum and transfers
   int sweep_block = 256;    // workgroup size of the fused sweep
   bool sweep_forced = false;  // fused / split chosen by the CPM_SWEEP environment variable
@@ -142,15 +169,30 @@ struct DevLevel {
   int32_t* runP3 = nullptr;  // full-multigrid interpolation from level+1 (cubic)
   double* fracP3 = nullptr;
   double* qdiag = nullptr;  // (E N)_ii
+  double* q1diag = nullptr; // delta - diag(A) of Remark 3.2's operator
+  double* wd1 = nullptr;    // omega / diag(A) of that operator (set per c, omega)
   double* acoef = nullptr;  // variable diffusion coefficient a(cp(x_i)) (cpm_set_diffusion)
   double* vcD = nullptr;    // c + sigma_i of the flux-form operator, for vc_c
   double* wd = nullptr;     // omega / diag(A) of the standard relaxation (set per c, omega)
+  uint8_t* parity = nullptr;  // colour of the red-black sweeps: parity of the grid index sum
+  double* wdR = nullptr;      // wd on red nodes, 0 on black ones
+  double* wdB = nullptr;      // wd on black nodes, 0 on red ones
   bool fusedOK = false;
   bool fused = false;  // sweeps as one fused pass instead of neighbour sum + extension
   int32_t* patchRow = nullptr;   // grouped rows (HostLevel::patchBase), rows x patchGroups
   int32_t* patchPk = nullptr;    // per node (group << kPatchBits) | offset
   int64_t patchGroups = 0;
   uint32_t* patchMask = nullptr;
+  // tiled sweep (HostLevel::tileSlot ...); use_tile: the level sweeps with it
+  int64_t ntiles = 0;
+  bool use_tile = false;
+  int32_t* tileSlot = nullptr;
+  int32_t* tileOrg = nullptr;
+  int32_t* tileRow = nullptr;
+  int32_t* tperm = nullptr;
+  int32_t* tloc = nullptr;
+  double* fracT = nullptr;
+  float* fracT32 = nullptr;
 };
 
 // Build every level of the band hierarchy on the host.  Returns CPM_OK or an error with
@@ -159,5 +201,11 @@ cpm_status build_host_levels(const cpm_surface& s, const cpm_grid& g, int dim,
                              std::vector<HostLevel>& levels, std::string& err);
 
 void set_error(const std::string& msg);
+
+// Reach of an analytic surface (level sets: a curvature bound).
+double surface_reach(const cpm_surface& s);
+
+// OpenMP threads of the calling host thread's band construction.
+void set_host_build_threads(int n);
 
 }  // namespace cpm

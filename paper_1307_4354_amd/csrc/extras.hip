@@ -50,9 +50,11 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
   if (st != CPM_OK) return st;
   hipStream_t s = band->stream;
   const int64_t n0 = band->dev[0].n;
-  double *g = nullptr, *u = nullptr;
-  if (hipMalloc((void**)&g, n0 * sizeof(double)) != hipSuccess || hipMalloc((void**)&u, n0 * sizeof(double)) != hipSuccess) {
-    if (g) (void)hipFree(g);
+  double* g = (double*)dev_alloc(band, n0 * sizeof(double));
+  double* u = (double*)dev_alloc(band, n0 * sizeof(double));
+  if (!g || !u) {
+    dev_free(band, g);
+    dev_free(band, u);
     set_error("cpm_autotune: allocation failed");
     return CPM_E_NOMEM;
   }
@@ -70,11 +72,14 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
     float best = 1e30f;
     bool best_lds = D.use_lds;
     int best_blk = D.ext_block;
-    for (int cand = 0; cand < 4; ++cand) {
-      const bool lds = cand == 3;
+    bool best_pf = D.ext_prefetch;
+    for (int cand = 0; cand < 5; ++cand) {
+      const bool lds = cand >= 3;  // 3: LDS-staged, 4: LDS-staged with the node's data loaded first
       if (lds && !D.lds) continue;
+      if (cand == 4 && D.prefetch_forced) continue;
       D.use_lds = lds;
       D.ext_block = lds ? 256 : blocks[cand];
+      if (!D.prefetch_forced) D.ext_prefetch = cand == 4;
       const ExtAddr a = ext_addr(D);
       const LaunchCfg lc = ext_cfg(D);
       const float t = time_us(s, e0, e1, reps, [&] {
@@ -85,10 +90,12 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
         best = t;
         best_lds = lds;
         best_blk = D.ext_block;
+        best_pf = D.ext_prefetch;
       }
     }
     D.use_lds = best_lds;
     D.ext_block = best_blk;
+    D.ext_prefetch = best_pf;
     best = 1e30f;
     int best_n = D.nsum_block;
     for (int bi = 0; bi < 3; ++bi) {
@@ -103,8 +110,8 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
       }
     }
     D.nsum_block = best_n;
-    if (!D.fusedOK) continue;
-    // split sweep (both passes, tuned) against the fused pass
+    if (!D.fusedOK && D.ntiles <= 0) continue;
+    // split sweep (both passes, tuned) against the fused pass and the tiled pass
     const float t_split = time_us(s, e0, e1, reps, [&] {
       launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, u, u, inv_h2, g, nullptr, level_cfg(D), s);
       launch_ext<double, double>(band->dim, EXT_SMOOTH, D.n, g, ext_addr(D), D.band_order ? D.fracE : D.fracK,
@@ -113,7 +120,7 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
     float t_fused = 1e30f, t_gather = 1e30f;
     int best_g = D.sweep_block;
     bool best_slds = D.use_sweep_lds;
-    for (int cand = 0; cand < 4; ++cand) {
+    for (int cand = 0; cand < 4 && D.fusedOK; ++cand) {
       const bool slds = cand == 3;  // LDS-staged (fixed workgroup), else gathers
       if (slds && !D.sweep_lds) continue;
       D.use_sweep_lds = slds;
@@ -140,13 +147,28 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
     }
     D.sweep_block = best_g;  // the gather form's workgroup (the LDS form's is fixed)
     D.use_sweep_lds = best_slds;
-    if (!D.sweep_forced) D.fused = t_fused < t_split;
+    if (!D.sweep_forced) D.fused = D.fusedOK && t_fused < t_split;
+    if (D.ntiles > 0) {
+      int flip = 0;
+      const TileAddr ta = tile_addr(D);
+      const float t_tile = time_us(s, e0, e1, reps, [&] {
+        const double* src = flip ? g : u;
+        double* dst = flip ? u : g;
+        flip ^= 1;
+        launch_tile<double, double>(EXT_SMOOTH, D.n, ta, D.fracT, src, src, nullptr, dst, inv_h2, delta, 0.5 / delta,
+                                    nullptr, s);
+      });
+      if (!D.sweep_forced) {
+        D.use_tile = t_tile < std::min(t_split, D.fused ? t_fused : 1e30f);
+        if (D.use_tile) D.fused = false;
+      }
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(s);
-  (void)hipFree(g);
-  (void)hipFree(u);
+  dev_free(band, g);
+  dev_free(band, u);
   // captured graphs hold the old launch configurations
   for (auto& kv : band->graphs) (void)hipGraphExecDestroy(kv.second);
   band->graphs.clear();
@@ -157,7 +179,7 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
 }
 
 cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_block, int* nsum_block, int* fused,
-                           int* sweep_block, int* sweep_lds) {
+                           int* sweep_block, int* sweep_lds, int* tiled, int* ext_prefetch) {
   if (!band || level < 0 || level >= band->L) {
     set_error("cpm_band_tuning: invalid argument");
     return CPM_E_INVALID;
@@ -170,19 +192,22 @@ cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_bloc
   const bool slds = D.sweep_lds && D.use_sweep_lds;
   if (sweep_block) *sweep_block = slds ? kExtBlock : D.sweep_block;
   if (sweep_lds) *sweep_lds = slds ? 1 : 0;
+  if (tiled) *tiled = D.use_tile && D.ntiles > 0 ? 1 : 0;
+  if (ext_prefetch) *ext_prefetch = D.lds && D.use_lds && D.ext_prefetch ? 1 : 0;
   return CPM_OK;
 }
 
 cpm_status cpm_set_band_tuning(cpm_band band, int level, int use_lds, int ext_block, int nsum_block, int fused,
-                               int sweep_block, int sweep_lds) {
+                               int sweep_block, int sweep_lds, int tiled, int ext_prefetch) {
   if (!band || level < 0 || level >= band->L) {
     set_error("cpm_set_band_tuning: invalid argument");
     return CPM_E_INVALID;
   }
   DevLevel& D = band->dev[(size_t)level];
   auto blk_ok = [](int b) { return b == 128 || b == 256 || b == 512; };
-  if ((use_lds && !D.lds) || (fused && !D.fusedOK) || (sweep_lds && !D.sweep_lds) || !blk_ok(ext_block) ||
-      !blk_ok(nsum_block) || !blk_ok(sweep_block)) {
+  if ((use_lds && !D.lds) || (ext_prefetch && !use_lds) || (fused && !D.fusedOK) || (sweep_lds && !D.sweep_lds) ||
+      (tiled && D.ntiles <= 0) ||
+      (tiled && fused) || !blk_ok(ext_block) || !blk_ok(nsum_block) || !blk_ok(sweep_block)) {
     set_error("cpm_set_band_tuning: configuration not supported on this level");
     return CPM_E_INVALID;
   }
@@ -192,6 +217,8 @@ cpm_status cpm_set_band_tuning(cpm_band band, int level, int use_lds, int ext_bl
   D.fused = fused != 0;
   D.sweep_block = sweep_block;
   D.use_sweep_lds = sweep_lds != 0;
+  D.use_tile = tiled != 0;
+  D.ext_prefetch = ext_prefetch != 0;
   // captured graphs hold the old launch configurations
   for (auto& kv : band->graphs) (void)hipGraphExecDestroy(kv.second);
   band->graphs.clear();

@@ -20,6 +20,7 @@ enum ExtMode {
 struct LaunchCfg {
   int block = 256;      // neighbour sum, transfers, gather extension
   int xcd_remap = 1;    // map consecutive tiles to the same XCD (shared L2)
+  int prefetch = 0;     // LDS-staged extension: load the node's own data before the staging
 };
 
 // Stencil-ordered extension addressing of one level (see HostLevel).
@@ -54,6 +55,22 @@ struct SweepAddr {
   int32_t maxG = 0;
 };
 
+// Tiled sweep addressing (3-D levels with HostLevel::tileSlot ...).
+struct TileAddr {
+  const int32_t* slot;
+  const int32_t* row;
+  const int32_t* perm;
+  const int32_t* loc;
+  int64_t ntiles;
+};
+
+// One tiled Ruuth-Merriman pass over a level: mode EXT_SMOOTH out = u + wod r, EXT_RESID
+// out = r (and ||r||_inf into nrm if not null), r = b + E(f + N u) - delta u; f, b may be
+// null; frac in slot order; out must not overlap u.
+template <typename T, typename TO>
+void launch_tile(int mode, int64_t n, const TileAddr& a, const T* frac, const T* u, const T* f, const T* b, TO* out,
+                 T inv_h2, T delta, T wod, unsigned long long* nrm, hipStream_t s);
+
 // mode EXT_SMOOTH: uo = u + (omega/delta)(b + E f + (E N) u - delta u); EXT_RESID: uo = that
 // residual.  Ef and b may be null; uo must not overlap u.
 template <typename T>
@@ -86,11 +103,26 @@ void launch_prolong(int dim, int64_t nf, const T* ec, const int32_t* runP, const
 template <typename T>
 void launch_coarse_gemv(int n, const double* Z, int64_t ld, const T* x, T* y, hipStream_t s);
 
+// Remark 3.2's operator A u = delta u - E_1 (N u) + gamma (E_1 u - E_3 u) over the extension's
+// stencil-order addressing (a.perm, a.packed, a.origin), g = N u: mode EXT_APPLY out = A u,
+// EXT_RESID out = b - A u, EXT_SMOOTH out = u + wd (b - A u); out must not overlap u.
+void launch_p1(int dim, int mode, int64_t n, const double* g, const double* u, const ExtAddr& a, const double* frac,
+               const double* b, const double* wd, double* out, double delta, double gamma, const LaunchCfg& lc,
+               hipStream_t s);
+// [A_c | I] for that operator on the coarsest level (n x 2n, row-major)
+void launch_assemble_coarse_p1(int dim, int n, const int32_t* runE, const double* fracE, const int32_t* nbr,
+                               double delta, double gamma, double inv_h2, double* M, hipStream_t s);
+// red-black half-sweeps: wdR = wd on red nodes (even grid index sum), 0 elsewhere; wdB the rest
+void launch_split_colours(int64_t n, const double* wd, const uint8_t* parity, double* wdR, double* wdB,
+                          hipStream_t s);
 // standard relaxation: wd = omega / (delta - q) per node
 void launch_std_scale(int64_t n, const double* q, double delta, double omega, double* wd, hipStream_t s);
 // slot[0] = max |u - p| (0 when p is null), slot[1] = max |u|, as bit patterns (atomicMax;
 // the slots must be cleared first)
 void launch_incr(int64_t n, const double* u, const double* p, unsigned long long* slot, hipStream_t s);
+// Algorithm 4.1's printed residual r = f + N u - delta u at every node (nbr: 2d x n, -1 absent)
+void launch_resid_verbatim(int dim, int64_t n, const int32_t* nbr, const double* u, const double* f, double delta,
+                           double inv_h2, double* r, hipStream_t s);
 
 // Variable diffusion coefficient (flux form): g = (f + N~ u) / D on B_interp (u, f may be
 // null); D_i = c + sigma_i on every node; the coarsest level's [I - E D^{-1} N~ | E D^{-1}].

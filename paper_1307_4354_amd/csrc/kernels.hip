@@ -101,6 +101,294 @@ __global__ __launch_bounds__(kExtBlock) void k_ext_lds(int64_t n, const T* __res
   if (MODE != EXT_APPLY && nrm) block_max_atomic(nv, nrm);
 }
 
+// Tiled Ruuth-Merriman sweep (3-D): one workgroup per tile of kTileX x kTileY x kTileZ
+// stencil bases.  The workgroup stages u over the tile's box (the stencils of its nodes
+// widened by one cell on each side) and f over the stencils' box in LDS, row by row from the
+// tile's row table (each box row's in-band nodes are consecutive band entries, so a row is
+// one coalesced read), forms g = f + N u at every stencil node in LDS (the neighbour sum in
+// the order of the two-pass sweep's neighbour-sum pass), then every node interpolates g at
+// its closest point from LDS (the extension pass's order) and takes the Jacobi step:
+//   MODE EXT_SMOOTH: out = u + (omega/delta) r,  EXT_RESID: out = r,  r = b + E g - delta u.
+// out must not overlap u (other workgroups stage u while this one writes).  A node whose own
+// grid cell lies inside the box reads its u from LDS.
+constexpr int kTileStageU = (kBoxCells + kTileBlock - 1) / kTileBlock;
+constexpr int kTileStageF = (kGCells + kTileBlock - 1) / kTileBlock;
+
+template <typename T, typename TO, int MODE>
+__global__ __launch_bounds__(kTileBlock) void k_tile(int64_t n, const int32_t* __restrict__ tileSlot,
+                                                     const int32_t* __restrict__ tileRow,
+                                                     const int32_t* __restrict__ tperm,
+                                                     const int32_t* __restrict__ tloc, const T* __restrict__ frac,
+                                                     const T* __restrict__ u, const T* __restrict__ f,
+                                                     const T* __restrict__ b, TO* __restrict__ out, T inv_h2,
+                                                     T delta, T wod, unsigned long long* __restrict__ nrm,
+                                                     int remap) {
+  __shared__ T U[kBoxCells];
+  __shared__ T G[kGCells];
+  __shared__ int2 rows[kBoxRows];
+  const int64_t t = tile_of_block(remap);
+  const int tid = (int)threadIdx.x;
+  const int32_t s0 = tileSlot[t], s1 = tileSlot[t + 1];
+  const int2* __restrict__ rt = (const int2*)tileRow + t * kBoxRows;
+  for (int r = tid; r < kBoxRows; r += kTileBlock) rows[r] = rt[r];
+  __syncthreads();
+  // stage: every load issued before any LDS store (one memory round trip per thread)
+  T uv[kTileStageU], fv[kTileStageF];
+#pragma unroll
+  for (int j = 0; j < kTileStageU; ++j) {
+    const int e = tid + j * kTileBlock;
+    uv[j] = T(0);
+    if (e < kBoxCells) {
+      const int2 rr = rows[e / kBoxX];
+      const uint32_t below = (uint32_t)rr.y & ((1u << (e % kBoxX)) - 1u);
+      if (((uint32_t)rr.y >> (e % kBoxX)) & 1u) uv[j] = u[rr.x + __popc(below)];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kTileStageF; ++j) {
+    const int g = tid + j * kTileBlock;
+    fv[j] = T(0);
+    if (f && g < kGCells) {
+      const int x = g % kGX + 1, q = g / kGX;
+      const int2 rr = rows[(q / kGY + 1) * kBoxY + q % kGY + 1];
+      const uint32_t below = (uint32_t)rr.y & ((1u << x) - 1u);
+      if (((uint32_t)rr.y >> x) & 1u) fv[j] = f[rr.x + __popc(below)];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < kTileStageU; ++j) {
+    const int e = tid + j * kTileBlock;
+    if (e < kBoxCells) U[e] = uv[j];
+  }
+#pragma unroll
+  for (int j = 0; j < kTileStageF; ++j) {
+    const int g = tid + j * kTileBlock;
+    if (g < kGCells) G[g] = fv[j];
+  }
+  __syncthreads();
+  // g = f + N u at the stencils' box cells (zeros outside the band, never read); each thread
+  // updates the cells it staged
+#pragma unroll
+  for (int j = 0; j < kTileStageF; ++j) {
+    const int g = tid + j * kTileBlock;
+    if (g < kGCells) {
+      const int gx = g % kGX, q = g / kGX;
+      const int c = ((q / kGY + 1) * kBoxY + q % kGY + 1) * kBoxX + gx + 1;
+      T sum = U[c - 1] + U[c + 1];
+      sum += U[c - kBoxX];
+      sum += U[c + kBoxX];
+      sum += U[c - kBoxX * kBoxY];
+      sum += U[c + kBoxX * kBoxY];
+      T gj = sum * inv_h2;
+      if (f) gj += G[g];
+      G[g] = gj;
+    }
+  }
+  __syncthreads();
+  unsigned long long nv = 0ull;
+  for (int32_t k = s0 + tid; k < s1; k += kTileBlock) {
+    const int32_t i = tperm[k];
+    const int32_t loc = tloc[k];
+    T wx[4], wy[4], wz[4];
+    cubic_weights<T>(frac[k], wx);
+    cubic_weights<T>(frac[n + k], wy);
+    cubic_weights<T>(frac[2 * n + k], wz);
+    const T* gp = G + ((loc >> 10 & 31) * kGY + (loc >> 5 & 31)) * kGX + (loc & 31);
+    T tv = T(0);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      T tc = T(0);
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) tc += wy[bb] * run_dot_lds(gp + (c * kGY + bb) * kGX, wx);
+      tv += wz[c] * tc;
+    }
+    const T ui = (loc >> 30 & 1) ? U[((loc >> 25 & 31) * kBoxY + (loc >> 20 & 31)) * kBoxX + (loc >> 15 & 31)] : u[i];
+    T r = tv - delta * ui;
+    if (b) r += b[i];
+    if (MODE == EXT_SMOOTH) {
+      out[i] = (TO)(ui + wod * r);
+    } else {
+      if (out) out[i] = (TO)r;
+      nv = nv > abs_bits((double)r) ? nv : abs_bits((double)r);
+    }
+  }
+  if (MODE == EXT_RESID && nrm) block_max_atomic(nv, nrm);
+}
+
+// Remark 3.2's operator A u = delta u - E_1 (N u) + gamma (E_1 u - E_3 u) (linear
+// interpolation in front of the Laplacian, cubic in the gamma term) at the node in stencil
+// slot k: g = N u (from the neighbour-sum pass) and u are gathered through the cubic
+// stencil's x-runs; the linear stencil is the inner 2^D nodes of the cubic one, with 1-D
+// weights (1 - a, a) on its positions 1 and 2.  MODE EXT_APPLY: out = A u; EXT_RESID:
+// out = b - A u; EXT_SMOOTH: out = u + wd (b - A u) (b may be null); out must not overlap u.
+template <int D, int MODE>
+__global__ __launch_bounds__(kMaxBlock) void k_p1(int64_t n, const double* __restrict__ g,
+                                                  const double* __restrict__ u, const int32_t* __restrict__ perm,
+                                                  const int32_t* __restrict__ packed,
+                                                  const int32_t* __restrict__ origin, const double* __restrict__ frac,
+                                                  const double* __restrict__ b, const double* __restrict__ wd,
+                                                  double* __restrict__ out, double delta, double gamma, int remap) {
+  constexpr int S = D == 2 ? 4 : 16;
+  const int64_t k = tile_of_block(remap) * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const int32_t i = perm[k];
+  const int32_t pk = packed[k];
+  const int32_t* org = origin + (int64_t)(pk >> kXoffBits) * S;
+  const int32_t xo = pk & ((1 << kXoffBits) - 1);
+  double wx[4], wy[4], wz[4] = {1.0, 0.0, 0.0, 0.0};
+  const double ax = frac[k], ay = frac[n + k], az = D == 3 ? frac[2 * n + k] : 0.0;
+  cubic_weights<double>(ax, wx);
+  cubic_weights<double>(ay, wy);
+  if (D == 3) cubic_weights<double>(az, wz);
+  const double lx[2] = {1.0 - ax, ax}, ly[2] = {1.0 - ay, ay}, lz[2] = {1.0 - az, az};
+  double t1 = 0.0, t2 = 0.0, t3 = 0.0;  // E_1 g, E_1 u, E_3 u
+  constexpr int NC = D == 2 ? 1 : 4;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+    for (int bb = 0; bb < 4; ++bb) {
+      const int32_t r0 = org[bb + 4 * c] + xo;
+      s3 += wy[bb] * run_dot(u + r0, wx);
+      if (bb == 1 || bb == 2) {
+        s1 += ly[bb - 1] * (lx[0] * g[r0 + 1] + lx[1] * g[r0 + 2]);
+        s2 += ly[bb - 1] * (lx[0] * u[r0 + 1] + lx[1] * u[r0 + 2]);
+      }
+    }
+    t3 += wz[c] * s3;
+    if (D == 2) {
+      t1 = s1;
+      t2 = s2;
+    } else if (c == 1 || c == 2) {
+      t1 += lz[c - 1] * s1;
+      t2 += lz[c - 1] * s2;
+    }
+  }
+  const double ui = u[i];
+  const double Au = (delta * ui - t1) + gamma * (t2 - t3);
+  if (MODE == EXT_APPLY) {
+    out[i] = Au;
+  } else {
+    const double r = (b ? b[i] : 0.0) - Au;
+    out[i] = MODE == EXT_RESID ? r : ui + wd[i] * r;
+  }
+}
+
+// Row i of [A | I] for Remark 3.2's operator A = delta I - E_1 N + gamma (E_1 - E_3) (one lane
+// per row, so no two lanes write the same row).
+template <int D>
+__global__ void k_assemble_coarse_p1(int n, const int32_t* __restrict__ runE, const double* __restrict__ fracE,
+                                     const int32_t* __restrict__ nbr, double delta, double gamma, double inv_h2,
+                                     double* __restrict__ M) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t ld = 2 * (int64_t)n;
+  double* row = M + (int64_t)i * ld;
+  row[i] += delta;
+  row[n + i] = 1.0;
+  double wx[4], wy[4], wz[4] = {1.0, 0.0, 0.0, 0.0};
+  const double ax = fracE[i], ay = fracE[n + i], az = D == 3 ? fracE[2 * n + i] : 0.0;
+  cubic_weights<double>(ax, wx);
+  cubic_weights<double>(ay, wy);
+  if (D == 3) cubic_weights<double>(az, wz);
+  const double l1[3][4] = {{0.0, 1.0 - ax, ax, 0.0}, {0.0, 1.0 - ay, ay, 0.0}, {D == 3 ? 0.0 : 1.0, 1.0 - az, az, 0.0}};
+  const int nruns = D == 2 ? 4 : 16;
+  for (int r = 0; r < nruns; ++r) {
+    const int bb = r & 3, c = r >> 2;
+    const int32_t j0 = runE[(int64_t)r * n + i];
+    for (int a = 0; a < 4; ++a) {
+      const int32_t j = j0 + a;
+      row[j] -= gamma * (wx[a] * wy[bb] * wz[c]);
+      const double w1 = l1[0][a] * l1[1][bb] * (D == 3 ? l1[2][c] : 1.0);
+      if (w1 == 0.0) continue;
+      row[j] += gamma * w1;
+      for (int q = 0; q < 2 * D; ++q) {
+        const int32_t m = nbr[(int64_t)q * n + j];
+        if (m >= 0) row[m] -= w1 * inv_h2;
+      }
+    }
+  }
+}
+
+// The LDS-staged extension with the node's own data (band index, local run offsets, closest-
+// point fractions, and u at the node) loaded before the staging instead of after it: on large
+// levels, where many workgroups take turns on a CU, those loads then overlap the staging's
+// round trips.  Arithmetic as in k_ext_lds, term for term.
+template <int D, typename T, typename TO, int MODE>
+__global__ __launch_bounds__(kExtBlock) void k_ext_ldsp(int64_t n, const T* __restrict__ g,
+                                                        const int32_t* __restrict__ perm,
+                                                        const int32_t* __restrict__ packedL,
+                                                        const int32_t* __restrict__ blkE,
+                                                        const int32_t* __restrict__ gidx,
+                                                        const int32_t* __restrict__ blkG,
+                                                        const int32_t* __restrict__ lorg,
+                                                        const T* __restrict__ frac, const T* __restrict__ b,
+                                                        T* __restrict__ u, TO* __restrict__ out, T delta, T wod,
+                                                        unsigned long long* __restrict__ nrm, int remap,
+                                                        int lo_offset, const T* __restrict__ wd) {
+  constexpr int S = D == 2 ? 4 : 16;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  T* gl = (T*)smem;
+  int32_t* lo = (int32_t*)(smem + lo_offset);
+  const int64_t blk = tile_of_block(remap);
+  const int64_t k = blk * kExtBlock + threadIdx.x;
+  const bool live = k < n;
+  int32_t i = 0, pk = 0;
+  T fx = T(0), fy = T(0), fz = T(0), ui = T(0), bi = T(0), wdi = T(0);
+  if (live) {
+    i = perm[k];
+    pk = packedL[k];
+    fx = frac[k];
+    fy = frac[n + k];
+    if (D == 3) fz = frac[2 * n + k];
+    if (MODE != EXT_PLAIN) ui = u[i];
+    if (b && (MODE == EXT_SMOOTH || MODE == EXT_RESID)) bi = b[i];
+    if (wd && (MODE == EXT_SMOOTH || MODE == EXT_RESID)) wdi = wd[i];
+  }
+  ext_stage<T>(blk, g, blkE, gidx, blkG, lorg, S, gl, lo);
+  unsigned long long nv = 0ull;
+  if (live) {
+    const int32_t* org = lo + (pk >> kXoffBits) * S;
+    const T* gx = gl + (pk & ((1 << kXoffBits) - 1));
+    T wx[4], wy[4], wz[4];
+    cubic_weights<T>(fx, wx);
+    cubic_weights<T>(fy, wy);
+    T t = T(0);
+    if (D == 2) {
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) t += wy[bb] * run_dot_lds(gx + org[bb], wx);
+    } else {
+      cubic_weights<T>(fz, wz);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        T tc = T(0);
+#pragma unroll
+        for (int bb = 0; bb < 4; ++bb) tc += wy[bb] * run_dot_lds(gx + org[bb + 4 * c], wx);
+        t += wz[c] * tc;
+      }
+    }
+    if (MODE == EXT_SMOOTH) {
+      T r = t - delta * ui;
+      if (b) r += bi;
+      u[i] = ui + (wd ? wdi : wod) * r;
+      if (out) out[i] = (TO)t;
+      nv = abs_bits((double)r);
+    } else if (MODE == EXT_RESID) {
+      T r = t - delta * ui;
+      if (b) r += bi;
+      if (wd) r *= wdi;
+      if (out) out[i] = (TO)r;
+      nv = abs_bits((double)r);
+    } else if (MODE == EXT_APPLY) {
+      out[i] = (TO)(delta * ui - t);
+    } else {
+      if (out) out[i] = (TO)t;
+      nv = abs_bits((double)t);
+    }
+  }
+  if (MODE != EXT_APPLY && nrm) block_max_atomic(nv, nrm);
+}
+
 // f_c[j] = linear interpolation at cp(x_j^c) of fine-band values r_f; u_c[j] = 0
 template <int D, typename T>
 __global__ __launch_bounds__(kMaxBlock) void k_restrict(int64_t nc, const T* __restrict__ rf,
@@ -326,9 +614,14 @@ void launch_ext(int dim, int mode, int64_t n, const T* g, const ExtAddr& a, cons
     const size_t shm = (size_t)lo_off + (size_t)a.maxG * S * sizeof(int32_t);
     const unsigned gl = (unsigned)((n + kExtBlock - 1) / kExtBlock);
     const int rm = lc.xcd_remap;
-#define CPM_EXTL_CASE(DD, MM)                                                                         \
-  k_ext_lds<DD, T, TO, MM><<<gl, kExtBlock, shm, s>>>(n, g, a.perm, a.packedL, a.blkE, a.gidx, a.blkG, a.lorg, \
-                                                       frac, b, u, out, delta, wod, nrm, rm, lo_off, wd)
+#define CPM_EXTL_CASE(DD, MM)                                                                              \
+  if (lc.prefetch)                                                                                         \
+    k_ext_ldsp<DD, T, TO, MM><<<gl, kExtBlock, shm, s>>>(n, g, a.perm, a.packedL, a.blkE, a.gidx, a.blkG,    \
+                                                         a.lorg, frac, b, u, out, delta, wod, nrm, rm, lo_off, \
+                                                         wd);                                                \
+  else                                                                                                     \
+    k_ext_lds<DD, T, TO, MM><<<gl, kExtBlock, shm, s>>>(n, g, a.perm, a.packedL, a.blkE, a.gidx, a.blkG,     \
+                                                        a.lorg, frac, b, u, out, delta, wod, nrm, rm, lo_off, wd)
     if (dim == 2) {
       switch (mode) {
         case EXT_SMOOTH: CPM_EXTL_CASE(2, EXT_SMOOTH); break;
@@ -368,6 +661,48 @@ void launch_ext(int dim, int mode, int64_t n, const T* g, const ExtAddr& a, cons
     }
   }
 #undef CPM_EXT_CASE
+}
+
+template <typename T, typename TO>
+void launch_tile(int mode, int64_t n, const TileAddr& a, const T* frac, const T* u, const T* f, const T* b, TO* out,
+                 T inv_h2, T delta, T wod, unsigned long long* nrm, hipStream_t s) {
+  if (n <= 0 || a.ntiles <= 0) return;
+  const unsigned gr = (unsigned)a.ntiles;
+  if (mode == EXT_SMOOTH)
+    k_tile<T, TO, EXT_SMOOTH><<<gr, kTileBlock, 0, s>>>(n, a.slot, a.row, a.perm, a.loc, frac, u, f, b, out, inv_h2,
+                                                       delta, wod, nrm, 1);
+  else
+    k_tile<T, TO, EXT_RESID><<<gr, kTileBlock, 0, s>>>(n, a.slot, a.row, a.perm, a.loc, frac, u, f, b, out, inv_h2,
+                                                      delta, wod, nrm, 1);
+}
+
+void launch_p1(int dim, int mode, int64_t n, const double* g, const double* u, const ExtAddr& a, const double* frac,
+               const double* b, const double* wd, double* out, double delta, double gamma, const LaunchCfg& lc,
+               hipStream_t s) {
+  if (n <= 0) return;
+  const unsigned gr = grid_for(n, lc.block);
+#define CPM_P1_CASE(DD, MM) \
+  k_p1<DD, MM><<<gr, lc.block, 0, s>>>(n, g, u, a.perm, a.packed, a.origin, frac, b, wd, out, delta, gamma, lc.xcd_remap)
+  if (dim == 2) {
+    if (mode == EXT_APPLY) CPM_P1_CASE(2, EXT_APPLY);
+    else if (mode == EXT_RESID) CPM_P1_CASE(2, EXT_RESID);
+    else CPM_P1_CASE(2, EXT_SMOOTH);
+  } else {
+    if (mode == EXT_APPLY) CPM_P1_CASE(3, EXT_APPLY);
+    else if (mode == EXT_RESID) CPM_P1_CASE(3, EXT_RESID);
+    else CPM_P1_CASE(3, EXT_SMOOTH);
+  }
+#undef CPM_P1_CASE
+}
+
+void launch_assemble_coarse_p1(int dim, int n, const int32_t* runE, const double* fracE, const int32_t* nbr,
+                               double delta, double gamma, double inv_h2, double* M, hipStream_t s) {
+  if (n <= 0) return;
+  launch_fill<double>(2 * (int64_t)n * n, M, 0.0, s);
+  if (dim == 2)
+    k_assemble_coarse_p1<2><<<grid_for(n, 128), 128, 0, s>>>(n, runE, fracE, nbr, delta, gamma, inv_h2, M);
+  else
+    k_assemble_coarse_p1<3><<<grid_for(n, 128), 128, 0, s>>>(n, runE, fracE, nbr, delta, gamma, inv_h2, M);
 }
 
 template <typename T>
@@ -520,8 +855,48 @@ __global__ __launch_bounds__(256) void k_incr(int64_t n, const double* __restric
   block_max_atomic(m, slot + 1);
 }
 
+__global__ void k_split_colours(int64_t n, const double* __restrict__ wd, const uint8_t* __restrict__ parity,
+                                double* __restrict__ wdR, double* __restrict__ wdB) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const bool red = parity[i] == 0;
+  wdR[i] = red ? wd[i] : 0.0;
+  wdB[i] = red ? 0.0 : wd[i];
+}
+
+void launch_split_colours(int64_t n, const double* wd, const uint8_t* parity, double* wdR, double* wdB,
+                          hipStream_t s) {
+  if (n > 0) k_split_colours<<<grid_for(n, 256), 256, 0, s>>>(n, wd, parity, wdR, wdB);
+}
+
 void launch_incr(int64_t n, const double* u, const double* p, unsigned long long* slot, hipStream_t s) {
   if (n > 0) k_incr<<<grid_for(n, 256), 256, 0, s>>>(n, u, p, slot);
+}
+
+// The residual of Algorithm 4.1 step 2 as printed: r = f - (cI - L) u = f + N u - delta u at
+// every node, neighbours outside the band dropped.
+template <int D>
+__global__ __launch_bounds__(256) void k_resid_verbatim(int64_t n, const int32_t* __restrict__ nbr,
+                                                        const double* __restrict__ u, const double* __restrict__ f,
+                                                        double delta, double inv_h2, double* __restrict__ r) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double sum = 0.0;
+#pragma unroll
+  for (int q = 0; q < 2 * D; ++q) {
+    const int32_t j = nbr[q * n + i];
+    if (j >= 0) sum += u[j];
+  }
+  r[i] = (f[i] + sum * inv_h2) - delta * u[i];
+}
+
+void launch_resid_verbatim(int dim, int64_t n, const int32_t* nbr, const double* u, const double* f, double delta,
+                           double inv_h2, double* r, hipStream_t s) {
+  if (n <= 0) return;
+  if (dim == 2)
+    k_resid_verbatim<2><<<grid_for(n, 256), 256, 0, s>>>(n, nbr, u, f, delta, inv_h2, r);
+  else
+    k_resid_verbatim<3><<<grid_for(n, 256), 256, 0, s>>>(n, nbr, u, f, delta, inv_h2, r);
 }
 
 template <int D, typename T>
@@ -641,6 +1016,14 @@ template void launch_sweep<double>(int, int, int64_t, const double*, double*, co
                                    hipStream_t);
 template void launch_sweep<float>(int, int, int64_t, const float*, float*, const float*, const float*,
                                   const SweepAddr&, const float*, float, float, float, const LaunchCfg&, hipStream_t);
+template void launch_tile<double, double>(int, int64_t, const TileAddr&, const double*, const double*, const double*,
+                                          const double*, double*, double, double, double, unsigned long long*,
+                                          hipStream_t);
+template void launch_tile<double, float>(int, int64_t, const TileAddr&, const double*, const double*, const double*,
+                                         const double*, float*, double, double, double, unsigned long long*,
+                                         hipStream_t);
+template void launch_tile<float, float>(int, int64_t, const TileAddr&, const float*, const float*, const float*,
+                                        const float*, float*, float, float, float, unsigned long long*, hipStream_t);
 template void launch_restrict<double>(int, int64_t, const double*, const int32_t*, const double*, double*,
                                       double*, const LaunchCfg&, hipStream_t);
 template void launch_restrict<float>(int, int64_t, const float*, const int32_t*, const float*, float*,

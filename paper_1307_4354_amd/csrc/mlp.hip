@@ -123,9 +123,11 @@ __device__ __forceinline__ float node_features(int64_t k, int64_t n, const T* __
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int32_t base = grow[q * groups] + toff;
+    // a row with its outer nodes present and its middle one absent stores them adjacently
+    const int gap = ((mask >> (3 * q)) & 7u) == 5u;
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
-      int64_t a = (int64_t)base + dx;
+      int64_t a = (int64_t)base + dx - (dx == 2 ? gap : 0);
       a = a < 0 ? 0 : (a >= n ? n - 1 : a);
       patch[dx + 3 * q] = r[a];
     }
@@ -377,6 +379,37 @@ __global__ void k_adam(int count, float* __restrict__ w, float* __restrict__ m1,
   wb[i] = f2bf(wn);
 }
 
+// Training target of the learned step at every node: the undamped Ruuth-Merriman correction
+// in the network's units, t_i = r_i / s_i clipped to [-clip, clip] (0 where s_i = 0).
+__global__ void k_targets(int64_t n, const double* __restrict__ r, const float* __restrict__ scale, double clip,
+                          float* __restrict__ T) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float s = scale[i];
+  double t = s > 0.0f ? r[i] / (double)s : 0.0;
+  t = t > clip ? clip : (t < -clip ? -clip : t);
+  T[i] = (float)t;
+}
+
+// loss = (1/m) sum (Y - T)^2 in double, one workgroup (fixed summation order).
+__global__ __launch_bounds__(1024) void k_mse(int64_t m, const float* __restrict__ Y, const float* __restrict__ T,
+                                              double* __restrict__ loss) {
+  __shared__ double part[16];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+    const double d = (double)Y[i] - (double)T[i];
+    acc += d * d;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += part[w];
+    *loss = t / (double)m;
+  }
+}
+
 // fractions in the extension's processing order, and in band order
 template <typename T>
 const T* frac_k(const DevLevel& D);
@@ -436,8 +469,7 @@ cpm_status cpm_set_smoother_weights(cpm_band band, const uint16_t* w_bf16, doubl
     set_error("cpm_set_smoother_weights: invalid argument");
     return CPM_E_INVALID;
   }
-  if (!band->mlpW && hipMalloc((void**)&band->mlpW, kWCount * sizeof(uint16_t)) != hipSuccess) {
-    band->mlpW = nullptr;
+  if (!band->mlpW && !(band->mlpW = (uint16_t*)dev_alloc(band, kWCount * sizeof(uint16_t)))) {
     set_error("device allocation failed");
     return CPM_E_NOMEM;
   }
@@ -520,6 +552,29 @@ cpm_status cpm_smoother_features(cpm_band band, int level, double c, const doubl
                                              scale);
   if ((st = check_launch("cpm_smoother_features")) != CPM_OK) return st;
   return leave(band, stream);
+}
+
+cpm_status cpm_smoother_pairs(cpm_band band, int level, double c, const double* f, const double* u, uint16_t* X,
+                              float* T, float* scale, double clip, void* work, void* stream) {
+  if (!T || !(clip > 0.0)) {
+    set_error("cpm_smoother_pairs: invalid argument");
+    return CPM_E_INVALID;
+  }
+  cpm_status st = cpm_smoother_features(band, level, c, f, u, X, scale, work, stream);
+  if (st != CPM_OK) return st;
+  const int64_t n = band->dev[(size_t)level].n;
+  const double* r = (const double*)work + n;  // the residual cpm_smoother_features left there
+  k_targets<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)stream>>>(n, r, scale, clip, T);
+  return check_launch("cpm_smoother_pairs");
+}
+
+cpm_status cpm_mlp_loss(int64_t m, const float* Y, const float* T, double* loss, void* stream) {
+  if (m <= 0 || !Y || !T || !loss) {
+    set_error("cpm_mlp_loss: invalid argument");
+    return CPM_E_INVALID;
+  }
+  k_mse<<<1, 1024, 0, (hipStream_t)stream>>>(m, Y, T, loss);
+  return check_launch("cpm_mlp_loss");
 }
 
 }  // extern "C"

@@ -8,7 +8,8 @@ and interpolation weights) and the patch scale s.  The target is the correction 
 undamped Ruuth-Merriman step from that state, in the network's units:
 t_i = r_i / s_i with r = E f - A w (the step moves w_i by r_i / delta).  It is a function
 of the features the network sees, so the regression is well posed and its minimiser is
-a stable smoother.  Targets that ask one local step to do the work of several sweeps, or
+a stable smoother; the library computes these targets (cpm_smoother_pairs) and the loss
+(cpm_mlp_loss).  Targets that ask one local step to do the work of several sweeps, or
 to predict the total error u* - w, need information outside the 3^d residual patch; the
 networks fitted to them gave V-cycles that diverge.  Forward, backward and the Adam update
 all run in the library's kernels; torch only holds device memory and draws the minibatch
@@ -81,18 +82,14 @@ def generate_pairs(problems: Sequence[Tuple[object, float, int]], cycles: int = 
         pre = cpm.make_params(c=prob.c, nu1=nu1, nu2=0, omega=omega)
         nbytes = cpm.cpm_workspace_size(band, p)
         work = torch.empty(max(nbytes, 16 * n), dtype=torch.uint8, device="cuda")
-        ef = torch.empty_like(f)
-        cpm.cpm_extend(band, 0, f, ef)
-        aw = torch.empty_like(f)
         u = torch.zeros_like(f)
         X = torch.empty((n, N_IN), dtype=torch.int16, device="cuda")
+        t = torch.empty(n, dtype=torch.float32, device="cuda")
         sc = torch.empty(n, dtype=torch.float32, device="cuda")
 
         def add(w):
-            cpm.cpm_smoother_features(band, 0, prob.c, f, w, X, sc, work)
-            cpm.cpm_apply(band, 0, prob.c, w, aw, work)
-            keep = sc > 0
-            t = ((ef - aw) / sc.double().clamp_min(1e-300)).clamp(-clip, clip).float()
+            cpm.cpm_smoother_pairs(band, 0, prob.c, f, w, X, t, sc, clip, work)
+            keep = sc > 0  # nodes whose residual patch is not zero
             Xs.append(X[keep].clone())
             Ts.append(t[keep].clone())
 
@@ -127,6 +124,7 @@ def train(pairs: Pairs, steps: int = 2000, batch: int = 65536, lr: float = 1e-3,
     G = torch.zeros_like(w)
     Y = torch.empty(batch, dtype=torch.float32, device="cuda")
     Hh = torch.empty((batch, 64), dtype=torch.float32, device="cuda")
+    loss_d = torch.zeros(1, dtype=torch.float64, device="cuda")
     losses = []
     for step in range(1, steps + 1):
         idx = torch.randint(0, N, (batch,), device="cuda", generator=gen)
@@ -136,7 +134,8 @@ def train(pairs: Pairs, steps: int = 2000, batch: int = 65536, lr: float = 1e-3,
         cpm.cpm_mlp_backward(batch, Xb, wb, Hh, Y, Tb, G)
         cpm.cpm_mlp_adam(step, lr, w, m1, m2, G, wb)
         if step % log_every == 0 or step == 1:
-            losses.append(float(((Y - Tb) ** 2).mean()))
+            cpm.cpm_mlp_loss(batch, Y, Tb, loss_d)
+            losses.append(float(loss_d.item()))
     return TrainResult(wb.cpu().numpy().view(np.uint16).copy(), losses)
 
 
@@ -145,5 +144,7 @@ def evaluate_loss(pairs: Pairs, w_bits: np.ndarray, limit: int = 1 << 20) -> flo
     n = min(limit, pairs.X.shape[0])
     wb = torch.as_tensor(np.asarray(w_bits, dtype=np.uint16).view(np.int16)).to("cuda")
     Y = torch.empty(n, dtype=torch.float32, device="cuda")
+    loss_d = torch.zeros(1, dtype=torch.float64, device="cuda")
     cpm.cpm_mlp_forward(n, pairs.X[:n].contiguous(), wb, Y, None)
-    return float(((Y - pairs.T[:n]) ** 2).mean())
+    cpm.cpm_mlp_loss(n, Y, pairs.T[:n].contiguous(), loss_d)
+    return float(loss_d.item())

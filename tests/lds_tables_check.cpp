@@ -3,6 +3,8 @@
 // inside the workgroup's staged range and holds the band index that the gather form of the
 // same pass reads.  Also checks the grouped patch rows of the learned smoother.  Prints one line per level and "ALL OK" or "FAIL"; exit status 1 on a
 // mismatch.
+#include <algorithm>
+#include <array>
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -49,12 +51,23 @@ static long check_level(const HostLevel& H, int dim) {
   return bad;
 }
 
-// Learned-smoother patch rows in grouped form: for every node and every row with a present
-// node, the group's row plus the node's offset is the node's own row.
-static long check_patches(const HostLevel& H, int dim) {
+// Learned-smoother patch rows in grouped form: for every node and every present node of its
+// 3^dim patch, the address the kernels form (the group's row plus the node's offset plus dx,
+// one less for the +1 node of a row whose middle node is absent) is the band index of that
+// grid node, found here by a binary search of the sorted grid keys.  Counts the gapped rows.
+static long check_patches(const HostLevel& H, int dim, long* gaps) {
   if (!H.patchOK) return 0;
   const int rows = dim == 2 ? 3 : 9;
   const int64_t n = H.n, G = H.patchGroups;
+  std::vector<std::array<int32_t, 3>> keys((size_t)n);
+  for (int64_t i = 0; i < n; ++i)
+    keys[(size_t)i] = {dim == 3 ? H.idx[(size_t)(i * dim + 2)] : 0, H.idx[(size_t)(i * dim + 1)],
+                       H.idx[(size_t)(i * dim)]};
+  auto find = [&](int32_t x, int32_t y, int32_t z) -> int64_t {
+    const std::array<int32_t, 3> k = {z, y, x};
+    auto it = std::lower_bound(keys.begin(), keys.end(), k);
+    return (it != keys.end() && *it == k) ? (int64_t)(it - keys.begin()) : -1;
+  };
   long bad = 0;
   for (int64_t i = 0; i < n; ++i) {
     const int64_t g = H.patchPk[i] >> kPatchBits;
@@ -63,9 +76,85 @@ static long check_patches(const HostLevel& H, int dim) {
       ++bad;
       continue;
     }
-    for (int r = 0; r < rows; ++r)
-      if ((H.patchMask[i] >> (3 * r)) & 7u) bad += H.patchBase[(size_t)(r * G + g)] + t != H.patchRow[(size_t)(r * n + i)];
+    const int32_t* m = &H.idx[(size_t)(i * dim)];
+    for (int r = 0; r < rows; ++r) {
+      const uint32_t rm = (H.patchMask[i] >> (3 * r)) & 7u;
+      const int dy = r % 3 - 1, dz = dim == 3 ? r / 3 - 1 : 0;
+      const int gap = rm == 5u;
+      *gaps += gap;
+      for (int dx = 0; dx < 3; ++dx) {
+        const int64_t j = find(m[0] + dx - 1, m[1] + dy, dim == 3 ? m[2] + dz : 0);
+        const bool present = (rm >> dx) & 1u;
+        if (present != (j >= 0)) {
+          ++bad;
+          continue;
+        }
+        if (!present) continue;
+        const int64_t addr = (int64_t)H.patchBase[(size_t)(r * G + g)] + t + dx - (dx == 2 ? gap : 0);
+        bad += addr != j;
+      }
+    }
   }
+  return bad;
+}
+
+// Tiled-sweep tables: every tile's slots are its nodes; for every node, every stencil node
+// (and each of its six Laplacian neighbours) lies in its box row's staged x range, at the
+// band index the gather form of the extension reads; the node's own box cell, when flagged,
+// holds the node itself.  Returns mismatches; *tiles gets the tile count.
+static long check_tiles(const HostLevel& H, long* tiles) {
+  *tiles = H.ntiles;
+  if (H.ntiles <= 0) return 0;
+  const int64_t n = H.n;
+  long bad = 0;
+  std::vector<int> seen((size_t)n, 0);
+  auto row_index = [&](int64_t t, int y, int z, int x, int64_t* idx) -> bool {
+    if (y < 0 || y >= kBoxY || z < 0 || z >= kBoxZ || x < 0 || x >= kBoxX) return false;
+    const int32_t* rr = &H.tileRow[(size_t)(2 * (t * kBoxRows + z * kBoxY + y))];
+    const uint32_t mask = (uint32_t)rr[1];
+    if (!((mask >> x) & 1u)) return false;
+    *idx = (int64_t)rr[0] + __builtin_popcount(mask & ((1u << x) - 1u));
+    return *idx >= 0 && *idx < n;
+  };
+  for (int64_t t = 0; t < H.ntiles; ++t) {
+    const int64_t s0 = H.tileSlot[(size_t)t], s1 = H.tileSlot[(size_t)t + 1];
+    if (s1 < s0) ++bad;
+    for (int64_t k = s0; k < s1; ++k) {
+      const int32_t i = H.tperm[(size_t)k];
+      if (i < 0 || i >= n) {
+        ++bad;
+        continue;
+      }
+      seen[(size_t)i]++;
+      const int32_t loc = H.tloc[(size_t)k];
+      const int lx = loc & 31, ly = loc >> 5 & 31, lz = loc >> 10 & 31;
+      if (lx >= kTileX || ly >= kTileY || lz >= kTileZ) ++bad;
+      for (int c = 0; c < 4; ++c)
+        for (int b = 0; b < 4; ++b)
+          for (int a = 0; a < 4; ++a) {
+            const int x = lx + a + 1, y = ly + b + 1, z = lz + c + 1;  // box cell of the stencil node
+            int64_t j = -1;
+            if (!row_index(t, y, z, x, &j) || j != (int64_t)H.runE[(size_t)((b + 4 * c) * n + i)] + a) {
+              ++bad;
+              continue;
+            }
+            const int d[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+            for (int q = 0; q < 6; ++q) {
+              int64_t jn = -1;
+              if (!row_index(t, y + d[q][1], z + d[q][2], x + d[q][0], &jn) ||
+                  jn != (int64_t)H.nbr[(size_t)(q * n + j)])
+                ++bad;
+            }
+          }
+      for (int a = 0; a < 3; ++a)
+        bad += H.fracT[(size_t)(a * n + k)] != H.fracE[(size_t)(a * n + i)];
+      if (loc >> 30 & 1) {
+        int64_t j = -1;
+        if (!row_index(t, loc >> 20 & 31, loc >> 25 & 31, loc >> 15 & 31, &j) || j != i) ++bad;
+      }
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) bad += seen[(size_t)i] != 1;
   return bad;
 }
 
@@ -82,6 +171,9 @@ int main() {
       {{CPM_SPHERE, {0.1, -0.2, 0.05}, 1.0, 0.0}, 1.0 / 24, 3, 3},
       {{CPM_TORUS, {0.0, 0.0, 0.0}, 1.0, 0.4}, 1.0 / 32, 3, 3},
       {{CPM_DZIUK, {0.0, 0.0, 0.0}, 1.0, 0.0}, 1.0 / 16, 2, 3},
+      {{CPM_TORUS, {0.0, 0.0, 0.0}, 1.0, 0.25}, 1.0 / 16, 3, 3},  // gapped patch rows on level 1
+      {{CPM_SPHERE, {0.0, 0.0, 0.0}, 1.0, 0.0}, 1.0 / 64, 2, 3},   // tiled-sweep tables on level 0
+      {{CPM_TORUS, {0.05, 0.0, 0.0}, 1.0, 0.4}, 1.0 / 64, 2, 3},
   };
   long fails = 0;
   for (const Case& c : cases) {
@@ -93,10 +185,12 @@ int main() {
       return 1;
     }
     for (size_t l = 0; l < lv.size(); ++l) {
-      const long bad = check_level(lv[l], c.dim) + check_patches(lv[l], c.dim);
-      std::printf("kind %d h = 1/%g level %zu: n = %ld, sweep tables %s, patch groups %ld, mismatches %ld\n",
+      long gaps = 0, tiles = 0;
+      const long bad = check_level(lv[l], c.dim) + check_patches(lv[l], c.dim, &gaps) + check_tiles(lv[l], &tiles);
+      std::printf("kind %d h = 1/%g level %zu: n = %ld, sweep tables %s, patch groups %ld, gapped rows %ld, "
+                  "tiles %ld, mismatches %ld\n",
                   c.s.kind, 1.0 / c.h, l, (long)lv[l].n, lv[l].blkE2.empty() ? "absent" : "present",
-                  (long)lv[l].patchGroups, bad);
+                  (long)lv[l].patchGroups, gaps, tiles, bad);
       fails += bad;
     }
   }

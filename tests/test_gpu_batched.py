@@ -1,13 +1,19 @@
-"""Batched solves: each problem of an uneven batch, solved in one batched launch sequence,
-equals its own unbatched mixed-precision solve (same cycles, same iterate), and reaches the
-tolerance.  The unbatched solve is itself checked against the oracle in test_gpu_parity.
+"""Batched solves: each problem of an uneven batch (spheres and tori, 3 and 4 levels) against
+the oracle's mixed-precision solve of the same problem (cycle count, per-cycle residual) and
+its float64 solution; each problem also equals its own unbatched mixed-precision solve.
 The batched kernels sweep with the two passes (neighbour sum, then extension), so the
 unbatched reference solves are pinned to that form (CPM_SWEEP=split) for bitwise equality."""
+import dataclasses
+import math
+
 import numpy as np
 import pytest
 
 import workloads as W
-from tests.gpu_util import build_gpu, dev, host, log, torch_cuda, workspace
+from oracle import band as ob
+from oracle import mixed as omx
+from oracle import vcycle as ov
+from tests.gpu_util import build_gpu, dev, host, log, rel_inf, torch_cuda, workspace
 
 pytestmark = pytest.mark.gpu
 
@@ -23,6 +29,74 @@ def _setup(items):
         bands.append(b)
         fs.append(dev(it.problem.f(cp)))
     return bands, fs
+
+
+def _oracle_batch():
+    items = W.batch_problems(6, seed=W.SEED_BASE + 43, h_choices=(16, 32), coarse_h_inv=4)
+    out = []
+    for k, it in enumerate(items):
+        h_inv = 16 if k % 3 == 0 else 32
+        out.append(dataclasses.replace(it, h0=1.0 / h_inv, levels=int(round(math.log2(h_inv / 4))) + 1))
+    return out
+
+
+def test_batched_matches_oracle():
+    """Six problems (three spheres, three tori; h = 1/16 and 1/32, coarsened to 1/4) in one
+    batched solve against the oracle: cycle count within one of the oracle's mixed-precision
+    solve, each cycle's relative residual within 1 % of it (float32 inner cycles round
+    differently), the final iterate within 1e-9 of the oracle's float64 solution."""
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    items = _oracle_batch()
+    bands, fs, refs = [], [], []
+    for k, it in enumerate(items):
+        s = it.problem.surface
+        H = ob.build_hierarchy(s, it.h0, it.levels, it.lam2)
+        f = it.problem.f(H.levels[0].cp)
+        mx = omx.solve_mixed(H, f, ov.Params(), rtol=1e-10, max_cycles=80)
+        r64 = ov.solve(H, f, ov.Params(), rtol=1e-10, max_cycles=80)
+        log("oracle problem %d: %s h=1/%d n=%s, mixed %d cycles, f64 %d cycles" % (
+            k, s.kind, round(1 / it.h0), [l.n for l in H.levels], mx.cycles, r64.cycles))
+        refs.append((mx, r64))
+        bands.append(build_gpu(s, it.h0, it.levels, it.lam2))
+        fs.append(dev(f))
+    p = cpm.make_params(precision=cpm.CPM_MIXED)
+    us = [torch.zeros_like(f) for f in fs]
+    nbytes = cpm.cpm_workspace_size_batched(bands, p)
+    work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    status, stats = cpm.cpm_solve_batched(bands, p, fs, us, work, nbytes, rtol=1e-10, max_cycles=80)
+    assert status == cpm.CPM_OK
+    for k, (st, u, (mx, r64)) in enumerate(zip(stats, us, refs)):
+        err = rel_inf(host(u), r64.u)
+        log("problem %d: %d cycles (oracle %d), relres %.3e, rel diff to f64 oracle %.2e" % (
+            k, st.cycles, mx.cycles, st.relres, err))
+        assert abs(st.cycles - mx.cycles) <= 1
+        hg, ho = st.history(), mx.relres
+        for j in range(min(len(hg), len(ho))):
+            assert abs(hg[j] - ho[j]) <= 1e-2 * ho[j], (k, j, hg[j], ho[j])
+        assert st.relres < 1e-10
+        assert err < 1e-9
+    # one host synchronization per graph launch of several cycles
+    cyc = max(st.cycles for st in stats)
+    assert stats[0].cycles_per_launch > 1
+    assert stats[0].host_syncs <= -(-cyc // stats[0].cycles_per_launch) + 1
+
+
+def test_batched_stops_at_max_cycles():
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    items = W.batch_problems(3, seed=W.SEED_BASE + 44, h_choices=(16,), coarse_h_inv=4)
+    bands, fs = _setup(items)
+    p = cpm.make_params(precision=cpm.CPM_MIXED)
+    us = [torch.zeros_like(f) for f in fs]
+    nbytes = cpm.cpm_workspace_size_batched(bands, p)
+    work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    status, stats = cpm.cpm_solve_batched(bands, p, fs, us, work, nbytes, rtol=1e-10, max_cycles=5,
+                                          raise_on_noconv=False)
+    assert status == cpm.CPM_E_NOCONV
+    assert all(st.cycles == 5 for st in stats)
 
 
 def test_batched_equals_unbatched_mixed(monkeypatch):
@@ -52,15 +126,17 @@ def test_batched_equals_unbatched_mixed(monkeypatch):
 
 
 def test_batched_converged_problem_is_frozen():
-    """A problem that starts at its solution does no cycle while the others run."""
+    """A problem with E f = 0 gets u = 0 (from a non-zero start) and no cycle while the others
+    run."""
     import paper_1307_4354_amd as cpm
 
     torch = torch_cuda()
     items = W.batch_problems(3, seed=W.SEED_BASE + 41, h_choices=(16,), coarse_h_inv=4)
     bands, fs = _setup(items)
     p = cpm.make_params(precision=cpm.CPM_MIXED)
-    fs[1].zero_()  # E f = 0: solved by u = 0 before any cycle
+    fs[1].zero_()  # E f = 0: solved by u = 0 before any cycle, whatever the start
     us = [torch.zeros_like(f) for f in fs]
+    us[1].fill_(0.5)
     nbytes = cpm.cpm_workspace_size_batched(bands, p)
     work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     status, stats = cpm.cpm_solve_batched(bands, p, fs, us, work, nbytes, rtol=1e-10, max_cycles=80)

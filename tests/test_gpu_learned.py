@@ -19,6 +19,22 @@ def _rand_weights(seed, scale=0.3):
                    rng.standard_normal(64) * scale, 0.25)
 
 
+def _near_jacobi_weights(seed, noise=0.02, omega=0.8):
+    """A network with every weight random (scale `noise`) except two hidden units that carry
+    the Jacobi step omega * x_centre: a non-trivial network whose cycle contracts."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.standard_normal((64, 64)) * noise
+    b1 = rng.standard_normal(64) * noise
+    w2 = rng.standard_normal(64) * noise
+    W1[0, :] = 0.0
+    W1[1, :] = 0.0
+    W1[0, 13] = 1.0
+    W1[1, 13] = -1.0
+    b1[:2] = 0.0
+    w2[0], w2[1] = omega, -omega
+    return om.pack(W1, b1, w2, 0.0)
+
+
 def _bits_dev(bits):
     return dev(np.asarray(bits, dtype=np.uint16).view(np.int16))
 
@@ -42,8 +58,12 @@ def test_mlp_forward_matches_oracle(m):
     assert np.max(np.abs(h - h_ref)) <= 1e-4 * max(1.0, np.max(np.abs(h_ref)))
 
 
-@pytest.mark.parametrize("m", [100, 5000])
+@pytest.mark.parametrize("m", [100, 5000, 70001])
 def test_mlp_backward_matches_oracle(m):
+    """The backward kernel on the oracle's forward values (H, Y rounded to float32): every
+    element of dW1 against the oracle's gradient that rounds the hidden error to bfloat16 as
+    the matrix cores take it, within float32 accumulation (1e-5 of the sum of the terms'
+    magnitudes); b1, w2, b2 element by element to float32 accumulation."""
     log("mlp backward m=%d" % m)
     import paper_1307_4354_amd as cpm
 
@@ -52,71 +72,129 @@ def test_mlp_backward_matches_oracle(m):
     X = om.bf16_round(rng.uniform(-1, 1, (m, 64)).astype(np.float32))
     T = rng.standard_normal(m).astype(np.float32)
     w = _rand_weights(8)
-    _, g_ref = om.loss_and_grad(X, T.astype(np.float64), w)
+    y_ref, h_ref = om.forward(X, w)
+    H32, Y32 = h_ref.astype(np.float32), y_ref.astype(np.float32)
+    g_ref = om.backward_bf16(X, w, H32, Y32, T)
     Xd, Wd = _bits_dev(om.bf16_bits(X)), _bits_dev(w)
-    Y = torch.empty(m, dtype=torch.float32, device="cuda")
-    H = torch.empty((m, 64), dtype=torch.float32, device="cuda")
     G = torch.empty(om.N_W, dtype=torch.float32, device="cuda")
-    cpm.cpm_mlp_forward(m, Xd, Wd, Y, H)
-    cpm.cpm_mlp_backward(m, Xd, Wd, H, Y, dev(T), G)
+    cpm.cpm_mlp_backward(m, Xd, Wd, dev(H32), dev(Y32), dev(T), G)
     g = host(G).astype(np.float64)
     o = 64 * 64
-    # dW1 is contracted on the matrix cores with dH rounded to bf16 (relative 2^-9 per term)
-    assert np.linalg.norm(g[:o] - g_ref[:o]) <= 1e-2 * np.linalg.norm(g_ref[:o])
-    # b1, w2, b2 are float32 sums
-    assert np.max(np.abs(g[o:] - g_ref[o:])) <= 1e-4 * max(1e-6, np.max(np.abs(g_ref[o:])))
+    dy = (np.float32(2.0) / np.float32(m)) * (Y32 - T)
+    dh = np.abs(np.where(H32 > 0, dy[:, None] * om.unpack(w)[2].astype(np.float32)[None, :], 0.0))
+    mag = dh.astype(np.float64).T @ np.abs(X.astype(np.float64))  # sum of |terms| per element
+    assert np.all(np.abs(g[:o] - g_ref[:o]) <= 1e-5 * mag.ravel() + 1e-30)
+    mag_b1 = dh.astype(np.float64).sum(axis=0)
+    assert np.all(np.abs(g[o:o + 64] - g_ref[o:o + 64]) <= 1e-5 * mag_b1 + 1e-30)
+    mag_w2 = H32.astype(np.float64).T @ np.abs(dy.astype(np.float64))
+    assert np.all(np.abs(g[o + 64:o + 128] - g_ref[o + 64:o + 128]) <= 1e-5 * mag_w2 + 1e-30)
+    assert abs(g[-1] - g_ref[-1]) <= 1e-5 * float(np.abs(dy).astype(np.float64).sum())
+
+
+def test_mlp_loss_matches_definition():
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    rng = np.random.default_rng(3)
+    for m in (1, 1000, 65536):
+        Y = rng.standard_normal(m).astype(np.float32)
+        T = rng.standard_normal(m).astype(np.float32)
+        out = torch.zeros(1, dtype=torch.float64, device="cuda")
+        cpm.cpm_mlp_loss(m, dev(Y), dev(T), out)
+        ref = float(np.mean((Y.astype(np.float64) - T.astype(np.float64)) ** 2))
+        assert abs(float(host(out)[0]) - ref) <= 1e-12 * ref
 
 
 def _learned_case():
     return W.config_sphere(16, 3)
 
 
-def test_features_match_oracle():
-    log("smoother features")
+def _features_check(cfg, level, u_seed):
     import paper_1307_4354_amd as cpm
 
     torch = torch_cuda()
-    cfg = _learned_case()
     H = oracle_for(cfg)
-    lev = H.levels[0]
-    f = cfg.problem.f(lev.cp)
-    u = W.random_vector(lev.n, 5) * 0.01
-    r = ov.residual(H, 0, u, f, ov.Params())
+    lev = H.levels[level]
+    f = cfg.problem.f(lev.cp) if level == 0 else W.random_vector(lev.n, u_seed + 1)
+    u = W.random_vector(lev.n, u_seed) * 0.01
+    r = ov.residual(H, level, u, f, ov.Params())
     X_ref, s_ref = om.features(lev, r)
     band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
     X = torch.empty((lev.n, 64), dtype=torch.int16, device="cuda")
     s = torch.empty(lev.n, dtype=torch.float32, device="cuda")
     work = torch.empty(2 * lev.n, dtype=torch.float64, device="cuda")
-    cpm.cpm_smoother_features(band, 0, 1.0, dev(f), dev(u), X, s, work)
+    cpm.cpm_smoother_features(band, level, 1.0, dev(f), dev(u), X, s, work)
     Xg = om.from_bf16_bits(host(X).view(np.uint16))
     assert np.allclose(host(s), s_ref.astype(np.float32), rtol=1e-6)
-    diff = Xg != X_ref.astype(np.float32)
-    # identical except where a double-rounding boundary of bf16 is hit (weights computed in
-    # a different but equivalent product order)
-    assert diff.mean() < 1e-3
-    assert np.max(np.abs(Xg - X_ref)) <= 2 ** -7
+    ref = X_ref.astype(np.float32)
+    diff = Xg != ref
+    # both sides round the same float32 quotient to bfloat16; the residual itself is summed in
+    # another order (rounding-level differences), which can move a value across a rounding
+    # boundary: then the two differ by one bfloat16 step, and only rarely
+    log("features level %d: %d of %d entries differ" % (level, int(diff.sum()), diff.size))
+    assert diff.mean() < 1e-5
+    ulp = np.abs(ref) * 2.0 ** -7
+    assert np.all(np.abs(Xg - ref)[diff] <= ulp[diff] * (1 + 1e-6) + 1e-38)
+    # training targets: the undamped step r / s in the network's units, clipped
+    T = torch.empty(lev.n, dtype=torch.float32, device="cuda")
+    cpm.cpm_smoother_pairs(band, level, 1.0, dev(f), dev(u), X, T, s, 16.0, work)
+    safe = np.where(s_ref > 0, s_ref, 1.0)
+    t_ref = np.where(s_ref > 0, np.clip(r / safe, -16.0, 16.0), 0.0).astype(np.float32)
+    assert np.all(np.abs(host(T) - t_ref) <= 1e-6 * np.abs(t_ref) + 1e-30)
 
 
-def test_learned_vcycle_matches_oracle():
-    log("learned V-cycle parity")
+def test_features_match_oracle():
+    log("smoother features")
+    _features_check(_learned_case(), 0, 5)
+
+
+def test_features_match_oracle_with_gapped_patch_rows():
+    """Level 1 of the torus R = 1, r = 0.25 at h = 1/16 has patch rows whose middle node is
+    outside the band while both outer ones are inside."""
+    log("smoother features, gapped rows")
+    _features_check(_gap_case(), 1, 6)
+
+
+def _gap_case():
+    return W.SolverConfig("torus_r0.25_h16", W.torus_modes(1.0, 0.25, W.SEED_BASE + 50), 1.0 / 16, 3, W.LAM2_3D)
+
+
+@pytest.mark.parametrize("case", ["sphere16", "torus_gapped"])
+def test_learned_vcycles_match_oracle(case):
+    """Four learned V-cycles (network on levels 0 and 1) against the oracle's learned cycle,
+    iterate by iterate, with a network whose every weight is non-zero and whose cycle
+    contracts (a diverging cycle amplifies any rounding difference).  The network runs in
+    float32 on the GPU (bf16 MFMA, float32 accumulation of 40 products per hidden unit, 64
+    per output) and in float64 in the oracle on the same bf16 inputs and weights, so every
+    learned update differs by about 1e-6 of its size; a cycle makes 24 of them (6 sweeps on
+    each of two levels, before and after the coarse correction), and the differences add up
+    until the cycle's contraction damps them: the iterates agree to 2e-4 relative (measured:
+    6e-6 after one cycle, 4e-5 after two); the residual E f - A u weighs those differences by
+    A's large diagonal (6/h^2), so the per-cycle residuals agree to 1e-2 relative (measured:
+    1.2e-3 after three cycles)."""
+    log("learned V-cycle parity %s" % case)
     import paper_1307_4354_amd as cpm
 
     torch = torch_cuda()
-    cfg = _learned_case()
+    cfg = _learned_case() if case == "sphere16" else _gap_case()
     H = oracle_for(cfg)
     f = cfg.problem.f(H.levels[0].cp)
-    w = _rand_weights(9, scale=0.05)
-    ref = ov.solve(H, f, ov.Params(learned=w), rtol=0.0, max_cycles=2, keep_iterates=True)
+    w = _near_jacobi_weights(9)
+    ref = ov.solve(H, f, ov.Params(learned=w), rtol=0.0, max_cycles=4, keep_iterates=True)
+    assert ref.relres[-1] < 0.1 * ref.relres[0]
     band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
     cpm.cpm_set_smoother_weights(band, w, 10.0)
     p = cpm.make_params(smoother=cpm.CPM_SMOOTH_LEARNED)
     work, nbytes = workspace(band, p)
     fd = dev(f)
     ud = torch.zeros_like(fd)
-    st = cpm.cpm_solve(band, p, fd, ud, work, nbytes, rtol=0.0, max_cycles=1, raise_on_noconv=False)
-    assert st.cycles == 1
-    err = rel_inf(host(ud), ref.iterates[0])
-    assert err < 1e-4, err
+    for k in range(4):
+        st = cpm.cpm_solve(band, p, fd, ud, work, nbytes, rtol=0.0, max_cycles=1, raise_on_noconv=False)
+        assert st.cycles == 1 and st.fallback_cycle < 0
+        err = rel_inf(host(ud), ref.iterates[k])
+        log("cycle %d: rel diff %.3e, relres %.4e vs %.4e" % (k, err, st.relres, ref.relres[k]))
+        assert err < 2e-4, (k, err)
+        assert abs(st.relres - ref.relres[k]) <= 1e-2 * ref.relres[k]
 
 
 def test_learned_cycles_from_the_stopping_residual():

@@ -85,8 +85,10 @@ def _gpu_iterates(cfg, ncycles, params=None, check_sweep=None):
     f = cfg.problem.f(H.levels[0].cp)
     band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
     if check_sweep is not None:
-        fused = [cpm.cpm_band_tuning(band, l)[3] for l in range(band.levels - 1)]
+        tun = [cpm.cpm_band_tuning(band, l) for l in range(band.levels - 1)]
+        fused, tiled = [t[3] for t in tun], [t[6] for t in tun]
         assert all(fused) if check_sweep == "fused" else not any(fused), fused
+        assert all(tiled) if check_sweep == "tile" else not any(tiled), tiled
     p = params or cpm.make_params(c=cfg.problem.c, nu1=cfg.nu1, nu2=cfg.nu2, omega=cfg.omega)
     work, nbytes = workspace(band, p)
     fd = dev(f)
@@ -104,12 +106,16 @@ def _gpu_iterates(cfg, ncycles, params=None, check_sweep=None):
     ("sphere64_first4", W.config_sphere(64, 5), 4),
     ("torus32", W.SolverConfig("t32", W.torus_modes(1.0, 0.4, 7), 1 / 32, 3, W.LAM2_3D), 20),
 ], ids=["circle64", "sphere32", "sphere64_first4", "torus32"])
-@pytest.mark.parametrize("sweep", ["split", "fused"])
+@pytest.mark.parametrize("sweep", ["split", "fused", "tile"])
 def test_vcycle_iterates_match_oracle(name, cfg, ncyc, sweep, monkeypatch):
-    """Both sweep forms (neighbour sum + extension passes, or the fused E f + (E N) u pass,
-    pinned with CPM_SWEEP when the band is built) give the oracle's iterates."""
+    """Every sweep form (neighbour sum + extension passes, the fused E f + (E N) u pass, the
+    tiled pass that forms f + N u in LDS; pinned with CPM_SWEEP when the band is built, tiles
+    built on every 3-D level) gives the oracle's iterates."""
+    if sweep == "tile" and cfg.problem.surface.dim == 2:
+        pytest.skip("the tiled pass is 3-D only")
     log("V-cycle iterate parity: %s (%d cycles, %s sweeps)" % (name, ncyc, sweep))
     monkeypatch.setenv("CPM_SWEEP", sweep)
+    monkeypatch.setenv("CPM_TILE_MIN_NODES", "1000")
     H, f, its, rels = _gpu_iterates(cfg, ncyc, check_sweep=sweep)
     ref = ov.solve(H, f, ov.Params(c=cfg.problem.c), rtol=0.0, max_cycles=ncyc, keep_iterates=True)
     for k in range(ncyc):
@@ -147,12 +153,15 @@ def test_solve_matches_oracle(name, cfg):
     ("circle64", W.config_circle(64, 4)),
     ("torus32", W.config_torus_mixed(32, 3)),
 ], ids=["circle64", "torus32"])
-@pytest.mark.parametrize("sweep", ["split", "fused"])
+@pytest.mark.parametrize("sweep", ["split", "fused", "tile"])
 def test_mixed_precision_matches_oracle(name, cfg, sweep, monkeypatch):
+    if sweep == "tile" and cfg.problem.surface.dim == 2:
+        pytest.skip("the tiled pass is 3-D only")
     log("mixed precision parity: %s (%s sweeps)" % (name, sweep))
     import paper_1307_4354_amd as cpm
 
     monkeypatch.setenv("CPM_SWEEP", sweep)
+    monkeypatch.setenv("CPM_TILE_MIN_NODES", "1000")
     torch = torch_cuda()
     H = oracle_for(cfg)
     f = cfg.problem.f(H.levels[0].cp)
@@ -173,13 +182,14 @@ def test_mixed_precision_matches_oracle(name, cfg, sweep, monkeypatch):
     assert rel_inf(host(ud), ref64.u) < 1e-9
 
 
-@pytest.mark.parametrize("sweep", ["split", "fused"])
+@pytest.mark.parametrize("sweep", ["split", "fused", "tile"])
 def test_graph_replays_match_eager_cycles(sweep, monkeypatch):
     """cpm_run_cycles (captured graph, replayed) gives the same iterates as eager cycles, bit
     for bit, also where its later cycles start from the residual the previous cycle left."""
     import paper_1307_4354_amd as cpm
 
     monkeypatch.setenv("CPM_SWEEP", sweep)
+    monkeypatch.setenv("CPM_TILE_MIN_NODES", "1000")
     torch = torch_cuda()
     cfg = W.config_sphere(32, 4)
     H = oracle_for(cfg)
@@ -246,6 +256,80 @@ def test_fused_sweep_lds_equals_gathers(name, cfg, precision, monkeypatch):
         assert np.array_equal(out["1"][k], out["0"][k]), k
 
 
+@pytest.mark.parametrize("name,cfg", [
+    ("sphere64", W.config_sphere(64, 5)),
+    ("torus32", W.config_torus_mixed(32, 3)),
+], ids=["sphere64", "torus32"])
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_tiled_sweep_equals_two_passes(name, cfg, precision, monkeypatch):
+    """The tiled pass forms f + N u in LDS in the neighbour-sum pass's order and interpolates
+    it in the extension pass's order: cycles with it on every level agree with the two-pass
+    cycles to rounding (the same expressions; the compiler may contract them differently)."""
+    log("tiled sweep vs two passes: %s %s" % (name, precision))
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    prec = cpm.CPM_F64 if precision == "f64" else cpm.CPM_MIXED
+    monkeypatch.setenv("CPM_TILE_MIN_NODES", "1000")
+    out = {}
+    fd = None
+    for form in ("tile", "split"):
+        monkeypatch.setenv("CPM_SWEEP", form)
+        band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+        if fd is None:
+            fd = dev(cfg.problem.f(band.export(0)[1]))
+        tun = [cpm.cpm_band_tuning(band, l) for l in range(band.levels - 1)]
+        assert all(t[6] == (form == "tile") for t in tun)
+        p = cpm.make_params(c=cfg.problem.c, precision=prec)
+        work, nbytes = workspace(band, p)
+        ud = torch.zeros_like(fd)
+        hist = torch.zeros(8, dtype=torch.float64, device="cuda")
+        its = []
+        for _ in range(4):
+            cpm.cpm_run_cycles(band, p, fd, ud, work, nbytes, 1, 1, hist)
+            its.append(host(ud).copy())
+        out[form] = its
+        del work, band
+    tol = 1e-13 if precision == "f64" else 1e-5
+    for k in range(4):
+        err = rel_inf(out["tile"][k], out["split"][k])
+        log("cycle %d: rel diff %.3e (bitwise equal: %s)" % (k, err, np.array_equal(out["tile"][k], out["split"][k])))
+        assert err <= tol, (k, err)
+
+
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_ext_prefetch_equals_plain_lds(precision, monkeypatch):
+    """The LDS-staged extension that loads each node's own data before the staging does the
+    same arithmetic as the one that loads it after: cycles agree bit for bit."""
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    cfg = W.config_sphere(32, 4)
+    prec = cpm.CPM_F64 if precision == "f64" else cpm.CPM_MIXED
+    monkeypatch.setenv("CPM_SWEEP", "split")
+    out = {}
+    fd = None
+    for pf in ("1", "0"):
+        monkeypatch.setenv("CPM_EXT_PREFETCH", pf)
+        band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+        if fd is None:
+            fd = dev(cfg.problem.f(band.export(0)[1]))
+        tun = [cpm.cpm_band_tuning(band, l) for l in range(band.levels - 1)]
+        assert all(t[0] and t[7] == (pf == "1") for t in tun), tun
+        p = cpm.make_params(precision=prec)
+        work, nbytes = workspace(band, p)
+        ud = torch.zeros_like(fd)
+        hist = torch.zeros(8, dtype=torch.float64, device="cuda")
+        its = []
+        for _ in range(4):
+            cpm.cpm_run_cycles(band, p, fd, ud, work, nbytes, 1, 1, hist)
+            its.append(host(ud).copy())
+        out[pf] = its
+        del work, band
+    for k in range(4):
+        assert np.array_equal(out["1"][k], out["0"][k]), k
+
+
 def test_calls_run_on_the_callers_stream():
     """Cycles enqueued on a side stream are ordered with that stream's later work (no
     synchronisation in between) and give the default stream's iterates bit for bit."""
@@ -283,7 +367,7 @@ def test_set_band_tuning():
     band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
     for l in range(band.levels - 1):
         cpm.cpm_set_band_tuning(band, l, False, 128, 512, True, 512, False)
-        assert cpm.cpm_band_tuning(band, l) == (False, 128, 512, True, 512, False)
+        assert cpm.cpm_band_tuning(band, l) == (False, 128, 512, True, 512, False, False, False)
     with pytest.raises(cpm.CpmError):
         cpm.cpm_set_band_tuning(band, 0, True, 100, 256, False, 256, False)  # workgroup size
     before = cpm.cpm_band_tuning(band, 0)
@@ -310,7 +394,7 @@ def test_autotune_on_bands_that_cannot_cycle():
     band = build_gpu(cfg.problem.surface, cfg.h0, 1, cfg.lam2)
     assert band.n(0) > 12000
     cpm.cpm_autotune(band)
-    assert len(cpm.cpm_band_tuning(band, 0)) == 6
+    assert len(cpm.cpm_band_tuning(band, 0)) == 8
     fd = dev(cfg.problem.f(band.export(0)[1]))
     p = cpm.make_params()
     work, nbytes = workspace(band, p)
@@ -387,7 +471,8 @@ def test_autotuned_solve_matches_oracle():
     band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
     cpm.cpm_autotune(band)
     for l in range(band.levels):
-        lds, eb, nb, fused, sb, slds = cpm.cpm_band_tuning(band, l)
+        lds, eb, nb, fused, sb, slds, tiled, pf = cpm.cpm_band_tuning(band, l)
+        assert lds or not pf
         assert eb in (128, 256, 512) and nb in (128, 256, 512) and sb in (128, 256, 512)
         assert sb == 256 or not slds
     p = cpm.make_params()

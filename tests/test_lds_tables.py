@@ -3,7 +3,10 @@ builder with g++ and runs it.  For circles, spheres (centred and off-centre), a 
 Dziuk's surface it checks, on every level and for every node, that each LDS address the
 LDS-staged extension and fused sweep form lies in its workgroup's staged range and holds the
 band index the gather form of the same pass reads (so the two forms read the same values), and
-that the learned smoother's grouped patch rows give back every node's own rows."""
+that the learned smoother's grouped patch rows address every present patch node (rows with
+an absent middle node included) at the band index a search of the sorted grid keys finds, and
+that the tiled sweep's row tables stage, for every node, its stencil nodes and their Laplacian
+neighbours at the band indices the extension and the neighbour sum read."""
 import os
 import subprocess
 
@@ -26,3 +29,10 @@ def test_lds_staging_tables(tmp_path):
     # the fused sweep's tables exist on the levels that have its addressing
     assert "sweep tables present" in out.stdout
     assert "patch groups 0," not in out.stdout.split("level 0:")[1].split("\n")[0]
+    # rows whose middle node is absent (outer nodes present) occur and are addressed
+    assert any("gapped rows 0," not in ln for ln in out.stdout.splitlines() if "gapped rows" in ln)
+    # tiled-sweep tables exist on the large levels, and on every 3-D level when asked for
+    assert any("tiles 0," not in ln for ln in out.stdout.splitlines() if "tiles" in ln)
+    env = dict(os.environ, CPM_TILE_MIN_NODES="1000")
+    out2 = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=600, env=env)
+    assert out2.returncode == 0 and "ALL OK" in out2.stdout, out2.stdout[-3000:]
