@@ -222,6 +222,14 @@ typedef enum { CPM_DTYPE_F64 = 0, CPM_DTYPE_F32 = 1 } cpm_dtype;
 cpm_status cpm_apply(cpm_band band, int level, int dtype, double c, const void* u, void* Au, void* work,
                      void* stream);
 
+/* cpm_apply without a workspace, for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops): the work vector is a file-scope device array of 32 MiB that
+ * every GPU the library runs on holds until the process ends (4 Mi doubles / 8 Mi floats).
+ * Levels whose work vector would exceed it are refused with CPM_E_WORKSPACE.  No device
+ * memory is allocated or freed.  All calls on one GPU share that array: calls that overlap in
+ * time on one GPU (two streams, or two host threads) race and must be ordered by the caller. */
+cpm_status cpm_apply_static(cpm_band band, int level, int dtype, double c, const void* u, void* Au, void* stream);
+
 /* A u for the family of Sec. 3.1: A = c I - M, M = E_p L - gamma (I - E_3), gamma = 2d/h^2,
  * p = 3 (cpm_apply) or p = 1 (Remark 3.2: linear interpolation in front of the Laplacian, a
  * sparser matrix with the same second order, the operator of Table 3.1):

@@ -86,6 +86,7 @@ def _load():
         "cpm_workspace_size": (c_int, [vp, POINTER(cpm_params), POINTER(c_size_t)]),
         "cpm_apply": (c_int, [vp, c_int, c_int, c_double, vp, vp, vp, vp]),
         "cpm_apply_pq": (c_int, [vp, c_int, c_int, c_double, vp, vp, vp, vp]),
+        "cpm_apply_static": (c_int, [vp, c_int, c_int, c_double, vp, vp, vp]),
         "cpm_extend": (c_int, [vp, c_int, vp, vp, vp]),
         "cpm_vcycle": (c_int, [vp, POINTER(cpm_params), vp, vp, vp, c_size_t, POINTER(c_double), vp]),
         "cpm_solve": (c_int, [vp, POINTER(cpm_params), vp, vp, vp, c_size_t, c_double, c_int,
@@ -299,6 +300,14 @@ def cpm_apply(band: Band, level: int, c: float, u, Au, work, stream=None) -> Non
 
 def cpm_apply_pq(band: Band, level: int, p: int, c: float, u, Au, work, stream=None) -> None:
     _check(_lib.cpm_apply_pq(band.handle, level, int(p), float(c), _ptr(u), _ptr(Au), _ptr(work), _stream(stream)))
+
+
+def cpm_apply_static(band: Band, level: int, c: float, u, Au, stream=None) -> None:
+    """cpm_apply without a workspace argument (the library's static scratch array)."""
+    import torch
+
+    dt = CPM_DTYPE_F32 if getattr(u, "dtype", None) == torch.float32 else CPM_DTYPE_F64
+    _check(_lib.cpm_apply_static(band.handle, level, dt, float(c), _ptr(u), _ptr(Au), _stream(stream)))
 
 
 def cpm_extend(band: Band, level: int, g, out, stream=None) -> None:
