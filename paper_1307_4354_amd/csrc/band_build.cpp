@@ -462,15 +462,27 @@ struct StageSet {
   }
 };
 
-// LDS staging tables of the extension (see HostLevel): for every workgroup of kExtBlock
-// consecutive stencil slots, merge the x-runs its nodes read into segments of consecutive
+// LDS staging tables of the extension (see HostLevel): for every workgroup of kExtBlock *
+// extNpt consecutive stencil slots, merge the x-runs its nodes read into segments of consecutive
 // band indices, lay the segments out one after another in LDS and record, per local group
 // (a group cut at the workgroup boundary), where each x-run starts in LDS.  Levels with the
 // fused-sweep addressing also get the fused sweep's tables on the same workgroups: rows
 // widened by one node on each side in x, plus the cross rows.
 void build_lds_tables(HostLevel& Lv, int S, int SX) {
   const int64_t n = Lv.n;
-  const int64_t nb = (n + kExtBlock - 1) / kExtBlock;
+  bool sweep = Lv.fusedOK && !Lv.originX.empty();
+  // slots per workgroup: 2 per thread on the largest levels (where the fused sweep, which
+  // keeps one per thread, has no tables); CPM_EXT_NPT = 1, 2 or 4 overrides, and a value above
+  // 1 drops the fused sweep's LDS tables (that pass then takes its gather form)
+  int npt = !sweep && n >= kExtNptMinNodes ? 2 : 1;
+  if (const char* e = std::getenv("CPM_EXT_NPT")) {
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4) npt = v;
+    if (npt > 1) sweep = false;
+  }
+  Lv.extNpt = npt;
+  const int64_t wg = (int64_t)kExtBlock * npt;
+  const int64_t nb = (n + wg - 1) / wg;
   const int32_t xmask = (1 << kXoffBits) - 1;
   Lv.blkE.assign((size_t)nb + 1, 0);
   Lv.blkG.assign((size_t)nb + 1, 0);
@@ -479,7 +491,6 @@ void build_lds_tables(HostLevel& Lv, int S, int SX) {
   Lv.packedL.assign((size_t)n, 0);
   Lv.maxE = 0;
   Lv.maxG = 0;
-  const bool sweep = Lv.fusedOK && !Lv.originX.empty();
   Lv.blkE2.assign(sweep ? (size_t)nb + 1 : 0, 0);
   Lv.gidx2.clear();
   Lv.lorg2.clear();
@@ -487,7 +498,7 @@ void build_lds_tables(HostLevel& Lv, int S, int SX) {
   std::vector<std::pair<int32_t, int32_t>> iv;  // [start, end) intervals of band indices
   StageSet set2;
   for (int64_t b = 0; b < nb; ++b) {
-    const int64_t k0 = b * kExtBlock, k1 = std::min<int64_t>(n, k0 + kExtBlock);
+    const int64_t k0 = b * wg, k1 = std::min<int64_t>(n, k0 + wg);
     // local groups: runs of equal global group id
     std::vector<int64_t> lg_first;
     std::vector<int32_t> lg_gid, lg_xmin, lg_xmax;
@@ -579,10 +590,13 @@ cpm_status build_stencil_order(HostLevel& Lv, int level, std::string& err) {
     by[(size_t)i] = Lv.idx[(size_t)(j * dim + 1)];
     if (dim == 3) bz[(size_t)i] = Lv.idx[(size_t)(j * dim + 2)];
   }
-  // Visit order: stencil bases grouped into blocks of B^dim cells ordered along a Morton
-  // curve, (z, y, x) inside a block.  Consecutive workgroups then touch a compact region
-  // of the band, whose rows stay in L2 while their neighbours are processed.
-  int block_bits = -1;  // no blocking (plain (z, y, x) order) unless CPM_MORTON_BITS is set
+  // Visit order: stencil bases grouped into blocks of 8^dim cells ordered along a Morton
+  // curve, (z, y, x) inside a block.  A workgroup's slots then hold a compact patch of the
+  // surface rather than a strip along y, so the union of their stencils (the values it
+  // stages) is about half as large, and consecutive workgroups touch neighbouring regions
+  // whose rows stay in L2.  CPM_MORTON_BITS sets log2 of the block edge; a negative value
+  // gives the plain (z, y, x) order.
+  int block_bits = 3;
   if (const char* e = std::getenv("CPM_MORTON_BITS")) block_bits = std::atoi(e);
   int32_t mn[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
   for (int64_t i = 0; i < n; ++i) {
@@ -897,7 +911,7 @@ void build_tiles(HostLevel& Lv) {
   const int64_t n = Lv.n;
   auto fdiv = [](int32_t a, int32_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
   std::vector<int32_t> tc((size_t)(3 * n));
-  int32_t mn[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, mx[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+  int32_t mn[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
   const int32_t T[3] = {kTileX, kTileY, kTileZ};
   for (int64_t i = 0; i < n; ++i) {
     const int32_t j = Lv.runE[(size_t)i];  // run (0, 0) starts at the stencil base
@@ -905,15 +919,17 @@ void build_tiles(HostLevel& Lv) {
       const int32_t t = fdiv(Lv.idx[(size_t)(j * 3 + a)], T[a]);
       tc[(size_t)(3 * i + a)] = t;
       mn[a] = std::min(mn[a], t);
-      mx[a] = std::max(mx[a], t);
     }
   }
-  const uint64_t NX = (uint64_t)(mx[0] - mn[0] + 1), NY = (uint64_t)(mx[1] - mn[1] + 1);
+  // tiles in Morton order of their coordinates, so that consecutive workgroups (one per tile)
+  // stage overlapping boxes while the shared rows are still in L2
   std::vector<std::pair<uint64_t, int32_t>> key((size_t)n);
 #pragma omp parallel for
   for (int64_t i = 0; i < n; ++i) {
-    const uint64_t k = ((uint64_t)(tc[(size_t)(3 * i + 2)] - mn[2]) * NY + (uint64_t)(tc[(size_t)(3 * i + 1)] - mn[1])) * NX +
-                       (uint64_t)(tc[(size_t)(3 * i)] - mn[0]);
+    uint64_t k = 0;
+    for (int bit = 0; bit < 21; ++bit)
+      for (int a = 0; a < 3; ++a)
+        k |= (uint64_t)(((uint32_t)(tc[(size_t)(3 * i + a)] - mn[a]) >> bit) & 1u) << (3 * bit + a);
     key[(size_t)i] = {k, (int32_t)i};
   }
   std::sort(key.begin(), key.end());

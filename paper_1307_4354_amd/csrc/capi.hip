@@ -369,6 +369,7 @@ ExtAddr ext_addr(const DevLevel& D) {
     a.lorg = D.lorg;
     a.maxE = D.maxE;
     a.maxG = D.maxG;
+    a.npt = D.ext_npt;
   }
   return a;
 }
@@ -1242,7 +1243,10 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     }
     // LDS-staged extension unless disabled or a workgroup would stage too many values
     const char* lds_env = std::getenv("CPM_EXT_LDS");
-    D.lds = !band_order && H.maxE <= kMaxStaged && !(lds_env && std::strcmp(lds_env, "0") == 0);
+    const size_t lds_bytes = (((size_t)H.maxE * sizeof(double) + 15) & ~(size_t)15) +
+                             (size_t)H.maxG * (H.dim == 2 ? 4 : 16) * sizeof(int32_t);
+    D.lds = !band_order && H.maxE <= kMaxStaged && lds_bytes <= (size_t)kMaxDynLds &&
+            !(lds_env && std::strcmp(lds_env, "0") == 0);
     // default before autotuning: LDS staging pays on levels up to ~2M nodes
     D.use_lds = D.lds && H.n < (int64_t)(2 << 20);
     if (const char* pe = std::getenv("CPM_EXT_PREFETCH")) {
@@ -1251,6 +1255,7 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     }
     D.maxE = H.maxE;
     D.maxG = H.maxG;
+    D.ext_npt = H.extNpt;
     if (D.lds) {
       if (st == CPM_OK) st = upload(b, &D.packedL, H.packedL);
       if (st == CPM_OK) st = upload(b, &D.blkE, H.blkE);

@@ -45,6 +45,7 @@ struct HostLevel {
   std::vector<int32_t> lorg;    // local groups * 4^(dim-1)
   std::vector<int32_t> packedL; // n
   int32_t maxE = 0, maxG = 0;   // largest staged set / local-group count of one workgroup
+  int32_t extNpt = 1;           // workgroup of kExtBlock * extNpt stencil slots
   // Laplacian neighbours of interpolation-stencil nodes only (B_interp, ascending): the
   // +-x neighbours are j -+ 1, the others stored as -y,+y(,-z,+z) slot-major
   std::vector<int32_t> ilist;   // m
@@ -102,7 +103,10 @@ constexpr int kXoffBits = 10;
 constexpr int kPatchBits = 8;  // node offset bits of a learned-smoother patch group
 constexpr int kPatchRun = 1 << kPatchBits;
 constexpr int kExtBlock = 256;      // workgroup size of the LDS-staged extension
+constexpr int64_t kExtNptMinNodes = 4 << 20;  // levels at least this large (without the fused
+                                              // sweep's tables) stage for 2 slots per thread
 constexpr int kMaxStaged = 8192;    // staged values per workgroup above which a level keeps the gather path
+constexpr int kMaxDynLds = 65536;  // dynamic LDS bytes a staged extension workgroup may take
 constexpr int kMaxGroups = 1 << (31 - kXoffBits);
 // largest level that gets the fused-sweep addressing
 constexpr int64_t kFusedMaxNodes = 2 << 20;
@@ -136,6 +140,7 @@ struct DevLevel {
   int sweep_block = 256;    // workgroup size of the fused sweep
   bool sweep_forced = false;  // fused / split chosen by the CPM_SWEEP environment variable
   int32_t maxE = 0, maxG = 0;
+  int ext_npt = 1;
   int32_t* blkE = nullptr;
   int32_t* gidx = nullptr;
   int32_t* blkG = nullptr;

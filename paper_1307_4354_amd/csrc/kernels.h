@@ -36,6 +36,7 @@ struct ExtAddr {
   const int32_t* lorg = nullptr;
   int32_t maxE = 0;
   int32_t maxG = 0;
+  int32_t npt = 1;  // workgroup = kExtBlock * npt stencil slots
 };
 
 // Fused sweep addressing (stencil order): ExtAddr's perm, packed, origin plus the cross-row

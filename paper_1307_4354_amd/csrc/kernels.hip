@@ -77,7 +77,10 @@ __global__ __launch_bounds__(kExtBlock) void k_sweep_lds(int64_t n, const T* __r
   if (k < n) sweep_node_lds<D, T, MODE>(k, n, gl, lo, u, uo, Ef, b, perm, packedL, frac, inv_h2, delta, wod);
 }
 
-template <int D, typename T, typename TO, int MODE>
+// NPT consecutive runs of kExtBlock stencil slots per workgroup (the staging tables are built
+// for workgroups of kExtBlock * NPT slots): on large levels a bigger workgroup stages fewer
+// values per node, since the stencils of neighbouring nodes overlap.
+template <int D, typename T, typename TO, int MODE, int NPT>
 __global__ __launch_bounds__(kExtBlock) void k_ext_lds(int64_t n, const T* __restrict__ g,
                                                        const int32_t* __restrict__ perm,
                                                        const int32_t* __restrict__ packedL,
@@ -95,9 +98,16 @@ __global__ __launch_bounds__(kExtBlock) void k_ext_lds(int64_t n, const T* __res
   int32_t* lo = (int32_t*)(smem + lo_offset);
   const int64_t blk = tile_of_block(remap);
   ext_stage<T>(blk, g, blkE, gidx, blkG, lorg, S, gl, lo);
-  const int64_t k = blk * kExtBlock + threadIdx.x;
   unsigned long long nv = 0ull;
-  if (k < n) nv = ext_node_lds<D, T, TO, MODE>(k, n, gl, lo, perm, packedL, frac, b, u, out, delta, wod, wd);
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int64_t k = (blk * NPT + j) * kExtBlock + threadIdx.x;
+    if (k < n) {
+      const unsigned long long v = ext_node_lds<D, T, TO, MODE>(k, n, gl, lo, perm, packedL, frac, b, u, out, delta,
+                                                                wod, wd);
+      nv = v > nv ? v : nv;
+    }
+  }
   if (MODE != EXT_APPLY && nrm) block_max_atomic(nv, nrm);
 }
 
@@ -173,7 +183,9 @@ __global__ __launch_bounds__(kTileBlock) void k_tile(int64_t n, const int32_t* _
     const int g = tid + j * kTileBlock;
     if (g < kGCells) {
       const int gx = g % kGX, q = g / kGX;
-      const int c = ((q / kGY + 1) * kBoxY + q % kGY + 1) * kBoxX + gx + 1;
+      const int rr = (q / kGY + 1) * kBoxY + q % kGY + 1;
+      if (!(((uint32_t)rows[rr].y >> (gx + 1)) & 1u)) continue;  // not in the band: never read
+      const int c = rr * kBoxX + gx + 1;
       T sum = U[c - 1] + U[c + 1];
       sum += U[c - kBoxX];
       sum += U[c + kBoxX];
@@ -313,8 +325,8 @@ __global__ void k_assemble_coarse_p1(int n, const int32_t* __restrict__ runE, co
 // The LDS-staged extension with the node's own data (band index, local run offsets, closest-
 // point fractions, and u at the node) loaded before the staging instead of after it: on large
 // levels, where many workgroups take turns on a CU, those loads then overlap the staging's
-// round trips.  Arithmetic as in k_ext_lds, term for term.
-template <int D, typename T, typename TO, int MODE>
+// round trips.  Arithmetic as in k_ext_lds, term for term; NPT as there.
+template <int D, typename T, typename TO, int MODE, int NPT>
 __global__ __launch_bounds__(kExtBlock) void k_ext_ldsp(int64_t n, const T* __restrict__ g,
                                                         const int32_t* __restrict__ perm,
                                                         const int32_t* __restrict__ packedL,
@@ -331,34 +343,48 @@ __global__ __launch_bounds__(kExtBlock) void k_ext_ldsp(int64_t n, const T* __re
   T* gl = (T*)smem;
   int32_t* lo = (int32_t*)(smem + lo_offset);
   const int64_t blk = tile_of_block(remap);
-  const int64_t k = blk * kExtBlock + threadIdx.x;
-  const bool live = k < n;
-  int32_t i = 0, pk = 0;
-  T fx = T(0), fy = T(0), fz = T(0), ui = T(0), bi = T(0), wdi = T(0);
-  if (live) {
-    i = perm[k];
-    pk = packedL[k];
-    fx = frac[k];
-    fy = frac[n + k];
-    if (D == 3) fz = frac[2 * n + k];
-    if (MODE != EXT_PLAIN) ui = u[i];
-    if (b && (MODE == EXT_SMOOTH || MODE == EXT_RESID)) bi = b[i];
-    if (wd && (MODE == EXT_SMOOTH || MODE == EXT_RESID)) wdi = wd[i];
+  int32_t i[NPT], pk[NPT];
+  T fx[NPT], fy[NPT], fz[NPT], ui[NPT], bi[NPT], wdi[NPT];
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int64_t k = (blk * NPT + j) * kExtBlock + threadIdx.x;
+    i[j] = 0;
+    pk[j] = 0;
+    fx[j] = fy[j] = fz[j] = ui[j] = bi[j] = wdi[j] = T(0);
+    if (k < n) {
+      i[j] = perm[k];
+      pk[j] = packedL[k];
+      fx[j] = frac[k];
+      fy[j] = frac[n + k];
+      if (D == 3) fz[j] = frac[2 * n + k];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int64_t k = (blk * NPT + j) * kExtBlock + threadIdx.x;
+    if (k < n) {
+      if (MODE != EXT_PLAIN) ui[j] = u[i[j]];
+      if (b && (MODE == EXT_SMOOTH || MODE == EXT_RESID)) bi[j] = b[i[j]];
+      if (wd && (MODE == EXT_SMOOTH || MODE == EXT_RESID)) wdi[j] = wd[i[j]];
+    }
   }
   ext_stage<T>(blk, g, blkE, gidx, blkG, lorg, S, gl, lo);
   unsigned long long nv = 0ull;
-  if (live) {
-    const int32_t* org = lo + (pk >> kXoffBits) * S;
-    const T* gx = gl + (pk & ((1 << kXoffBits) - 1));
+#pragma unroll
+  for (int j = 0; j < NPT; ++j) {
+    const int64_t k = (blk * NPT + j) * kExtBlock + threadIdx.x;
+    if (k >= n) continue;
+    const int32_t* org = lo + (pk[j] >> kXoffBits) * S;
+    const T* gx = gl + (pk[j] & ((1 << kXoffBits) - 1));
     T wx[4], wy[4], wz[4];
-    cubic_weights<T>(fx, wx);
-    cubic_weights<T>(fy, wy);
+    cubic_weights<T>(fx[j], wx);
+    cubic_weights<T>(fy[j], wy);
     T t = T(0);
     if (D == 2) {
 #pragma unroll
       for (int bb = 0; bb < 4; ++bb) t += wy[bb] * run_dot_lds(gx + org[bb], wx);
     } else {
-      cubic_weights<T>(fz, wz);
+      cubic_weights<T>(fz[j], wz);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         T tc = T(0);
@@ -367,24 +393,26 @@ __global__ __launch_bounds__(kExtBlock) void k_ext_ldsp(int64_t n, const T* __re
         t += wz[c] * tc;
       }
     }
+    unsigned long long v = 0ull;
     if (MODE == EXT_SMOOTH) {
-      T r = t - delta * ui;
-      if (b) r += bi;
-      u[i] = ui + (wd ? wdi : wod) * r;
-      if (out) out[i] = (TO)t;
-      nv = abs_bits((double)r);
+      T r = t - delta * ui[j];
+      if (b) r += bi[j];
+      u[i[j]] = ui[j] + (wd ? wdi[j] : wod) * r;
+      if (out) out[i[j]] = (TO)t;
+      v = abs_bits((double)r);
     } else if (MODE == EXT_RESID) {
-      T r = t - delta * ui;
-      if (b) r += bi;
-      if (wd) r *= wdi;
-      if (out) out[i] = (TO)r;
-      nv = abs_bits((double)r);
+      T r = t - delta * ui[j];
+      if (b) r += bi[j];
+      if (wd) r *= wdi[j];
+      if (out) out[i[j]] = (TO)r;
+      v = abs_bits((double)r);
     } else if (MODE == EXT_APPLY) {
-      out[i] = (TO)(delta * ui - t);
+      out[i[j]] = (TO)(delta * ui[j] - t);
     } else {
-      if (out) out[i] = (TO)t;
-      nv = abs_bits((double)t);
+      if (out) out[i[j]] = (TO)t;
+      v = abs_bits((double)t);
     }
+    nv = v > nv ? v : nv;
   }
   if (MODE != EXT_APPLY && nrm) block_max_atomic(nv, nrm);
 }
@@ -607,21 +635,30 @@ void launch_ext(int dim, int mode, int64_t n, const T* g, const ExtAddr& a, cons
                 TO* out, T delta, T wod, unsigned long long* nrm, const LaunchCfg& lc, hipStream_t s, const T* wd) {
   if (n <= 0) return;
   if (a.packedL) {
-    // LDS-staged path: fixed workgroup of kExtBlock stencil slots (the staging tables are
+    // LDS-staged path: workgroups of kExtBlock * npt stencil slots (the staging tables are
     // built for it); dynamic LDS = staged values + local-group run offsets
     const int S = dim == 2 ? 4 : 16;
     const int lo_off = (int)(((size_t)a.maxE * sizeof(T) + 15) & ~(size_t)15);
     const size_t shm = (size_t)lo_off + (size_t)a.maxG * S * sizeof(int32_t);
-    const unsigned gl = (unsigned)((n + kExtBlock - 1) / kExtBlock);
+    const int64_t wgn = (int64_t)kExtBlock * a.npt;
+    const unsigned gl = (unsigned)((n + wgn - 1) / wgn);
     const int rm = lc.xcd_remap;
-#define CPM_EXTL_CASE(DD, MM)                                                                              \
+#define CPM_EXTL_NPT(DD, MM, NP)                                                                           \
   if (lc.prefetch)                                                                                         \
-    k_ext_ldsp<DD, T, TO, MM><<<gl, kExtBlock, shm, s>>>(n, g, a.perm, a.packedL, a.blkE, a.gidx, a.blkG,    \
-                                                         a.lorg, frac, b, u, out, delta, wod, nrm, rm, lo_off, \
-                                                         wd);                                                \
+    k_ext_ldsp<DD, T, TO, MM, NP><<<gl, kExtBlock, shm, s>>>(n, g, a.perm, a.packedL, a.blkE, a.gidx,       \
+                                                             a.blkG, a.lorg, frac, b, u, out, delta, wod, nrm, \
+                                                             rm, lo_off, wd);                                \
   else                                                                                                     \
-    k_ext_lds<DD, T, TO, MM><<<gl, kExtBlock, shm, s>>>(n, g, a.perm, a.packedL, a.blkE, a.gidx, a.blkG,     \
-                                                        a.lorg, frac, b, u, out, delta, wod, nrm, rm, lo_off, wd)
+    k_ext_lds<DD, T, TO, MM, NP><<<gl, kExtBlock, shm, s>>>(n, g, a.perm, a.packedL, a.blkE, a.gidx, a.blkG, \
+                                                            a.lorg, frac, b, u, out, delta, wod, nrm, rm, lo_off, wd)
+#define CPM_EXTL_CASE(DD, MM)      \
+  if (a.npt == 4) {                \
+    CPM_EXTL_NPT(DD, MM, 4);       \
+  } else if (a.npt == 2) {         \
+    CPM_EXTL_NPT(DD, MM, 2);       \
+  } else {                         \
+    CPM_EXTL_NPT(DD, MM, 1);       \
+  }
     if (dim == 2) {
       switch (mode) {
         case EXT_SMOOTH: CPM_EXTL_CASE(2, EXT_SMOOTH); break;
@@ -638,6 +675,7 @@ void launch_ext(int dim, int mode, int64_t n, const T* g, const ExtAddr& a, cons
       }
     }
 #undef CPM_EXTL_CASE
+#undef CPM_EXTL_NPT
     return;
   }
   const unsigned gr = grid_for(n, lc.block);

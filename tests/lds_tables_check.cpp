@@ -15,14 +15,16 @@ using namespace cpm;
 
 static long check_level(const HostLevel& H, int dim) {
   const int S = dim == 2 ? 4 : 16, SX = dim == 2 ? 2 : 16, SR = S + SX;
-  const int64_t n = H.n, nb = (n + kExtBlock - 1) / kExtBlock;
+  const int64_t wg = (int64_t)kExtBlock * H.extNpt;
+  const int64_t n = H.n, nb = (n + wg - 1) / wg;
   const int32_t xmask = (1 << kXoffBits) - 1;
   long bad = 0;
+  if (H.extNpt != 1 && !H.blkE2.empty()) ++bad;  // the fused sweep runs one slot per thread
   for (int64_t b = 0; b < nb; ++b) {
     const int32_t e0 = H.blkE[b], e1 = H.blkE[b + 1];
     for (int32_t e = e0; e < e1; ++e) bad += H.gidx[e] < 0 || H.gidx[e] >= n;
     const int32_t q0 = H.blkG[b] * S;
-    for (int64_t k = b * kExtBlock; k < std::min<int64_t>(n, (b + 1) * kExtBlock); ++k) {
+    for (int64_t k = b * wg; k < std::min<int64_t>(n, (b + 1) * wg); ++k) {
       const int32_t lg = H.packedL[k] >> kXoffBits, xo = H.packedL[k] & xmask;
       const int32_t gid = H.packed[k] >> kXoffBits, xg = H.packed[k] & xmask;
       bad += xo != xg;
@@ -187,9 +189,9 @@ int main() {
     for (size_t l = 0; l < lv.size(); ++l) {
       long gaps = 0, tiles = 0;
       const long bad = check_level(lv[l], c.dim) + check_patches(lv[l], c.dim, &gaps) + check_tiles(lv[l], &tiles);
-      std::printf("kind %d h = 1/%g level %zu: n = %ld, sweep tables %s, patch groups %ld, gapped rows %ld, "
-                  "tiles %ld, mismatches %ld\n",
-                  c.s.kind, 1.0 / c.h, l, (long)lv[l].n, lv[l].blkE2.empty() ? "absent" : "present",
+      std::printf("kind %d h = 1/%g level %zu: n = %ld, slots per thread %d, sweep tables %s, patch groups %ld, "
+                  "gapped rows %ld, tiles %ld, mismatches %ld\n",
+                  c.s.kind, 1.0 / c.h, l, (long)lv[l].n, (int)lv[l].extNpt, lv[l].blkE2.empty() ? "absent" : "present",
                   (long)lv[l].patchGroups, gaps, tiles, bad);
       fails += bad;
     }

@@ -36,3 +36,10 @@ def test_lds_staging_tables(tmp_path):
     env = dict(os.environ, CPM_TILE_MIN_NODES="1000")
     out2 = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=600, env=env)
     assert out2.returncode == 0 and "ALL OK" in out2.stdout, out2.stdout[-3000:]
+    # workgroups of 2 and 4 slots per thread (the large-level form), and the plain (z, y, x)
+    # visit order instead of the Morton-blocked one
+    for extra in ({"CPM_EXT_NPT": "4"}, {"CPM_EXT_NPT": "2", "CPM_MORTON_BITS": "-1"}):
+        out3 = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=600,
+                              env=dict(os.environ, **extra))
+        assert out3.returncode == 0 and "ALL OK" in out3.stdout, (extra, out3.stdout[-3000:])
+        assert "slots per thread %s" % extra["CPM_EXT_NPT"] in out3.stdout
