@@ -285,7 +285,8 @@ cpm_status cpm_run_cycles(cpm_band band, const cpm_params* params, const double*
  * with HIP events on `stream` over `reps` back-to-back launches: which = 0 the
  * extension pass fused with Jacobi smoothing (the dominant kernel), 1 the neighbour-sum
  * pass, 2 restriction into `level` (level >= 1), 3 prolongation from level+1 into `level`
- * (level < levels-1), 4 the fused learned-smoother update from a fixed residual (level < 2,
+ * (level < levels-1), 4 the fused learned-smoother update from a fixed residual, held in
+ * float32 as the learned sweep keeps it (level < 2,
  * weights set, CPM_E_INVALID otherwise), 5 the fused one-pass sweep (levels that have its
  * addressing, CPM_E_INVALID otherwise), 6 the tiled sweep (levels that have its tables,
  * CPM_E_INVALID otherwise).  Level 0 runs on f and u, other levels on workspace vectors; the

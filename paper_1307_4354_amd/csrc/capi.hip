@@ -1839,9 +1839,9 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
       launch_fill<T>(D.n, B[level].f, (T)1.0, s);
     }
     launch_nsum<T>(band->dim, D.m, D.ilist, D.nbrI, uu, ff, (T)(1.0 / (D.h * D.h)), B[level].g, nullptr, lc, s);
-    if (which == 4)  // residual of the current iterate, read by every timed launch
-      launch_ext<T, T>(band->dim, EXT_RESID, D.n, B[level].g, ext_addr(D), fracK_of<T>(D), (const T*)nullptr, uu,
-                       B[level].r, (T)delta, (T)0, nullptr, ext_cfg(D), s);
+    if (which == 4)  // residual of the current iterate (float32, as the learned sweep keeps it)
+      launch_ext<T, float>(band->dim, EXT_RESID, D.n, B[level].g, ext_addr(D), fracK_of<T>(D), (const T*)nullptr,
+                           uu, reinterpret_cast<float*>(B[level].r), (T)delta, (T)0, nullptr, ext_cfg(D), s);
     for (int pass = 0; pass < 2; ++pass) {  // pass 0 warms up
       const int k = pass == 0 ? 1 : reps;
       if (pass == 1) (void)hipEventRecord(e0, s);
@@ -1870,7 +1870,8 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
                           (const T*)nullptr, sweep_addr(D), fracS_of<T>(D),
                           (T)(1.0 / (D.h * D.h)), (T)delta, (T)(params->omega / delta), sweep_cfg(D), s);
         } else {
-          launch_learned<T>(band, level, B[level].r, uu, params->c, s);
+          // the update as the learned sweep runs it: residual in float32
+          launch_learned_r<T, float>(band, level, reinterpret_cast<const float*>(B[level].r), uu, params->c, s);
         }
       }
       if (pass == 1) (void)hipEventRecord(e1, s);

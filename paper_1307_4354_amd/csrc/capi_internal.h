@@ -128,10 +128,13 @@ void enqueue_prologue(const cpm_band b, const cpm_params& p, const double* f, co
 cpm_status read_scalars(cpm_band b, double* r0, double* r1);
 cpm_status validate_params(const cpm_band b, const cpm_params* p);
 
-// fused learned update u += (s / delta) y on level l from the residual r (weights set,
-// level without patch gaps)
+// fused learned update u += (s / delta) y on level l from the residual r (weights set, patch
+// tables present); launch_learned_r takes the residual in another precision (float32 under a
+// float64 iterate, as the learned sweep stores it)
 template <typename T>
 void launch_learned(const cpm_band b, int l, const T* r, T* u, double c, hipStream_t s);
+template <typename T, typename R>
+void launch_learned_r(const cpm_band b, int l, const R* r, T* u, double c, hipStream_t s);
 // learned smoother sweep on level l (< 2): given g = f + N u already computed into g,
 // evaluate the residual, the features, the network and update u.
 template <typename T>

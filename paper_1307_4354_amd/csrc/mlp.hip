@@ -104,12 +104,12 @@ __device__ float mlp_wave(const uint16_t* X, int valid, const uint16_t* __restri
 }
 
 // Features of one node: residual patch / s, then the 1-D weights, then zeros.  Writes
-// NOUT bf16 into xrow; returns s.
-template <int D, typename T, int NOUT = kIn>
+// NOUT bf16 into xw, two per word (slot 2j in the low half of word j); returns s.
+template <int D, typename T, int NOUT = kIn, typename TF = T>
 __device__ __forceinline__ float node_features(int64_t k, int64_t n, const T* __restrict__ r,
                                                const int32_t* __restrict__ prow, const int32_t* __restrict__ ppk,
                                                int64_t groups, const uint32_t* __restrict__ pmask,
-                                               const T* __restrict__ frac, uint16_t* xrow) {
+                                               const TF* __restrict__ frac, uint32_t* xw) {
   constexpr int R = D == 2 ? 3 : 9;
   constexpr int P = 3 * R;
   const uint32_t mask = pmask[k];
@@ -118,8 +118,11 @@ __device__ __forceinline__ float node_features(int64_t k, int64_t n, const T* __
   const int32_t* grow = prow + (pk >> kPatchBits);
   const int32_t toff = pk & (kPatchRun - 1);
   // every load is issued unconditionally (the index clamped into the array, the value of an
-  // absent node discarded below), so the 3^D loads are in flight together
+  // absent node discarded below), so the 3^D loads are in flight together; the addresses are
+  // 32-bit byte offsets from r (a level's vector is far below 4 GiB), one register each
   T patch[P];
+  const char* rb = reinterpret_cast<const char*>(r);
+  const int32_t last = (int32_t)(n - 1);
 #pragma unroll
   for (int q = 0; q < R; ++q) {
     const int32_t base = grow[q * groups] + toff;
@@ -127,9 +130,9 @@ __device__ __forceinline__ float node_features(int64_t k, int64_t n, const T* __
     const int gap = ((mask >> (3 * q)) & 7u) == 5u;
 #pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
-      int64_t a = (int64_t)base + dx - (dx == 2 ? gap : 0);
-      a = a < 0 ? 0 : (a >= n ? n - 1 : a);
-      patch[dx + 3 * q] = r[a];
+      int32_t a = base + dx - (dx == 2 ? gap : 0);
+      a = a < 0 ? 0 : (a > last ? last : a);
+      patch[dx + 3 * q] = *reinterpret_cast<const T*>(rb + (uint32_t)a * (uint32_t)sizeof(T));
     }
   }
   T s = T(0);
@@ -142,16 +145,18 @@ __device__ __forceinline__ float node_features(int64_t k, int64_t n, const T* __
   // correctly rounded quotient by at most 2 float ulps, below the bf16 rounding step
   const float inv_s = s > T(0) ? 1.0f / (float)s : 0.0f;
 #pragma unroll
-  for (int q = 0; q < P; ++q) xrow[q] = f2bf((float)patch[q] * inv_s);
-  T w[4];
+  for (int j = 0; j < NOUT / 2; ++j) xw[j] = 0u;
+  // each slot's bf16 goes straight into its word, so no per-slot register is kept
+  auto put = [&](int q, float v) { xw[q >> 1] |= (uint32_t)f2bf(v) << (16 * (q & 1)); };
+#pragma unroll
+  for (int q = 0; q < P; ++q) put(q, (float)patch[q] * inv_s);
+  TF w[4];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    cubic_weights<T>(frac[a * n + k], w);
+    cubic_weights<TF>(frac[a * n + k], w);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) xrow[P + 4 * a + j] = f2bf((float)w[j]);
+    for (int j = 0; j < 4; ++j) put(P + 4 * a + j, (float)w[j]);
   }
-#pragma unroll
-  for (int q = P + 4 * D; q < NOUT; ++q) xrow[q] = 0;
   return (float)s;
 }
 
@@ -163,13 +168,11 @@ __global__ __launch_bounds__(256) void k_features(int64_t n, const T* __restrict
                                                   uint16_t* __restrict__ X, float* __restrict__ scale) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  uint16_t xr[kIn];
-  const float s = node_features<D, T>(i, n, r, prow, ppk, groups, pmask, frac, xr);
+  uint32_t xw[kIn / 2];
+  const float s = node_features<D, T>(i, n, r, prow, ppk, groups, pmask, frac, xw);
   uint64_t* dst = (uint64_t*)(X + (int64_t)i * kIn);
 #pragma unroll
-  for (int q = 0; q < kIn / 4; ++q)
-    dst[q] = (uint64_t)xr[4 * q] | ((uint64_t)xr[4 * q + 1] << 16) | ((uint64_t)xr[4 * q + 2] << 32) |
-             ((uint64_t)xr[4 * q + 3] << 48);
+  for (int q = 0; q < kIn / 4; ++q) dst[q] = (uint64_t)xw[2 * q] | ((uint64_t)xw[2 * q + 1] << 32);
   scale[i] = s;
 }
 
@@ -184,9 +187,12 @@ __global__ __launch_bounds__(256) void k_features(int64_t n, const T* __restrict
 // one xor-32 shuffle per k-step.  Only the k-steps that hold features are issued (5 of 8 in
 // 3-D); the last slot of the last step, a zero of the network's input, carries a constant 1
 // whose A entry is b1, so the bias is added inside the float32 accumulation.  The used
-// columns of W1 (with b1) and w2 are staged once per workgroup in LDS.
-template <int D, typename T>
-__global__ __launch_bounds__(256) void k_learned(int64_t n, const T* __restrict__ r, const int32_t* __restrict__ prow,
+// columns of W1 (with b1) and w2 are staged once per workgroup in LDS.  The residual may come
+// in float32 (R = float) under a float64 iterate: the features take it in float32 anyway, and
+// the largest float32-rounded entry is the float32-rounded largest entry, so the scale s and
+// the update are the same bit for bit; the patch then holds half the registers.
+template <int D, typename T, typename R = T>
+__global__ __launch_bounds__(256) void k_learned(int64_t n, const R* __restrict__ r, const int32_t* __restrict__ prow,
                                                  const int32_t* __restrict__ ppk, int64_t groups,
                                                  const uint32_t* __restrict__ pmask, const T* __restrict__ frac,
                                                  const uint16_t* __restrict__ W, T inv_delta, T* __restrict__ u) {
@@ -210,18 +216,13 @@ __global__ __launch_bounds__(256) void k_learned(int64_t n, const T* __restrict_
   const int64_t k = (blockIdx.x * 4 + (threadIdx.x >> 6)) * (int64_t)64 + lane;
   uint32_t xw[4 * KS];  // own feature row, bf16 pairs (slot 2j in the low half of word j)
   float s = 0.0f;
-  {
-    uint16_t xs[8 * KS];
-    if (k < n) {
-      s = node_features<D, T, 8 * KS>(k, n, r, prow, ppk, groups, pmask, frac, xs);
-    } else {
+  if (k < n) {
+    s = node_features<D, R, 8 * KS, T>(k, n, r, prow, ppk, groups, pmask, frac, xw);
+  } else {
 #pragma unroll
-      for (int q = 0; q < 8 * KS; ++q) xs[q] = 0;
-    }
-    xs[KB] = 0x3F80;  // 1.0
-#pragma unroll
-    for (int j = 0; j < 4 * KS; ++j) xw[j] = (uint32_t)xs[2 * j] | ((uint32_t)xs[2 * j + 1] << 16);
+    for (int j = 0; j < 4 * KS; ++j) xw[j] = 0u;
   }
+  xw[KB >> 1] |= 0x3F80u << (16 * (KB & 1));  // the constant 1.0 (a zero slot of the input)
   // own chunk (k = 8 ks + 4 half) and the partner's chunk for the other node block
   uint32_t own[2 * KS], got[2 * KS];
 #pragma unroll
@@ -233,30 +234,28 @@ __global__ __launch_bounds__(256) void k_learned(int64_t n, const T* __restrict_
       got[2 * ks + e] = __shfl_xor(half ? lo : hi, 32);
     }
   }
+  // one 32x32 accumulator tile at a time (hidden block mb of node block nb): 16 accumulator
+  // registers live instead of 32, for one more wavefront per SIMD
   float y = 0.0f;
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
     const bool mine = nb == half;  // this lane's own node is column col of node block nb
-    f32x16 acc[2];
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[mb][v] = 0.0f;
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      const u32x2 bw = {mine ? own[2 * ks] : got[2 * ks], mine ? own[2 * ks + 1] : got[2 * ks + 1]};
-      const bf16x4 bv = __builtin_bit_cast(bf16x4, bw);
-#pragma unroll
-      for (int mb = 0; mb < 2; ++mb) {
-        const bf16x4 av = *(const bf16x4*)&w1s[(mb * 32 + col) * WS + ks * 8 + half * 4];
-        acc[mb] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc[mb], 0, 0, 0);
-      }
-    }
     float p = 0.0f;
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < 2; ++mb) {
+      f32x16 acc;
 #pragma unroll
-      for (int v = 0; v < 16; ++v) p += fmaxf(acc[mb][v], 0.0f) * w2s[mb * 32 + 8 * (v >> 2) + 4 * half + (v & 3)];
+      for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const u32x2 bw = {mine ? own[2 * ks] : got[2 * ks], mine ? own[2 * ks + 1] : got[2 * ks + 1]};
+        const bf16x4 bv = __builtin_bit_cast(bf16x4, bw);
+        const bf16x4 av = *(const bf16x4*)&w1s[(mb * 32 + col) * WS + ks * 8 + half * 4];
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) p += fmaxf(acc[v], 0.0f) * w2s[mb * 32 + 8 * (v >> 2) + 4 * half + (v & 3)];
+    }
     p += __shfl_xor(p, 32);
     if (mine) y = p;
   }
@@ -427,30 +426,38 @@ const float* frac_b<float>(const DevLevel& D) { return D.fracE32; }
 }  // namespace
 
 // The fused network update u += (s / delta) y on level l from the residual r.
-template <typename T>
-void launch_learned(const cpm_band b, int l, const T* r, T* u, double c, hipStream_t s) {
+template <typename T, typename R>
+void launch_learned_r(const cpm_band b, int l, const R* r, T* u, double c, hipStream_t s) {
   const DevLevel& D = b->dev[(size_t)l];
   const double delta = level_delta(b, l, c);
   const unsigned gr = (unsigned)((D.n + 255) / 256);  // 64 nodes per wavefront, 4 per block
   if (b->dim == 2)
-    k_learned<2, T><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchPk, D.patchGroups, D.patchMask, frac_b<T>(D),
-                                       b->mlpW, (T)(1.0 / delta), u);
+    k_learned<2, T, R><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchPk, D.patchGroups, D.patchMask, frac_b<T>(D),
+                                          b->mlpW, (T)(1.0 / delta), u);
   else
-    k_learned<3, T><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchPk, D.patchGroups, D.patchMask, frac_b<T>(D),
-                                       b->mlpW, (T)(1.0 / delta), u);
+    k_learned<3, T, R><<<gr, 256, 0, s>>>(D.n, r, D.patchRow, D.patchPk, D.patchGroups, D.patchMask, frac_b<T>(D),
+                                          b->mlpW, (T)(1.0 / delta), u);
 }
 
-// r = b + E g - delta u into B.r, then the fused network update of u.
+template <typename T>
+void launch_learned(const cpm_band b, int l, const T* r, T* u, double c, hipStream_t s) {
+  launch_learned_r<T, T>(b, l, r, u, c, s);
+}
+
+// r = b + E g - delta u into B.r (in float32: the network reads no more of it, see k_learned),
+// then the fused network update of u.
 template <typename T>
 void learned_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g, T* r, double c, hipStream_t s) {
   (void)f;
   const DevLevel& D = b->dev[(size_t)l];
   const double delta = level_delta(b, l, c);
-  launch_ext<T, T>(b->dim, EXT_RESID, D.n, g, ext_addr(D), frac_k<T>(D), rhsA, u, r, (T)delta, (T)0, nullptr,
-                   ext_cfg(D), s);
-  launch_learned<T>(b, l, r, u, c, s);
+  float* r32 = reinterpret_cast<float*>(r);
+  launch_ext<T, float>(b->dim, EXT_RESID, D.n, g, ext_addr(D), frac_k<T>(D), rhsA, u, r32, (T)delta, (T)0, nullptr,
+                       ext_cfg(D), s);
+  launch_learned_r<T, float>(b, l, r32, u, c, s);
 }
 
+template void launch_learned_r<double, float>(const cpm_band, int, const float*, double*, double, hipStream_t);
 template void launch_learned<double>(const cpm_band, int, const double*, double*, double, hipStream_t);
 template void launch_learned<float>(const cpm_band, int, const float*, float*, double, hipStream_t);
 template void learned_sweep<double>(const cpm_band, int, double*, const double*, const double*, double*, double*,
