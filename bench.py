@@ -97,7 +97,7 @@ def _host_info():
 # (24 B), one read of g (8), u read and write (16): 48 B per node in FP64; the fused one-pass
 # sweep moves the fractions, u and E f read, u' written: 56 B; the tiled pass the fractions,
 # u and f read, u' written: 48 B.
-def _dominant_kernel(tuning, n0, ntiles=0):
+def _dominant_kernel(tuning, n0, ntiles=0, ext_slots=256):
     use_lds, ext_block, _, fused, sweep_block, sweep_lds, tiled, prefetch = tuning
     if tiled:
         return ("k_tile<double, double, 0>", ntiles * 256, 48.0, 6,
@@ -106,9 +106,15 @@ def _dominant_kernel(tuning, n0, ntiles=0):
         name = ("k_sweep_lds" if sweep_lds else "k_sweep") + "<3, double, 0>"
         blk = 256 if sweep_lds else sweep_block
         return name, -(-n0 // blk) * blk, 56.0, 5, "fused one-pass sweep E f + (E N) u (Jacobi step), level 0"
-    name = ("k_ext_ldsp" if prefetch else ("k_ext_lds" if use_lds else "k_ext")) + "<3, double, double, 0>"
-    blk = 256 if use_lds else ext_block
-    return name, -(-n0 // blk) * blk, 48.0, 0, "extension + Jacobi smoothing pass, level 0"
+    # the LDS-staged form runs 256 lanes per workgroup over ext_slots stencil slots (a
+    # template argument of its kernels)
+    if use_lds:
+        name = "%s<3, double, double, 0, %d>" % ("k_ext_ldsp" if prefetch else "k_ext_lds", ext_slots // 256)
+        grid = -(-n0 // ext_slots) * 256
+    else:
+        name = "k_ext<3, double, double, 0>"
+        grid = -(-n0 // ext_block) * ext_block
+    return name, grid, 48.0, 0, "extension + Jacobi smoothing pass, level 0"
 
 
 def _traffic_file(workload):
@@ -183,7 +189,7 @@ def headline_torus256(args):
 
     # dominant kernel: the finest level's smoothing pass, timed with HIP events on the stream
     # it is launched on
-    kname, grid0, bpn, which, what = _dominant_kernel(tuning[0], n0)
+    kname, grid0, bpn, which, what = _dominant_kernel(tuning[0], n0, ext_slots=cpm.cpm_band_ext_slots(band, 0))
     ud.zero_()
     avg_us = cpm.cpm_time_kernel(band, p64, which, 0, args.kernel_reps, fd, ud, work, nb64)
     alg_bytes = bpn * n0
@@ -578,7 +584,7 @@ def run_sphere64(args):
 
     # dominant kernel: the finest level's smoothing pass, timed with HIP events on the stream it
     # runs on
-    kname, grid0, bpn, which, _ = _dominant_kernel(tuning[0], n0)
+    kname, grid0, bpn, which, _ = _dominant_kernel(tuning[0], n0, ext_slots=cpm.cpm_band_ext_slots(band, 0))
     ud.zero_()
     avg_us = cpm.cpm_time_kernel(band, p64, which, 0, args.kernel_reps, fd, ud, work, nb64)
     alg_bytes = bpn * n0

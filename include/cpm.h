@@ -329,9 +329,11 @@ cpm_status cpm_autotune(cpm_band band, void* stream);
  * tiled = 1 when the level sweeps with the tiled pass (3-D levels of 2^18 nodes or more whose
  * tables exist: f + N u formed in LDS over each tile's box, then the extension, one pass);
  * ext_prefetch = 1 when the LDS-staged extension loads each node's own data (band index, run
- * offsets, fractions, u) before its workgroup stages the interpolated values. */
+ * offsets, fractions, u) before its workgroup stages the interpolated values; ext_slots =
+ * stencil slots per workgroup of the LDS-staged extension (its 256 lanes take 1, 2 or 4 slots
+ * each, fixed when the band is built; 0 on a level without the staging tables). */
 cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_block, int* nsum_block, int* fused,
-                           int* sweep_block, int* sweep_lds, int* tiled, int* ext_prefetch);
+                           int* sweep_block, int* sweep_lds, int* tiled, int* ext_prefetch, int* ext_slots);
 
 /* Set one level's launch configuration by hand (for instance one found by cpm_autotune in
  * an earlier process): use_lds = LDS-staged extension (levels that have its tables),

@@ -100,7 +100,7 @@ def _load():
         "cpm_autotune": (c_int, [vp, vp]),
         "cpm_set_band_tuning": (c_int, [vp, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int, c_int]),
         "cpm_band_tuning": (c_int, [vp, c_int, POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int),
-                                    POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
+                                    POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
         "cpm_set_smoother_weights": (c_int, [vp, vp, c_double]),
         "cpm_set_diffusion": (c_int, [vp, c_int, vp]),
         "cpm_mlp_forward": (c_int, [c_int64, vp, vp, vp, vp, vp]),
@@ -431,7 +431,16 @@ def cpm_set_band_tuning(band: Band, level: int, use_lds: bool, ext_block: int, n
 
 def cpm_band_tuning(band: Band, level: int):
     """(use_lds, ext_block, nsum_block, fused, sweep_block, sweep_lds, tiled, ext_prefetch) of one level."""
-    v = [c_int() for _ in range(8)]
+    v = [c_int() for _ in range(9)]
     _check(_lib.cpm_band_tuning(band.handle, int(level), *[byref(x) for x in v]))
-    a, b, c, d, e, g, t, pf = [x.value for x in v]
+    a, b, c, d, e, g, t, pf, _ = [x.value for x in v]
     return bool(a), b, c, bool(d), e, bool(g), bool(t), bool(pf)
+
+
+def cpm_band_ext_slots(band: Band, level: int) -> int:
+    """Stencil slots per workgroup of the LDS-staged extension on one level (cpm_band_tuning's
+    ext_slots; 0 without the staging tables)."""
+    v = c_int()
+    z = [None] * 8
+    _check(_lib.cpm_band_tuning(band.handle, int(level), *z, byref(v)))
+    return v.value

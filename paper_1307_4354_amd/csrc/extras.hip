@@ -179,7 +179,7 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
 }
 
 cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_block, int* nsum_block, int* fused,
-                           int* sweep_block, int* sweep_lds, int* tiled, int* ext_prefetch) {
+                           int* sweep_block, int* sweep_lds, int* tiled, int* ext_prefetch, int* ext_slots) {
   if (!band || level < 0 || level >= band->L) {
     set_error("cpm_band_tuning: invalid argument");
     return CPM_E_INVALID;
@@ -194,6 +194,7 @@ cpm_status cpm_band_tuning(cpm_band band, int level, int* use_lds, int* ext_bloc
   if (sweep_lds) *sweep_lds = slds ? 1 : 0;
   if (tiled) *tiled = D.use_tile && D.ntiles > 0 ? 1 : 0;
   if (ext_prefetch) *ext_prefetch = D.lds && D.use_lds && D.ext_prefetch ? 1 : 0;
+  if (ext_slots) *ext_slots = D.lds ? kExtBlock * D.ext_npt : 0;
   return CPM_OK;
 }
 

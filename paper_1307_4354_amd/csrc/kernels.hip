@@ -207,7 +207,9 @@ __global__ __launch_bounds__(kTileBlock) void k_tile(int64_t n, const int32_t* _
     cubic_weights<T>(frac[2 * n + k], wz);
     const T* gp = G + ((loc >> 10 & 31) * kGY + (loc >> 5 & 31)) * kGX + (loc & 31);
     T tv = T(0);
-#pragma unroll
+    // one z-plane of the stencil at a time: 16 LDS values in flight instead of 64 keeps the
+    // registers at a level that lets more wavefronts share a CU
+#pragma unroll 1
     for (int c = 0; c < 4; ++c) {
       T tc = T(0);
 #pragma unroll

@@ -6,7 +6,9 @@ band nodes, the mixed-precision workload), on outputs the oracle computes one by
 * the band is ordered (x fastest) and contains every node of the sampled nodes' cubic
   stencils and their axis neighbours (the containment property of Sec. 3.1);
 * the extension E u of a seeded random vector, at the sampled nodes, equals the oracle's
-  stencil sum to rounding;
+  stencil sum to rounding, in the gather form and in the LDS-staged form the bench times
+  (workgroups of 512 stencil slots, the node's own data loaded before the staging), and the
+  operator A u = delta u - E(N u) does too;
 * a mixed-precision solve reaches 1e-10 and agrees with the double-precision solve.
 """
 import numpy as np
@@ -59,10 +61,31 @@ def test_torus256_sampled_parity():
             assert np.all(lookup(Q) >= 0)
     u = W.random_vector(n, W.SEED_BASE + 61)
     out = torch.empty(n, dtype=torch.float64, device="cuda")
-    cpm.cpm_extend(band, 0, dev(u), out)
     ref = np.sum(ob.tensor_weights(W1) * u[cols], axis=1)
-    got = host(out)[sel]
-    assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(u))
+    # A u at the sampled nodes: (N u) at each stencil node from its axis neighbours
+    inv_h2 = 1.0 / (h * h)
+    Mf = M.reshape(-1, 3)
+    nu = np.zeros(Mf.shape[0])
+    for a in range(3):
+        for sg in (-1, 1):
+            Q = Mf.copy()
+            Q[:, a] += sg
+            nu += u[lookup(Q)] * inv_h2
+    delta = cfg.problem.c + 6.0 * inv_h2
+    ref_a = delta * u[sel] - np.sum(ob.tensor_weights(W1) * nu.reshape(sel.size, -1), axis=1)
+    assert cpm.cpm_band_ext_slots(band, 0) == 512  # two slots per lane on an 8.5M-node level
+    assert cpm.cpm_band_ext_slots(band, 1) == 256
+    tun = cpm.cpm_band_tuning(band, 0)
+    wa = torch.empty(n, dtype=torch.float64, device="cuda")
+    for lds, pf in ((False, False), (True, False), (True, True)):
+        cpm.cpm_set_band_tuning(band, 0, lds, 256, tun[2], False, tun[4], False, False, pf)
+        cpm.cpm_extend(band, 0, dev(u), out)
+        got = host(out)[sel]
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(u)), (lds, pf)
+        cpm.cpm_apply(band, 0, cfg.problem.c, dev(u), out, wa)
+        got = host(out)[sel]
+        assert np.max(np.abs(got - ref_a)) <= 1e-12 * np.max(np.abs(ref_a)), (lds, pf)
+    del wa
     # solves at full size: mixed precision against double precision
     f = cfg.problem.f(cp)
     fd = dev(f)
