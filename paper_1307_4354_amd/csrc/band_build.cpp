@@ -731,6 +731,27 @@ cpm_status build_stencil_order(HostLevel& Lv, int level, std::string& err) {
       return CPM_E_BAND;
     }
   }
+  // segments: consecutive list positions whose band indices and every neighbour index
+  // advance by one together (every list node has all its axis neighbours in the band)
+  Lv.nsSeg.clear();
+  Lv.nsChunkSeg.clear();
+  Lv.nsSegOff.assign((size_t)m, 0);
+  int64_t seg = -1;
+  for (int64_t k = 0; k < m; ++k) {
+    const int32_t j = Lv.ilist[(size_t)k];
+    bool fresh = k == 0 || j != Lv.ilist[(size_t)(k - 1)] + 1;
+    for (int q = 0; q < nq && !fresh; ++q)
+      fresh = Lv.nbrI[(size_t)(q * m + k)] != Lv.nbrI[(size_t)(q * m + k - 1)] + 1;
+    if (fresh) {
+      ++seg;
+      Lv.nsSeg.push_back((int32_t)k);
+      Lv.nsSeg.push_back(j);
+      for (int q = 0; q < kNsumSegWords - 2; ++q)
+        Lv.nsSeg.push_back(q < nq ? Lv.nbrI[(size_t)(q * m + k)] : -1);
+    }
+    if ((k & (kNsumChunk - 1)) == 0) Lv.nsChunkSeg.push_back((int32_t)seg);
+    Lv.nsSegOff[(size_t)k] = (uint8_t)(seg - Lv.nsChunkSeg.back());  // < kNsumChunk segments per chunk
+  }
   return CPM_OK;
 }
 

@@ -110,7 +110,7 @@ static cpm_status upload_f32(const cpm_band b, float** dst, const std::vector<do
 static void free_dev(cpm_band b) {
   for (auto& D : b->dev) {
     void* ps[] = {D.runE,  D.nbr,   D.fracE,  D.fracE32, D.runP,    D.fracP,  D.fracP32, D.runR,
-                  D.fracR, D.fracR32, D.perm, D.packed, D.origin, D.fracK, D.fracK32, D.ilist, D.nbrI,
+                  D.fracR, D.fracR32, D.perm, D.packed, D.origin, D.fracK, D.fracK32, D.ilist, D.nbrI, D.nsSeg, D.nsChunkSeg, D.nsSegOff,
                   D.patchRow, D.patchPk, D.patchMask, D.packedB, D.packedL, D.blkE, D.gidx, D.blkG, D.lorg, D.originX,
                   D.qdiag, D.wd, D.acoef, D.vcD, D.runP3, D.fracP3, D.blkE2, D.gidx2, D.lorg2,
                   D.tileSlot, D.tileRow, D.tperm, D.tloc, D.fracT, D.fracT32, D.parity, D.wdR, D.wdB, D.q1diag, D.wd1};
@@ -358,6 +358,13 @@ template <>
 const double* fracE_of<double>(const DevLevel& D) { return D.fracE; }
 template <>
 const float* fracE_of<float>(const DevLevel& D) { return D.fracE32; }
+NsumAddr nsum_addr(const DevLevel& D) {
+  NsumAddr a{D.m, D.ilist, D.nbrI};
+  a.seg = D.nsSeg;
+  a.chunkSeg = D.nsChunkSeg;
+  a.segOff = D.nsSegOff;
+  return a;
+}
 ExtAddr ext_addr(const DevLevel& D) {
   if (D.band_order) return ExtAddr{nullptr, D.packedB, D.origin};
   ExtAddr a{D.perm, D.packed, D.origin};
@@ -449,7 +456,7 @@ void smooth_sweep(const cpm_band b, int l, T* u, const T* f, const T* rhsA, T* g
   if (u_zero && f)
     gg = f;
   else
-    launch_nsum<T>(b->dim, D.m, D.ilist, D.nbrI, u, f, (T)(1.0 / (D.h * D.h)), g, nullptr, lc, s);
+    launch_nsum<T>(b->dim, nsum_addr(D), u, f, (T)(1.0 / (D.h * D.h)), g, nullptr, lc, s);
   if (b->learned_active && l < 2 && b->mlpW && D.patchRow) {
     learned_sweep<T>(b, l, u, f, rhsA, const_cast<T*>(gg), r, c, s);
     return;
@@ -633,7 +640,7 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
     launch_ext<T, T>(b->dim, EXT_RESID, D.n, f, ext_addr(D), fracK_of<T>(D), rhsA, B[l].u, B[l].r, (T)delta,
                      (T)0, nullptr, ext_cfg(D), s);
   } else {
-    launch_nsum<T>(b->dim, D.m, D.ilist, D.nbrI, B[l].u, f, (T)(1.0 / (D.h * D.h)), B[l].g, nullptr, lc, s);
+    launch_nsum<T>(b->dim, nsum_addr(D), B[l].u, f, (T)(1.0 / (D.h * D.h)), B[l].g, nullptr, lc, s);
     launch_ext<T, T>(b->dim, EXT_RESID, D.n, B[l].g, ext_addr(D), fracK_of<T>(D), rhsA, B[l].u, B[l].r, (T)delta,
                      (T)0, nullptr, ext_cfg(D), s);
   }
@@ -686,7 +693,7 @@ static void vcycle_std(const cpm_band b, int l, LevelBufs<double>* B, const cpm_
   // one Jacobi sweep, or the red then the black half-sweep (the cubic-E extension pass updates
   // only the node it visits, so each half-sweep is in place; the black one reads the new reds)
   auto half = [&](const double* wd) {
-    launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, B[l].u, nullptr, inv_h2, B[l].g, nullptr, lc, s);
+    launch_nsum<double>(b->dim, nsum_addr(D), B[l].u, nullptr, inv_h2, B[l].g, nullptr, lc, s);
     if (el1) {
       launch_p1(b->dim, EXT_SMOOTH, D.n, B[l].g, B[l].u, ea, D.fracK, B[l].f, wd, B[l].t, delta, gamma, ext_cfg(D),
                 s);
@@ -712,7 +719,7 @@ static void vcycle_std(const cpm_band b, int l, LevelBufs<double>* B, const cpm_
                                B[l].t, 0.0, 0.0, nullptr, ext_cfg(D), s);
     v = B[l].t;
   }
-  launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, v, nullptr, inv_h2, B[l].g, nullptr, lc, s);
+  launch_nsum<double>(b->dim, nsum_addr(D), v, nullptr, inv_h2, B[l].g, nullptr, lc, s);
   if (el1)
     launch_p1(b->dim, EXT_RESID, D.n, B[l].g, v, ea, D.fracK, B[l].f, nullptr, B[l].r, delta, gamma, ext_cfg(D), s);
   else
@@ -792,7 +799,7 @@ void enqueue_resid64(const cpm_band b, const double* f, const double* u, double*
                                  level_delta(b, 0, c), 0.0, b->dscal, s);
     return;
   }
-  launch_nsum<double>(b->dim, D.m, D.ilist, D.nbrI, u, f, 1.0 / (D.h * D.h), g, b->dscal, lc, s);
+  launch_nsum<double>(b->dim, nsum_addr(D), u, f, 1.0 / (D.h * D.h), g, b->dscal, lc, s);
   if (r64)
     launch_ext<double, double>(b->dim, EXT_RESID, D.n, g, ext_addr(D), fracK_of<double>(D), nullptr,
                                const_cast<double*>(u), r64, level_delta(b, 0, c), 0.0, b->dscal, ext_cfg(D), s);
@@ -1211,6 +1218,13 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
     if (st == CPM_OK) st = upload_f32(b, &D.fracK32, H.fracK);
     if (st == CPM_OK) st = upload(b, &D.ilist, H.ilist);
     if (st == CPM_OK) st = upload(b, &D.nbrI, H.nbrI);
+    // the neighbour sum reads its segment tables unless CPM_NSUM_SEG=0
+    const char* nseg_env = std::getenv("CPM_NSUM_SEG");
+    if (!H.nsSegOff.empty() && !(nseg_env && std::strcmp(nseg_env, "0") == 0)) {
+      if (st == CPM_OK) st = upload(b, &D.nsSeg, H.nsSeg);
+      if (st == CPM_OK) st = upload(b, &D.nsChunkSeg, H.nsChunkSeg);
+      if (st == CPM_OK) st = upload(b, &D.nsSegOff, H.nsSegOff);
+    }
     if (H.patchOK && !H.patchBase.empty()) {
       if (st == CPM_OK) st = upload(b, &D.patchRow, H.patchBase);
       if (st == CPM_OK) st = upload(b, &D.patchPk, H.patchPk);
@@ -1534,13 +1548,13 @@ cpm_status cpm_apply(cpm_band band, int level, int dtype, double c, const void* 
   if (st != CPM_OK) return st;
   const LaunchCfg lc = level_cfg(D);
   if (dtype == CPM_DTYPE_F64) {
-    launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, (const double*)u, nullptr, 1.0 / (D.h * D.h), (double*)work,
+    launch_nsum<double>(band->dim, nsum_addr(D), (const double*)u, nullptr, 1.0 / (D.h * D.h), (double*)work,
                         nullptr, lc, band->stream);
     launch_ext<double, double>(band->dim, EXT_APPLY, D.n, (const double*)work, ext_addr(D), fracK_of<double>(D),
                                nullptr, (double*)u, (double*)Au, level_delta(band, level, c), 0.0, nullptr, ext_cfg(D),
                                band->stream);
   } else {
-    launch_nsum<float>(band->dim, D.m, D.ilist, D.nbrI, (const float*)u, nullptr, (float)(1.0 / (D.h * D.h)),
+    launch_nsum<float>(band->dim, nsum_addr(D), (const float*)u, nullptr, (float)(1.0 / (D.h * D.h)),
                        (float*)work, nullptr, lc, band->stream);
     launch_ext<float, float>(band->dim, EXT_APPLY, D.n, (const float*)work, ext_addr(D), fracK_of<float>(D), nullptr,
                              (float*)u, (float*)Au, (float)level_delta(band, level, c), 0.0f, nullptr, ext_cfg(D),
@@ -1562,7 +1576,7 @@ cpm_status cpm_apply_pq(cpm_band band, int level, int p, double c, const double*
   cpm_status st = enter(band, stream);
   if (st != CPM_OK) return st;
   const double inv_h2 = 1.0 / (D.h * D.h);
-  launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, u, nullptr, inv_h2, work, nullptr, level_cfg(D), band->stream);
+  launch_nsum<double>(band->dim, nsum_addr(D), u, nullptr, inv_h2, work, nullptr, level_cfg(D), band->stream);
   launch_p1(band->dim, EXT_APPLY, D.n, work, u, ExtAddr{D.perm, D.packed, D.origin}, D.fracK, nullptr, nullptr, Au,
             level_delta(band, level, c), 2.0 * band->dim * inv_h2, ext_cfg(D), band->stream);
   if ((st = check_launch("cpm_apply_pq")) != CPM_OK) return st;
@@ -1841,7 +1855,7 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
       launch_fill<T>(D.n, B[level].u, (T)0.25, s);
       launch_fill<T>(D.n, B[level].f, (T)1.0, s);
     }
-    launch_nsum<T>(band->dim, D.m, D.ilist, D.nbrI, uu, ff, (T)(1.0 / (D.h * D.h)), B[level].g, nullptr, lc, s);
+    launch_nsum<T>(band->dim, nsum_addr(D), uu, ff, (T)(1.0 / (D.h * D.h)), B[level].g, nullptr, lc, s);
     if (which == 4)  // residual of the current iterate (float32, as the learned sweep keeps it)
       launch_ext<T, float>(band->dim, EXT_RESID, D.n, B[level].g, ext_addr(D), fracK_of<T>(D), (const T*)nullptr,
                            uu, reinterpret_cast<float*>(B[level].r), (T)delta, (T)0, nullptr, ext_cfg(D), s);
@@ -1853,7 +1867,7 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
           launch_ext<T, T>(band->dim, EXT_SMOOTH, D.n, B[level].g, ext_addr(D), fracK_of<T>(D), nullptr, uu, (T*)nullptr,
                            (T)delta, (T)(params->omega / delta), nullptr, ext_cfg(D), s);
         } else if (which == 1) {
-          launch_nsum<T>(band->dim, D.m, D.ilist, D.nbrI, uu, ff, (T)(1.0 / (D.h * D.h)), B[level].g, nullptr, lc, s);
+          launch_nsum<T>(band->dim, nsum_addr(D), uu, ff, (T)(1.0 / (D.h * D.h)), B[level].g, nullptr, lc, s);
         } else if (which == 2) {
           const DevLevel& F = band->dev[(size_t)(level - 1)];
           (void)F;

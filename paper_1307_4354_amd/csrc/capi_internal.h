@@ -106,6 +106,7 @@ LaunchCfg level_cfg(const DevLevel& D);
 LaunchCfg ext_cfg(const DevLevel& D);
 LaunchCfg sweep_cfg(const DevLevel& D);
 ExtAddr ext_addr(const DevLevel& D);
+NsumAddr nsum_addr(const DevLevel& D);
 SweepAddr sweep_addr(const DevLevel& D);
 TileAddr tile_addr(const DevLevel& D);
 // Whole-cycle choice of every level's sweep form (second stage of cpm_autotune).

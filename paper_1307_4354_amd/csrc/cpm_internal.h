@@ -50,6 +50,14 @@ struct HostLevel {
   // +-x neighbours are j -+ 1, the others stored as -y,+y(,-z,+z) slot-major
   std::vector<int32_t> ilist;   // m
   std::vector<int32_t> nbrI;    // (2*dim-2) * m
+  // the same list as segments of consecutive band entries whose +-y, +-z neighbours are
+  // consecutive band entries too: per segment {first list position, first band index, the
+  // 2*dim-2 neighbours of that node} (kNsumSegWords ints); per chunk of kNsumChunk list
+  // positions the segment holding its first position, per position its segment's offset from
+  // that one (< kNsumChunk, so one byte)
+  std::vector<int32_t> nsSeg;
+  std::vector<int32_t> nsChunkSeg;
+  std::vector<uint8_t> nsSegOff;
   // fused sweep (E f + (E N) u in one pass): per stencil group, the band index of the first
   // node of each cross row of the stencil widened by the axis neighbours, for the group's
   // reference x (rows (y0-1, z0+c), (y0+4, z0+c), (y0+b, z0-1), (y0+b, z0+4) in 3-D; (y0-1),
@@ -106,6 +114,9 @@ constexpr int kExtBlock = 256;      // workgroup size of the LDS-staged extensio
 constexpr int64_t kExtNptMinNodes = 4 << 20;  // levels at least this large (without the fused
                                               // sweep's tables) stage for 2 slots per thread
 constexpr int kMaxStaged = 8192;    // staged values per workgroup above which a level keeps the gather path
+constexpr int kNsumChunkBits = 8;  // neighbour-sum segment tables: chunks of 256 list positions
+constexpr int kNsumChunk = 1 << kNsumChunkBits;
+constexpr int kNsumSegWords = 6;   // per segment: first position, first band index, 4 neighbours
 constexpr int kMaxDynLds = 65536;  // dynamic LDS bytes a staged extension workgroup may take
 constexpr int kMaxGroups = 1 << (31 - kXoffBits);
 // largest level that gets the fused-sweep addressing
@@ -154,6 +165,9 @@ struct DevLevel {
   float* fracK32 = nullptr;
   int32_t* ilist = nullptr;
   int32_t* nbrI = nullptr;
+  int32_t* nsSeg = nullptr;
+  int32_t* nsChunkSeg = nullptr;
+  uint8_t* nsSegOff = nullptr;
   int32_t* runE = nullptr;
   int32_t* nbr = nullptr;
   double* fracE = nullptr;

@@ -102,7 +102,7 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
       LaunchCfg lc;
       lc.block = blocks[bi];
       const float t = time_us(s, e0, e1, reps, [&] {
-        launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, u, u, inv_h2, g, nullptr, lc, s);
+        launch_nsum<double>(band->dim, nsum_addr(D), u, u, inv_h2, g, nullptr, lc, s);
       });
       if (t < best) {
         best = t;
@@ -113,7 +113,7 @@ cpm_status cpm_autotune(cpm_band band, void* stream) {
     if (!D.fusedOK && D.ntiles <= 0) continue;
     // split sweep (both passes, tuned) against the fused pass and the tiled pass
     const float t_split = time_us(s, e0, e1, reps, [&] {
-      launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, u, u, inv_h2, g, nullptr, level_cfg(D), s);
+      launch_nsum<double>(band->dim, nsum_addr(D), u, u, inv_h2, g, nullptr, level_cfg(D), s);
       launch_ext<double, double>(band->dim, EXT_SMOOTH, D.n, g, ext_addr(D), D.band_order ? D.fracE : D.fracK,
                                  nullptr, u, (double*)nullptr, delta, 0.5 / delta, nullptr, ext_cfg(D), s);
     });

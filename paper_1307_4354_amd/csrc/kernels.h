@@ -79,9 +79,21 @@ void launch_sweep(int dim, int mode, int64_t n, const T* u, T* uo, const T* Ef, 
                   const T* frac, T inv_h2, T delta, T wod, const LaunchCfg& lc, hipStream_t s);
 
 // g = f + N u on the m nodes of B_interp (ilist), f may be null.
+// Neighbour-sum addressing: the B_interp list with its +-y, +-z neighbours, and (segOff set)
+// the same list as segments of consecutive entries (see HostLevel::nsSeg), which the kernel
+// reads instead of the two per-node index arrays.
+struct NsumAddr {
+  int64_t m;
+  const int32_t* ilist;
+  const int32_t* nbrI;
+  const int32_t* seg = nullptr;
+  const int32_t* chunkSeg = nullptr;
+  const uint8_t* segOff = nullptr;
+};
+
 template <typename T>
-void launch_nsum(int dim, int64_t m, const int32_t* ilist, const int32_t* nbrI, const T* u, const T* f, T inv_h2,
-                 T* g, unsigned long long* zero_slot, const LaunchCfg& lc, hipStream_t s);
+void launch_nsum(int dim, const NsumAddr& a, const T* u, const T* f, T inv_h2, T* g, unsigned long long* zero_slot,
+                 const LaunchCfg& lc, hipStream_t s);
 
 // out/u types: the output of EXT_RESID may be float while T is double (mixed precision).
 // frac: fractions in stencil order.

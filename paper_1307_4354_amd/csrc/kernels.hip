@@ -25,6 +25,30 @@ __global__ __launch_bounds__(kMaxBlock) void k_nsum(int64_t m, const int32_t* __
   if (k < m) nsum_node<D, T>(k, m, ilist, nbrI, u, f, inv_h2, g);
 }
 
+// The neighbour sum from the segment tables: list position k belongs to segment
+// chunkSeg[k / kNsumChunk] + segOff[k], whose node t positions in has band index j0 + t and
+// neighbours nb_q + t.  Arithmetic as nsum_node's, term for term.
+template <int D, typename T>
+__global__ __launch_bounds__(kMaxBlock) void k_nsum_seg(int64_t m, const int32_t* __restrict__ seg,
+                                                        const int32_t* __restrict__ chunkSeg,
+                                                        const uint8_t* __restrict__ segOff,
+                                                        const T* __restrict__ u, const T* __restrict__ f,
+                                                        T inv_h2, T* __restrict__ g,
+                                                        unsigned long long* __restrict__ zero_slot, int remap) {
+  if (zero_slot && blockIdx.x == 0 && threadIdx.x == 0) *zero_slot = 0ull;
+  const int64_t k = tile_of_block(remap) * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int32_t* sg = seg + (int64_t)(chunkSeg[k >> kNsumChunkBits] + segOff[k]) * kNsumSegWords;
+  const int32_t t = (int32_t)k - sg[0];
+  const int32_t j = sg[1] + t;
+  T s = u[j - 1] + u[j + 1];
+#pragma unroll
+  for (int q = 0; q < 2 * D - 2; ++q) s += u[sg[2 + q] + t];
+  T gj = s * inv_h2;
+  if (f) gj += f[j];
+  g[j] = gj;
+}
+
 template <int D, typename T, typename TO, int MODE>
 __global__ __launch_bounds__(kMaxBlock) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_ext(
     int64_t n, const T* __restrict__ g,
@@ -619,17 +643,27 @@ inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 
 // ------------------------------------------------------------------------------------
 
 template <typename T>
-void launch_nsum(int dim, int64_t m, const int32_t* ilist, const int32_t* nbrI, const T* u, const T* f, T inv_h2,
-                 T* g, unsigned long long* zero_slot, const LaunchCfg& lc, hipStream_t s) {
+void launch_nsum(int dim, const NsumAddr& a, const T* u, const T* f, T inv_h2, T* g, unsigned long long* zero_slot,
+                 const LaunchCfg& lc, hipStream_t s) {
+  const int64_t m = a.m;
   if (m <= 0) {
     if (zero_slot) k_zero_u64<<<1, 64, 0, s>>>(zero_slot, 1);
     return;
   }
   const unsigned gr = grid_for(m, lc.block);
+  if (a.segOff) {
+    if (dim == 2)
+      k_nsum_seg<2, T><<<gr, lc.block, 0, s>>>(m, a.seg, a.chunkSeg, a.segOff, u, f, inv_h2, g, zero_slot,
+                                               lc.xcd_remap);
+    else
+      k_nsum_seg<3, T><<<gr, lc.block, 0, s>>>(m, a.seg, a.chunkSeg, a.segOff, u, f, inv_h2, g, zero_slot,
+                                               lc.xcd_remap);
+    return;
+  }
   if (dim == 2)
-    k_nsum<2, T><<<gr, lc.block, 0, s>>>(m, ilist, nbrI, u, f, inv_h2, g, zero_slot, lc.xcd_remap);
+    k_nsum<2, T><<<gr, lc.block, 0, s>>>(m, a.ilist, a.nbrI, u, f, inv_h2, g, zero_slot, lc.xcd_remap);
   else
-    k_nsum<3, T><<<gr, lc.block, 0, s>>>(m, ilist, nbrI, u, f, inv_h2, g, zero_slot, lc.xcd_remap);
+    k_nsum<3, T><<<gr, lc.block, 0, s>>>(m, a.ilist, a.nbrI, u, f, inv_h2, g, zero_slot, lc.xcd_remap);
 }
 
 template <typename T, typename TO>
@@ -1038,10 +1072,10 @@ void launch_interp3(int dim, int64_t n, const double* v, const int32_t* runs, co
 }
 
 // explicit instantiations
-template void launch_nsum<double>(int, int64_t, const int32_t*, const int32_t*, const double*, const double*, double,
-                                  double*, unsigned long long*, const LaunchCfg&, hipStream_t);
-template void launch_nsum<float>(int, int64_t, const int32_t*, const int32_t*, const float*, const float*, float,
-                                 float*, unsigned long long*, const LaunchCfg&, hipStream_t);
+template void launch_nsum<double>(int, const NsumAddr&, const double*, const double*, double, double*,
+                                  unsigned long long*, const LaunchCfg&, hipStream_t);
+template void launch_nsum<float>(int, const NsumAddr&, const float*, const float*, float, float*,
+                                 unsigned long long*, const LaunchCfg&, hipStream_t);
 template void launch_ext<double, double>(int, int, int64_t, const double*, const ExtAddr&, const double*,
                                          const double*, double*, double*, double, double,
                                          unsigned long long*, const LaunchCfg&, hipStream_t, const double*);

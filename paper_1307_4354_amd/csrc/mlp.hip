@@ -547,7 +547,7 @@ cpm_status cpm_smoother_features(cpm_band band, int level, double c, const doubl
   const LaunchCfg lc = band_cfg(band, D.n);
   double* g = (double*)work;
   double* r = g + D.n;
-  launch_nsum<double>(band->dim, D.m, D.ilist, D.nbrI, u, f, 1.0 / (D.h * D.h), g, nullptr, lc, s);
+  launch_nsum<double>(band->dim, nsum_addr(D), u, f, 1.0 / (D.h * D.h), g, nullptr, lc, s);
   launch_ext<double, double>(band->dim, EXT_RESID, D.n, g, ExtAddr{D.perm, D.packed, D.origin}, D.fracK, nullptr,
                              const_cast<double*>(u), r, level_delta(band, level, c), 0.0, nullptr, lc, s);
   const unsigned gr = (unsigned)((D.n + 255) / 256);

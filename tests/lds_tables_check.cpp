@@ -160,6 +160,28 @@ static long check_tiles(const HostLevel& H, long* tiles) {
   return bad;
 }
 
+// Neighbour-sum segment tables: every list position's band index and +-y, +-z neighbours, as
+// the segmented kernel forms them, equal the per-node lists.
+static long check_nsum_segments(const HostLevel& H, int dim, long* nseg) {
+  const int64_t m = (int64_t)H.ilist.size();
+  const int nq = 2 * dim - 2;
+  *nseg = (long)(H.nsSeg.size() / kNsumSegWords);
+  if ((int64_t)H.nsSegOff.size() != m || (int64_t)H.nsChunkSeg.size() != (m + kNsumChunk - 1) / kNsumChunk) return 1;
+  long bad = 0;
+  for (int64_t k = 0; k < m; ++k) {
+    const int64_t sidx = (int64_t)H.nsChunkSeg[(size_t)(k >> kNsumChunkBits)] + H.nsSegOff[(size_t)k];
+    if (sidx < 0 || sidx >= *nseg) {
+      ++bad;
+      continue;
+    }
+    const int32_t* sg = &H.nsSeg[(size_t)(sidx * kNsumSegWords)];
+    const int32_t t = (int32_t)k - sg[0];
+    bad += t < 0 || sg[1] + t != H.ilist[(size_t)k];
+    for (int q = 0; q < nq; ++q) bad += sg[2 + q] + t != H.nbrI[(size_t)(q * m + k)];
+  }
+  return bad;
+}
+
 int main() {
   struct Case {
     cpm_surface s;
@@ -187,12 +209,13 @@ int main() {
       return 1;
     }
     for (size_t l = 0; l < lv.size(); ++l) {
-      long gaps = 0, tiles = 0;
-      const long bad = check_level(lv[l], c.dim) + check_patches(lv[l], c.dim, &gaps) + check_tiles(lv[l], &tiles);
+      long gaps = 0, tiles = 0, nseg = 0;
+      const long bad = check_level(lv[l], c.dim) + check_patches(lv[l], c.dim, &gaps) + check_tiles(lv[l], &tiles) +
+                       check_nsum_segments(lv[l], c.dim, &nseg);
       std::printf("kind %d h = 1/%g level %zu: n = %ld, slots per thread %d, sweep tables %s, patch groups %ld, "
-                  "gapped rows %ld, tiles %ld, mismatches %ld\n",
+                  "gapped rows %ld, tiles %ld, sum segments %ld (%.1f nodes each), mismatches %ld\n",
                   c.s.kind, 1.0 / c.h, l, (long)lv[l].n, (int)lv[l].extNpt, lv[l].blkE2.empty() ? "absent" : "present",
-                  (long)lv[l].patchGroups, gaps, tiles, bad);
+                  (long)lv[l].patchGroups, gaps, tiles, nseg, nseg ? (double)lv[l].ilist.size() / nseg : 0.0, bad);
       fails += bad;
     }
   }

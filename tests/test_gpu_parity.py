@@ -330,6 +330,51 @@ def test_ext_prefetch_equals_plain_lds(precision, monkeypatch):
         assert np.array_equal(out["1"][k], out["0"][k]), k
 
 
+@pytest.mark.parametrize("precision", ["f64", "mixed"])
+def test_visit_order_and_workgroup_slots_leave_cycles_unchanged(precision, monkeypatch):
+    """The stencil visit order (Morton-blocked, or plain (z, y, x)), the number of stencil
+    slots a staging workgroup takes per lane (1, 2, 4) and the neighbour sum's addressing
+    (segments of consecutive entries, or per-node lists) change only which workgroup handles
+    a node and where its indices come from, not its arithmetic: cycles agree bit for bit, on
+    the torus at h = 1/64."""
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    cfg = W.SolverConfig("t64", W.torus_modes(1.0, 0.4, 11), 1 / 64, 4, W.LAM2_3D)
+    prec = cpm.CPM_F64 if precision == "f64" else cpm.CPM_MIXED
+    monkeypatch.setenv("CPM_SWEEP", "split")
+    monkeypatch.setenv("CPM_EXT_PREFETCH", "1")
+    out = {}
+    fd = None
+    for tag, env in (("default", {}), ("plain_order", {"CPM_MORTON_BITS": "-1"}),
+                     ("npt2", {"CPM_EXT_NPT": "2"}), ("npt4", {"CPM_EXT_NPT": "4"}),
+                     ("nsum_lists", {"CPM_NSUM_SEG": "0"})):
+        for k in ("CPM_MORTON_BITS", "CPM_EXT_NPT", "CPM_NSUM_SEG"):
+            monkeypatch.delenv(k, raising=False)
+        for k, v in env.items():
+            monkeypatch.setenv(k, v)
+        band = build_gpu(cfg.problem.surface, cfg.h0, cfg.levels, cfg.lam2)
+        if fd is None:
+            fd = dev(cfg.problem.f(band.export(0)[1]))
+        slots = cpm.cpm_band_ext_slots(band, 0)
+        assert slots == 256 * int(env.get("CPM_EXT_NPT", "1")), (tag, slots)
+        assert cpm.cpm_band_tuning(band, 0)[0]  # the LDS-staged extension runs
+        p = cpm.make_params(precision=prec)
+        work, nbytes = workspace(band, p)
+        ud = torch.zeros_like(fd)
+        hist = torch.zeros(8, dtype=torch.float64, device="cuda")
+        its = []
+        for _ in range(3):
+            cpm.cpm_run_cycles(band, p, fd, ud, work, nbytes, 1, 1, hist)
+            its.append(host(ud).copy())
+        out[tag] = its
+        log("%s: %d slots per workgroup" % (tag, slots))
+        del work, band
+    for tag in ("plain_order", "npt2", "npt4", "nsum_lists"):
+        for k in range(3):
+            assert np.array_equal(out[tag][k], out["default"][k]), (tag, k)
+
+
 def test_calls_run_on_the_callers_stream():
     """Cycles enqueued on a side stream are ordered with that stream's later work (no
     synchronisation in between) and give the default stream's iterates bit for bit."""

@@ -5,7 +5,8 @@ LDS-staged extension and fused sweep form lies in its workgroup's staged range a
 band index the gather form of the same pass reads (so the two forms read the same values), and
 that the learned smoother's grouped patch rows address every present patch node (rows with
 an absent middle node included) at the band index a search of the sorted grid keys finds, and
-that the tiled sweep's row tables stage, for every node, its stencil nodes and their Laplacian
+that the neighbour sum's segment tables give every listed node's band index and axis
+neighbours, and that the tiled sweep's row tables stage, for every node, its stencil nodes and their Laplacian
 neighbours at the band indices the extension and the neighbour sum read."""
 import os
 import subprocess
@@ -26,6 +27,8 @@ def test_lds_staging_tables(tmp_path):
         pytest.fail("build failed:\n" + r.stdout[-3000:])
     out = subprocess.run([exe], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=600)
     assert out.returncode == 0 and "ALL OK" in out.stdout, out.stdout[-3000:]
+    # the neighbour sum's segment tables exist on every level
+    assert all("sum segments 0 " not in ln for ln in out.stdout.splitlines() if "level" in ln)
     # the fused sweep's tables exist on the levels that have its addressing
     assert "sweep tables present" in out.stdout
     assert "patch groups 0," not in out.stdout.split("level 0:")[1].split("\n")[0]
