@@ -40,6 +40,17 @@ struct LvItem {  // one (problem, level) of a smoothing / residual phase, float3
   const float* rhsA;  // A-space right-hand side on the problem's finest level, else null
   float delta, inv_h2, wod;
   int prob;
+  // LDS staging of the extension (packedL null: gathers), neighbour-sum segments (segOff null:
+  // per-node lists)
+  const int32_t* packedL;
+  const int32_t* blkE;
+  const int32_t* gidx;
+  const int32_t* blkG;
+  const int32_t* lorg;
+  int32_t lo_off;
+  const int32_t* seg;
+  const int32_t* chunkSeg;
+  const uint8_t* segOff;
 };
 
 struct TrItem {  // restriction into / prolongation into a level with n nodes
@@ -75,6 +86,15 @@ struct TopItem {  // finest level, float64 outer quantities
   float* e32;
   double delta, inv_h2;
   int prob;
+  const int32_t* packedL;  // as in LvItem
+  const int32_t* blkE;
+  const int32_t* gidx;
+  const int32_t* blkG;
+  const int32_t* lorg;
+  int32_t lo_off;
+  const int32_t* seg;
+  const int32_t* chunkSeg;
+  const uint8_t* segOff;
 };
 
 __device__ __forceinline__ int find_item(const int64_t* __restrict__ pre, int ni, int64_t t) {
@@ -98,22 +118,47 @@ __global__ __launch_bounds__(kMaxBlock) void kb_nsum(const LvItem* __restrict__ 
     const LvItem& B = it[q];
     if (done[B.prob]) continue;
     const int64_t k = (t - pre[q]) * blockDim.x + threadIdx.x;
-    if (k < B.m) nsum_node<D, float>(k, B.m, B.ilist, B.nbrI, B.u, B.rhsA ? nullptr : B.f, B.inv_h2, B.g);
+    if (k >= B.m) continue;
+    if (B.segOff)
+      nsum_seg_node<D, float>(k, B.seg, B.chunkSeg, B.segOff, B.u, B.rhsA ? nullptr : B.f, B.inv_h2, B.g);
+    else
+      nsum_node<D, float>(k, B.m, B.ilist, B.nbrI, B.u, B.rhsA ? nullptr : B.f, B.inv_h2, B.g);
   }
+}
+
+// One tile of an extension pass over an item: LDS-staged (the tile is the item's staging
+// workgroup; needs 256 lanes) when the item has the tables, else through gathers.  The
+// staging synchronizes the workgroup, and the workgroup's next tile reuses the LDS, hence
+// the closing barrier; both branches are uniform over the workgroup.
+template <int D, typename T, typename TO, int MODE, typename Item>
+__device__ __forceinline__ unsigned long long kb_ext_tile(const Item& B, int64_t lb, const T* g, const T* frac,
+                                                          const T* b, T* u, TO* out, T delta, T wod, char* smem) {
+  constexpr int S = D == 2 ? 4 : 16;
+  unsigned long long nv = 0ull;
+  if (B.packedL && blockDim.x == kExtBlock) {
+    T* gl = (T*)smem;
+    int32_t* lo = (int32_t*)(smem + B.lo_off);
+    ext_stage<T>(lb, g, B.blkE, B.gidx, B.blkG, B.lorg, S, gl, lo);
+    const int64_t k = lb * kExtBlock + threadIdx.x;
+    if (k < B.n) nv = ext_node_lds<D, T, TO, MODE>(k, B.n, gl, lo, B.perm, B.packedL, frac, b, u, out, delta, wod);
+    __syncthreads();
+  } else {
+    const int64_t k = lb * blockDim.x + threadIdx.x;
+    if (k < B.n) nv = ext_node<D, T, TO, MODE>(k, B.n, g, B.perm, B.packed, B.origin, frac, b, u, out, delta, wod);
+  }
+  return nv;
 }
 
 template <int D, int MODE>
 __global__ __launch_bounds__(kMaxBlock) void kb_ext(const LvItem* __restrict__ it, const int64_t* __restrict__ pre,
                                                     int ni, const int* __restrict__ done) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
   const int64_t total = pre[ni];
   for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
     const int q = find_item(pre, ni, t);
     const LvItem& B = it[q];
     if (done[B.prob]) continue;
-    const int64_t k = (t - pre[q]) * blockDim.x + threadIdx.x;
-    if (k < B.n)
-      (void)ext_node<D, float, float, MODE>(k, B.n, B.g, B.perm, B.packed, B.origin, B.frac, B.rhsA, B.u, B.r,
-                                            B.delta, B.wod);
+    (void)kb_ext_tile<D, float, float, MODE>(B, t - pre[q], B.g, B.frac, B.rhsA, B.u, B.r, B.delta, B.wod, smem);
   }
 }
 
@@ -124,18 +169,19 @@ __global__ __launch_bounds__(kMaxBlock) void kb_ext(const LvItem* __restrict__ i
 template <int D>
 __global__ __launch_bounds__(kMaxBlock) void kb_first(const LvItem* __restrict__ it, const int64_t* __restrict__ pre,
                                                       int ni, const int* __restrict__ done) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
   const int64_t total = pre[ni];
   for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
     const int q = find_item(pre, ni, t);
     const LvItem& B = it[q];
     if (done[B.prob]) continue;
-    const int64_t k = (t - pre[q]) * blockDim.x + threadIdx.x;
-    if (k >= B.n) continue;
-    if (B.rhsA)
-      B.u[k] = B.wod * B.rhsA[k];
-    else
-      (void)ext_node<D, float, float, EXT_SMOOTH>(k, B.n, B.f, B.perm, B.packed, B.origin, B.frac, nullptr, B.u,
-                                                  B.r, B.delta, B.wod);
+    if (B.rhsA) {
+      const int64_t k = (t - pre[q]) * blockDim.x + threadIdx.x;
+      if (k < B.n) B.u[k] = B.wod * B.rhsA[k];
+    } else {
+      (void)kb_ext_tile<D, float, float, EXT_SMOOTH>(B, t - pre[q], B.f, B.frac, (const float*)nullptr, B.u, B.r,
+                                                    B.delta, B.wod, smem);
+    }
   }
 }
 
@@ -199,6 +245,7 @@ template <int D, int OP>
 __global__ __launch_bounds__(kMaxBlock) void kb_top(const TopItem* __restrict__ it, const int64_t* __restrict__ pre,
                                                     int ni, const int* __restrict__ done,
                                                     unsigned long long* __restrict__ slots) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
   const int64_t total = pre[ni];
   for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
     const int q = find_item(pre, ni, t);
@@ -206,17 +253,20 @@ __global__ __launch_bounds__(kMaxBlock) void kb_top(const TopItem* __restrict__ 
     if (done[B.prob]) continue;
     const int64_t k = (t - pre[q]) * blockDim.x + threadIdx.x;
     if (OP == 0) {
-      if (k < B.m) nsum_node<D, double>(k, B.m, B.ilist, B.nbrI, B.u, B.f, B.inv_h2, B.g);
-    } else if (OP == 1 || OP == 4) {
-      unsigned long long nv = 0ull;
-      if (k < B.n) {
-        if (OP == 1)
-          nv = ext_node<D, double, float, EXT_RESID>(k, B.n, B.g, B.perm, B.packed, B.origin, B.frac, nullptr, B.u,
-                                                     B.b32, B.delta, 0.0);
+      if (k < B.m) {
+        if (B.segOff)
+          nsum_seg_node<D, double>(k, B.seg, B.chunkSeg, B.segOff, B.u, B.f, B.inv_h2, B.g);
         else
-          nv = ext_node<D, double, double, EXT_PLAIN>(k, B.n, B.f, B.perm, B.packed, B.origin, B.frac, nullptr,
-                                                      nullptr, (double*)nullptr, 0.0, 0.0);
+          nsum_node<D, double>(k, B.m, B.ilist, B.nbrI, B.u, B.f, B.inv_h2, B.g);
       }
+    } else if (OP == 1 || OP == 4) {
+      unsigned long long nv;
+      if (OP == 1)
+        nv = kb_ext_tile<D, double, float, EXT_RESID>(B, t - pre[q], B.g, B.frac, (const double*)nullptr, B.u, B.b32,
+                                                      B.delta, 0.0, smem);
+      else
+        nv = kb_ext_tile<D, double, double, EXT_PLAIN>(B, t - pre[q], B.f, B.frac, (const double*)nullptr,
+                                                       (double*)nullptr, (double*)nullptr, 0.0, 0.0, smem);
       block_max_atomic(nv, slots + 2 * B.prob + (OP == 4 ? 1 : 0));
     } else if (OP == 2) {
       if (k < B.n) B.e32[k] = 0.0f;
@@ -317,6 +367,31 @@ Layout layout(int nprob, const cpm_band* bands) {
   return L;
 }
 
+// LDS bytes one staging workgroup of a level takes for values of vsize bytes (the layout of
+// launch_ext), 0 when the level has no staging tables for workgroups of kExtBlock slots
+size_t stage_bytes(const DevLevel& D, int dim, size_t vsize) {
+  if (!D.lds || D.ext_npt != 1) return 0;
+  const size_t lo = ((size_t)D.maxE * vsize + 15) & ~(size_t)15;
+  return lo + (size_t)D.maxG * (dim == 2 ? 4 : 16) * sizeof(int32_t);
+}
+
+template <typename Item>
+void set_tables(Item& it, const DevLevel& D, size_t vsize, int dim) {
+  it.packedL = nullptr;
+  const size_t bytes = stage_bytes(D, dim, vsize);
+  if (bytes > 0 && bytes <= (size_t)kMaxDynLds) {
+    it.packedL = D.packedL;
+    it.blkE = D.blkE;
+    it.gidx = D.gidx;
+    it.blkG = D.blkG;
+    it.lorg = D.lorg;
+    it.lo_off = (int32_t)(((size_t)D.maxE * vsize + 15) & ~(size_t)15);
+  }
+  it.seg = D.nsSeg;
+  it.chunkSeg = D.nsChunkSeg;
+  it.segOff = D.nsSegOff;
+}
+
 }  // namespace
 }  // namespace cpm
 
@@ -398,6 +473,7 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
   int* ndone = (int*)((char*)hist + al((size_t)nprob * CPM_MAX_HISTORY * 8));
   // ---- build the plan
   Plan plan;
+  size_t shm_lv = 0, shm_top = 0;  // dynamic LDS of the staged extension launches
   struct PV {
     float *u, *f, *g, *r;
   };
@@ -450,6 +526,8 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
         it.inv_h2 = (float)(1.0 / (D.h * D.h));
         it.wod = (float)(P.omega / delta);
         it.prob = p;
+        set_tables(it, D, sizeof(float), b->dim);
+        if (it.packedL) shm_lv = std::max(shm_lv, stage_bytes(D, b->dim, sizeof(float)));
         plan.lv[a].push_back(it);
         // restriction from this level into the next coarser one (absolute a - 1)
         const DevLevel& C = b->dev[(size_t)(l + 1)];
@@ -501,6 +579,8 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
     t.delta = level_delta(b, 0, P.c);
     t.inv_h2 = 1.0 / (D0.h * D0.h);
     t.prob = p;
+    set_tables(t, D0, sizeof(double), b->dim);
+    if (t.packedL) shm_top = std::max(shm_top, stage_bytes(D0, b->dim, sizeof(double)));
     plan.top.push_back(t);
   }
   // ---- upload item tables; prefixes per block size candidate
@@ -607,19 +687,19 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
     if (!pn.ni) return;
     if (dim == 2) {
       kb_nsum<2><<<grid(pn.total, gm), bs, 0, st2>>>((const LvItem*)pn.items, pn.pre, pn.ni, done);
-      kb_ext<2, EXT_SMOOTH><<<grid(pe.total, gm), bs, 0, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
+      kb_ext<2, EXT_SMOOTH><<<grid(pe.total, gm), bs, shm_lv, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
     } else {
       kb_nsum<3><<<grid(pn.total, gm), bs, 0, st2>>>((const LvItem*)pn.items, pn.pre, pn.ni, done);
-      kb_ext<3, EXT_SMOOTH><<<grid(pe.total, gm), bs, 0, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
+      kb_ext<3, EXT_SMOOTH><<<grid(pe.total, gm), bs, shm_lv, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
     }
   };
   auto enqueue_first = [&](const PhaseSet& S, int bs, int gm, int a, hipStream_t st2) {
     const DevPhase& pe = S.ext[a];
     if (!pe.ni) return;
     if (dim == 2)
-      kb_first<2><<<grid(pe.total, gm), bs, 0, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
+      kb_first<2><<<grid(pe.total, gm), bs, shm_lv, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
     else
-      kb_first<3><<<grid(pe.total, gm), bs, 0, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
+      kb_first<3><<<grid(pe.total, gm), bs, shm_lv, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
   };
   // ---- tile-size autotuning: time one smoothing sweep of the largest phase per candidate
   {
@@ -667,18 +747,18 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
     if (dim == 2) {
       switch (op) {
         case 0: kb_top<2, 0><<<gr, bs, 0, st2>>>(it, ph.pre, ph.ni, done, slots); break;
-        case 1: kb_top<2, 1><<<gr, bs, 0, st2>>>(it, ph.pre, ph.ni, done, slots); break;
+        case 1: kb_top<2, 1><<<gr, bs, shm_top, st2>>>(it, ph.pre, ph.ni, done, slots); break;
         case 2: kb_top<2, 2><<<gr, bs, 0, st2>>>(it, ph.pre, ph.ni, done, slots); break;
         case 3: kb_top<2, 3><<<gr, bs, 0, st2>>>(it, ph.pre, ph.ni, done, slots); break;
-        default: kb_top<2, 4><<<gr, bs, 0, st2>>>(it, ph.pre, ph.ni, done, slots); break;
+        default: kb_top<2, 4><<<gr, bs, shm_top, st2>>>(it, ph.pre, ph.ni, done, slots); break;
       }
     } else {
       switch (op) {
         case 0: kb_top<3, 0><<<gr, bs, 0, st2>>>(it, ph.pre, ph.ni, done, slots); break;
-        case 1: kb_top<3, 1><<<gr, bs, 0, st2>>>(it, ph.pre, ph.ni, done, slots); break;
+        case 1: kb_top<3, 1><<<gr, bs, shm_top, st2>>>(it, ph.pre, ph.ni, done, slots); break;
         case 2: kb_top<3, 2><<<gr, bs, 0, st2>>>(it, ph.pre, ph.ni, done, slots); break;
         case 3: kb_top<3, 3><<<gr, bs, 0, st2>>>(it, ph.pre, ph.ni, done, slots); break;
-        default: kb_top<3, 4><<<gr, bs, 0, st2>>>(it, ph.pre, ph.ni, done, slots); break;
+        default: kb_top<3, 4><<<gr, bs, shm_top, st2>>>(it, ph.pre, ph.ni, done, slots); break;
       }
     }
   };
@@ -717,10 +797,10 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
       if (pn.ni) {
         if (dim == 2) {
           kb_nsum<2><<<grid(pn.total, gm), bs, 0, st2>>>((const LvItem*)pn.items, pn.pre, pn.ni, done);
-          kb_ext<2, EXT_RESID><<<grid(pe.total, gm), bs, 0, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
+          kb_ext<2, EXT_RESID><<<grid(pe.total, gm), bs, shm_lv, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
         } else {
           kb_nsum<3><<<grid(pn.total, gm), bs, 0, st2>>>((const LvItem*)pn.items, pn.pre, pn.ni, done);
-          kb_ext<3, EXT_RESID><<<grid(pe.total, gm), bs, 0, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
+          kb_ext<3, EXT_RESID><<<grid(pe.total, gm), bs, shm_lv, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
         }
       }
       transfer(S.rs[a - 1], 1, st2);

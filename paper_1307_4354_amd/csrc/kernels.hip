@@ -25,9 +25,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_nsum(int64_t m, const int32_t* __
   if (k < m) nsum_node<D, T>(k, m, ilist, nbrI, u, f, inv_h2, g);
 }
 
-// The neighbour sum from the segment tables: list position k belongs to segment
-// chunkSeg[k / kNsumChunk] + segOff[k], whose node t positions in has band index j0 + t and
-// neighbours nb_q + t.  Arithmetic as nsum_node's, term for term.
+// The neighbour sum from the segment tables (nsum_seg_node).
 template <int D, typename T>
 __global__ __launch_bounds__(kMaxBlock) void k_nsum_seg(int64_t m, const int32_t* __restrict__ seg,
                                                         const int32_t* __restrict__ chunkSeg,
@@ -37,16 +35,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_nsum_seg(int64_t m, const int32_t
                                                         unsigned long long* __restrict__ zero_slot, int remap) {
   if (zero_slot && blockIdx.x == 0 && threadIdx.x == 0) *zero_slot = 0ull;
   const int64_t k = tile_of_block(remap) * blockDim.x + threadIdx.x;
-  if (k >= m) return;
-  const int32_t* sg = seg + (int64_t)(chunkSeg[k >> kNsumChunkBits] + segOff[k]) * kNsumSegWords;
-  const int32_t t = (int32_t)k - sg[0];
-  const int32_t j = sg[1] + t;
-  T s = u[j - 1] + u[j + 1];
-#pragma unroll
-  for (int q = 0; q < 2 * D - 2; ++q) s += u[sg[2 + q] + t];
-  T gj = s * inv_h2;
-  if (f) gj += f[j];
-  g[j] = gj;
+  if (k < m) nsum_seg_node<D, T>(k, seg, chunkSeg, segOff, u, f, inv_h2, g);
 }
 
 template <int D, typename T, typename TO, int MODE>

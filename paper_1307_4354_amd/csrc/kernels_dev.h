@@ -71,6 +71,25 @@ __device__ __forceinline__ void nsum_node(int64_t k, int64_t m, const int32_t* _
   g[j] = gj;
 }
 
+// The same sum from the segment tables: list position k lies in segment
+// chunkSeg[k / kNsumChunk] + segOff[k], whose t-th node has band index j0 + t and neighbours
+// nb_q + t.  Arithmetic as nsum_node's, term for term.
+template <int D, typename T>
+__device__ __forceinline__ void nsum_seg_node(int64_t k, const int32_t* __restrict__ seg,
+                                              const int32_t* __restrict__ chunkSeg,
+                                              const uint8_t* __restrict__ segOff, const T* __restrict__ u,
+                                              const T* __restrict__ f, T inv_h2, T* __restrict__ g) {
+  const int32_t* sg = seg + (int64_t)(chunkSeg[k >> kNsumChunkBits] + segOff[k]) * kNsumSegWords;
+  const int32_t t = (int32_t)k - sg[0];
+  const int32_t j = sg[1] + t;
+  T s = u[j - 1] + u[j + 1];
+#pragma unroll
+  for (int q = 0; q < 2 * D - 2; ++q) s += u[sg[2 + q] + t];
+  T gj = s * inv_h2;
+  if (f) gj += f[j];
+  g[j] = gj;
+}
+
 // Variable coefficient: g_j = (f_j + sum_q abar_q u_q / h^2) / D_j at node k of B_interp,
 // abar_q = (a_j + a_q) / 2 over the 2d axis neighbours q (the flux form D^b diag(A^f a) D^f),
 // D_j = c + sigma_j precomputed.  u may be null (g = f / D), f may be null.
