@@ -180,13 +180,12 @@ __global__ __launch_bounds__(256) void k_features(int64_t n, const T* __restrict
 // patch rows overlap, so the residual gathers coalesce).
 // Layer 1 is computed transposed, H^T (hidden x node) = W1 * X^T, so that after the matrix
 // cores a lane holds 16 hidden units of one node and layer 2 is a per-lane sum plus one
-// exchange with lane ^ 32.  Operand layouts of v_mfma_f32_32x32x8_bf16 (lane l, half = l/32,
-// col = l%32): A = W1 rows (hidden unit col, k = 8 ks + 4 half .. + 3) read from global
-// memory; B = X^T columns (node col, same k range).  A lane computes the whole feature row of
+// exchange with lane ^ 32.  The matrix cores run gfx950's double-rate
+// v_mfma_f32_32x32x16_bf16 (operand layouts below).  A lane computes the whole feature row of
 // its own node; the k-chunk its partner lane needs for the other node block arrives through
-// one xor-32 shuffle per k-step.  Only the k-steps that hold features are issued (5 of 8 in
-// 3-D); the last slot of the last step, a zero of the network's input, carries a constant 1
-// whose A entry is b1, so the bias is added inside the float32 accumulation.  The used
+// xor-32 shuffles.  Only the k-steps that hold features are issued (3 of 4 in 3-D); the last
+// slot of the last step, a zero of the network's input, carries a constant 1 whose A entry is
+// b1, so the bias is added inside the float32 accumulation.  The used
 // columns of W1 (with b1) and w2 are staged once per workgroup in LDS.  The residual may come
 // in float32 (R = float) under a float64 iterate: the features take it in float32 anyway, and
 // the largest float32-rounded entry is the float32-rounded largest entry, so the scale s and
@@ -197,15 +196,16 @@ __global__ __launch_bounds__(256) void k_learned(int64_t n, const R* __restrict_
                                                  const uint32_t* __restrict__ pmask, const T* __restrict__ frac,
                                                  const uint16_t* __restrict__ W, T inv_delta, T* __restrict__ u) {
   constexpr int NF = (D == 2 ? 9 : 27) + 4 * D;  // features in use
-  constexpr int KS = (NF + 1 + 7) / 8;            // k-steps, with room for the constant slot
-  constexpr int KB = 8 * KS - 1;                  // slot of the constant 1 (a zero input)
-  static_assert(KB >= NF && 8 * KS <= kIn, "feature layout");
-  constexpr int WS = 8 * KS + 4;  // LDS row of W1 in bf16, padded against bank conflicts
-  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-  __shared__ uint16_t w1s[64 * WS];  // the 8 KS used columns of W1, b1 in column KB
+  constexpr int KS = (NF + 1 + 15) / 16;          // k-steps of 16, with room for the constant slot
+  constexpr int KB = 16 * KS - 1;                 // slot of the constant 1 (a zero input)
+  static_assert(KB >= NF && 16 * KS <= kIn, "feature layout");
+  constexpr int WS = 16 * KS + 8;  // LDS row of W1 in bf16 (16-byte aligned rows, padded)
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+  __shared__ __attribute__((aligned(16))) uint16_t w1s[64 * WS];  // the 16 KS used columns of W1, b1 in column KB
   __shared__ float w2s[64];
-  for (int e = threadIdx.x; e < 64 * 2 * KS; e += blockDim.x) {
-    const int row = e / (2 * KS), c = 4 * (e % (2 * KS));
+  for (int e = threadIdx.x; e < 64 * 4 * KS; e += blockDim.x) {
+    const int row = e / (4 * KS), c = 4 * (e % (4 * KS));
     bf16x4 q = *(const bf16x4*)(W + row * kIn + c);
     if (c + 3 == KB) q[3] = (short)W[kB1 + row];
     *(bf16x4*)&w1s[row * WS + c] = q;
@@ -214,28 +214,31 @@ __global__ __launch_bounds__(256) void k_learned(int64_t n, const R* __restrict_
   __syncthreads();
   const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
   const int64_t k = (blockIdx.x * 4 + (threadIdx.x >> 6)) * (int64_t)64 + lane;
-  uint32_t xw[4 * KS];  // own feature row, bf16 pairs (slot 2j in the low half of word j)
+  uint32_t xw[8 * KS];  // own feature row, bf16 pairs (slot 2j in the low half of word j)
   float s = 0.0f;
   if (k < n) {
-    s = node_features<D, R, 8 * KS, T>(k, n, r, prow, ppk, groups, pmask, frac, xw);
+    s = node_features<D, R, 16 * KS, T>(k, n, r, prow, ppk, groups, pmask, frac, xw);
   } else {
 #pragma unroll
-    for (int j = 0; j < 4 * KS; ++j) xw[j] = 0u;
+    for (int j = 0; j < 8 * KS; ++j) xw[j] = 0u;
   }
   xw[KB >> 1] |= 0x3F80u << (16 * (KB & 1));  // the constant 1.0 (a zero slot of the input)
-  // own chunk (k = 8 ks + 4 half) and the partner's chunk for the other node block
-  uint32_t own[2 * KS], got[2 * KS];
+  // v_mfma_f32_32x32x16_bf16 operands (lane l, half = l/32, col = l%32): A = W1 row (hidden
+  // unit col of the block), k = 16 ks + 8 half .. + 7; B = X^T column (node col), the same k
+  // range; D element v of lane l = row 8 (v/4) + 4 half + v%4, column col.  A lane's own node
+  // is column col of node block half; the 8 k-slots the partner lane needs for the other node
+  // block arrive through one xor-32 exchange of four words per k-step.
+  uint32_t own[4 * KS], got[4 * KS];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const uint32_t lo = xw[4 * ks + e], hi = xw[4 * ks + 2 + e];
-      own[2 * ks + e] = half ? hi : lo;
-      got[2 * ks + e] = __shfl_xor(half ? lo : hi, 32);
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t lo = xw[8 * ks + e], hi = xw[8 * ks + 4 + e];
+      own[4 * ks + e] = half ? hi : lo;
+      got[4 * ks + e] = __shfl_xor(half ? lo : hi, 32);
     }
   }
-  // one 32x32 accumulator tile at a time (hidden block mb of node block nb): 16 accumulator
-  // registers live instead of 32, for one more wavefront per SIMD
+  // one 32x32 accumulator tile at a time (hidden block mb of node block nb)
   float y = 0.0f;
 #pragma unroll
   for (int nb = 0; nb < 2; ++nb) {
@@ -248,10 +251,11 @@ __global__ __launch_bounds__(256) void k_learned(int64_t n, const R* __restrict_
       for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const u32x2 bw = {mine ? own[2 * ks] : got[2 * ks], mine ? own[2 * ks + 1] : got[2 * ks + 1]};
-        const bf16x4 bv = __builtin_bit_cast(bf16x4, bw);
-        const bf16x4 av = *(const bf16x4*)&w1s[(mb * 32 + col) * WS + ks * 8 + half * 4];
-        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc, 0, 0, 0);
+        const u32x4 bw = {mine ? own[4 * ks] : got[4 * ks], mine ? own[4 * ks + 1] : got[4 * ks + 1],
+                          mine ? own[4 * ks + 2] : got[4 * ks + 2], mine ? own[4 * ks + 3] : got[4 * ks + 3]};
+        const bf16x8 bv = __builtin_bit_cast(bf16x8, bw);
+        const bf16x8 av = *(const bf16x8*)&w1s[(mb * 32 + col) * WS + ks * 16 + half * 8];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
       }
 #pragma unroll
       for (int v = 0; v < 16; ++v) p += fmaxf(acc[v], 0.0f) * w2s[mb * 32 + 8 * (v >> 2) + 4 * half + (v & 3)];
