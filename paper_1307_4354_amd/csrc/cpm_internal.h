@@ -107,7 +107,9 @@ struct HostLevel {
   std::vector<int32_t> runR;   // 2^(dim-1) * n: x-runs in level-1's band
 };
 
-constexpr int kXoffBits = 10;
+constexpr int kXoffBits = 6;  // x-offset bits of a stencil group: a group lies inside one Morton
+                              // block (offsets below 8), or, in the plain order, is cut at 64
+                              // nodes; the group id keeps 25 bits (levels of 10^8 nodes)
 constexpr int kPatchBits = 8;  // node offset bits of a learned-smoother patch group
 constexpr int kPatchRun = 1 << kPatchBits;
 constexpr int kExtBlock = 256;      // workgroup size of the LDS-staged extension
