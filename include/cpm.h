@@ -268,7 +268,10 @@ cpm_status cpm_vcycle(cpm_band band, const cpm_params* params, const double* f, 
  * CPM_MIXED precision each outer step is one float32 V-cycle on the correction equation
  * A e = r with r evaluated in double.  With params->fmg the given u is replaced by the
  * full-multigrid start first (its one cycle per level is not counted in stats->cycles).
- * Returns CPM_E_NOCONV / CPM_E_DIVERGED with stats filled. */
+ * Returns CPM_E_NOCONV / CPM_E_DIVERGED with stats filled; CPM_E_NOCONV also before
+ * max_cycles when the stopping quantity has not dropped below 0.99 of its best value for 8
+ * cycles (it has reached the rounding floor of its evaluation: the residual's cancellation
+ * between delta u and E(N u) grows like the 2d/h^2 of the finest level). */
 cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, double* u,
                      void* work, size_t work_bytes, double rtol, int max_cycles,
                      cpm_stats* stats, void* stream);

@@ -1723,6 +1723,12 @@ cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, d
   }
   double prev = p.precision == CPM_F64 ? NAN : r0 / bn;
   st = CPM_E_NOCONV;
+  // stagnation: the stopping quantity has not dropped below 0.99 of its best value for
+  // kStallCycles cycles (it has reached the rounding floor of its own evaluation)
+  constexpr int kStallCycles = 8;
+  double best = INFINITY;
+  int best_k = -1;
+  bool stalled = false;
   for (int k = 0; k < max_cycles; ++k) {
     // cycles after the first start from the residual the previous one left
     const bool r_ready = k > 0;
@@ -1747,16 +1753,34 @@ cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, d
     if (band->learned_active && std::isfinite(prev) && prev > 0 && rel / prev > band->rho_plain) {
       band->learned_active = false;
       S->fallback_cycle = k;
+      best = INFINITY;  // the plain cycle starts its own record
     }
     prev = rel;
     if (rel < rtol) {
       st = CPM_OK;
       break;
     }
+    if (rel < 0.99 * best) {
+      best = rel;
+      best_k = k;
+    } else if (k - best_k >= kStallCycles) {
+      stalled = true;
+      break;
+    }
   }
   band->learned_active = false;
   S->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  if (st == CPM_E_NOCONV) set_error("maximum number of cycles reached");
+  if (st == CPM_E_NOCONV) {
+    if (stalled) {
+      std::ostringstream os;
+      os << "stagnated: the stopping quantity has not dropped below 0.99 of its best value " << best
+         << " for " << kStallCycles << " cycles (last " << S->relres << ", rtol " << rtol
+         << "); a steady value is the rounding floor of its evaluation at this resolution and precision";
+      set_error(os.str());
+    } else {
+      set_error("maximum number of cycles reached");
+    }
+  }
   cpm_status ls = leave(band, stream);
   return st != CPM_OK ? st : ls;
 }

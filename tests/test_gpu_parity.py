@@ -477,6 +477,17 @@ def test_error_paths():
     # not converged within the cycle budget
     st = cpm.cpm_solve(band, p, fd, ud, work, nbytes, 1e-30, 2, raise_on_noconv=False)
     assert st.status == cpm.CPM_E_NOCONV and st.cycles == 2
+    # a tolerance below the rounding floor of the residual: the solve stops once the residual
+    # has stagnated for 8 cycles, well before the cycle budget, and says so
+    ud.zero_()
+    with pytest.raises(cpm.CpmError, match="stagnated") as ei:
+        cpm.cpm_solve(band, p, fd, ud, work, nbytes, 1e-30, 500)
+    assert ei.value.status == cpm.CPM_E_NOCONV
+    ud.zero_()
+    st = cpm.cpm_solve(band, p, fd, ud, work, nbytes, 1e-30, 500, raise_on_noconv=False)
+    hist = st.history()
+    assert st.cycles < 100 and min(hist) < 1e-10, (st.cycles, min(hist))
+    assert min(hist[-8:]) >= 0.99 * min(hist[:-8]), hist[-10:]
     # NaN right-hand side is reported as divergence (a NaN at a node outside every
     # interpolation stencil would never reach E f, so poison all entries)
     fd.fill_(float("nan"))
