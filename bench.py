@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--workload", default="torus256",
-                    choices=["torus256", "sphere64", "batched256", "learned"],
+                    choices=["torus256", "sphere64", "batched256", "learned", "torus512"],
                     help="torus256 (default, the headline line); the others are secondary measurements")
     ap.add_argument("--nprob", type=int, default=256, help="batched256: number of problems")
     ap.add_argument("--train-steps", type=int, default=3000, help="learned: Adam steps")
@@ -494,7 +494,54 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     {"torus256": headline_torus256, "sphere64": run_sphere64, "batched256": run_batched256,
-     "learned": run_learned}[args.workload](args)
+     "learned": run_learned, "torus512": run_torus512}[args.workload](args)
+
+
+def run_torus512(args):
+    """The headline torus one refinement further (h = 1/512, 7 levels, 34 million finest
+    nodes): FP64 and mixed cycle rates, times to 1e-10 from u = 0, and the band's device
+    memory (the band's arrays go through torch's caching allocator for the count)."""
+    import torch
+
+    import paper_1307_4354_amd as cpm
+    import workloads as W
+
+    cfg = W.config_torus_mixed(512)
+    s = cfg.problem.surface
+    cpm.use_torch_allocator(True)
+    m0 = torch.cuda.memory_allocated()
+    t0 = time.perf_counter()
+    band = cpm.cpm_build_band(cpm.make_surface(s.kind, s.R, s.r, s.center), cfg.h0, cfg.levels, cfg.lam2)
+    t_build = time.perf_counter() - t0
+    band_bytes = torch.cuda.memory_allocated() - m0
+    sizes = band.sizes()
+    _, cp = band.export(0)
+    fd = torch.as_tensor(cfg.problem.f(cp)).to("cuda")
+    t0 = time.perf_counter()
+    cpm.cpm_autotune(band)
+    t_tune = time.perf_counter() - t0
+    out = {"metric": "band DOF*V-cycles/s, torus h=1/512 (secondary workload)", "unit": "DOF*V-cycles/s",
+           "n_per_level": sizes, "band_build_s": t_build, "autotune_s": t_tune,
+           "band_device_bytes": int(band_bytes)}
+    for name, prec in (("f64", cpm.CPM_F64), ("mixed", cpm.CPM_MIXED)):
+        p = cpm.make_params(c=cfg.problem.c, nu1=cfg.nu1, nu2=cfg.nu2, omega=cfg.omega, precision=prec)
+        nb = cpm.cpm_workspace_size(band, p)
+        work = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        ud = torch.zeros_like(fd)
+        hist = torch.zeros(2 * PER_LAUNCH + 8, dtype=torch.float64, device="cuda")
+        for _ in range(2):  # both graphs of the timed run captured
+            cpm.cpm_run_cycles(band, p, fd, ud, work, nb, 2 * PER_LAUNCH, PER_LAUNCH, hist)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cpm.cpm_run_cycles(band, p, fd, ud, work, nb, 2 * PER_LAUNCH, PER_LAUNCH, hist)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / (2 * PER_LAUNCH)
+        del work
+        _, sol = _solve(cpm, torch, band, p, fd, max_cycles=100)
+        out[name] = {"value": sizes[0] / dt, "ms_per_cycle": dt * 1e3, "time_to_1e-10": sol,
+                     "workspace_bytes": int(nb)}
+    band.free()
+    print(json.dumps(out), flush=True)
 
 
 def run_sphere64(args):
