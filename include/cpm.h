@@ -193,6 +193,11 @@ cpm_status cpm_band_levels(cpm_band band, int* levels, int* dim);
  * sphere, min(r, R - r) for a torus, the smallest radius of curvature for the level set).
  * Such coarse levels are allowed: nodes at a tie take the documented closest point on S. */
 #define CPM_BAND_BEYOND_REACH 1
+/* CPM_BAND_RESID_SUBSET: the residual passed to the restriction into the next level is formed
+ * only at the fine nodes that the restriction's linear stencils read (Sec. 4.3: it samples
+ * the residual near the surface; about a third of a 3-D level), the other entries of that
+ * vector being left as they were. */
+#define CPM_BAND_RESID_SUBSET 2
 cpm_status cpm_band_info(cpm_band band, int level, int64_t* n, double* h, int* flags);
 
 /* Copy one level's grid multi-indices (n x dim int32, row-major) and closest points

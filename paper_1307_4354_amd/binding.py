@@ -23,6 +23,7 @@ CPM_CIRCLE, CPM_SPHERE, CPM_TORUS, CPM_DZIUK = 0, 1, 2, 3
 CPM_F64, CPM_MIXED = 0, 1
 CPM_DTYPE_F64, CPM_DTYPE_F32 = 0, 1
 CPM_BAND_BEYOND_REACH = 1
+CPM_BAND_RESID_SUBSET = 2
 CPM_RESIDUAL_CONSISTENT, CPM_RESIDUAL_VERBATIM = 0, 1
 CPM_SMOOTH_JACOBI, CPM_SMOOTH_LEARNED, CPM_SMOOTH_STANDARD, CPM_SMOOTH_STANDARD_RB = 0, 1, 2, 3
 CPM_MAX_HISTORY = 256

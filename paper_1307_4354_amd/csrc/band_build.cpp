@@ -462,6 +462,15 @@ struct StageSet {
   }
 };
 
+// LDS staging tables of the extension over a list of ns stencil slots (packed per slot,
+// the level's group origins), for workgroups of kExtBlock * npt consecutive slots: the staged
+// band indices and, per local group, the LDS offset of each x-run for x-offset 0 (the
+// extension part of build_lds_tables, on an arbitrary slot list).
+static void stage_slot_list(int64_t ns, const std::vector<int32_t>& packed, const std::vector<int32_t>& origin,
+                            int S, int npt, std::vector<int32_t>& blkE, std::vector<int32_t>& gidx,
+                            std::vector<int32_t>& blkG, std::vector<int32_t>& lorg, std::vector<int32_t>& packedL,
+                            int32_t& maxE, int32_t& maxG);
+
 // LDS staging tables of the extension (see HostLevel): for every workgroup of kExtBlock *
 // extNpt consecutive stencil slots, merge the x-runs its nodes read into segments of consecutive
 // band indices, lay the segments out one after another in LDS and record, per local group
@@ -575,6 +584,93 @@ void build_lds_tables(HostLevel& Lv, int S, int SX) {
     Lv.blkE2[(size_t)b + 1] = Lv.blkE2[(size_t)b] + set2.size;
     Lv.maxE2 = std::max(Lv.maxE2, set2.size);
   }
+}
+
+static void stage_slot_list(int64_t ns, const std::vector<int32_t>& packed, const std::vector<int32_t>& origin,
+                            int S, int npt, std::vector<int32_t>& blkE, std::vector<int32_t>& gidx,
+                            std::vector<int32_t>& blkG, std::vector<int32_t>& lorg, std::vector<int32_t>& packedL,
+                            int32_t& maxE, int32_t& maxG) {
+  const int64_t wg = (int64_t)kExtBlock * npt, nb = (ns + wg - 1) / wg;
+  const int32_t xmask = (1 << kXoffBits) - 1;
+  blkE.assign((size_t)nb + 1, 0);
+  blkG.assign((size_t)nb + 1, 0);
+  gidx.clear();
+  lorg.clear();
+  packedL.assign((size_t)ns, 0);
+  maxE = 0;
+  maxG = 0;
+  std::vector<std::pair<int32_t, int32_t>> iv;
+  std::vector<int32_t> lg_gid, lg_xmin, lg_xmax;
+  StageSet set;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t k0 = b * wg, k1 = std::min<int64_t>(ns, k0 + wg);
+    lg_gid.clear();
+    lg_xmin.clear();
+    lg_xmax.clear();
+    for (int64_t k = k0; k < k1; ++k) {
+      const int32_t gid = packed[(size_t)k] >> kXoffBits, xo = packed[(size_t)k] & xmask;
+      if (lg_gid.empty() || lg_gid.back() != gid) {
+        lg_gid.push_back(gid);
+        lg_xmin.push_back(xo);
+        lg_xmax.push_back(xo);
+      } else {
+        lg_xmin.back() = std::min(lg_xmin.back(), xo);
+        lg_xmax.back() = std::max(lg_xmax.back(), xo);
+      }
+      packedL[(size_t)k] = (int32_t)(((lg_gid.size() - 1) << kXoffBits) | (size_t)xo);
+    }
+    iv.clear();
+    for (size_t q = 0; q < lg_gid.size(); ++q)
+      for (int s = 0; s < S; ++s) {
+        const int32_t o = origin[(size_t)lg_gid[q] * S + s];
+        iv.emplace_back(o + lg_xmin[q], o + lg_xmax[q] + 4);
+      }
+    set.build(iv);
+    set.append_indices(gidx);
+    for (size_t q = 0; q < lg_gid.size(); ++q)
+      for (int s = 0; s < S; ++s) lorg.push_back(set.lds_of(origin[(size_t)lg_gid[q] * S + s], lg_xmin[q]));
+    blkE[(size_t)b + 1] = blkE[(size_t)b] + set.size;
+    blkG[(size_t)b + 1] = blkG[(size_t)b] + (int32_t)lg_gid.size();
+    maxE = std::max(maxE, set.size);
+    maxG = std::max(maxG, (int32_t)lg_gid.size());
+  }
+}
+
+// The residual-for-restriction subset of fine level F (see HostLevel::rsN): the fine nodes that
+// the linear restriction stencils of coarse level C read, in F's stencil order, with F's
+// groups, and their staging tables.  CPM_RESID_SUBSET=0 leaves it empty.
+static void build_resid_subset(HostLevel& F, const HostLevel& C) {
+  F.rsN = 0;
+  std::vector<int32_t>().swap(F.rsPerm);
+  std::vector<int32_t>().swap(F.rsPackedL);
+  std::vector<double>().swap(F.rsFrac);
+  if (const char* e = std::getenv("CPM_RESID_SUBSET"))
+    if (std::strcmp(e, "0") == 0) return;
+  if (F.blkE.empty() || F.perm.empty()) return;
+  const int dim = F.dim, S = dim == 2 ? 4 : 16, nr = 1 << (dim - 1);
+  const int64_t n = F.n, nc = C.n;
+  std::vector<uint8_t> need((size_t)n, 0);
+  for (int r = 0; r < nr; ++r)
+    for (int64_t j = 0; j < nc; ++j) {
+      const int32_t a = C.runR[(size_t)(r * nc + j)];
+      need[(size_t)a] = 1;
+      need[(size_t)a + 1] = 1;
+    }
+  std::vector<int32_t> packed;
+  for (int64_t k = 0; k < n; ++k) {
+    const int32_t i = F.perm[(size_t)k];
+    if (!need[(size_t)i]) continue;
+    F.rsPerm.push_back(i);
+    packed.push_back(F.packed[(size_t)k]);
+  }
+  const int64_t ns = (int64_t)F.rsPerm.size();
+  F.rsFrac.assign((size_t)(dim * ns), 0.0);
+  for (int64_t k = 0; k < ns; ++k)
+    for (int a = 0; a < dim; ++a) F.rsFrac[(size_t)(a * ns + k)] = F.fracE[(size_t)(a * n + F.rsPerm[(size_t)k])];
+  F.rsNpt = ns >= kExtNptMinNodes ? 2 : 1;
+  stage_slot_list(ns, packed, F.origin, S, F.rsNpt, F.rsBlkE, F.rsGidx, F.rsBlkG, F.rsLorg, F.rsPackedL, F.rsMaxE,
+                  F.rsMaxG);
+  F.rsN = ns;
 }
 
 // Stencil-ordered extension addressing and the B_interp neighbour lists of one level.
@@ -1156,6 +1252,7 @@ cpm_status build_host_levels(const cpm_surface& s, const cpm_grid& g, int dim,
       err = os.str();
       return CPM_E_BAND;
     }
+    build_resid_subset(F, C);
   }
   for (auto& Lv : levels) std::vector<int32_t>().swap(Lv.map);
   return CPM_OK;

@@ -110,7 +110,7 @@ static cpm_status upload_f32(const cpm_band b, float** dst, const std::vector<do
 static void free_dev(cpm_band b) {
   for (auto& D : b->dev) {
     void* ps[] = {D.runE,  D.nbr,   D.fracE,  D.fracE32, D.runP,    D.fracP,  D.fracP32, D.runR,
-                  D.fracR, D.fracR32, D.perm, D.packed, D.origin, D.fracK, D.fracK32, D.ilist, D.nbrI, D.nsSeg, D.nsChunkSeg, D.nsSegOff,
+                  D.fracR, D.fracR32, D.perm, D.packed, D.origin, D.fracK, D.fracK32, D.ilist, D.nbrI, D.nsSeg, D.nsChunkSeg, D.nsSegOff, D.rs_perm, D.rs_packedL, D.rs_blkE, D.rs_gidx, D.rs_blkG, D.rs_lorg, D.rs_frac, D.rs_frac32,
                   D.patchRow, D.patchPk, D.patchMask, D.packedB, D.packedL, D.blkE, D.gidx, D.blkG, D.lorg, D.originX,
                   D.qdiag, D.wd, D.acoef, D.vcD, D.runP3, D.fracP3, D.blkE2, D.gidx2, D.lorg2,
                   D.tileSlot, D.tileRow, D.tperm, D.tloc, D.fracT, D.fracT32, D.parity, D.wdR, D.wdB, D.q1diag, D.wd1};
@@ -358,6 +358,28 @@ template <>
 const double* fracE_of<double>(const DevLevel& D) { return D.fracE; }
 template <>
 const float* fracE_of<float>(const DevLevel& D) { return D.fracE32; }
+// Extension over the restriction's fine nodes (HostLevel::rsN): LDS-staged only; valid when
+// D.rs_n > 0 and the level runs the LDS-staged extension.
+static ExtAddr ext_addr_rs(const DevLevel& D) {
+  ExtAddr a{D.rs_perm, nullptr, nullptr};
+  a.packedL = D.rs_packedL;
+  a.blkE = D.rs_blkE;
+  a.gidx = D.rs_gidx;
+  a.blkG = D.rs_blkG;
+  a.lorg = D.rs_lorg;
+  a.maxE = D.rs_maxE;
+  a.maxG = D.rs_maxG;
+  a.npt = D.rs_npt;
+  return a;
+}
+template <typename T>
+static const T* rs_frac_of(const DevLevel& D);
+template <>
+const double* rs_frac_of<double>(const DevLevel& D) { return D.rs_frac; }
+template <>
+const float* rs_frac_of<float>(const DevLevel& D) { return D.rs_frac32; }
+static bool resid_subset(const DevLevel& D) { return D.rs_n > 0 && D.lds && D.use_lds && !D.band_order; }
+
 NsumAddr nsum_addr(const DevLevel& D) {
   NsumAddr a{D.m, D.ilist, D.nbrI};
   a.seg = D.nsSeg;
@@ -635,14 +657,20 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
       resid_done = true;
     }
   }
+  // the restriction reads r only at its stencils' fine nodes: where the level has that
+  // subset's tables, the residual is formed there alone (the other entries are never read)
+  const bool rs = resid_subset(D);
+  const int64_t rn = rs ? D.rs_n : D.n;
+  const ExtAddr ra = rs ? ext_addr_rs(D) : ext_addr(D);
+  const T* rfrac = rs ? rs_frac_of<T>(D) : fracK_of<T>(D);
   if (resid_done) {
   } else if (u_zero && nu1 == 0 && f) {
-    launch_ext<T, T>(b->dim, EXT_RESID, D.n, f, ext_addr(D), fracK_of<T>(D), rhsA, B[l].u, B[l].r, (T)delta,
-                     (T)0, nullptr, ext_cfg(D), s);
+    launch_ext<T, T>(b->dim, EXT_RESID, rn, f, ra, rfrac, rhsA, B[l].u, B[l].r, (T)delta, (T)0, nullptr, ext_cfg(D),
+                     s);
   } else {
     launch_nsum<T>(b->dim, nsum_addr(D), B[l].u, f, (T)(1.0 / (D.h * D.h)), B[l].g, nullptr, lc, s);
-    launch_ext<T, T>(b->dim, EXT_RESID, D.n, B[l].g, ext_addr(D), fracK_of<T>(D), rhsA, B[l].u, B[l].r, (T)delta,
-                     (T)0, nullptr, ext_cfg(D), s);
+    launch_ext<T, T>(b->dim, EXT_RESID, rn, B[l].g, ra, rfrac, rhsA, B[l].u, B[l].r, (T)delta, (T)0, nullptr,
+                     ext_cfg(D), s);
   }
   launch_restrict<T>(b->dim, C.n, B[l].r, C.runR, fracR_of<T>(C), B[l + 1].f, B[l + 1].u, level_cfg(C), s);
   for (int v = 0; v < visits; ++v) vcycle_level<T>(b, l + 1, B, nullptr, p, s, v == 0);
@@ -1280,6 +1308,25 @@ cpm_status cpm_build_band(const cpm_surface* surface, const cpm_grid* grid, void
       if (st == CPM_OK) st = upload(b, &D.blkG, H.blkG);
       if (st == CPM_OK) st = upload(b, &D.lorg, H.lorg);
     }
+    // the residual before restriction over the restriction's fine nodes only
+    if (D.lds && H.rsN > 0) {
+      const size_t rs_bytes = (((size_t)H.rsMaxE * sizeof(double) + 15) & ~(size_t)15) +
+                              (size_t)H.rsMaxG * (H.dim == 2 ? 4 : 16) * sizeof(int32_t);
+      if (H.rsMaxE <= kMaxStaged && rs_bytes <= (size_t)kMaxDynLds) {
+        if (st == CPM_OK) st = upload(b, &D.rs_perm, H.rsPerm);
+        if (st == CPM_OK) st = upload(b, &D.rs_packedL, H.rsPackedL);
+        if (st == CPM_OK) st = upload(b, &D.rs_blkE, H.rsBlkE);
+        if (st == CPM_OK) st = upload(b, &D.rs_gidx, H.rsGidx);
+        if (st == CPM_OK) st = upload(b, &D.rs_blkG, H.rsBlkG);
+        if (st == CPM_OK) st = upload(b, &D.rs_lorg, H.rsLorg);
+        if (st == CPM_OK) st = upload(b, &D.rs_frac, H.rsFrac);
+        if (st == CPM_OK) st = upload_f32(b, &D.rs_frac32, H.rsFrac);
+        D.rs_n = H.rsN;
+        D.rs_maxE = H.rsMaxE;
+        D.rs_maxG = H.rsMaxG;
+        D.rs_npt = H.rsNpt;
+      }
+    }
     // LDS-staged fused sweep (on the extension's workgroups) unless disabled by
     // CPM_SWEEP_LDS=0 or a workgroup would stage too many values; it is the default form of
     // the fused pass where present
@@ -1450,6 +1497,7 @@ cpm_status cpm_band_info(cpm_band band, int level, int64_t* n, double* h, int* f
   if (flags) {
     const double lam2 = band->grid.lam2 > 0 ? band->grid.lam2 : (band->dim == 2 ? 13.0 : 17.0);
     *flags = std::sqrt(lam2) * D.h >= surface_reach(band->surf) ? CPM_BAND_BEYOND_REACH : 0;
+    if (resid_subset(D)) *flags |= CPM_BAND_RESID_SUBSET;
   }
   return CPM_OK;
 }

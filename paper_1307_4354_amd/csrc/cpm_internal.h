@@ -58,6 +58,14 @@ struct HostLevel {
   std::vector<int32_t> nsSeg;
   std::vector<int32_t> nsChunkSeg;
   std::vector<uint8_t> nsSegOff;
+  // the residual that the restriction into level+1 reads is needed only at the fine nodes of
+  // its linear stencils (about a third of a level): the LDS-staged extension's tables over
+  // those nodes alone, in this level's stencil order (their groups and run origins are the
+  // level's own); empty on the coarsest level and when the level has no staging tables
+  int64_t rsN = 0;
+  std::vector<int32_t> rsPerm, rsPackedL, rsBlkE, rsGidx, rsBlkG, rsLorg;
+  std::vector<double> rsFrac;  // dim * rsN, slot order
+  int32_t rsMaxE = 0, rsMaxG = 0, rsNpt = 1;
   // fused sweep (E f + (E N) u in one pass): per stencil group, the band index of the first
   // node of each cross row of the stencil widened by the axis neighbours, for the group's
   // reference x (rows (y0-1, z0+c), (y0+4, z0+c), (y0+b, z0-1), (y0+b, z0+4) in 3-D; (y0-1),
@@ -170,6 +178,12 @@ struct DevLevel {
   int32_t* nsSeg = nullptr;
   int32_t* nsChunkSeg = nullptr;
   uint8_t* nsSegOff = nullptr;
+  int64_t rs_n = 0;  // residual-for-restriction subset (see HostLevel::rsN); 0: full level
+  int32_t *rs_perm = nullptr, *rs_packedL = nullptr, *rs_blkE = nullptr, *rs_gidx = nullptr, *rs_blkG = nullptr,
+          *rs_lorg = nullptr;
+  double* rs_frac = nullptr;
+  float* rs_frac32 = nullptr;
+  int32_t rs_maxE = 0, rs_maxG = 0, rs_npt = 1;
   int32_t* runE = nullptr;
   int32_t* nbr = nullptr;
   double* fracE = nullptr;

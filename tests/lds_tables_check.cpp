@@ -4,6 +4,7 @@
 // same pass reads.  Also checks the grouped patch rows of the learned smoother.  Prints one line per level and "ALL OK" or "FAIL"; exit status 1 on a
 // mismatch.
 #include <algorithm>
+#include <cstdlib>
 #include <array>
 #include <cstdio>
 #include <string>
@@ -182,6 +183,55 @@ static long check_nsum_segments(const HostLevel& H, int dim, long* nseg) {
   return bad;
 }
 
+// Residual-for-restriction subset of level F (coarse level C): its slots are exactly the fine
+// nodes C's restriction stencils read, in F's stencil order, and every LDS address its staged
+// extension forms holds the band index the gather form reads for that node.
+static long check_resid_subset(const HostLevel& F, const HostLevel* C, int dim, long* nsub) {
+  *nsub = (long)F.rsN;
+  if (!C) return F.rsN != 0;
+  if (F.rsN == 0) return std::getenv("CPM_RESID_SUBSET") ? 0 : 1;
+  const int S = dim == 2 ? 4 : 16, nr = 1 << (dim - 1);
+  const int64_t n = F.n, nc = C->n, ns = F.rsN;
+  const int32_t xmask = (1 << kXoffBits) - 1;
+  long bad = 0;
+  std::vector<char> need((size_t)n, 0), seen((size_t)n, 0);
+  for (int r = 0; r < nr; ++r)
+    for (int64_t j = 0; j < nc; ++j) {
+      need[(size_t)C->runR[(size_t)(r * nc + j)]] = 1;
+      need[(size_t)C->runR[(size_t)(r * nc + j)] + 1] = 1;
+    }
+  // the subset is the needed set, in increasing stencil-slot order
+  std::vector<int64_t> slot_of((size_t)n, -1);
+  for (int64_t k = 0; k < n; ++k) slot_of[(size_t)F.perm[(size_t)k]] = k;
+  int64_t prev = -1;
+  for (int64_t k = 0; k < ns; ++k) {
+    const int32_t i = F.rsPerm[(size_t)k];
+    bad += i < 0 || i >= n || !need[(size_t)i] || seen[(size_t)i] || slot_of[(size_t)i] <= prev;
+    if (i >= 0 && i < n) {
+      seen[(size_t)i] = 1;
+      prev = slot_of[(size_t)i];
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) bad += need[(size_t)i] && !seen[(size_t)i];
+  const int64_t wg = (int64_t)kExtBlock * F.rsNpt, nb = (ns + wg - 1) / wg;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int32_t e0 = F.rsBlkE[(size_t)b], e1 = F.rsBlkE[(size_t)b + 1], q0 = F.rsBlkG[(size_t)b] * S;
+    for (int64_t k = b * wg; k < std::min<int64_t>(ns, (b + 1) * wg); ++k) {
+      const int32_t i = F.rsPerm[(size_t)k];
+      const int32_t lg = F.rsPackedL[(size_t)k] >> kXoffBits, xo = F.rsPackedL[(size_t)k] & xmask;
+      const int32_t gid = F.packedB[(size_t)i] >> kXoffBits, xg = F.packedB[(size_t)i] & xmask;
+      bad += xo != xg;
+      for (int s = 0; s < S; ++s)
+        for (int a = 0; a < 4; ++a) {
+          const int32_t L = F.rsLorg[(size_t)(q0 + lg * S + s)] + xo + a, G = F.origin[(size_t)gid * S + s] + xg + a;
+          bad += L < 0 || L >= e1 - e0 || F.rsGidx[(size_t)(e0 + L)] != G;
+        }
+      for (int a = 0; a < dim; ++a) bad += F.rsFrac[(size_t)(a * ns + k)] != F.fracE[(size_t)(a * n + i)];
+    }
+  }
+  return bad;
+}
+
 int main() {
   struct Case {
     cpm_surface s;
@@ -209,13 +259,14 @@ int main() {
       return 1;
     }
     for (size_t l = 0; l < lv.size(); ++l) {
-      long gaps = 0, tiles = 0, nseg = 0;
+      long gaps = 0, tiles = 0, nseg = 0, nsub = 0;
       const long bad = check_level(lv[l], c.dim) + check_patches(lv[l], c.dim, &gaps) + check_tiles(lv[l], &tiles) +
-                       check_nsum_segments(lv[l], c.dim, &nseg);
+                       check_nsum_segments(lv[l], c.dim, &nseg) +
+                       check_resid_subset(lv[l], l + 1 < lv.size() ? &lv[l + 1] : nullptr, c.dim, &nsub);
       std::printf("kind %d h = 1/%g level %zu: n = %ld, slots per thread %d, sweep tables %s, patch groups %ld, "
-                  "gapped rows %ld, tiles %ld, sum segments %ld (%.1f nodes each), mismatches %ld\n",
+                  "gapped rows %ld, tiles %ld, sum segments %ld (%.1f nodes each), restriction subset %ld, mismatches %ld\n",
                   c.s.kind, 1.0 / c.h, l, (long)lv[l].n, (int)lv[l].extNpt, lv[l].blkE2.empty() ? "absent" : "present",
-                  (long)lv[l].patchGroups, gaps, tiles, nseg, nseg ? (double)lv[l].ilist.size() / nseg : 0.0, bad);
+                  (long)lv[l].patchGroups, gaps, tiles, nseg, nseg ? (double)lv[l].ilist.size() / nseg : 0.0, nsub, bad);
       fails += bad;
     }
   }

@@ -333,10 +333,11 @@ def test_ext_prefetch_equals_plain_lds(precision, monkeypatch):
 @pytest.mark.parametrize("precision", ["f64", "mixed"])
 def test_visit_order_and_workgroup_slots_leave_cycles_unchanged(precision, monkeypatch):
     """The stencil visit order (Morton-blocked, or plain (z, y, x)), the number of stencil
-    slots a staging workgroup takes per lane (1, 2, 4) and the neighbour sum's addressing
-    (segments of consecutive entries, or per-node lists) change only which workgroup handles
-    a node and where its indices come from, not its arithmetic: cycles agree bit for bit, on
-    the torus at h = 1/64."""
+    slots a staging workgroup takes per lane (1, 2, 4), the neighbour sum's addressing
+    (segments of consecutive entries, or per-node lists) and the residual before restriction
+    (formed at the restriction's fine nodes only, or everywhere) change only which workgroup
+    handles a node, where its indices come from and which never-read entries are written,
+    not the arithmetic: cycles agree bit for bit, on the torus at h = 1/64."""
     import paper_1307_4354_amd as cpm
 
     torch = torch_cuda()
@@ -348,8 +349,8 @@ def test_visit_order_and_workgroup_slots_leave_cycles_unchanged(precision, monke
     fd = None
     for tag, env in (("default", {}), ("plain_order", {"CPM_MORTON_BITS": "-1"}),
                      ("npt2", {"CPM_EXT_NPT": "2"}), ("npt4", {"CPM_EXT_NPT": "4"}),
-                     ("nsum_lists", {"CPM_NSUM_SEG": "0"})):
-        for k in ("CPM_MORTON_BITS", "CPM_EXT_NPT", "CPM_NSUM_SEG"):
+                     ("nsum_lists", {"CPM_NSUM_SEG": "0"}), ("resid_full", {"CPM_RESID_SUBSET": "0"})):
+        for k in ("CPM_MORTON_BITS", "CPM_EXT_NPT", "CPM_NSUM_SEG", "CPM_RESID_SUBSET"):
             monkeypatch.delenv(k, raising=False)
         for k, v in env.items():
             monkeypatch.setenv(k, v)
@@ -358,6 +359,8 @@ def test_visit_order_and_workgroup_slots_leave_cycles_unchanged(precision, monke
             fd = dev(cfg.problem.f(band.export(0)[1]))
         slots = cpm.cpm_band_ext_slots(band, 0)
         assert slots == 256 * int(env.get("CPM_EXT_NPT", "1")), (tag, slots)
+        subset = bool(band.flags(0) & cpm.CPM_BAND_RESID_SUBSET)
+        assert subset == (tag != "resid_full"), (tag, band.flags(0))
         assert cpm.cpm_band_tuning(band, 0)[0]  # the LDS-staged extension runs
         p = cpm.make_params(precision=prec)
         work, nbytes = workspace(band, p)
@@ -370,7 +373,7 @@ def test_visit_order_and_workgroup_slots_leave_cycles_unchanged(precision, monke
         out[tag] = its
         log("%s: %d slots per workgroup" % (tag, slots))
         del work, band
-    for tag in ("plain_order", "npt2", "npt4", "nsum_lists"):
+    for tag in ("plain_order", "npt2", "npt4", "nsum_lists", "resid_full"):
         for k in range(3):
             assert np.array_equal(out[tag][k], out["default"][k]), (tag, k)
 
