@@ -668,6 +668,10 @@ static void build_resid_subset(HostLevel& F, const HostLevel& C) {
   for (int64_t k = 0; k < ns; ++k)
     for (int a = 0; a < dim; ++a) F.rsFrac[(size_t)(a * ns + k)] = F.fracE[(size_t)(a * n + F.rsPerm[(size_t)k])];
   F.rsNpt = ns >= kExtNptMinNodes ? 2 : 1;
+  if (const char* e = std::getenv("CPM_RESID_NPT")) {  // slots per lane of its staging workgroups
+    const int v = std::atoi(e);
+    if (v == 1 || v == 2 || v == 4) F.rsNpt = v;
+  }
   stage_slot_list(ns, packed, F.origin, S, F.rsNpt, F.rsBlkE, F.rsGidx, F.rsBlkG, F.rsLorg, F.rsPackedL, F.rsMaxE,
                   F.rsMaxG);
   F.rsN = ns;

@@ -51,6 +51,17 @@ struct LvItem {  // one (problem, level) of a smoothing / residual phase, float3
   const int32_t* seg;
   const int32_t* chunkSeg;
   const uint8_t* segOff;
+  // the residual before restriction over the restriction's fine nodes (rs_packedL null: the
+  // whole level)
+  int64_t rs_n;
+  const int32_t* rs_perm;
+  const int32_t* rs_packedL;
+  const int32_t* rs_blkE;
+  const int32_t* rs_gidx;
+  const int32_t* rs_blkG;
+  const int32_t* rs_lorg;
+  const float* rs_frac;
+  int32_t rs_lo_off;
 };
 
 struct TrItem {  // restriction into / prolongation into a level with n nodes
@@ -159,6 +170,34 @@ __global__ __launch_bounds__(kMaxBlock) void kb_ext(const LvItem* __restrict__ i
     const LvItem& B = it[q];
     if (done[B.prob]) continue;
     (void)kb_ext_tile<D, float, float, MODE>(B, t - pre[q], B.g, B.frac, B.rhsA, B.u, B.r, B.delta, B.wod, smem);
+  }
+}
+
+// Residual before restriction: over the restriction's fine nodes (LDS-staged, 256 lanes)
+// where the item has that subset's tables, else over the whole level as kb_ext does.
+template <int D>
+__global__ __launch_bounds__(kMaxBlock) void kb_resid(const LvItem* __restrict__ it, const int64_t* __restrict__ pre,
+                                                      int ni, const int* __restrict__ done) {
+  constexpr int S = D == 2 ? 4 : 16;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  const int64_t total = pre[ni];
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int q = find_item(pre, ni, t);
+    const LvItem& B = it[q];
+    if (done[B.prob]) continue;
+    const int64_t lb = t - pre[q];
+    if (B.rs_packedL && blockDim.x == kExtBlock) {
+      float* gl = (float*)smem;
+      int32_t* lo = (int32_t*)(smem + B.rs_lo_off);
+      ext_stage<float>(lb, B.g, B.rs_blkE, B.rs_gidx, B.rs_blkG, B.rs_lorg, S, gl, lo);
+      const int64_t k = lb * kExtBlock + threadIdx.x;
+      if (k < B.rs_n)
+        (void)ext_node_lds<D, float, float, EXT_RESID>(k, B.rs_n, gl, lo, B.rs_perm, B.rs_packedL, B.rs_frac, B.rhsA,
+                                                       B.u, B.r, B.delta, B.wod);
+      __syncthreads();
+    } else {
+      (void)kb_ext_tile<D, float, float, EXT_RESID>(B, lb, B.g, B.frac, B.rhsA, B.u, B.r, B.delta, B.wod, smem);
+    }
   }
 }
 
@@ -360,7 +399,7 @@ Layout layout(int nprob, const cpm_band* bands) {
   const size_t items = (size_t)nprob * (3 * kMaxLevels + 2);
   const size_t isz = std::max(std::max(sizeof(LvItem), sizeof(TrItem)), std::max(sizeof(CoItem), sizeof(TopItem)));
   const size_t arrays = 3 * kMaxLevels + 2;    // item arrays, each padded to 256 bytes
-  const size_t prefixes = 4 * kMaxLevels + 3;  // prefix arrays per block-size candidate
+  const size_t prefixes = 5 * kMaxLevels + 3;  // prefix arrays per block-size candidate
   L.table_bytes = al(items * isz) + arrays * 256 + 3 * prefixes * (al((size_t)(nprob + 1) * sizeof(int64_t)) + 256);
   L.scal_bytes = al((size_t)nprob * 2 * 8) + al((size_t)nprob * 4) * 2 + al((size_t)nprob * CPM_MAX_HISTORY * 8) + 256;
   L.total = L.vec_bytes + L.table_bytes + L.scal_bytes + 1024;
@@ -373,6 +412,29 @@ size_t stage_bytes(const DevLevel& D, int dim, size_t vsize) {
   if (!D.lds || D.ext_npt != 1) return 0;
   const size_t lo = ((size_t)D.maxE * vsize + 15) & ~(size_t)15;
   return lo + (size_t)D.maxG * (dim == 2 ? 4 : 16) * sizeof(int32_t);
+}
+
+// LDS bytes of the residual subset's staging workgroup (float values), 0 without its tables
+size_t rs_stage_bytes(const DevLevel& D, int dim) {
+  if (D.rs_n <= 0 || !D.lds || D.rs_npt != 1 || !D.rs_frac32) return 0;
+  const size_t lo = ((size_t)D.rs_maxE * sizeof(float) + 15) & ~(size_t)15;
+  return lo + (size_t)D.rs_maxG * (dim == 2 ? 4 : 16) * sizeof(int32_t);
+}
+
+void set_rs_tables(LvItem& it, const DevLevel& D, int dim) {
+  it.rs_packedL = nullptr;
+  it.rs_n = 0;
+  const size_t bytes = rs_stage_bytes(D, dim);
+  if (bytes == 0 || bytes > (size_t)kMaxDynLds) return;
+  it.rs_n = D.rs_n;
+  it.rs_perm = D.rs_perm;
+  it.rs_packedL = D.rs_packedL;
+  it.rs_blkE = D.rs_blkE;
+  it.rs_gidx = D.rs_gidx;
+  it.rs_blkG = D.rs_blkG;
+  it.rs_lorg = D.rs_lorg;
+  it.rs_frac = D.rs_frac32;
+  it.rs_lo_off = (int32_t)(((size_t)D.rs_maxE * sizeof(float) + 15) & ~(size_t)15);
 }
 
 template <typename Item>
@@ -473,7 +535,7 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
   int* ndone = (int*)((char*)hist + al((size_t)nprob * CPM_MAX_HISTORY * 8));
   // ---- build the plan
   Plan plan;
-  size_t shm_lv = 0, shm_top = 0;  // dynamic LDS of the staged extension launches
+  size_t shm_lv = 0, shm_top = 0, shm_rs = 0;  // dynamic LDS of the staged extension launches
   struct PV {
     float *u, *f, *g, *r;
   };
@@ -528,6 +590,8 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
         it.prob = p;
         set_tables(it, D, sizeof(float), b->dim);
         if (it.packedL) shm_lv = std::max(shm_lv, stage_bytes(D, b->dim, sizeof(float)));
+        set_rs_tables(it, D, b->dim);
+        if (it.rs_packedL) shm_rs = std::max(shm_rs, rs_stage_bytes(D, b->dim));
         plan.lv[a].push_back(it);
         // restriction from this level into the next coarser one (absolute a - 1)
         const DevLevel& C = b->dev[(size_t)(l + 1)];
@@ -599,7 +663,7 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
     return (const void*)(tab + o);
   };
   struct PhaseSet {
-    DevPhase nsum[kMaxLevels], ext[kMaxLevels], rs[kMaxLevels], pr[kMaxLevels], co, top_n, top_m;
+    DevPhase nsum[kMaxLevels], ext[kMaxLevels], rsx[kMaxLevels], rs[kMaxLevels], pr[kMaxLevels], co, top_n, top_m;
   };
   std::vector<PhaseSet> sets(3);
   const void* lv_items[kMaxLevels];
@@ -631,16 +695,18 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
     const int bs = cand_block[ci];
     PhaseSet& S = sets[(size_t)ci];
     for (int a = 0; a < plan.A; ++a) {
-      std::vector<int64_t> cn, cm, cr, cp;
+      std::vector<int64_t> cn, cm, cx, cr, cp;
       for (auto& it : plan.lv[a]) {
         cn.push_back(tiles(it.n, bs));
         cm.push_back(tiles(it.m, bs));
+        cx.push_back(it.rs_packedL && bs == kExtBlock ? tiles(it.rs_n, bs) : tiles(it.n, bs));
       }
       for (auto& it : plan.rs[a]) cr.push_back(tiles(it.n, bs));
       for (auto& it : plan.pr[a]) cp.push_back(tiles(it.n, bs));
       if (!cn.empty()) {
         put_prefix(cn, S.ext[a], lv_items[a]);
         put_prefix(cm, S.nsum[a], lv_items[a]);
+        put_prefix(cx, S.rsx[a], lv_items[a]);
       }
       if (!cr.empty()) put_prefix(cr, S.rs[a], rs_items[a]);
       if (!cp.empty()) put_prefix(cp, S.pr[a], pr_items[a]);
@@ -793,14 +859,15 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
           enqueue_sweep(S, bs, gm, a, st2);
       }
       const DevPhase& pn = S.nsum[a];
-      const DevPhase& pe = S.ext[a];
+      const DevPhase& px = S.rsx[a];
+      const size_t shm_x = std::max(shm_lv, shm_rs);
       if (pn.ni) {
         if (dim == 2) {
           kb_nsum<2><<<grid(pn.total, gm), bs, 0, st2>>>((const LvItem*)pn.items, pn.pre, pn.ni, done);
-          kb_ext<2, EXT_RESID><<<grid(pe.total, gm), bs, shm_lv, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
+          kb_resid<2><<<grid(px.total, gm), bs, shm_x, st2>>>((const LvItem*)px.items, px.pre, px.ni, done);
         } else {
           kb_nsum<3><<<grid(pn.total, gm), bs, 0, st2>>>((const LvItem*)pn.items, pn.pre, pn.ni, done);
-          kb_ext<3, EXT_RESID><<<grid(pe.total, gm), bs, shm_lv, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
+          kb_resid<3><<<grid(px.total, gm), bs, shm_x, st2>>>((const LvItem*)px.items, px.pre, px.ni, done);
         }
       }
       transfer(S.rs[a - 1], 1, st2);
