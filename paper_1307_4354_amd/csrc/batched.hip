@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -767,8 +768,17 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
     else
       kb_first<3><<<grid(pe.total, gm), bs, shm_lv, st2>>>((const LvItem*)pe.items, pe.pre, pe.ni, done);
   };
-  // ---- tile-size autotuning: time one smoothing sweep of the largest phase per candidate
-  {
+  // ---- tile-size autotuning: time one smoothing sweep of the largest phase per candidate;
+  // CPM_BATCH_BLOCK = 128 | 256 | 512 fixes the workgroup size instead
+  int forced = -1;
+  if (const char* e = std::getenv("CPM_BATCH_BLOCK")) {
+    const int v = std::atoi(e);
+    for (int ci = 0; ci < 3; ++ci)
+      if (cand_block[ci] == v) forced = ci;
+  }
+  if (forced >= 0) {
+    sel = forced;
+  } else {
     int abig = 0;
     int64_t nbig = -1;
     for (int a = 1; a < plan.A; ++a) {
@@ -801,8 +811,8 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
       }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    launch_fill<float>((int64_t)(LY.vec_bytes / 4), (float*)vec, 0.0f, s);
   }
+  launch_fill<float>((int64_t)(LY.vec_bytes / 4), (float*)vec, 0.0f, s);
   const PhaseSet& S = sets[(size_t)sel];
   const int bs = cand_block[sel];
   const int gm = gmult;

@@ -338,9 +338,13 @@ __global__ void k_assemble_coarse_p1(int n, const int32_t* __restrict__ runE, co
 }
 
 // The LDS-staged extension with the node's own data (band index, local run offsets, closest-
-// point fractions, and u at the node) loaded before the staging instead of after it: on large
+// point fractions, and u at the node) loaded before the barrier instead of after it: on large
 // levels, where many workgroups take turns on a CU, those loads then overlap the staging's
-// round trips.  Arithmetic as in k_ext_lds, term for term; NPT as there.
+// round trips.  With 4-byte values the staging indices go out together with the node's data
+// and the staged values together with u (two dependent round trips before the barrier); with
+// 8-byte values the node's data and u go first and the staging follows (measured on the
+// largest level, each order is about 2 % faster for its value size).  Arithmetic as in
+// k_ext_lds, term for term; NPT as there.
 template <int D, typename T, typename TO, int MODE, int NPT>
 __global__ __launch_bounds__(kExtBlock) void k_ext_ldsp(int64_t n, const T* __restrict__ g,
                                                         const int32_t* __restrict__ perm,
@@ -360,30 +364,79 @@ __global__ __launch_bounds__(kExtBlock) void k_ext_ldsp(int64_t n, const T* __re
   const int64_t blk = tile_of_block(remap);
   int32_t i[NPT], pk[NPT];
   T fx[NPT], fy[NPT], fz[NPT], ui[NPT], bi[NPT], wdi[NPT];
+  if constexpr (sizeof(T) == 4) {
+    // the staging of ext_stage, split around the node's loads
+    const int32_t tid = (int32_t)threadIdx.x;
+    const int32_t e0 = blkE[blk], e1 = blkE[blk + 1];
+    const int32_t q0 = blkG[blk] * S, q1 = blkG[blk + 1] * S;
+    int32_t gi[kStageUnroll], lq[kStageUnroll];
 #pragma unroll
-  for (int j = 0; j < NPT; ++j) {
-    const int64_t k = (blk * NPT + j) * kExtBlock + threadIdx.x;
-    i[j] = 0;
-    pk[j] = 0;
-    fx[j] = fy[j] = fz[j] = ui[j] = bi[j] = wdi[j] = T(0);
-    if (k < n) {
-      i[j] = perm[k];
-      pk[j] = packedL[k];
-      fx[j] = frac[k];
-      fy[j] = frac[n + k];
-      if (D == 3) fz[j] = frac[2 * n + k];
+    for (int j = 0; j < kStageUnroll; ++j) {
+      const int32_t e = e0 + tid + j * kExtBlock, q = q0 + tid + j * kExtBlock;
+      gi[j] = e < e1 ? gidx[e] : -1;
+      lq[j] = q < q1 ? lorg[q] : 0;
     }
-  }
 #pragma unroll
-  for (int j = 0; j < NPT; ++j) {
-    const int64_t k = (blk * NPT + j) * kExtBlock + threadIdx.x;
-    if (k < n) {
-      if (MODE != EXT_PLAIN) ui[j] = u[i[j]];
-      if (b && (MODE == EXT_SMOOTH || MODE == EXT_RESID)) bi[j] = b[i[j]];
-      if (wd && (MODE == EXT_SMOOTH || MODE == EXT_RESID)) wdi[j] = wd[i[j]];
+    for (int j = 0; j < NPT; ++j) {
+      const int64_t k = (blk * NPT + j) * kExtBlock + tid;
+      i[j] = 0;
+      pk[j] = 0;
+      fx[j] = fy[j] = fz[j] = ui[j] = bi[j] = wdi[j] = T(0);
+      if (k < n) {
+        i[j] = perm[k];
+        pk[j] = packedL[k];
+        fx[j] = frac[k];
+        fy[j] = frac[n + k];
+        if (D == 3) fz[j] = frac[2 * n + k];
+      }
     }
+    T gv[kStageUnroll];
+#pragma unroll
+    for (int j = 0; j < kStageUnroll; ++j) gv[j] = gi[j] >= 0 ? g[gi[j]] : T(0);
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      const int64_t k = (blk * NPT + j) * kExtBlock + tid;
+      if (k < n) {
+        if (MODE != EXT_PLAIN) ui[j] = u[i[j]];
+        if (b && (MODE == EXT_SMOOTH || MODE == EXT_RESID)) bi[j] = b[i[j]];
+        if (wd && (MODE == EXT_SMOOTH || MODE == EXT_RESID)) wdi[j] = wd[i[j]];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kStageUnroll; ++j) {
+      const int32_t e = e0 + tid + j * kExtBlock, q = q0 + tid + j * kExtBlock;
+      if (e < e1) gl[e - e0] = gv[j];
+      if (q < q1) lo[q - q0] = lq[j];
+    }
+    for (int32_t e = e0 + tid + kStageUnroll * kExtBlock; e < e1; e += kExtBlock) gl[e - e0] = g[gidx[e]];
+    for (int32_t q = q0 + tid + kStageUnroll * kExtBlock; q < q1; q += kExtBlock) lo[q - q0] = lorg[q];
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      const int64_t k = (blk * NPT + j) * kExtBlock + threadIdx.x;
+      i[j] = 0;
+      pk[j] = 0;
+      fx[j] = fy[j] = fz[j] = ui[j] = bi[j] = wdi[j] = T(0);
+      if (k < n) {
+        i[j] = perm[k];
+        pk[j] = packedL[k];
+        fx[j] = frac[k];
+        fy[j] = frac[n + k];
+        if (D == 3) fz[j] = frac[2 * n + k];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < NPT; ++j) {
+      const int64_t k = (blk * NPT + j) * kExtBlock + threadIdx.x;
+      if (k < n) {
+        if (MODE != EXT_PLAIN) ui[j] = u[i[j]];
+        if (b && (MODE == EXT_SMOOTH || MODE == EXT_RESID)) bi[j] = b[i[j]];
+        if (wd && (MODE == EXT_SMOOTH || MODE == EXT_RESID)) wdi[j] = wd[i[j]];
+      }
+    }
+    ext_stage<T>(blk, g, blkE, gidx, blkG, lorg, S, gl, lo);
   }
-  ext_stage<T>(blk, g, blkE, gidx, blkG, lorg, S, gl, lo);
   unsigned long long nv = 0ull;
 #pragma unroll
   for (int j = 0; j < NPT; ++j) {

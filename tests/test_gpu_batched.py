@@ -125,6 +125,39 @@ def test_batched_equals_unbatched_mixed(monkeypatch):
     assert stats[0].tile_block in (128, 256, 512)
 
 
+def test_batched_forms_give_the_same_solve(monkeypatch):
+    """The batched solve is the same bit for bit whether its workgroups stage the extension in
+    LDS (256 lanes) or gather (128 lanes), and whether the residual before restriction covers
+    only the restriction's fine nodes (the default) or every node (CPM_RESID_SUBSET=0): the
+    restriction reads that residual at those nodes only."""
+    import paper_1307_4354_amd as cpm
+
+    torch = torch_cuda()
+    items = W.batch_problems(4, seed=W.SEED_BASE + 45, h_choices=(16, 32), coarse_h_inv=4)
+    p = cpm.make_params(precision=cpm.CPM_MIXED)
+    runs = {}
+    for block, subset in (("256", "1"), ("256", "0"), ("128", "1")):
+        monkeypatch.setenv("CPM_BATCH_BLOCK", block)
+        monkeypatch.setenv("CPM_RESID_SUBSET", subset)
+        bands, fs = _setup(items)
+        flagged = [bool(b.flags(0) & cpm.CPM_BAND_RESID_SUBSET) for b in bands]
+        assert any(flagged) if subset == "1" else not any(flagged)
+        us = [torch.zeros_like(f) for f in fs]
+        nbytes = cpm.cpm_workspace_size_batched(bands, p)
+        work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        status, stats = cpm.cpm_solve_batched(bands, p, fs, us, work, nbytes, rtol=1e-10, max_cycles=80)
+        assert status == cpm.CPM_OK
+        assert stats[0].tile_block == int(block)
+        log("batched block %s, residual subset %s: cycles %s" % (block, subset, [st.cycles for st in stats]))
+        runs[(block, subset)] = ([host(u) for u in us], [st.history() for st in stats])
+    ref_u, ref_h = runs[("256", "1")]
+    for key in (("256", "0"), ("128", "1")):
+        us, hs = runs[key]
+        for k in range(len(items)):
+            assert np.array_equal(us[k], ref_u[k]), (key, k)
+            assert np.array_equal(hs[k], ref_h[k]), (key, k)
+
+
 def test_batched_converged_problem_is_frozen():
     """A problem with E f = 0 gets u = 0 (from a non-zero start) and no cycle while the others
     run."""
