@@ -10,6 +10,12 @@
       kernel at one grid size, calibrated by the same counters on the largest plain copy
       dispatch of the run (B bytes read and B bytes written), and the SHA-256 of the
       kernel's source files, so a reader can tell whether the counters are stale.
+
+  python -m paper_1307_4354_amd.prof_summary rates KERNEL_TRACE_CSV --fetch CSV --write CSV
+      --copy-bytes B --cmd "..." [--top N]
+      Markdown table per (kernel, grid size) of the trace's average duration beside the
+      copy-calibrated FETCH_SIZE + WRITE_SIZE per dispatch (medians) of the counter runs, and
+      the HBM rate they give; the kernels are ranked by their total traced time.
 """
 from __future__ import annotations
 
@@ -95,6 +101,44 @@ def traffic(args) -> dict:
             "sources": args.sources, "source_sha256": sources_sha256(args.sources)}
 
 
+def rates_table(args) -> str:
+    rows = list(csv.DictReader(open(args.csv)))
+    dur: Dict[tuple, List[int]] = collections.defaultdict(list)
+    for r in rows:
+        dur[(r["Kernel_Name"], int(r["Grid_Size_X"]))].append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    fr = _counter(args.fetch, "FETCH_SIZE")
+    wr = _counter(args.write, "WRITE_SIZE")
+    kf = args.copy_bytes / (_copy_kib(fr) * 1024.0)
+    kw = args.copy_bytes / (_copy_kib(wr) * 1024.0)
+    fk: Dict[tuple, List[float]] = collections.defaultdict(list)
+    wk: Dict[tuple, List[float]] = collections.defaultdict(list)
+    for src, dst in ((fr, fk), (wr, wk)):
+        for r in src:
+            dst[(r["Kernel_Name"], int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+    total = sum(sum(v) for v in dur.values())
+    out = ["Command: `%s`" % args.cmd, "",
+           "Durations from the kernel trace; traffic = median FETCH_SIZE x %.3f + median WRITE_SIZE x %.3f "
+           "per dispatch (factors from a plain copy of %.0f bytes in the counter runs); rate = traffic / "
+           "average duration.  Kernels with no counter dispatch at that grid size are left out." %
+           (kf, kw, args.copy_bytes), "",
+           "| share of traced time | calls | avg us | fetch MB | write MB | GB/s | grid | kernel |",
+           "|---:|---:|---:|---:|---:|---:|---:|---|"]
+    shown = 0
+    for key, v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
+        if key not in fk or key not in wk:
+            continue
+        avg_ns = sum(v) / len(v)
+        fb = statistics.median(fk[key]) * 1024.0 * kf
+        wb = statistics.median(wk[key]) * 1024.0 * kw
+        out.append("| %.1f%% | %d | %.2f | %.1f | %.1f | %.0f | %d | `%s` |" % (
+            100.0 * sum(v) / total, len(v), avg_ns / 1e3, fb / 1e6, wb / 1e6, (fb + wb) / avg_ns, key[1],
+            _short(key[0])))
+        shown += 1
+        if shown >= args.top:
+            break
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -110,9 +154,18 @@ def main(argv=None) -> None:
     q.add_argument("--copy-bytes", type=float, required=True)
     q.add_argument("--cmd", required=True)
     q.add_argument("--sources", nargs="*", default=EXT_SOURCES)
+    rt = sub.add_parser("rates")
+    rt.add_argument("csv")
+    rt.add_argument("--fetch", required=True)
+    rt.add_argument("--write", required=True)
+    rt.add_argument("--copy-bytes", type=float, required=True)
+    rt.add_argument("--cmd", required=True)
+    rt.add_argument("--top", type=int, default=25)
     a = ap.parse_args(argv)
     if a.mode == "trace":
         sys.stdout.write(trace_table(a.csv, a.cmd, a.top))
+    elif a.mode == "rates":
+        sys.stdout.write(rates_table(a))
     else:
         json.dump(traffic(a), sys.stdout, indent=1)
         sys.stdout.write("\n")
