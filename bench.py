@@ -237,7 +237,10 @@ def headline_torus256(args):
         "roofline": roofline,
     }
     if not args.no_extras:
-        line["h1/64_oracle"] = oracle_at_64(args, cpm, torch)
+        o64 = oracle_at_64(args, cpm, torch)
+        if "cpu_baseline" in o64:
+            line["cpu_baseline"] = o64.pop("cpu_baseline")
+        line["h1/64_oracle"] = o64
         line["extras"] = secondary_surfaces(cpm, torch)
     print(json.dumps(line), flush=True)
 
