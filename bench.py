@@ -199,6 +199,11 @@ def headline_torus256(args):
                 "traffic": _measured_traffic(_traffic_file("torus256"), kname, grid0),
                 "kernel": "%s (%s)" % (kname, what), "grid": grid0, "avg_launch_us": round(avg_us, 3),
                 "alg_bytes_per_node": bpn, "alg_bytes_per_launch": int(alg_bytes)}
+    if roofline["traffic"]:
+        # the counter-measured bytes over the same live launch time, beside the algorithmic rate
+        tr = roofline["traffic"] / (avg_us * 1e-6) / 1e9
+        roofline["traffic_rate"] = round(tr, 1)
+        roofline["traffic_frac"] = round(tr / HBM_PEAK_GBS, 4)
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
