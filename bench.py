@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=20)
+    ap.add_argument("--cpu-cycles", type=int, default=100)
     ap.add_argument("--kernel-reps", type=int, default=100)
     ap.add_argument("--no-solve", action="store_true", help="skip the time-to-tolerance solves")
     ap.add_argument("--no-extras", action="store_true",
