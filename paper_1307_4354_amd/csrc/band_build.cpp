@@ -766,7 +766,7 @@ cpm_status build_stencil_order(HostLevel& Lv, int level, std::string& err) {
   for (int64_t k = 0; k < n; ++k) {
     const int32_t i = order[(size_t)k];
     const int32_t dx = bx[(size_t)i] - gx0;
-    bool fresh = g < 0 || by[(size_t)i] != gy || bz[(size_t)i] != gz || dx >= (1 << kXoffBits);
+    bool fresh = g < 0 || by[(size_t)i] != gy || bz[(size_t)i] != gz || dx < 0 || dx >= (1 << kXoffBits);
     if (!fresh) {
       for (int s = 0; s < S; ++s)
         if (Lv.runE[(size_t)(s * n + i)] - dx != org[(size_t)s]) {
