@@ -309,8 +309,10 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
  * problems, and 8 consecutive V-cycles of the whole batch are one captured HIP graph.
  * Each problem stops on the device, through its own flag, when it reaches rtol or
  * max_cycles, so it performs exactly the cycles of its own solve; the host reads the
- * number of finished problems once per graph launch.  A problem with E f = 0 gets u = 0
- * and no cycle.  f[k], u[k] are device vectors of problem k (u[k]: the start, normally 0);
+ * number of finished problems once per graph launch.  The workgroup size of the batched
+ * launches is timed on the first solve of a batch (its bands, their sizes, the device) and
+ * reused by later solves of the same batch.  A problem with E f = 0 gets u = 0 and no
+ * cycle.  f[k], u[k] are device vectors of problem k (u[k]: the start, normally 0);
  * work has cpm_workspace_size_batched bytes.  precision must be CPM_MIXED.  stats: nprob
  * entries (NULL allowed).  Returns CPM_E_NOCONV if any problem missed rtol,
  * CPM_E_DIVERGED if any residual was not finite.  Synchronous on return. */

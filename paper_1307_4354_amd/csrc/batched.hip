@@ -18,6 +18,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "capi_internal.h"
@@ -407,6 +409,23 @@ Layout layout(int nprob, const cpm_band* bands) {
   return L;
 }
 
+// Workgroup-size choices of earlier batched solves, keyed by the device, the batch's bands
+// (handle and per-level sizes) and the smoothing counts: a repeated solve of the same batch
+// reuses the timed choice instead of timing the candidates again.  A stale entry (a band freed
+// and another built at the same address with the same sizes) only costs speed.
+std::mutex g_tune_mu;
+std::map<std::vector<int64_t>, std::pair<int, int>> g_tune_cache;
+
+std::vector<int64_t> tune_key(int nprob, const cpm_band* bands, const cpm_params& P, int device) {
+  std::vector<int64_t> k{device, nprob, P.nu1, P.nu2};
+  for (int p = 0; p < nprob; ++p) {
+    k.push_back((int64_t)(uintptr_t)bands[p]);
+    k.push_back(bands[p]->L);
+    for (int l = 0; l < bands[p]->L; ++l) k.push_back(bands[p]->dev[(size_t)l].n);
+  }
+  return k;
+}
+
 // LDS bytes one staging workgroup of a level takes for values of vsize bytes (the layout of
 // launch_ext), 0 when the level has no staging tables for workgroups of kExtBlock slots
 size_t stage_bytes(const DevLevel& D, int dim, size_t vsize) {
@@ -776,9 +795,22 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
     for (int ci = 0; ci < 3; ++ci)
       if (cand_block[ci] == v) forced = ci;
   }
+  int dev_id = 0;
+  (void)hipGetDevice(&dev_id);
+  const std::vector<int64_t> tkey = tune_key(nprob, bands, P, dev_id);
+  bool cached = false;
+  if (forced < 0) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto itc = g_tune_cache.find(tkey);
+    if (itc != g_tune_cache.end()) {
+      sel = itc->second.first;
+      gmult = itc->second.second;
+      cached = true;
+    }
+  }
   if (forced >= 0) {
     sel = forced;
-  } else {
+  } else if (!cached) {
     int abig = 0;
     int64_t nbig = -1;
     for (int a = 1; a < plan.A; ++a) {
@@ -811,6 +843,8 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
       }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[tkey] = {sel, gmult};
   }
   launch_fill<float>((int64_t)(LY.vec_bytes / 4), (float*)vec, 0.0f, s);
   const PhaseSet& S = sets[(size_t)sel];
