@@ -413,6 +413,7 @@ Layout layout(int nprob, const cpm_band* bands) {
 // (handle and per-level sizes) and the smoothing counts: a repeated solve of the same batch
 // reuses the timed choice instead of timing the candidates again.  A stale entry (a band freed
 // and another built at the same address with the same sizes) only costs speed.
+constexpr size_t kTuneCacheMax = 64;
 std::mutex g_tune_mu;
 std::map<std::vector<int64_t>, std::pair<int, int>> g_tune_cache;
 
@@ -844,6 +845,7 @@ cpm_status cpm_solve_batched(int nprob, const cpm_band* bands, const cpm_params*
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tune_cache.size() >= kTuneCacheMax) g_tune_cache.clear();  // bounded: many distinct batches
     g_tune_cache[tkey] = {sel, gmult};
   }
   launch_fill<float>((int64_t)(LY.vec_bytes / 4), (float*)vec, 0.0f, s);
