@@ -179,6 +179,7 @@ def headline_torus256(args):
     if not args.no_solve:
         for name, p in (("f64", p64), ("mixed", pmx),
                         ("f64_fmg_start", cpm.make_params(c=cfg.problem.c, fmg=True)),
+                        ("mixed_fmg_start", cpm.make_params(c=cfg.problem.c, fmg=True, precision=cpm.CPM_MIXED)),
                         ("f64_W_cycle", cpm.make_params(c=cfg.problem.c, gamma=2))):
             sol[name], tt[name] = _solve(cpm, torch, band, p, fd, max_cycles=80)
         tt["speedup_mixed_over_f64"] = tt["f64"]["seconds"] / tt["mixed"]["seconds"]

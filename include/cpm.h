@@ -113,8 +113,10 @@ typedef struct {
   int fmg;            /* cpm_solve only: 1 = start from the full-multigrid (nested iteration)
                          approximation instead of the given u: f restricted to every level,
                          coarsest solved, then per finer level cubic closest-point
-                         interpolation of the coarser solution and one cycle (precision
-                         CPM_F64, smoother CPM_SMOOTH_JACOBI) */
+                         interpolation of the coarser solution and one cycle (smoother
+                         CPM_SMOOTH_JACOBI; the start runs in double precision, also before
+                         CPM_MIXED cycles, whose workspace then holds the double-precision
+                         layout too) */
   int residual_mode;  /* CPM_RESIDUAL_CONSISTENT (0): the residual passed to the coarse grid
                          is E f - A u (= E(f + N u) - delta u), whose fixed point solves
                          A u = E f.  CPM_RESIDUAL_VERBATIM (1): Algorithm 4.1 step 2 as printed,
@@ -215,7 +217,8 @@ cpm_status cpm_band_export(cpm_band band, int level, int32_t* idx_host, double* 
 cpm_status cpm_band_export_stencils(cpm_band band, int level, int32_t* runE, int32_t* nbr,
                                     int32_t* runP, int32_t* runR);
 
-/* Bytes of device workspace a vcycle / solve with these parameters needs. */
+/* Bytes of device workspace a vcycle / solve with these parameters needs (CPM_MIXED with
+ * fmg: the larger of the mixed and the double-precision layouts). */
 cpm_status cpm_workspace_size(cpm_band band, const cpm_params* params, size_t* bytes);
 
 typedef enum { CPM_DTYPE_F64 = 0, CPM_DTYPE_F32 = 1 } cpm_dtype;

@@ -16,7 +16,7 @@ same and the refinement converges to the double-precision fixed point A^{-1} E f
 """
 from __future__ import annotations
 
-from typing import List
+from typing import List, Optional
 
 import numpy as np
 import scipy.linalg as sla
@@ -64,13 +64,14 @@ def _vcycle32(H32: _H32, H: Hierarchy, l: int, e: np.ndarray, rhs: np.ndarray, a
 
 
 def solve_mixed(H: Hierarchy, f: np.ndarray, p: Params, rtol: float = 1e-10,
-                max_cycles: int = 60) -> SolveResult:
-    """Outer loop in float64, one float32 V-cycle per outer step (A-space RHS on level 0)."""
+                max_cycles: int = 60, u0: Optional[np.ndarray] = None) -> SolveResult:
+    """Outer loop in float64, one float32 V-cycle per outer step (A-space RHS on level 0),
+    from u0 (default 0; e.g. the float64 full-multigrid start of vcycle.fmg_start)."""
     H32 = _H32(H)
     lu = sla.lu_factor(coarse_matrix(H, p.c))
     d0 = delta(H, 0, p.c)
     bn = rhs_norm(H, f)
-    u = np.zeros(H.levels[0].n)
+    u = np.zeros(H.levels[0].n) if u0 is None else np.array(u0, dtype=np.float64)
     res: List[float] = []
     inc: List[float] = []
     r = H.E[0] @ (f + H.N[0] @ u) - d0 * u

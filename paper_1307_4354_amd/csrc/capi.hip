@@ -308,7 +308,7 @@ static T* carve(char*& p, size_t count) {
   return r;
 }
 
-size_t workspace_bytes(const cpm_band b, int precision) {
+size_t layout_bytes(const cpm_band b, int precision) {
   size_t tot = 0;
   for (int l = 0; l < b->L; ++l) {
     const size_t n = (size_t)b->dev[(size_t)l].n;
@@ -320,6 +320,14 @@ size_t workspace_bytes(const cpm_band b, int precision) {
     }
   }
   return tot + 256;
+}
+
+// The caller's workspace: the level vectors of its precision; a mixed-precision solve with
+// the full-multigrid start first runs that start in the float64 layout of the same buffer.
+size_t workspace_bytes(const cpm_band b, const cpm_params& p) {
+  size_t s = layout_bytes(b, p.precision);
+  if (p.fmg && p.precision != CPM_F64) s = std::max(s, layout_bytes(b, CPM_F64));
+  return s;
 }
 
 template <typename T>
@@ -992,7 +1000,7 @@ cpm_status tune_sweep_forms(cpm_band b) {
   cpm_status st = ensure_coarse(b, 1.0);
   if (st != CPM_OK) return st;
   const int64_t n0 = b->dev[0].n;
-  const size_t wb = workspace_bytes(b, CPM_F64);
+  const size_t wb = layout_bytes(b, CPM_F64);
   double* f = (double*)dev_alloc(b, n0 * sizeof(double));
   double* u = (double*)dev_alloc(b, n0 * sizeof(double));
   void* work = dev_alloc(b, wb);
@@ -1123,8 +1131,8 @@ cpm_status validate_params(const cpm_band b, const cpm_params* p) {
     set_error("cycle index gamma must be in 0..4");
     return CPM_E_INVALID;
   }
-  if (p->fmg && (p->precision != CPM_F64 || p->smoother != CPM_SMOOTH_JACOBI)) {
-    set_error("the full-multigrid start runs with precision CPM_F64 and smoother CPM_SMOOTH_JACOBI");
+  if (p->fmg && p->smoother != CPM_SMOOTH_JACOBI) {
+    set_error("the full-multigrid start runs with smoother CPM_SMOOTH_JACOBI");
     return CPM_E_INVALID;
   }
   if (p->fmg && !fmg_ok(b)) {
@@ -1579,7 +1587,7 @@ cpm_status cpm_workspace_size(cpm_band band, const cpm_params* params, size_t* b
     set_error("null argument");
     return CPM_E_INVALID;
   }
-  *bytes = workspace_bytes(band, params->precision);
+  *bytes = workspace_bytes(band, *params);
   return CPM_OK;
 }
 
@@ -1699,7 +1707,7 @@ cpm_status cpm_vcycle(cpm_band band, const cpm_params* params, const double* f, 
     set_error("cpm_vcycle runs the double-precision cycles (Jacobi or standard relaxation) only");
     return CPM_E_INVALID;
   }
-  if (work_bytes < workspace_bytes(band, params->precision)) {
+  if (work_bytes < workspace_bytes(band, *params)) {
     set_error("workspace too small");
     return CPM_E_WORKSPACE;
   }
@@ -1731,7 +1739,7 @@ cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, d
   }
   cpm_status st = validate_params(band, params);
   if (st != CPM_OK) return st;
-  if (work_bytes < workspace_bytes(band, params->precision)) {
+  if (work_bytes < workspace_bytes(band, *params)) {
     set_error("workspace too small");
     return CPM_E_WORKSPACE;
   }
@@ -1767,9 +1775,17 @@ cpm_status cpm_solve(cpm_band band, const cpm_params* params, const double* f, d
   }
   if (p.fmg) {
     enqueue_fmg(band, p, f, u, work, band->stream);
+    if (p.precision != CPM_F64) {
+      // the start used the workspace in its double-precision layout: the mixed cycle's
+      // first residual (float32 copy in the finest level's f) is that of the start
+      LevelBufs<float> B[kMaxLevels];
+      double* g64 = nullptr;
+      carve_levels<float>(band, work, B, &g64);
+      enqueue_resid64(band, f, u, g64, B[0].f, p.c, band->stream);
+    }
     if ((st = check_launch("full-multigrid start")) != CPM_OK) return st;
   }
-  double prev = p.precision == CPM_F64 ? NAN : r0 / bn;
+  double prev = p.precision == CPM_F64 || p.fmg ? NAN : r0 / bn;
   st = CPM_E_NOCONV;
   // stagnation: the stopping quantity has not dropped below 0.99 of its best value for
   // kStallCycles cycles (it has reached the rounding floor of its own evaluation)
@@ -1841,7 +1857,7 @@ cpm_status cpm_run_cycles(cpm_band band, const cpm_params* params, const double*
   }
   cpm_status st = validate_params(band, params);
   if (st != CPM_OK) return st;
-  if (work_bytes < workspace_bytes(band, params->precision)) {
+  if (work_bytes < workspace_bytes(band, *params)) {
     set_error("workspace too small");
     return CPM_E_WORKSPACE;
   }
@@ -1888,7 +1904,7 @@ cpm_status cpm_time_kernel(cpm_band band, const cpm_params* params, int which, i
   }
   cpm_status st = validate_params(band, params);
   if (st != CPM_OK) return st;
-  if (work_bytes < workspace_bytes(band, params->precision)) {
+  if (work_bytes < workspace_bytes(band, *params)) {
     set_error("workspace too small");
     return CPM_E_WORKSPACE;
   }

@@ -116,7 +116,8 @@ cpm_status enter(cpm_band b, void* user);
 cpm_status leave(cpm_band b, void* user);
 cpm_status check_launch(const char* what);
 cpm_status ensure_coarse(cpm_band b, double c);
-size_t workspace_bytes(const cpm_band b, int precision);
+size_t layout_bytes(const cpm_band b, int precision);
+size_t workspace_bytes(const cpm_band b, const cpm_params& p);
 template <typename T>
 void carve_levels(const cpm_band b, void* work, LevelBufs<T>* B, double** g64);
 template <typename T>

@@ -4,7 +4,8 @@
   contracts at least as fast per cycle.
 * The full-multigrid start (nested iteration from the coarsest level) is already within a
   small factor of the discretization error (the classical FMG property), and the solve from
-  it reaches the same fixed point in fewer cycles than from u = 0.
+  it reaches the same fixed point in fewer cycles than from u = 0; so does the mixed-precision
+  refinement started from it.
 """
 import numpy as np
 import pytest
@@ -46,3 +47,22 @@ def test_fmg_start_reaches_discretization_error(cfg):
     from_fmg = ov.solve(H, f, p, rtol=1e-11, max_cycles=80, fmg=True)
     assert from_fmg.cycles < conv.cycles
     assert np.max(np.abs(from_fmg.u - conv.u)) <= 1e-9 * np.max(np.abs(conv.u))
+
+
+def test_mixed_solve_from_fmg_start_reaches_the_direct_solution():
+    """The mixed-precision refinement started from the float64 full-multigrid start reaches
+    the sparse direct solution of A u = E f (its float64 residual decides the fixed point)
+    in fewer outer cycles than from u = 0."""
+    from oracle import mixed as omx
+
+    cfg = W.config_circle(64, 4)
+    H = _hier(cfg)
+    f = cfg.problem.f(H.levels[0].cp)
+    p = ov.Params()
+    u0 = ov.fmg_start(H, f, p, ov.CoarseSolver(H, p))
+    from0 = omx.solve_mixed(H, f, p, rtol=1e-10, max_cycles=60)
+    fromf = omx.solve_mixed(H, f, p, rtol=1e-10, max_cycles=60, u0=u0)
+    u_star = od.solve_direct(H.levels[0], H.E[0] @ f, 1.0)
+    assert fromf.relres[-1] < 1e-10
+    assert np.max(np.abs(fromf.u - u_star)) <= 1e-9 * np.max(np.abs(u_star))
+    assert len(fromf.relres) < len(from0.relres)
