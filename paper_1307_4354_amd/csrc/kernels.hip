@@ -383,11 +383,11 @@ __global__ __launch_bounds__(kExtBlock) void k_ext_ldsp(int64_t n, const T* __re
       pk[j] = 0;
       fx[j] = fy[j] = fz[j] = ui[j] = bi[j] = wdi[j] = T(0);
       if (k < n) {
-        i[j] = perm[k];
-        pk[j] = packedL[k];
-        fx[j] = frac[k];
-        fy[j] = frac[n + k];
-        if (D == 3) fz[j] = frac[2 * n + k];
+        i[j] = ld_nt(perm + k);
+        pk[j] = ld_nt(packedL + k);
+        fx[j] = ld_nt(frac + k);
+        fy[j] = ld_nt(frac + n + k);
+        if (D == 3) fz[j] = ld_nt(frac + 2 * n + k);
       }
     }
     T gv[kStageUnroll];
@@ -419,11 +419,11 @@ __global__ __launch_bounds__(kExtBlock) void k_ext_ldsp(int64_t n, const T* __re
       pk[j] = 0;
       fx[j] = fy[j] = fz[j] = ui[j] = bi[j] = wdi[j] = T(0);
       if (k < n) {
-        i[j] = perm[k];
-        pk[j] = packedL[k];
-        fx[j] = frac[k];
-        fy[j] = frac[n + k];
-        if (D == 3) fz[j] = frac[2 * n + k];
+        i[j] = ld_nt(perm + k);
+        pk[j] = ld_nt(packedL + k);
+        fx[j] = ld_nt(frac + k);
+        fy[j] = ld_nt(frac + n + k);
+        if (D == 3) fz[j] = ld_nt(frac + 2 * n + k);
       }
     }
 #pragma unroll
@@ -524,13 +524,13 @@ __global__ __launch_bounds__(256) void k_gemv(int n, const double* __restrict__ 
     double z[8], xv[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      z[q] = zr[j + q * 256];
+      z[q] = ld_nt(zr + j + q * 256);
       xv[q] = (double)x[j + q * 256];
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) s += z[q] * xv[q];
   }
-  for (; j < n; j += 256) s += zr[j] * (double)x[j];
+  for (; j < n; j += 256) s += ld_nt(zr + j) * (double)x[j];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   __shared__ double part[4];
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
