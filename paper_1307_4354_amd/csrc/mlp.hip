@@ -112,9 +112,9 @@ __device__ __forceinline__ float node_features(int64_t k, int64_t n, const T* __
                                                const TF* __restrict__ frac, uint32_t* xw) {
   constexpr int R = D == 2 ? 3 : 9;
   constexpr int P = 3 * R;
-  const uint32_t mask = pmask[k];
+  const uint32_t mask = ld_nt(pmask + k);
   // the node's rows: its group's rows (one per group of consecutive nodes) plus its offset
-  const int32_t pk = ppk[k];
+  const int32_t pk = ld_nt(ppk + k);
   const int32_t* grow = prow + (pk >> kPatchBits);
   const int32_t toff = pk & (kPatchRun - 1);
   // every load is issued unconditionally (the index clamped into the array, the value of an
@@ -153,7 +153,7 @@ __device__ __forceinline__ float node_features(int64_t k, int64_t n, const T* __
   TF w[4];
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    cubic_weights<TF>(frac[a * n + k], w);
+    cubic_weights<TF>(ld_nt(frac + a * n + k), w);
 #pragma unroll
     for (int j = 0; j < 4; ++j) put(P + 4 * a + j, (float)w[j]);
   }
