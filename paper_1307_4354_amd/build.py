@@ -20,7 +20,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 ARCH = os.environ.get("CPM_OFFLOAD_ARCH", "gfx950")
 
 HOST_SOURCES = ["band_build.cpp"]
-HIP_SOURCES = ["kernels.hip", "capi.hip", "extras.hip", "mlp.hip", "batched.hip", "noalloc.hip"]
+HIP_SOURCES = ["kernels.hip", "capi.hip", "extras.hip", "mlp.hip", "batched.hip", "noalloc.hip", "coarse.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-fPIC", "-std=c++17", "--offload-arch=" + ARCH,

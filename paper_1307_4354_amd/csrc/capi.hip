@@ -219,7 +219,20 @@ static cpm_status coarse_inverse(cpm_band b, double c, int kind, double** M, dou
   return CPM_OK;
 }
 
-cpm_status ensure_coarse(cpm_band b, double c) { return coarse_inverse(b, c, 0, &b->coarseM, &b->coarse_c); }
+cpm_status ensure_coarse(cpm_band b, double c) {
+  if (b->coarseM && b->coarse_c == c) return CPM_OK;
+  b->coarse_cols = 0;
+  cpm_status st = coarse_inverse(b, c, 0, &b->coarseM, &b->coarse_c);
+  if (st != CPM_OK) return st;
+  // Z = A_c^{-1} E_c is zero outside the B_interp columns: keep those in the left half
+  const DevLevel& D = b->dev[(size_t)(b->L - 1)];
+  if (D.ilist && D.m > 0 && D.m < D.n) {
+    launch_compact_cols((int)D.n, (int)D.m, 2 * D.n, b->coarseM, D.ilist, b->stream);
+    if ((st = check_launch("coarse column compaction")) != CPM_OK) return st;
+    b->coarse_cols = (int)D.m;
+  }
+  return CPM_OK;
+}
 
 // Variable coefficient: D = c + sigma on every level for this c.
 static cpm_status ensure_vc_diag(cpm_band b, double c) {
@@ -608,7 +621,10 @@ void vcycle_level(const cpm_band b, int l, LevelBufs<T>* B, const T* rhsA, const
   const LaunchCfg lc = level_cfg(D);
   if (l == b->L - 1) {
     // coarsest: u = A_c^{-1} E_c f  (f-space right-hand side)
-    launch_coarse_gemv<T>((int)D.n, b->coarseM + D.n, 2 * D.n, B[l].f, B[l].u, s);
+    if (b->coarse_cols > 0)
+      launch_coarse_gemv_cols<T>((int)D.n, b->coarse_cols, b->coarseM, 2 * D.n, D.ilist, B[l].f, B[l].u, s);
+    else
+      launch_coarse_gemv<T>((int)D.n, b->coarseM + D.n, 2 * D.n, B[l].f, B[l].u, s);
     return;
   }
   const T* f = rhsA ? nullptr : B[l].f;

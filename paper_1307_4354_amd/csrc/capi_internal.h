@@ -47,9 +47,11 @@ struct cpm_band_s {
   // captures the cycle graphs (the legacy default stream cannot be captured)
   hipStream_t stream = nullptr;
   hipStream_t own = nullptr;
-  // coarsest level: [A_c | Z] after Gauss-Jordan, Z = A_c^{-1} E_c at column offset n
+  // coarsest level: [A_c | Z] after Gauss-Jordan, Z = A_c^{-1} E_c at column offset n; with
+  // coarse_cols > 0 the left half of each row also holds Z's B_interp columns (list order)
   double coarse_c = 0.0 / 0.0;
   double* coarseM = nullptr;
+  int coarse_cols = 0;
   // standard relaxation: [A_c | A_c^{-1}] for coarse_std_c, per-level omega / diag(A) for (std_c, std_omega)
   double* coarseS = nullptr;
   double coarse_std_c = 0.0 / 0.0;
@@ -116,6 +118,11 @@ cpm_status enter(cpm_band b, void* user);
 cpm_status leave(cpm_band b, void* user);
 cpm_status check_launch(const char* what);
 cpm_status ensure_coarse(cpm_band b, double c);
+// the coarsest solve on Z's B_interp columns (csrc/coarse.hip)
+void launch_compact_cols(int n, int m, int64_t ld, double* M, const int32_t* col, hipStream_t s);
+template <typename T>
+void launch_coarse_gemv_cols(int n, int m, const double* Z, int64_t ld, const int32_t* col, const T* x, T* y,
+                             hipStream_t s);
 size_t layout_bytes(const cpm_band b, int precision);
 size_t workspace_bytes(const cpm_band b, const cpm_params& p);
 template <typename T>
