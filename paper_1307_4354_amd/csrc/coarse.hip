@@ -9,6 +9,8 @@
 // as it was for the batched solver, which reads it in place.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "capi_internal.h"
 #include "kernels_dev.h"
 
