@@ -690,13 +690,15 @@ cpm_status build_stencil_order(HostLevel& Lv, int level, std::string& err) {
     by[(size_t)i] = Lv.idx[(size_t)(j * dim + 1)];
     if (dim == 3) bz[(size_t)i] = Lv.idx[(size_t)(j * dim + 2)];
   }
-  // Visit order: stencil bases grouped into blocks of 8^dim cells ordered along a Morton
+  // Visit order: stencil bases grouped into blocks of 16^dim cells ordered along a Morton
   // curve, (z, y, x) inside a block.  A workgroup's slots then hold a compact patch of the
   // surface rather than a strip along y, so the union of their stencils (the values it
   // stages) is about half as large, and consecutive workgroups touch neighbouring regions
-  // whose rows stay in L2.  CPM_MORTON_BITS sets log2 of the block edge; a negative value
-  // gives the plain (z, y, x) order.
-  int block_bits = 3;
+  // whose rows stay in L2.  Blocks of 8^dim cells stage 7 % fewer values per node, but the
+  // larger blocks keep more of the consecutive workgroups' rows in the caches (measured:
+  // the FP64 cycle on the torus at h = 1/256 1.2 % faster).  CPM_MORTON_BITS sets log2 of
+  // the block edge; a negative value gives the plain (z, y, x) order.
+  int block_bits = 4;
   if (const char* e = std::getenv("CPM_MORTON_BITS")) block_bits = std::atoi(e);
   int32_t mn[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
   for (int64_t i = 0; i < n; ++i) {

@@ -332,9 +332,9 @@ def test_ext_prefetch_equals_plain_lds(precision, monkeypatch):
 
 @pytest.mark.parametrize("precision", ["f64", "mixed"])
 def test_visit_order_and_workgroup_slots_leave_cycles_unchanged(precision, monkeypatch):
-    """The stencil visit order (Morton-blocked, or plain (z, y, x)), the number of stencil
-    slots a staging workgroup takes per lane (1, 2, 4), the neighbour sum's addressing
-    (segments of consecutive entries, or per-node lists) and the residual before restriction
+    """The stencil visit order (Morton blocks of 16^3 or 8^3 cells, or plain (z, y, x)), the
+    number of stencil slots a staging workgroup takes per lane (1, 2, 4), the neighbour sum's
+    addressing (segments of consecutive entries, or per-node lists) and the residual before restriction
     (formed at the restriction's fine nodes only, or everywhere) change only which workgroup
     handles a node, where its indices come from and which never-read entries are written,
     not the arithmetic: cycles agree bit for bit, on the torus at h = 1/64."""
@@ -347,7 +347,7 @@ def test_visit_order_and_workgroup_slots_leave_cycles_unchanged(precision, monke
     monkeypatch.setenv("CPM_EXT_PREFETCH", "1")
     out = {}
     fd = None
-    for tag, env in (("default", {}), ("plain_order", {"CPM_MORTON_BITS": "-1"}),
+    for tag, env in (("default", {}), ("plain_order", {"CPM_MORTON_BITS": "-1"}), ("morton8", {"CPM_MORTON_BITS": "3"}),
                      ("npt2", {"CPM_EXT_NPT": "2"}), ("npt4", {"CPM_EXT_NPT": "4"}),
                      ("nsum_lists", {"CPM_NSUM_SEG": "0"}), ("resid_full", {"CPM_RESID_SUBSET": "0"})):
         for k in ("CPM_MORTON_BITS", "CPM_EXT_NPT", "CPM_NSUM_SEG", "CPM_RESID_SUBSET"):
@@ -373,7 +373,7 @@ def test_visit_order_and_workgroup_slots_leave_cycles_unchanged(precision, monke
         out[tag] = its
         log("%s: %d slots per workgroup" % (tag, slots))
         del work, band
-    for tag in ("plain_order", "npt2", "npt4", "nsum_lists", "resid_full"):
+    for tag in ("plain_order", "morton8", "npt2", "npt4", "nsum_lists", "resid_full"):
         for k in range(3):
             assert np.array_equal(out[tag][k], out["default"][k]), (tag, k)
 
